@@ -1,0 +1,296 @@
+"""FP64 CPU oracle for the fire-temperature inversion.
+
+TEST INFRASTRUCTURE ONLY: the slow, plain reference the GPU library is checked
+against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import it; the product path never does.  It shares no code
+with the GPU library (``paper_2608_07580_amd``) and does not import it.
+
+Parts (Keely et al., real-time physics inversion of VSWIR fire spectra):
+  * ``gauss_hermite``: physicists' Gauss-Hermite rule, nodes by the
+    Golub-Welsch eigenvalue method (eigenvalues of the symmetric Jacobi matrix
+    of the Hermite recurrence), weights by the Christoffel function.  Used to
+    integrate the lognormal temperature pdf of the thermal term, Sec. 2.2
+    eq. (thermal).
+  * ``band_tables``: Gaussian spectral-response resampling of the
+    high-resolution atmosphere onto the instrument bands (Sec. 2.4 resamples
+    spectra onto the instrument grid with a Gaussian SRF) and the per-band
+    factors of eq. (solar).
+  * ``forward`` / ``retrieve``: the C oracle (``oracle.c``): forward model of
+    eq. (fm)/(solar)/(thermal) with the analytic Jacobian, the masked loss of
+    eq. (loss) minimised in the z coordinate of eq. (affine) by
+    Levenberg-Marquardt, Gauss-Newton covariance and mixture moments.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# status bits of the retrieval (same meaning as the public status word)
+ST_GTOL, ST_XTOL, ST_FTOL, ST_MAXITER = 1, 2, 4, 8
+ST_NONFINITE, ST_DAMPING, ST_COVSING, ST_ATBOUND = 16, 32, 64, 128
+ST_NODOF = 1024
+ST_CONVERGED = ST_GTOL | ST_XTOL | ST_FTOL
+
+LAMBDA_REF_NM = 1440.0
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (OpenMP, -O2, IEEE)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-D_GNU_SOURCE", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        fp = C.POINTER(C.c_float)
+        L.orc_planck.restype = C.c_double
+        L.orc_planck.argtypes = [C.c_double, C.c_double, dp]
+        L.orc_planck_many.restype = None
+        L.orc_planck_many.argtypes = [C.c_long, dp, dp, dp, dp]
+        L.orc_forward.restype = C.c_int
+        L.orc_forward.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, C.c_int, dp, dp,
+                                  C.c_int, C.c_long, dp, dp, dp, C.c_int]
+        L.orc_retrieve.restype = C.c_int
+        L.orc_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
+                                   C.c_int, dp, dp, dp, dp, C.c_long, fp,
+                                   C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.c_int,
+                                   dp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_uint)]
+        L.orc_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
+
+
+# ----------------------------------------------------------------------------
+# Gauss-Hermite rule (Golub & Welsch 1969)
+# ----------------------------------------------------------------------------
+def _orthonormal_hermite(q: int, x):
+    """p_0..p_q at x, orthonormal for the weight e^{-x^2}:
+    p_0 = pi^-1/4, p_{j+1} = sqrt(2/(j+1)) x p_j - sqrt(j/(j+1)) p_{j-1}."""
+    p = np.empty((q + 1,) + np.shape(x))
+    p[0] = np.pi ** -0.25
+    if q >= 1:
+        p[1] = np.sqrt(2.0) * x * p[0]
+    for j in range(1, q):
+        p[j + 1] = np.sqrt(2.0 / (j + 1)) * x * p[j] - np.sqrt(j / (j + 1.0)) * p[j - 1]
+    return p
+
+
+def gauss_hermite(q: int = 32):
+    """Nodes x_k and weights w_k with sum_k w_k f(x_k) ~ int e^{-x^2} f(x) dx.
+
+    Golub-Welsch: the monic Hermite recurrence p_{k+1} = x p_k - (k/2) p_{k-1}
+    gives a symmetric tridiagonal Jacobi matrix (zero diagonal, off-diagonal
+    sqrt(k/2)) whose eigenvalues are the nodes.  The nodes get one Newton
+    polish on the orthonormal p_q (p_q' = sqrt(2q) p_{q-1}), and the weights
+    come from the Christoffel function w_k = 1 / sum_{j<q} p_j(x_k)^2, which
+    keeps full relative accuracy for the ~1e-23 tail weights."""
+    k = np.arange(1, q, dtype=np.float64)
+    J = np.diag(np.sqrt(k / 2.0), 1) + np.diag(np.sqrt(k / 2.0), -1)
+    x = np.linalg.eigvalsh(J)
+    x = 0.5 * (x - x[::-1])                      # exact symmetry about 0
+    p = _orthonormal_hermite(q, x)
+    x = x - p[q] / (np.sqrt(2.0 * q) * p[q - 1])
+    x = 0.5 * (x - x[::-1])
+    p = _orthonormal_hermite(q, x)
+    w = 1.0 / np.sum(p[:q] ** 2, axis=0)
+    w = 0.5 * (w + w[::-1])
+    return x, w
+
+
+# ----------------------------------------------------------------------------
+# Band tables: Gaussian SRF resampling of the high-resolution atmosphere
+# ----------------------------------------------------------------------------
+@dataclass
+class Tables:
+    lam: np.ndarray    # band centre [B] nm
+    K: np.ndarray      # E cos(sza) / pi   [B]
+    tau2: np.ndarray   # tau_down * tau_up [B]
+    tup: np.ndarray    # tau_up [B]
+    ratm: np.ndarray   # rho_atm [B]
+    S: np.ndarray      # spherical albedo [B]
+    lsat: np.ndarray | None  # [B] float32 saturation level, or None
+
+    @property
+    def B(self):
+        return int(self.lam.shape[0])
+
+
+def srf_matrix(lam_b, fwhm_b, hr_lam):
+    """Row-normalised Gaussian response of each band on the high-resolution
+    grid, truncated at +-4 sigma (sigma = FWHM / (2 sqrt(2 ln 2)))."""
+    sig = np.asarray(fwhm_b, np.float64) / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+    d = hr_lam[None, :] - np.asarray(lam_b, np.float64)[:, None]
+    w = np.exp(-0.5 * (d / sig[:, None]) ** 2)
+    w[np.abs(d) > 4.0 * sig[:, None]] = 0.0
+    s = w.sum(axis=1)
+    if np.any(s <= 0):
+        raise ValueError("a band's response window holds no high-resolution sample")
+    return w / s[:, None]
+
+
+def band_tables(atm) -> Tables:
+    """Per-band factors of eq. (solar): each atmospheric quantity is resampled
+    to band resolution separately; tau2 = resampled tau_down * resampled tau_up."""
+    W = srf_matrix(atm.wavelength_nm, atm.fwhm_nm, atm.hr_lambda_nm)
+    E = W @ atm.e_solar
+    tdn = W @ atm.tau_down
+    tup = W @ atm.tau_up
+    ratm = W @ atm.rho_atm
+    S = W @ atm.s_sph
+    return Tables(lam=np.ascontiguousarray(atm.wavelength_nm, np.float64),
+                  K=E * atm.cos_sza / np.pi, tau2=tdn * tup, tup=tup, ratm=ratm, S=S,
+                  lsat=None if atm.sat_level is None else np.asarray(atm.sat_level, np.float32))
+
+
+# ----------------------------------------------------------------------------
+# Physics helpers
+# ----------------------------------------------------------------------------
+def planck(lam_nm, T, with_derivative: bool = False):
+    """Planck radiance W m^-2 sr^-1 nm^-1 (and T dB/dT) from the C oracle."""
+    lam_nm, T = np.broadcast_arrays(np.asarray(lam_nm, np.float64), np.asarray(T, np.float64))
+    lam_c = np.ascontiguousarray(lam_nm.ravel())
+    T_c = np.ascontiguousarray(T.ravel())
+    out = np.empty_like(lam_c)
+    der = np.empty_like(lam_c) if with_derivative else None
+    lib().orc_planck_many(lam_c.size, _dp(lam_c), _dp(T_c), _dp(out), _dp(der))
+    if with_derivative:
+        return out.reshape(lam_nm.shape), der.reshape(lam_nm.shape)
+    return out.reshape(lam_nm.shape)
+
+
+def n_state(model: int) -> int:
+    return {1: 5, 2: 8}[model]
+
+
+def x_to_z(x, lo, hi):
+    """eq. (affine): z = 2 (x - lo) / (hi - lo) - 1."""
+    return 2.0 * (np.asarray(x) - lo) / (hi - lo) - 1.0
+
+
+def z_to_x(z, lo, hi):
+    """eq. (affine) inverse: x = lo + (hi - lo)(z + 1) / 2."""
+    return lo + 0.5 * (hi - lo) * (np.asarray(z) + 1.0)
+
+
+def mixture_moments(eta, mu_hot, sd_hot, mu_smol, sd_smol):
+    """Sec. 2.2 moment matching of the two-component mixture:
+    E[T] = eta mu_hot + (1-eta) mu_smol,
+    Var[T] = eta sd_hot^2 + (1-eta) sd_smol^2 + eta (1-eta)(mu_hot - mu_smol)^2."""
+    et = eta * mu_hot + (1.0 - eta) * mu_smol
+    var = eta * sd_hot**2 + (1.0 - eta) * sd_smol**2 + eta * (1.0 - eta) * (mu_hot - mu_smol) ** 2
+    return et, np.sqrt(var)
+
+
+def forward(tab: Tables, state, model: int, q: int = 32, jacobian: bool = False,
+            nthreads: int = 0):
+    """Model radiance [P, B] (and dL/dx [P, B, n]) for physical states [P, n]."""
+    n = n_state(model)
+    st = np.ascontiguousarray(np.atleast_2d(state), dtype=np.float64)
+    assert st.shape[1] == n
+    P = st.shape[0]
+    gx, gw = gauss_hermite(q)
+    L = np.empty((P, tab.B))
+    J = np.empty((P, tab.B, n)) if jacobian else None
+    rc = lib().orc_forward(tab.B, _dp(tab.lam), _dp(tab.K), _dp(tab.tau2), _dp(tab.tup),
+                           _dp(tab.ratm), _dp(tab.S), q, _dp(gx), _dp(gw), model, P,
+                           _dp(st), _dp(L), _dp(J), nthreads)
+    if rc != 0:
+        raise ValueError("orc_forward: bad arguments")
+    return (L, J) if jacobian else L
+
+
+@dataclass
+class LMOptions:
+    max_iter: int = 50
+    xtol: float = 1e-6
+    ftol: float = 1e-10
+    gtol: float = 1e-10
+    kappa: float = 1e-5
+
+
+@dataclass
+class Result:
+    state: np.ndarray
+    cov: np.ndarray
+    moments: np.ndarray
+    rrr: np.ndarray
+    iters: np.ndarray
+    status: np.ndarray
+
+    @property
+    def converged(self):
+        return (self.status & ST_CONVERGED) != 0
+
+
+def retrieve(tab: Tables, lobs, model: int, lo, hi, x0, z0=None, q: int = 32,
+             opts: LMOptions | None = None, nthreads: int = 0) -> Result:
+    """FP64 Levenberg-Marquardt retrieval of every pixel of lobs [P, B] (float32)."""
+    opts = opts or LMOptions()
+    n = n_state(model)
+    lobs = np.ascontiguousarray(lobs, dtype=np.float32)
+    P = lobs.shape[0]
+    assert lobs.shape[1] == tab.B
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    x0 = np.ascontiguousarray(x0, np.float64)
+    z0c = None if z0 is None else np.ascontiguousarray(z0, np.float64).reshape(P, n)
+    gx, gw = gauss_hermite(q)
+    out = Result(state=np.empty((P, n)), cov=np.empty((P, n * (n + 1) // 2)),
+                 moments=np.empty((P, 2)), rrr=np.empty(P),
+                 iters=np.empty(P, np.int32), status=np.empty(P, np.uint32))
+    lsat = None if tab.lsat is None else np.ascontiguousarray(tab.lsat, np.float32)
+    rc = lib().orc_retrieve(tab.B, _dp(tab.lam), _dp(tab.K), _dp(tab.tau2), _dp(tab.tup),
+                            _dp(tab.ratm), _dp(tab.S), _fp(lsat), q, _dp(gx), _dp(gw),
+                            model, _dp(lo), _dp(hi), _dp(x0), _dp(z0c), P, _fp(lobs),
+                            opts.max_iter, opts.xtol, opts.ftol, opts.gtol, opts.kappa,
+                            nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),
+                            _dp(out.rrr), out.iters.ctypes.data_as(C.POINTER(C.c_int)),
+                            out.status.ctypes.data_as(C.POINTER(C.c_uint)))
+    if rc != 0:
+        raise ValueError("orc_retrieve: bad arguments")
+    return out
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def unpack_cov(packed, n):
+    """Packed upper triangle (row-major) -> full symmetric [.., n, n]."""
+    packed = np.asarray(packed)
+    out = np.empty(packed.shape[:-1] + (n, n))
+    pos = 0
+    for i in range(n):
+        for j in range(i, n):
+            out[..., i, j] = packed[..., pos]
+            out[..., j, i] = packed[..., pos]
+            pos += 1
+    return out

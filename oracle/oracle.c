@@ -1,0 +1,523 @@
+/*
+ * FP64 CPU oracle for the per-pixel sub-pixel fire-temperature inversion.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it; the product never does.
+ * It shares no code, header, table or constant generator with the GPU path.
+ *
+ * What it computes (cited to Keely et al., "Real-time physics inversion for
+ * retrieval of sub-pixel wildfire temperatures from VSWIR imaging
+ * spectroscopy"):
+ *   - Planck spectral radiance B(lambda, T)                 (Sec. 2.2, eq. thermal)
+ *   - forward model L = L_s + L_t                           (Sec. 2.2, eq. fm)
+ *       L_s = E cos(sza)/pi [rho_atm + tau_dn tau_up rho / (1 - S rho)]   (eq. solar)
+ *       L_t = f tau_up  int p(T) B(lambda, T) dT                            (eq. thermal)
+ *     with p(T) a lognormal of mean m and s.d. s (one component) or the
+ *     eta-weighted mixture of a smouldering and a flaming lognormal (Sec. 2.2,
+ *     two-component mixture), integrated by Gauss-Hermite quadrature in log T,
+ *     and a linear reflectance rho = rho0 + rho1 (lambda - 1440 nm).
+ *   - analytic Jacobian of L with respect to the physical state
+ *   - the masked least-squares loss (Sec. 2.5, eq. loss) minimised in the
+ *     normalised coordinate z of eq. (affine) with z clipped to [-1, 1]
+ *     after every update (Sec. 2.5)
+ *   - a Levenberg-Marquardt solve (the paper uses Adam; the damped
+ *     Gauss-Newton scheme here follows Madsen, Nielsen & Tingleff 2004 with
+ *     Marquardt diagonal scaling, gain-ratio damping updates and an active
+ *     set for variables held at a bound)
+ *   - the Gauss-Newton state covariance at convergence, and the
+ *     moment-matched E[T], sigma[T] of the temperature mixture (Sec. 2.2,
+ *     mixture moments).
+ * Everything is IEEE double with libm exp/expm1/log1p; no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NMAX 8
+#define QMAX 128
+
+/* ---- physical constants: exact SI values ---------------------------------- */
+static const double H_PLANCK = 6.62607015e-34;
+static const double C_LIGHT = 299792458.0;
+static const double K_BOLTZ = 1.380649e-23;
+static const double LAMBDA_REF_NM = 1440.0;
+
+/* status bits (mirrors the public status word, defined independently) */
+#define ST_GTOL 1u
+#define ST_XTOL 2u
+#define ST_FTOL 4u
+#define ST_MAXITER 8u
+#define ST_NONFINITE 16u
+#define ST_DAMPING 32u
+#define ST_COVSING 64u
+#define ST_ATBOUND 128u
+#define ST_NODOF 1024u
+
+int orc_version(void) { return 1; }
+
+/* Planck radiance per nm, W m^-2 sr^-1 nm^-1, and its log-temperature
+ * derivative T dB/dT.  x = h c / (lambda k T);
+ *   B = 2 h c^2 lambda^-5 / (e^x - 1) = 2 h c^2 lambda^-5 e^-x / (1 - e^-x),
+ *   T dB/dT = B x e^x / (e^x - 1) = B x / (1 - e^-x). */
+double orc_planck(double lam_nm, double T, double* tdbdt)
+{
+    const double lam = lam_nm * 1e-9;
+    const double x = H_PLANCK * C_LIGHT / (lam * K_BOLTZ * T);
+    const double one_minus = -expm1(-x);           /* 1 - e^-x, no cancellation */
+    const double b = 2.0 * H_PLANCK * C_LIGHT * C_LIGHT / pow(lam, 5.0) * exp(-x) / one_minus * 1e-9;
+    if (tdbdt) *tdbdt = b * x / one_minus;
+    return b;
+}
+
+void orc_planck_many(long n, const double* lam_nm, const double* T, double* out, double* tdbdt)
+{
+    for (long i = 0; i < n; ++i) out[i] = orc_planck(lam_nm[i], T[i], tdbdt ? &tdbdt[i] : 0);
+}
+
+/* Lognormal with mean m and s.d. s: log T ~ N(mu, sig^2) with
+ * sig^2 = ln(1 + s^2/m^2), mu = ln m - sig^2/2.  Also the partial
+ * derivatives of (mu, sig) with respect to (m, s). */
+static void lognormal_params(double m, double s, double* mu, double* sig,
+                             double dmu[2], double dsig[2])
+{
+    const double q = m * m + s * s;
+    const double sig2 = log1p(s * s / (m * m));
+    *sig = sqrt(sig2);
+    *mu = log(m) - 0.5 * sig2;
+    const double dsig2_dm = -2.0 * s * s / (m * q);
+    const double dsig2_ds = 2.0 * s / q;
+    dmu[0] = 1.0 / m - 0.5 * dsig2_dm;
+    dmu[1] = -0.5 * dsig2_ds;
+    dsig[0] = dsig2_dm / (2.0 * (*sig));
+    dsig[1] = dsig2_ds / (2.0 * (*sig));
+}
+
+/* Quadrature of the Planck radiance over one lognormal component:
+ *   I     = pi^-1/2 sum_k w_k B(lam, T_k),   T_k = exp(mu + sqrt2 sig x_k)
+ *   I_mu  = dI/dmu  = pi^-1/2 sum_k w_k T_k dB/dT
+ *   I_sig = dI/dsig = pi^-1/2 sum_k w_k sqrt2 x_k T_k dB/dT                */
+static void component_integrals(double lam, double mu, double sig, int Q,
+                                const double* gx, const double* gw,
+                                double* I, double* Imu, double* Isig)
+{
+    const double inv_sqrt_pi = 1.0 / sqrt(M_PI);
+    double si = 0.0, sm = 0.0, ss = 0.0;
+    for (int k = 0; k < Q; ++k) {
+        const double t = exp(mu + M_SQRT2 * sig * gx[k]);
+        double tdb;
+        const double b = orc_planck(lam, t, &tdb);
+        const double w = gw[k] * inv_sqrt_pi;
+        si += w * b;
+        sm += w * tdb;
+        ss += w * M_SQRT2 * gx[k] * tdb;
+    }
+    *I = si; *Imu = sm; *Isig = ss;
+}
+
+typedef struct {
+    int B;
+    const double *lam, *K, *tau2, *tup, *ratm, *S;
+    int Q;
+    const double *gx, *gw;
+} scene_t;
+
+static int n_of_model(int model) { return model == 1 ? 5 : (model == 2 ? 8 : -1); }
+
+/* Forward model at one band for physical state x; fills dL/dx if dl != 0. */
+static double model_band(const scene_t* sc, int b, int model, const double* x, double* dl)
+{
+    const double lam = sc->lam[b];
+    const int n = n_of_model(model);
+    const double r0 = x[n - 2], r1 = x[n - 1];
+    const double rho = r0 + r1 * (lam - LAMBDA_REF_NM);
+    const double den = 1.0 - sc->S[b] * rho;
+    const double ls = sc->K[b] * (sc->ratm[b] + sc->tau2[b] * rho / den);
+    const double f = x[0];
+    const double tup = sc->tup[b];
+    double thermal_I;
+    if (model == 1) {
+        double mu, sig, dmu[2], dsig[2], I, Imu, Isig;
+        lognormal_params(x[1], x[2], &mu, &sig, dmu, dsig);
+        component_integrals(lam, mu, sig, sc->Q, sc->gx, sc->gw, &I, &Imu, &Isig);
+        thermal_I = I;
+        if (dl) {
+            dl[0] = tup * I;
+            dl[1] = f * tup * (Imu * dmu[0] + Isig * dsig[0]);
+            dl[2] = f * tup * (Imu * dmu[1] + Isig * dsig[1]);
+        }
+    } else {
+        const double eta = x[1];
+        double mus, sigs, dmus[2], dsigs[2], Is, Imus, Isigs;
+        double muh, sigh, dmuh[2], dsigh[2], Ih, Imuh, Isigh;
+        lognormal_params(x[2], x[3], &mus, &sigs, dmus, dsigs);
+        lognormal_params(x[4], x[5], &muh, &sigh, dmuh, dsigh);
+        component_integrals(lam, mus, sigs, sc->Q, sc->gx, sc->gw, &Is, &Imus, &Isigs);
+        component_integrals(lam, muh, sigh, sc->Q, sc->gx, sc->gw, &Ih, &Imuh, &Isigh);
+        thermal_I = eta * Ih + (1.0 - eta) * Is;
+        if (dl) {
+            dl[0] = tup * thermal_I;
+            dl[1] = f * tup * (Ih - Is);
+            dl[2] = f * tup * (1.0 - eta) * (Imus * dmus[0] + Isigs * dsigs[0]);
+            dl[3] = f * tup * (1.0 - eta) * (Imus * dmus[1] + Isigs * dsigs[1]);
+            dl[4] = f * tup * eta * (Imuh * dmuh[0] + Isigh * dsigh[0]);
+            dl[5] = f * tup * eta * (Imuh * dmuh[1] + Isigh * dsigh[1]);
+        }
+    }
+    if (dl) {
+        dl[n - 2] = sc->K[b] * sc->tau2[b] / (den * den);
+        dl[n - 1] = dl[n - 2] * (lam - LAMBDA_REF_NM);
+    }
+    return ls + f * tup * thermal_I;
+}
+
+/* Forward model (and optionally dL/dx, layout [P][B][n]) for P states. */
+int orc_forward(int B, const double* lam, const double* K, const double* tau2,
+                const double* tup, const double* ratm, const double* S,
+                int Q, const double* gx, const double* gw,
+                int model, long P, const double* state, double* L, double* dLdx,
+                int nthreads)
+{
+    const int n = n_of_model(model);
+    if (n < 0 || Q <= 0 || Q > QMAX || B <= 0) return -1;
+    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (long p = 0; p < P; ++p) {
+        for (int b = 0; b < B; ++b) {
+            double dl[NMAX];
+            L[p * B + b] = model_band(&sc, b, model, state + p * n, dLdx ? dl : 0);
+            if (dLdx) for (int j = 0; j < n; ++j) dLdx[(p * B + b) * n + j] = dl[j];
+        }
+    }
+    return 0;
+}
+
+/* ---- small dense linear algebra -------------------------------------------- */
+/* Cholesky M = C C^T of an n x n symmetric matrix (row-major, lower C).
+ * Returns 0 if a pivot is not strictly positive. */
+static int cholesky(int n, const double* M, double* C)
+{
+    memset(C, 0, sizeof(double) * n * n);
+    for (int j = 0; j < n; ++j) {
+        double d = M[j * n + j];
+        for (int k = 0; k < j; ++k) d -= C[j * n + k] * C[j * n + k];
+        if (!(d > 0.0)) return 0;
+        const double cjj = sqrt(d);
+        C[j * n + j] = cjj;
+        for (int i = j + 1; i < n; ++i) {
+            double v = M[i * n + j];
+            for (int k = 0; k < j; ++k) v -= C[i * n + k] * C[j * n + k];
+            C[i * n + j] = v / cjj;
+        }
+    }
+    return 1;
+}
+
+/* Solve C C^T x = rhs. */
+static void chol_solve(int n, const double* C, const double* rhs, double* x)
+{
+    double y[NMAX];
+    for (int i = 0; i < n; ++i) {
+        double v = rhs[i];
+        for (int k = 0; k < i; ++k) v -= C[i * n + k] * y[k];
+        y[i] = v / C[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < n; ++k) v -= C[k * n + i] * x[k];
+        x[i] = v / C[i * n + i];
+    }
+}
+
+/* ---- one pixel's least-squares problem in z ------------------------------- */
+typedef struct {
+    const scene_t* sc;
+    int model, n;
+    const double *lo, *hi;
+    const float* lobs;      /* [B] */
+    const unsigned char* mask;  /* [B] 1 = band used */
+} problem_t;
+
+static void z_to_x(const problem_t* pb, const double* z, double* x)
+{
+    for (int j = 0; j < pb->n; ++j)
+        x[j] = pb->lo[j] + 0.5 * (pb->hi[j] - pb->lo[j]) * (z[j] + 1.0);
+}
+
+/* r = m (L_obs - L(x(z))), J = dr/dz; returns F = r.r and fills A = J^T J,
+ * g = J^T r (A row-major n x n). */
+static double evaluate(const problem_t* pb, const double* z, double* A, double* g)
+{
+    const int n = pb->n;
+    double x[NMAX], dx[NMAX];
+    z_to_x(pb, z, x);
+    for (int j = 0; j < n; ++j) dx[j] = 0.5 * (pb->hi[j] - pb->lo[j]);
+    memset(A, 0, sizeof(double) * n * n);
+    memset(g, 0, sizeof(double) * n);
+    double F = 0.0;
+    for (int b = 0; b < pb->sc->B; ++b) {
+        if (!pb->mask[b]) continue;
+        double dl[NMAX], jrow[NMAX];
+        const double L = model_band(pb->sc, b, pb->model, x, dl);
+        const double r = (double)pb->lobs[b] - L;
+        for (int j = 0; j < n; ++j) jrow[j] = -dl[j] * dx[j];
+        F += r * r;
+        for (int i = 0; i < n; ++i) {
+            g[i] += jrow[i] * r;
+            for (int j = 0; j < n; ++j) A[i * n + j] += jrow[i] * jrow[j];
+        }
+    }
+    return F;
+}
+
+/* variables held at a bound by a gradient pointing out of the box */
+static void active_set(int n, const double* z, const double* g, int* act)
+{
+    for (int j = 0; j < n; ++j)
+        act[j] = (z[j] <= -1.0 && g[j] > 0.0) || (z[j] >= 1.0 && g[j] < 0.0);
+}
+
+/* projected-gradient test: max_j |g_j| / sqrt(A_jj F) over free j */
+static int gradient_small(int n, const double* z, const double* A, const double* g,
+                          double F, double gtol)
+{
+    if (!(F > 0.0)) return 1;
+    int act[NMAX];
+    active_set(n, z, g, act);
+    for (int j = 0; j < n; ++j) {
+        if (act[j] || !(A[j * n + j] > 0.0)) continue;
+        if (fabs(g[j]) > gtol * sqrt(A[j * n + j] * F)) return 0;
+    }
+    return 1;
+}
+
+typedef struct {
+    int max_iter;
+    double xtol, ftol, gtol, kappa;
+} lmopt_t;
+
+/* Levenberg-Marquardt from z (in/out).  Returns status bits; *iters counts
+ * model evaluations after the initial one. */
+static unsigned lm_solve(const problem_t* pb, const lmopt_t* o, double* z,
+                         double* A, double* g, double* Fout, int* iters)
+{
+    const int n = pb->n;
+    double At[NMAX * NMAX], gt[NMAX], M[NMAX * NMAX], C[NMAX * NMAX];
+    double d[NMAX], zt[NMAX], h[NMAX], delta[NMAX], rhs[NMAX];
+    int act[NMAX];
+    unsigned st = 0;
+    *iters = 0;
+    double F = evaluate(pb, z, A, g);
+    if (!isfinite(F)) { *Fout = F; return ST_NONFINITE; }
+    if (gradient_small(n, z, A, g, F, o->gtol)) { *Fout = F; return ST_GTOL; }
+    double amax = 0.0;
+    for (int j = 0; j < n; ++j) amax = fmax(amax, A[j * n + j]);
+    if (!(amax > 0.0)) amax = 1.0;
+    for (int j = 0; j < n; ++j) d[j] = fmax(A[j * n + j], 1e-12 * amax);
+    double mu = 1e-3 * amax, nu = 2.0;
+
+    for (;;) {
+        if (*iters >= o->max_iter) { st = ST_MAXITER; break; }
+        /* damped step on the free variables, retried with more damping
+         * until it is a descent step of the quadratic model */
+        double pred = 0.0;
+        int have_step = 0, tries = 0;
+        while (!have_step) {
+            if (++tries > 64 || mu > 1e30 * amax) { st = ST_DAMPING; break; }
+            active_set(n, z, g, act);
+            for (int i = 0; i < n; ++i) {
+                for (int j = 0; j < n; ++j)
+                    M[i * n + j] = (act[i] || act[j]) ? 0.0 : A[i * n + j];
+                M[i * n + i] = act[i] ? 1.0 : A[i * n + i] + mu * d[i];
+                rhs[i] = act[i] ? 0.0 : -g[i];
+            }
+            if (!cholesky(n, M, C)) { mu *= nu; nu *= 2.0; continue; }
+            chol_solve(n, C, rhs, delta);
+            double hmax = 0.0;
+            for (int j = 0; j < n; ++j) {
+                double zz = z[j] + delta[j];
+                zz = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
+                zt[j] = zz;
+                h[j] = zz - z[j];
+                hmax = fmax(hmax, fabs(h[j]));
+            }
+            if (hmax <= o->xtol) { st = ST_XTOL; break; }
+            double hg = 0.0, hah = 0.0;
+            for (int i = 0; i < n; ++i) {
+                hg += h[i] * g[i];
+                for (int j = 0; j < n; ++j) hah += h[i] * A[i * n + j] * h[j];
+            }
+            pred = -(2.0 * hg + hah);
+            if (pred > 0.0) have_step = 1;
+            else { mu *= nu; nu *= 2.0; }
+        }
+        if (st) break;
+
+        const double Ft = evaluate(pb, zt, At, gt);
+        ++*iters;
+        const double rho = (F - Ft) / pred;
+        if (isfinite(Ft) && (rho > 0.0 || pred <= o->kappa * F)) {
+            const double Fold = F;
+            memcpy(z, zt, sizeof(double) * n);
+            memcpy(A, At, sizeof(double) * n * n);
+            memcpy(g, gt, sizeof(double) * n);
+            F = Ft;
+            const double rc = rho < 0.0 ? 0.0 : (rho > 1.0 ? 1.0 : rho);
+            const double t = 2.0 * rc - 1.0;
+            mu *= fmax(1.0 / 3.0, 1.0 - t * t * t);
+            nu = 2.0;
+            for (int j = 0; j < n; ++j) d[j] = fmax(d[j], A[j * n + j]);
+            if (pred <= o->ftol * Fold) { st = ST_FTOL; break; }
+            if (gradient_small(n, z, A, g, F, o->gtol)) { st = ST_GTOL; break; }
+        } else {
+            mu *= nu;
+            nu *= 2.0;
+        }
+    }
+    *Fout = F;
+    return st;
+}
+
+/* Gauss-Newton covariance sigma^2 A^-1 in z (sigma^2 = F / (N - n)), mapped
+ * to x; state variables whose Jacobian column is identically zero are
+ * unidentified: their rows/columns are NaN and COV_SINGULAR is set.  Output
+ * is the packed upper triangle, row-major. */
+static unsigned covariance(int n, const double* A, double F, int nvalid,
+                           const double* lo, const double* hi, double* cov)
+{
+    int keep[NMAX], nk = 0, idx[NMAX];
+    unsigned st = 0;
+    for (int j = 0; j < n; ++j) {
+        keep[j] = A[j * n + j] > 0.0;
+        if (keep[j]) idx[nk++] = j;
+    }
+    if (nk < n) st |= ST_COVSING;
+    double Ak[NMAX * NMAX], C[NMAX * NMAX], inv[NMAX * NMAX];
+    for (int a = 0; a < nk; ++a)
+        for (int b = 0; b < nk; ++b) Ak[a * nk + b] = A[idx[a] * n + idx[b]];
+    int ok = nk > 0 && cholesky(nk, Ak, C);
+    if (ok) {
+        for (int c = 0; c < nk; ++c) {
+            double e[NMAX] = {0}, col[NMAX];
+            e[c] = 1.0;
+            chol_solve(nk, C, e, col);
+            for (int r = 0; r < nk; ++r) inv[r * nk + c] = col[r];
+        }
+    } else {
+        st |= ST_COVSING;
+    }
+    const double s2 = F / (double)(nvalid - n);
+    int pos = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = i; j < n; ++j, ++pos) {
+            double v = NAN;
+            if (ok && keep[i] && keep[j]) {
+                int a = 0, b = 0;
+                while (idx[a] != i) ++a;
+                while (idx[b] != j) ++b;
+                v = s2 * inv[a * nk + b] * 0.25 * (hi[i] - lo[i]) * (hi[j] - lo[j]);
+            }
+            cov[pos] = v;
+        }
+    }
+    return st;
+}
+
+/* moment-matched mean and s.d. of the temperature distribution */
+static void moments_of(int model, const double* x, double* et, double* sdt)
+{
+    if (model == 1) { *et = x[1]; *sdt = x[2]; return; }
+    const double eta = x[1], ms = x[2], ss = x[3], mh = x[4], sh = x[5];
+    *et = eta * mh + (1.0 - eta) * ms;
+    const double dm = mh - ms;
+    const double var = eta * sh * sh + (1.0 - eta) * ss * ss + eta * (1.0 - eta) * dm * dm;
+    *sdt = sqrt(var);
+}
+
+/* Retrieve P pixels.  lobs is [P][B] float32 (widened to double).
+ * lsat: [B] saturation levels or NULL.  z0: [P][n] starting z or NULL
+ * (then x0 is mapped to z for every pixel).  Outputs are double:
+ * state [P][n] physical, cov [P][n(n+1)/2], moments [P][2], rrr [P],
+ * iters [P], status [P]. */
+int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
+                 const double* tup, const double* ratm, const double* S,
+                 const float* lsat, int Q, const double* gx, const double* gw,
+                 int model, const double* lo, const double* hi, const double* x0,
+                 const double* z0, long P, const float* lobs,
+                 int max_iter, double xtol, double ftol, double gtol, double kappa,
+                 int nthreads,
+                 double* state, double* cov, double* moments, double* rrr,
+                 int* iters, unsigned* status)
+{
+    const int n = n_of_model(model);
+    if (n < 0 || Q <= 0 || Q > QMAX || B <= 0 || P < 0) return -1;
+    for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
+    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
+    lmopt_t o = {max_iter, xtol, ftol, gtol, kappa};
+    const int ncov = n * (n + 1) / 2;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (long p = 0; p < P; ++p) {
+        const float* lp = lobs + p * B;
+        unsigned char* mask = (unsigned char*)malloc(B);
+        unsigned st = 0;
+        int nvalid = 0, finite_in = 1;
+        double lnorm2 = 0.0;
+        for (int b = 0; b < B; ++b) {
+            if (!isfinite(lp[b])) finite_in = 0;
+            mask[b] = lsat ? (lp[b] < lsat[b]) : 1;
+            if (mask[b]) { ++nvalid; lnorm2 += (double)lp[b] * (double)lp[b]; }
+        }
+        double z[NMAX], x[NMAX], A[NMAX * NMAX], g[NMAX], F = NAN;
+        int it = 0;
+        if (!finite_in) st = ST_NONFINITE;
+        else if (nvalid <= n) st = ST_NODOF;
+        if (!st) {
+            for (int j = 0; j < n; ++j) {
+                double zz = z0 ? z0[p * n + j]
+                               : 2.0 * (x0[j] - lo[j]) / (hi[j] - lo[j]) - 1.0;
+                z[j] = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
+            }
+            problem_t pb = {&sc, model, n, lo, hi, lp, mask};
+            st = lm_solve(&pb, &o, z, A, g, &F, &it);
+        }
+        double* cv = cov + p * ncov;
+        if (st & (ST_NONFINITE | ST_NODOF)) {
+            for (int j = 0; j < n; ++j) state[p * n + j] = NAN;
+            for (int j = 0; j < ncov; ++j) cv[j] = NAN;
+            moments[2 * p] = moments[2 * p + 1] = NAN;
+            rrr[p] = NAN;
+        } else {
+            for (int j = 0; j < n; ++j) {
+                x[j] = lo[j] + 0.5 * (hi[j] - lo[j]) * (z[j] + 1.0);
+                state[p * n + j] = x[j];
+                if (z[j] <= -1.0 || z[j] >= 1.0) st |= ST_ATBOUND;
+            }
+            st |= covariance(n, A, F, nvalid, lo, hi, cv);
+            moments_of(model, x, &moments[2 * p], &moments[2 * p + 1]);
+            rrr[p] = lnorm2 > 0.0 ? sqrt(F / lnorm2) : NAN;
+        }
+        iters[p] = it;
+        status[p] = st;
+        free(mask);
+    }
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

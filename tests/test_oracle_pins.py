@@ -1,0 +1,428 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Each test checks one part of the oracle against something that does not come
+from the oracle's own formulas: closed forms (Stefan-Boltzmann, Wien, Gaussian
+moments), library routines (numpy's Gauss-Hermite rule, lstsq, MINPACK),
+finite differences, brute force and Monte Carlo.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize, stats
+from scipy.special import gamma
+
+import scenegen
+
+H, C, KB = 6.62607015e-34, 299792458.0, 1.380649e-23
+SIGMA_SB = 2.0 * math.pi**5 * KB**4 / (15.0 * H**3 * C**2)   # closed form
+C2 = H * C / KB
+
+
+def _log_grid_integral(fun, lo_nm=5.0, hi_nm=1e9, n=200001):
+    """int f(lam) dlam = int f(lam) lam dln(lam), composite Simpson in ln(lam)."""
+    u = np.linspace(math.log(lo_nm), math.log(hi_nm), n)
+    lam = np.exp(u)
+    return integrate.simpson(fun(lam) * lam, x=u)
+
+
+# --------------------------------------------------------------------------
+# Planck function
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("T", [300.0, 600.0, 1000.0, 1500.0, 2200.0, 5778.0])
+def test_planck_stefan_boltzmann(oracle_mod, T):
+    """pi * int B(lam, T) dlam = sigma T^4 (Stefan-Boltzmann law)."""
+    tot = math.pi * _log_grid_integral(lambda lam: oracle_mod.planck(lam, T))
+    assert tot == pytest.approx(SIGMA_SB * T**4, rel=1e-9)
+
+
+@pytest.mark.parametrize("T", [500.0, 1000.0, 1700.0, 5778.0])
+def test_planck_wien_peak(oracle_mod, T):
+    """argmax_lam B = b / T, b = h c / (k x_w), x_w = 5 (1 - e^-x_w).
+    d ln B / d ln lam = -5 + (T dB/dT)/B, so the peak is where the oracle's
+    log-temperature derivative equals 5 B."""
+    xw = optimize.brentq(lambda x: x - 5.0 * (1.0 - math.exp(-x)), 1.0, 10.0, xtol=1e-15)
+    lam_w = C2 / (xw * T) * 1e9
+
+    def slope(lam):
+        b, d = oracle_mod.planck(lam, T, with_derivative=True)
+        return float(d / b - 5.0)
+    lam_peak = optimize.brentq(slope, 0.5 * lam_w, 2.0 * lam_w, xtol=1e-12, rtol=1e-15)
+    assert lam_peak == pytest.approx(lam_w, rel=1e-10)
+    # and B itself is maximal there (golden section on -B)
+    res = optimize.minimize_scalar(lambda lam: -float(oracle_mod.planck(lam, T)),
+                                   bounds=(0.5 * lam_w, 2.0 * lam_w), method="bounded",
+                                   options={"xatol": 1e-9 * lam_w})
+    assert res.x == pytest.approx(lam_w, rel=1e-6)
+
+
+def test_planck_temperature_derivative_fd(oracle_mod):
+    """T dB/dT against a Richardson-extrapolated central difference."""
+    rng = np.random.default_rng(7)
+    lam = rng.uniform(380, 2500, 200)
+    T = rng.uniform(350, 3000, 200)
+    _, d = oracle_mod.planck(lam, T, with_derivative=True)
+
+    def cd(h):
+        return (oracle_mod.planck(lam, T * (1 + h)) - oracle_mod.planck(lam, T * (1 - h))) / (2 * h)
+    fd = (4 * cd(5e-5) - cd(1e-4)) / 3.0
+    np.testing.assert_allclose(d, fd, rtol=1e-8)
+
+
+def test_planck_extreme_arguments(oracle_mod):
+    """x from 0.05 to 2.4e4: finite, non-negative, no overflow."""
+    b, d = oracle_mod.planck(np.array([2500.0, 380.0, 380.0]), np.array([1.1e5, 1.6, 1.0]),
+                             with_derivative=True)
+    assert np.all(np.isfinite(b)) and np.all(b >= 0) and np.all(np.isfinite(d))
+    assert b[1] == 0.0 and b[0] > 0
+
+
+# --------------------------------------------------------------------------
+# Gauss-Hermite rule
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [8, 16, 24, 32, 48])
+def test_gauss_hermite_moments(oracle_mod, q):
+    """sum_k w_k x_k^{2j} = Gamma(j + 1/2) for 2j <= 2q - 1; odd moments vanish."""
+    x, w = oracle_mod.gauss_hermite(q)
+    for j in range(q):
+        assert (w * x ** (2 * j)).sum() == pytest.approx(gamma(j + 0.5), rel=1e-13)
+    for j in range(q):
+        odd = (w * x ** (2 * j + 1)).sum()
+        assert abs(odd) <= 1e-13 * gamma(j + 1.0) + 1e-300
+
+
+@pytest.mark.parametrize("q", [16, 32])
+def test_gauss_hermite_vs_numpy(oracle_mod, q):
+    from numpy.polynomial.hermite import hermgauss
+    x, w = oracle_mod.gauss_hermite(q)
+    xr, wr = hermgauss(q)
+    np.testing.assert_allclose(x, xr, atol=1e-13)
+    np.testing.assert_allclose(w, wr, rtol=1e-12)
+    assert x.max() == pytest.approx(7.1258139098, abs=1e-9) if q == 32 else True
+
+
+# --------------------------------------------------------------------------
+# Thermal term: lognormal quadrature of the Planck function
+# --------------------------------------------------------------------------
+def _thermal_only_tables(oracle_mod, lam):
+    z = np.zeros_like(lam)
+    return oracle_mod.Tables(lam=lam, K=z.copy(), tau2=z.copy(), tup=np.ones_like(lam),
+                             ratm=z.copy(), S=z.copy(), lsat=None)
+
+
+@pytest.mark.parametrize("m,s", [(600.0, 50.0), (1000.0, 150.0), (1400.0, 300.0), (500.0, 300.0)])
+def test_lognormal_quadrature_stefan_boltzmann(oracle_mod, m, s):
+    """f = 1, tau_up = 1, no solar term: pi int L dlam = sigma E[T^4] with
+    E[T^4] = exp(4 mu + 8 sig^2) for log T ~ N(mu, sig^2)."""
+    u = np.linspace(math.log(5.0), math.log(1e9), 60001)
+    lam = np.exp(u)
+    tab = _thermal_only_tables(oracle_mod, lam)
+    L = oracle_mod.forward(tab, np.array([[1.0, m, s, 0.0, 0.0]]), 1)[0]
+    tot = math.pi * integrate.simpson(L * lam, x=u)
+    sig2 = math.log1p(s * s / (m * m))
+    mu = math.log(m) - 0.5 * sig2
+    assert tot == pytest.approx(SIGMA_SB * math.exp(4 * mu + 8 * sig2), rel=1e-9)
+
+
+def test_narrow_distribution_is_single_planck_injection(oracle_mod):
+    """s -> 0 collapses the thermal term to one Planck radiance: the single-
+    temperature injection model L_inj = L_bg + alpha tau_up B(lam, T_inj)
+    (Sec. 2.7, eq. inject)."""
+    atm = scenegen.make_atmosphere(0, 0)
+    tab = oracle_mod.band_tables(atm)
+    for alpha, tinj in [(0.02, 500.0), (0.1, 1100.0), (0.005, 1700.0)]:
+        fire = oracle_mod.forward(tab, np.array([[alpha, tinj, 1e-3, 0.2, 3e-5]]), 1)[0]
+        bg = oracle_mod.forward(tab, np.array([[0.0, tinj, 1e-3, 0.2, 3e-5]]), 1)[0]
+        inj = bg + alpha * tab.tup * oracle_mod.planck(tab.lam, tinj)
+        np.testing.assert_allclose(fire, inj, rtol=1e-6)
+
+
+def test_solar_term_closed_form(oracle_mod):
+    """f = 0: L = K [rho_atm + tau2 rho / (1 - S rho)] with rho linear in lam."""
+    rng = np.random.default_rng(3)
+    B = 50
+    lam = np.linspace(400, 2400, B)
+    tab = oracle_mod.Tables(lam=lam, K=rng.uniform(0.1, 0.5, B), tau2=rng.uniform(0.2, 0.8, B),
+                            tup=rng.uniform(0.5, 0.9, B), ratm=rng.uniform(0, 0.05, B),
+                            S=rng.uniform(0, 0.2, B), lsat=None)
+    r0, r1 = 0.3, -7e-5
+    L = oracle_mod.forward(tab, np.array([[0.0, 900.0, 100.0, r0, r1]]), 1)[0]
+    rho = r0 + r1 * (lam - 1440.0)
+    np.testing.assert_allclose(L, tab.K * (tab.ratm + tab.tau2 * rho / (1 - tab.S * rho)), rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Mixture moments (Sec. 2.2) and the affine map (eq. affine)
+# --------------------------------------------------------------------------
+def _lognormal_pdf(m, s):
+    sig = math.sqrt(math.log1p(s * s / (m * m)))
+    mu = math.log(m) - 0.5 * sig * sig
+    return stats.lognorm(s=sig, scale=math.exp(mu)).pdf
+
+
+@pytest.mark.parametrize("eta,ms,ss,mh,sh", [(0.3, 600.0, 80.0, 1200.0, 200.0),
+                                             (0.9, 700.0, 250.0, 1000.0, 60.0),
+                                             (0.05, 520.0, 50.0, 1450.0, 290.0)])
+def test_mixture_moments_numerical(oracle_mod, eta, ms, ss, mh, sh):
+    ps, ph = _lognormal_pdf(ms, ss), _lognormal_pdf(mh, sh)
+
+    def pdf(t):
+        return eta * ph(t) + (1 - eta) * ps(t)
+    e1 = integrate.quad(lambda t: t * pdf(t), 0, np.inf, epsabs=0, epsrel=1e-13, limit=400)[0]
+    e2 = integrate.quad(lambda t: t * t * pdf(t), 0, np.inf, epsabs=0, epsrel=1e-13, limit=400)[0]
+    et, sd = oracle_mod.mixture_moments(eta, mh, sh, ms, ss)
+    assert et == pytest.approx(e1, rel=1e-10)
+    assert sd == pytest.approx(math.sqrt(e2 - e1 * e1), rel=1e-9)
+
+
+def test_affine_roundtrip(oracle_mod):
+    lo, hi, _ = scenegen.default_prior(2)
+    rng = np.random.default_rng(0)
+    x = lo + (hi - lo) * rng.uniform(size=(100, 8))
+    z = oracle_mod.x_to_z(x, lo, hi)
+    assert np.all(np.abs(z) <= 1)
+    np.testing.assert_allclose(oracle_mod.z_to_x(z, lo, hi), x, rtol=4e-16, atol=1e-19)
+    np.testing.assert_array_equal(oracle_mod.x_to_z(lo, lo, hi), -1.0)
+    np.testing.assert_array_equal(oracle_mod.x_to_z(hi, lo, hi), 1.0)
+
+
+# --------------------------------------------------------------------------
+# Analytic Jacobian against finite differences
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("model", [1, 2])
+def test_jacobian_finite_difference(oracle_mod, model):
+    atm = scenegen.make_atmosphere(0, 1, rho_atm=0.01, s_sph=0.1)
+    tab = oracle_mod.band_tables(atm)
+    rng = np.random.default_rng(11 + model)
+    if model == 1:
+        X = scenegen.draw_states_lognormal1(rng, 12)
+    else:
+        X = scenegen.draw_states_lognormal2(rng, 12)
+        X[:, 0] = np.exp(rng.uniform(np.log(1e-3), np.log(0.2), 12))
+    _, J = oracle_mod.forward(tab, X, model, jacobian=True)
+    n = X.shape[1]
+    for j in range(n):
+        h = 1e-5 * np.maximum(np.abs(X[:, j]), 1e-3 if j < n - 1 else 1e-6)
+
+        def cd(hh):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[:, j] += hh
+            Xm[:, j] -= hh
+            return (oracle_mod.forward(tab, Xp, model) - oracle_mod.forward(tab, Xm, model)) / (2 * hh[:, None])
+        fd = (4 * cd(h / 2) - cd(h)) / 3.0
+        num = np.linalg.norm(J[:, :, j] - fd, axis=1)
+        den = np.linalg.norm(J[:, :, j], axis=1)
+        assert np.all(num <= 1e-6 * den + 1e-14), (j, (num / den).max())
+
+
+# --------------------------------------------------------------------------
+# The solver
+# --------------------------------------------------------------------------
+def _scene(oracle_mod, cfg=0, scene=0):
+    return oracle_mod.band_tables(scenegen.make_atmosphere(cfg, scene))
+
+
+def test_linear_subproblem_equals_lstsq(oracle_mod):
+    """With (m, s) pinned by a degenerate box and S = 0 the model is linear in
+    (f, rho0, rho1): the LM minimiser is the least-squares solution and its
+    covariance block is the OLS covariance F/(N - n) (X^T X)^-1."""
+    tab = _scene(oracle_mod)
+    m, s = 1100.0, 120.0
+    lo, hi, x0 = scenegen.default_prior(1)
+    lo = lo.copy(); hi = hi.copy(); x0 = x0.copy()
+    lo[1], hi[1], lo[2], hi[2] = m, m + 1e-7, s, s + 1e-7
+    x0[1], x0[2] = m, s
+    truth = np.array([[0.05, m, s, 0.25, 4e-5]])
+    L = oracle_mod.forward(tab, truth, 1)
+    noise = scenegen.noise_normals(0, 9, 1, tab.B)
+    lobs = (L * (1 + noise / 300)).astype(np.float32)
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0)
+    assert r.converged[0]
+    _, J = oracle_mod.forward(tab, np.array([[0.0, m, s, 0.0, 0.0]]), 1, jacobian=True)
+    X = J[0][:, [0, 3, 4]]
+    y = lobs[0].astype(np.float64)
+    beta, *_ = np.linalg.lstsq(X, y, rcond=None)
+    np.testing.assert_allclose(r.state[0, [0, 3, 4]], beta, rtol=1e-7)
+    # covariance: OLS covariance of the model linearised at the solution, with a
+    # finite-difference Jacobian in physical units (independent of the
+    # analytic Jacobian and of the z scaling)
+    xs = r.state[0]
+    cols = []
+    for j in range(5):
+        h = 1e-6 * max(abs(xs[j]), 1.0 if j in (1, 2) else 1e-4)
+        xp, xm = xs.copy(), xs.copy()
+        xp[j] += h
+        xm[j] -= h
+        cols.append((oracle_mod.forward(tab, xp[None], 1)[0] - oracle_mod.forward(tab, xm[None], 1)[0]) / (2 * h))
+    Xfd = np.stack(cols, 1)
+    rss = float(((y - oracle_mod.forward(tab, xs[None], 1)[0]) ** 2).sum())
+    ols = rss / (tab.B - 5) * np.linalg.inv(Xfd.T @ Xfd)
+    full = oracle_mod.unpack_cov(r.cov[0], 5)
+    np.testing.assert_allclose(full, ols, rtol=1e-4)
+
+
+def _variable_projection_grid(oracle_mod, tab, y, ms_grid):
+    """Brute force: on each (m, s) grid point solve the linear LS for
+    (f, rho0, rho1) exactly with f >= 0 (refit with f = 0 when the free
+    solution has f < 0) and return the smallest residual sum of squares."""
+    P = ms_grid.shape[0]
+    X = np.zeros((P, 5))
+    X[:, 1:3] = ms_grid
+    _, J = oracle_mod.forward(tab, X, 1, jacobian=True)
+    best = (np.inf, None)
+    sol_b = np.linalg.lstsq(J[0][:, [3, 4]], y, rcond=None)[0]
+    F0 = float(((y - J[0][:, [3, 4]] @ sol_b) ** 2).sum())
+    for p in range(P):
+        A = J[p][:, [0, 3, 4]]
+        beta = np.linalg.lstsq(A, y, rcond=None)[0]
+        F = float(((y - A @ beta) ** 2).sum()) if beta[0] >= 0 else F0
+        if F < best[0]:
+            best = (F, ms_grid[p])
+    return best
+
+
+def test_lm_reaches_brute_force_global_minimum(oracle_mod):
+    tab = _scene(oracle_mod)
+    lo, hi, x0 = scenegen.default_prior(1)
+    truths = np.array([[0.05, 900.0, 120.0, 0.2, 2e-5], [0.01, 1250.0, 250.0, 0.3, -5e-5]])
+    L = oracle_mod.forward(tab, truths, 1)
+    noise = scenegen.noise_normals(0, 5, 2, tab.B)
+    lobs = (L * (1 + noise / 300)).astype(np.float32)
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0, opts=oracle_mod.LMOptions(max_iter=200))
+    mg, sg = np.meshgrid(np.linspace(350, 2200, 75), np.linspace(1, 500, 60), indexing="ij")
+    grid = np.stack([mg.ravel(), sg.ravel()], 1)
+    for p in range(2):
+        y = lobs[p].astype(np.float64)
+        Fgrid, arg = _variable_projection_grid(oracle_mod, tab, y, grid)
+        Flm = float(((y - oracle_mod.forward(tab, r.state[p:p + 1], 1)[0]) ** 2).sum())
+        assert Flm <= Fgrid * (1 + 1e-12)
+        # the continuous optimum is within a grid cell of the grid's argmin
+        assert abs(r.state[p, 1] - arg[0]) <= 2 * 25.0 and abs(r.state[p, 2] - arg[1]) <= 2 * 8.5
+
+
+def test_lm_matches_minpack(oracle_mod):
+    """scipy.optimize.least_squares(method='lm') (MINPACK) on the same
+    residual reaches the same minimum cost for interior optima."""
+    tab = _scene(oracle_mod, 0, 2)
+    lo, hi, x0 = scenegen.default_prior(1)
+    truths = np.array([[0.08, 1000.0, 150.0, 0.2, 1e-5], [0.02, 800.0, 90.0, 0.1, -3e-5],
+                       [0.15, 1300.0, 200.0, 0.35, 6e-5]])
+    L = oracle_mod.forward(tab, truths, 1)
+    lobs = (L * (1 + scenegen.noise_normals(0, 6, 3, tab.B) / 300)).astype(np.float32)
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0, opts=oracle_mod.LMOptions(max_iter=200))
+    D = 0.5 * (hi - lo)
+    for p in range(3):
+        y = lobs[p].astype(np.float64)
+
+        def res(z):
+            return y - oracle_mod.forward(tab, oracle_mod.z_to_x(z, lo, hi)[None], 1)[0]
+
+        def jac(z):
+            return -oracle_mod.forward(tab, oracle_mod.z_to_x(z, lo, hi)[None], 1, jacobian=True)[1][0] * D
+        z_start = oracle_mod.x_to_z(r.state[p], lo, hi) + 1e-3
+        mp = optimize.least_squares(res, z_start, jac=jac, method="lm", xtol=1e-15, ftol=1e-15,
+                                    gtol=1e-15, max_nfev=2000)
+        F_mp = float((mp.fun ** 2).sum())
+        F_or = float((res(oracle_mod.x_to_z(r.state[p], lo, hi)) ** 2).sum())
+        assert F_or == pytest.approx(F_mp, rel=1e-8)
+        assert r.state[p, 1] == pytest.approx(oracle_mod.z_to_x(mp.x, lo, hi)[1], abs=0.05)
+
+
+def test_noise_free_exact_recovery(oracle_mod):
+    """Noise-free spectra (float32-rounded) with the truth inside the box:
+    the oracle returns the truth and a residual at the float32 floor."""
+    tab = _scene(oracle_mod)
+    lo, hi, x0 = scenegen.default_prior(1)
+    X = scenegen.config0_states(64, scene=3)
+    X = X[X[:, 0] >= 1e-3][:24]
+    lobs = oracle_mod.forward(tab, X, 1).astype(np.float32)
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0, opts=oracle_mod.LMOptions(max_iter=200))
+    assert np.all(r.converged)
+    assert np.all(r.rrr <= 1e-7)
+    np.testing.assert_allclose(r.state[:, 1], X[:, 1], atol=0.05)
+    np.testing.assert_allclose(r.state[:, 0], X[:, 0], rtol=2e-4)
+
+
+def test_covariance_monte_carlo(oracle_mod):
+    """With homoscedastic noise the spread of LM estimates over noise
+    redraws matches the Gauss-Newton covariance F/(N-n) A^-1."""
+    tab = _scene(oracle_mod)
+    lo, hi, x0 = scenegen.default_prior(1)
+    truth = np.array([0.1, 1200.0, 150.0, 0.25, 3e-5])
+    L = oracle_mod.forward(tab, truth[None], 1)[0]
+    sigma = 1e-3
+    R = 1000
+    noise = np.random.default_rng(21).standard_normal((R, tab.B))
+    lobs = (L[None] + sigma * noise).astype(np.float32)
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, truth, opts=oracle_mod.LMOptions(max_iter=100))
+    assert r.converged.mean() > 0.99
+    emp = np.cov(r.state.T)
+    gn = oracle_mod.unpack_cov(r.cov, 5).mean(axis=0)
+    ratio = np.diag(emp) / np.diag(gn)
+    assert np.all(np.abs(ratio - 1) < 0.15), ratio
+    corr_e = emp[0, 1] / math.sqrt(emp[0, 0] * emp[1, 1])
+    corr_g = gn[0, 1] / math.sqrt(gn[0, 0] * gn[1, 1])
+    assert abs(corr_e - corr_g) < 0.1
+
+
+def test_status_edge_cases(oracle_mod):
+    tab = _scene(oracle_mod)
+    lo, hi, x0 = scenegen.default_prior(1)
+    X = scenegen.config0_states(3)
+    lobs = oracle_mod.forward(tab, X, 1).astype(np.float32)
+    lobs[1, 7] = np.nan
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0, opts=oracle_mod.LMOptions(max_iter=1))
+    assert r.status[1] & oracle_mod.ST_NONFINITE and np.isnan(r.state[1]).all()
+    assert r.iters[0] <= 1 and (r.status[0] & (oracle_mod.ST_MAXITER | oracle_mod.ST_CONVERGED))
+    # every band saturated -> no degrees of freedom
+    tab.lsat = np.zeros(tab.B, np.float32)
+    r = oracle_mod.retrieve(tab, lobs[:1], 1, lo, hi, x0)
+    assert r.status[0] & oracle_mod.ST_NODOF
+    # empty batch
+    r = oracle_mod.retrieve(tab, lobs[:0], 1, lo, hi, x0)
+    assert r.state.shape == (0, 5)
+
+
+def test_background_pixel_reaches_zero_fraction(oracle_mod):
+    """Truth f = 0 with a strong default start: the fit drives f to its lower
+    bound or near it and reproduces the reflectance."""
+    tab = _scene(oracle_mod, 1, 0)
+    lo, hi, x0 = scenegen.default_prior(1)
+    X = scenegen.config0_states(32, scene=4)
+    X[:, 0] = 0.0
+    lobs = oracle_mod.forward(tab, X, 1).astype(np.float32)
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0, opts=oracle_mod.LMOptions(max_iter=200))
+    assert np.all(r.rrr < 1e-4)
+    np.testing.assert_allclose(r.state[:, 3], X[:, 3], atol=2e-3)
+
+
+# --------------------------------------------------------------------------
+# Band resampling and the synthetic inputs
+# --------------------------------------------------------------------------
+def test_srf_resampling(oracle_mod):
+    lam, fwhm = scenegen.band_grid()
+    hr = scenegen.hires_grid()
+    W = oracle_mod.srf_matrix(lam, fwhm, hr)
+    np.testing.assert_allclose(W.sum(axis=1), 1.0, rtol=1e-14)
+    # a Gaussian line of width w convolved with a Gaussian SRF of width sig is a
+    # Gaussian of width sqrt(w^2 + sig^2) (area preserved)
+    w = 6.0
+    c = 1500.0
+    line = np.exp(-0.5 * ((hr - c) / w) ** 2)
+    out = W @ line
+    sig = 8.5 / (2 * math.sqrt(2 * math.log(2)))
+    ana = w / math.sqrt(w * w + sig * sig) * np.exp(-0.5 * (lam - c) ** 2 / (w * w + sig * sig))
+    near = np.abs(lam - c) < 20
+    np.testing.assert_allclose(out[near], ana[near], rtol=2e-3, atol=1e-4)
+
+
+def test_generator_sun_and_transmittance():
+    hr = np.exp(np.linspace(math.log(20.0), math.log(1e8), 400001))
+    e = scenegen.solar_irradiance(hr)
+    tot = integrate.simpson(e * hr, x=np.log(hr))
+    assert tot == pytest.approx(1361.0, rel=1e-8)
+    grid = scenegen.hires_grid()
+    peak = grid[np.argmax(scenegen.solar_irradiance(grid))]
+    assert abs(peak - 2.8977719552e6 / 5778.0) <= 0.5
+    t = scenegen.transmittance(grid, np.array([0.95] * 4))
+    assert t.min() > 0.04 and t.max() <= 0.9
