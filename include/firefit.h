@@ -1,0 +1,235 @@
+/*
+ * firefit: per-pixel full-physics inversion of VSWIR radiance spectra for
+ * sub-pixel fire temperature, on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Keely et al., "Real-time physics inversion for retrieval of
+ * sub-pixel wildfire temperatures from VSWIR imaging spectroscopy"):
+ *   forward model   L = L_s + L_t                                     (Sec. 2.2, eq. fm)
+ *   solar term      L_s = E cos(sza)/pi [rho_atm + tau_dn tau_up rho/(1 - S rho)]  (eq. solar)
+ *   thermal term    L_t = f tau_up int p(T) B(lambda, T) dT                          (eq. thermal)
+ *   loss            sum_b m_b (L_obs,b - L_b)^2, m_b = 0 for saturated bands          (Sec. 2.5, eq. loss)
+ *   coordinates     z = 2 (x - lo)/(hi - lo) - 1, z clipped to [-1, 1]               (eq. affine)
+ *   summary         E[T], sigma[T] of the moment-matched temperature mixture        (Sec. 2.2)
+ * p(T) is a lognormal of mean m and s.d. s (FF_MODEL_LOGNORMAL_1) or the
+ * eta-weighted mixture of a smouldering and a flaming lognormal
+ * (FF_MODEL_LOGNORMAL_2), integrated by Gauss-Hermite quadrature in log T.
+ * The surface reflectance is linear, rho = rho0 + rho1 (lambda - 1440 nm).
+ * Each pixel is solved by Levenberg-Marquardt (damped Gauss-Newton on the
+ * loss in z, active set for variables held at a bound; the paper's own
+ * solver is Adam), and the Gauss-Newton state covariance is reported.
+ *
+ * Conventions for every entry point:
+ *  - Return value: ff_status, FF_OK (0) on success, negative on error.  No
+ *    entry point throws, aborts or exits.  The message of the last error of
+ *    the calling thread is available from ff_last_error().
+ *  - Argument errors (NULL pointers where a buffer is required, P < 0,
+ *    band-count mismatch, lo >= hi, unknown model/precision/quadrature
+ *    order) return FF_EINVAL before anything is launched.  HIP runtime
+ *    failures return FF_EDEVICE; allocation failures FF_ENOMEM.
+ *  - Device buffers ("_dev") are allocated and owned by the caller (for
+ *    example torch tensors' data_ptr()); the library only reads/writes them.
+ *    Host buffers ("host") are read during the call only.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*, NULL = default stream) and the call returns without waiting,
+ *    except ff_scene_create / ff_scene_band_tables / ff_gauss_hermite /
+ *    ff_retrieve, which are synchronous.
+ *  - Per-pixel failures are not call errors: they are reported in the
+ *    status word of each pixel (FF_ST_* bits).
+ *  - P = 0 is a valid no-op.
+ *  - Calls on different streams may run concurrently; one scene handle may
+ *    be used by several streams at once (it is read-only after creation).
+ */
+#ifndef FIREFIT_H
+#define FIREFIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ff_status;
+#define FF_OK 0
+#define FF_EINVAL (-1)
+#define FF_EDEVICE (-2)
+#define FF_ENOMEM (-3)
+#define FF_EUNSUPPORTED (-4)
+
+/* Temperature-distribution models and their state vectors (physical units):
+ *   FF_MODEL_LOGNORMAL_1: n = 5, x = (f, m, s, rho0, rho1)
+ *   FF_MODEL_LOGNORMAL_2: n = 8, x = (f, eta, m_s, s_s, m_h, s_h, rho0, rho1)
+ * f: emitting fraction scaling the thermal term (the paper's alpha),
+ * m/s: lognormal mean and s.d. in K, eta: weight of the flaming component,
+ * rho0: reflectance at 1440 nm, rho1: reflectance slope per nm. */
+#define FF_MODEL_LOGNORMAL_1 1
+#define FF_MODEL_LOGNORMAL_2 2
+#define FF_MAX_STATE 8
+
+/* Arithmetic of the forward model, Jacobian and reductions.  The damped
+ * Cholesky solve and the covariance inversion are FP64 in both. */
+#define FF_PRECISION_FP32 0
+#define FF_PRECISION_FP64 1
+
+/* Work distribution of the retrieval kernel. */
+#define FF_SCHEDULE_PERSISTENT 0   /* resident waves pull pixels from a device queue; a lane refills as its pixel converges */
+#define FF_SCHEDULE_STATIC 1       /* one pixel per lane, one launch covers all pixels */
+
+/* Per-pixel status bits. */
+#define FF_ST_CONVERGED_GTOL 1u    /* projected gradient small */
+#define FF_ST_CONVERGED_XTOL 2u    /* step below xtol in z */
+#define FF_ST_CONVERGED_FTOL 4u    /* predicted reduction below ftol * F */
+#define FF_ST_MAX_ITER 8u
+#define FF_ST_NONFINITE_INPUT 16u  /* NaN/Inf radiance or model: no solve */
+#define FF_ST_DAMPING_OVERFLOW 32u
+#define FF_ST_COV_SINGULAR 64u     /* some covariance rows are NaN (unidentified variables) */
+#define FF_ST_AT_BOUND 128u        /* some z_j = +-1 at the end */
+#define FF_ST_USED_FALLBACK 256u   /* warm start failed, result is from the default start */
+#define FF_ST_WARM_START 512u      /* solve started from the per-pixel start z0 */
+#define FF_ST_NO_DOF 1024u         /* fewer unmasked bands than n + 1: no solve */
+#define FF_ST_CONVERGED (FF_ST_CONVERGED_GTOL | FF_ST_CONVERGED_XTOL | FF_ST_CONVERGED_FTOL)
+
+/* Columns of the per-band table of a scene (FP64 copy via
+ * ff_scene_band_tables).  Row b holds, for band centre lambda_b (nm):
+ *   0 lambda_b, 1 K_b = E_b cos(sza)/pi, 2 tau_dn,b tau_up,b, 3 tau_up,b,
+ *   4 rho_atm,b, 5 S_b, 6 L_sat,b (+inf when no saturation level),
+ * where E, tau, rho_atm, S are the high-resolution atmosphere resampled with
+ * the band's Gaussian spectral response (truncated at +-4 sigma, weights
+ * normalised to 1).  The remaining columns are internal. */
+#define FF_TABLE_COLS 12
+
+/* Instrument: band centres and FWHM (nm), host arrays [n_bands]. */
+typedef struct ff_srf {
+    int32_t n_bands;
+    const double* wavelength_nm;
+    const double* fwhm_nm;
+} ff_srf;
+
+/* Atmosphere on a uniform high-resolution grid, host arrays [n_hr]:
+ * solar irradiance (W m^-2 nm^-1), transmittances, path reflectance and
+ * spherical albedo (eq. solar).  sat_level: per-band saturation radiance
+ * [n_bands] (bands with L_obs >= level are masked, eq. loss) or NULL. */
+typedef struct ff_atmosphere {
+    int32_t n_hr;
+    const double* lambda_nm;
+    const double* e_solar;
+    const double* tau_down;
+    const double* tau_up;
+    const double* rho_atm;
+    const double* s_sph;
+    double cos_sza;
+    const float* sat_level;
+} ff_atmosphere;
+
+/* Box and default start, physical units, first n entries used. */
+typedef struct ff_prior {
+    int32_t model;
+    double lo[FF_MAX_STATE];
+    double hi[FF_MAX_STATE];
+    double x0[FF_MAX_STATE];
+} ff_prior;
+
+typedef struct ff_options {
+    int32_t max_iter;      /* LM model evaluations after the first (default 50) */
+    int32_t precision;     /* FF_PRECISION_* (default FP32) */
+    int32_t n_quad;        /* Gauss-Hermite order: 8, 12, 16, 20, 24 or 32 (default 32); FP64 supports 32 */
+    int32_t schedule;      /* FF_SCHEDULE_* (default persistent) */
+    int32_t block_size;    /* threads per workgroup, multiple of 64, <= 1024 (0 = default 256) */
+    int32_t blocks_per_cu; /* persistent grid: workgroups per CU (0 = occupancy limit) */
+    int32_t fallback;      /* with a per-pixel start: re-solve failed pixels from x0 (default 1) */
+    int32_t reserved;
+    double xtol;           /* default 1e-6 (z units) */
+    double ftol;           /* default 1e-10 */
+    double gtol;           /* default 1e-10 */
+    double kappa;          /* accept a step whose predicted reduction is <= kappa F (default 1e-5) */
+    double tau;            /* initial damping = tau * max diag(J^T J) (default 1e-3) */
+} ff_options;
+
+/* Outputs, device arrays owned by the caller (any pointer may be NULL to
+ * skip that output):
+ *   state [P][n] physical units; cov_packed [P][n(n+1)/2] upper triangle of
+ *   the state covariance, row-major; moments [P][2] = E[T], sigma[T];
+ *   rrr [P] = ||r|| / ||m L_obs||; iters [P] = model evaluations after the
+ *   first; status [P] = FF_ST_* bits; state_f64 [P][n] double copy of state. */
+typedef struct ff_outputs {
+    float* state;
+    float* cov_packed;
+    float* moments;
+    float* rrr;
+    int32_t* iters;
+    uint32_t* status;
+    double* state_f64;
+} ff_outputs;
+
+typedef struct ff_scene ff_scene;
+
+const char* ff_version(void);
+const char* ff_status_string(ff_status s);
+const char* ff_last_error(void);
+
+/* Defaults of ff_options (see field comments).  Host only. */
+void ff_options_default(ff_options* opts);
+
+/* Default box and start of a model: f in [0, 0.5], m in [350, 2200] K (the
+ * temperature span of the paper's Sec. 2.2 grid), s in [1, 500] K, eta in
+ * [0, 1], smouldering mean in [350, 900] K and flaming mean in
+ * [900, 2200] K (the 900 K regime split of Sec. 3.4), rho0 in [-0.2, 1],
+ * rho1 in [-5e-4, 5e-4] /nm; start f = 0.01, m = 1000, s = 150, eta = 0.5,
+ * m_s = 650, m_h = 1200, rho0 = 0.2, rho1 = 0.  FF_EINVAL for an unknown model. */
+ff_status ff_prior_default(int32_t model, ff_prior* prior);
+
+/* Gauss-Hermite rule for weight e^{-x^2}: q nodes and weights (host arrays
+ * [q]), q in [1, 64].  Used for the lognormal temperature quadrature of
+ * eq. (thermal).  Synchronous, host only. */
+ff_status ff_gauss_hermite(int32_t q, double* nodes_host, double* weights_host);
+
+/* Build a scene: resample the atmosphere to the bands with a Gaussian SRF
+ * and store the per-band factors of eq. (solar) and the Planck constants on
+ * the current device.  Synchronous.  *out owns device memory; free it with
+ * ff_scene_destroy.  FF_EINVAL if a band's response window (+-4 sigma)
+ * contains no high-resolution sample or any array is NULL. */
+ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm, ff_scene** out);
+void ff_scene_destroy(ff_scene* scene);
+int32_t ff_scene_n_bands(const ff_scene* scene);
+
+/* Copy the scene's FP64 band table to host memory [n_bands][FF_TABLE_COLS].
+ * Synchronous. */
+ff_status ff_scene_band_tables(const ff_scene* scene, double* out_host);
+
+/* Forward model of eq. (fm) at P states.  state_dev: [P][n] physical units,
+ * float (FF_PRECISION_FP32) or double (FF_PRECISION_FP64).  radiance_dev:
+ * [P][n_bands] of the same type.  jac_dev: [P][n_bands][n] dL/dx of the same
+ * type, or NULL.  Asynchronous on stream. */
+ff_status ff_forward(const ff_scene* scene, int32_t model, int32_t precision, int32_t n_quad,
+                     const void* state_dev, int64_t P, void* radiance_dev, void* jac_dev,
+                     void* stream);
+
+/* Retrieve P pixels of one scene.  radiance_dev: [P][n_bands] float32,
+ * row-major (band-interleaved by pixel).  z0_dev: [P][n] per-pixel start in
+ * z (for example from a learned warm start) or NULL to start every pixel
+ * from prior->x0.  With z0_dev and opts->fallback, pixels whose solve from
+ * z0 does not converge are solved again from x0 (FF_ST_USED_FALLBACK).
+ * evals_dev: optional uint64 counter that receives += the number of model
+ * evaluations performed (NULL to skip).  Asynchronous on stream; internal
+ * queue counters are allocated stream-ordered. */
+ff_status ff_retrieve_scene(const ff_scene* scene, const float* radiance_dev, int64_t P,
+                            const ff_prior* prior, const float* z0_dev, const ff_options* opts,
+                            const ff_outputs* out, unsigned long long* evals_dev, void* stream);
+
+/* Ragged batch: n_scenes scenes (same band count) in one launch sequence;
+ * per-scene radiance, start and outputs.  z0_dev may be NULL, or an array
+ * of n_scenes pointers (each may be NULL). */
+ff_status ff_retrieve_batch(const ff_scene* const* scenes, const float* const* radiance_dev,
+                            const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                            const float* const* z0_dev, const ff_options* opts,
+                            const ff_outputs* outs, unsigned long long* evals_dev, void* stream);
+
+/* One-shot form: builds a scene from srf/atm, retrieves, destroys the scene.
+ * Synchronous (waits for stream). */
+ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,
+                      const ff_atmosphere* atm, const ff_prior* prior, const float* z0_dev,
+                      const ff_options* opts, const ff_outputs* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIREFIT_H */

@@ -1,0 +1,315 @@
+"""firefit: per-pixel full-physics inversion of VSWIR radiance for sub-pixel
+fire temperature on AMD Instinct MI355X (gfx950).
+
+Thin Python binding of the C-ABI library ``libfirefit.so`` (``include/firefit.h``):
+argument marshalling only.  Every step of the retrieval -- band resampling,
+forward model, Jacobian, reductions, damped solves, covariance, moments --
+runs in the library's HIP kernels.  torch is used for device memory and
+streams.  There is no CPU fallback: if the library is not built, importing
+works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfirefit.so")
+
+FF_OK, FF_EINVAL, FF_EDEVICE, FF_ENOMEM, FF_EUNSUPPORTED = 0, -1, -2, -3, -4
+MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2 = 1, 2
+PRECISION_FP32, PRECISION_FP64 = 0, 1
+SCHEDULE_PERSISTENT, SCHEDULE_STATIC = 0, 1
+MAX_STATE = 8
+TABLE_COLS = 12
+
+ST_CONVERGED_GTOL, ST_CONVERGED_XTOL, ST_CONVERGED_FTOL = 1, 2, 4
+ST_MAX_ITER, ST_NONFINITE_INPUT, ST_DAMPING_OVERFLOW = 8, 16, 32
+ST_COV_SINGULAR, ST_AT_BOUND, ST_USED_FALLBACK, ST_WARM_START, ST_NO_DOF = 64, 128, 256, 512, 1024
+ST_CONVERGED = ST_CONVERGED_GTOL | ST_CONVERGED_XTOL | ST_CONVERGED_FTOL
+
+N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8}
+
+# exported symbols of include/firefit.h
+EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_default",
+           "ff_prior_default", "ff_gauss_hermite", "ff_scene_create", "ff_scene_destroy",
+           "ff_scene_n_bands", "ff_scene_band_tables", "ff_forward", "ff_retrieve_scene",
+           "ff_retrieve_batch", "ff_retrieve")
+
+
+class FirefitError(RuntimeError):
+    pass
+
+
+# ----------------------------------------------------------------------------
+# C structures (layout of include/firefit.h)
+# ----------------------------------------------------------------------------
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+
+
+class ffSrf(C.Structure):
+    _fields_ = [("n_bands", C.c_int32), ("wavelength_nm", _dp), ("fwhm_nm", _dp)]
+
+
+class ffAtmosphere(C.Structure):
+    _fields_ = [("n_hr", C.c_int32), ("lambda_nm", _dp), ("e_solar", _dp), ("tau_down", _dp),
+                ("tau_up", _dp), ("rho_atm", _dp), ("s_sph", _dp), ("cos_sza", C.c_double),
+                ("sat_level", _fp)]
+
+
+class ffPrior(C.Structure):
+    _fields_ = [("model", C.c_int32), ("lo", C.c_double * MAX_STATE),
+                ("hi", C.c_double * MAX_STATE), ("x0", C.c_double * MAX_STATE)]
+
+
+class ffOptions(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("precision", C.c_int32), ("n_quad", C.c_int32),
+                ("schedule", C.c_int32), ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("fallback", C.c_int32), ("reserved", C.c_int32), ("xtol", C.c_double),
+                ("ftol", C.c_double), ("gtol", C.c_double), ("kappa", C.c_double),
+                ("tau", C.c_double)]
+
+
+class ffOutputs(C.Structure):
+    _fields_ = [("state", C.c_void_p), ("cov_packed", C.c_void_p), ("moments", C.c_void_p),
+                ("rrr", C.c_void_p), ("iters", C.c_void_p), ("status", C.c_void_p),
+                ("state_f64", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises FirefitError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FirefitError(f"{LIB_PATH} is missing: build it with paper_2608_07580_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        L.ff_version.restype = C.c_char_p
+        L.ff_status_string.restype = C.c_char_p
+        L.ff_status_string.argtypes = [C.c_int32]
+        L.ff_last_error.restype = C.c_char_p
+        L.ff_options_default.argtypes = [C.POINTER(ffOptions)]
+        L.ff_prior_default.argtypes = [C.c_int32, C.POINTER(ffPrior)]
+        L.ff_gauss_hermite.argtypes = [C.c_int32, _dp, _dp]
+        L.ff_scene_create.argtypes = [C.POINTER(ffSrf), C.POINTER(ffAtmosphere), C.POINTER(C.c_void_p)]
+        L.ff_scene_destroy.argtypes = [C.c_void_p]
+        L.ff_scene_destroy.restype = None
+        L.ff_scene_n_bands.argtypes = [C.c_void_p]
+        L.ff_scene_band_tables.argtypes = [C.c_void_p, _dp]
+        L.ff_forward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ff_retrieve_scene.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(ffPrior),
+                                        C.c_void_p, C.POINTER(ffOptions), C.POINTER(ffOutputs),
+                                        C.c_void_p, C.c_void_p]
+        L.ff_retrieve_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                        C.POINTER(C.c_int64), C.c_int32, C.POINTER(ffPrior),
+                                        C.POINTER(C.c_void_p), C.POINTER(ffOptions),
+                                        C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
+        L.ff_retrieve.argtypes = [C.c_void_p, C.c_int64, C.POINTER(ffSrf), C.POINTER(ffAtmosphere),
+                                  C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
+                                  C.POINTER(ffOutputs), C.c_void_p]
+        for name in ("ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
+                     "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != FF_OK:
+        msg = lib().ff_last_error().decode()
+        raise FirefitError(f"{what}: {lib().ff_status_string(rc).decode()} ({rc}): {msg}")
+
+
+def version() -> str:
+    return lib().ff_version().decode()
+
+
+def gauss_hermite(q: int = 32):
+    x = np.empty(q)
+    w = np.empty(q)
+    _check(lib().ff_gauss_hermite(q, x.ctypes.data_as(_dp), w.ctypes.data_as(_dp)), "ff_gauss_hermite")
+    return x, w
+
+
+def default_options(**kw) -> ffOptions:
+    o = ffOptions()
+    lib().ff_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class Prior:
+    model: int
+    lo: np.ndarray
+    hi: np.ndarray
+    x0: np.ndarray
+
+    def to_c(self) -> ffPrior:
+        p = ffPrior()
+        p.model = self.model
+        n = N_STATE[self.model]
+        for j in range(MAX_STATE):
+            p.lo[j] = float(self.lo[j]) if j < n else 0.0
+            p.hi[j] = float(self.hi[j]) if j < n else 1.0
+            p.x0[j] = float(self.x0[j]) if j < n else 0.5
+        return p
+
+
+def default_prior(model: int = MODEL_LOGNORMAL_1) -> Prior:
+    p = ffPrior()
+    _check(lib().ff_prior_default(model, C.byref(p)), "ff_prior_default")
+    n = N_STATE[model]
+    return Prior(model, np.array(p.lo[:n]), np.array(p.hi[:n]), np.array(p.x0[:n]))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Scene:
+    """Per-scene band tables on the current device (ff_scene)."""
+
+    def __init__(self, atmosphere):
+        a = atmosphere
+        self._keep = [np.ascontiguousarray(x, np.float64) for x in
+                      (a.wavelength_nm, a.fwhm_nm, a.hr_lambda_nm, a.e_solar, a.tau_down,
+                       a.tau_up, a.rho_atm, a.s_sph)]
+        lam, fwhm, hr, e, tdn, tup, ratm, ssph = self._keep
+        sat = None if getattr(a, "sat_level", None) is None else np.ascontiguousarray(a.sat_level, np.float32)
+        self._sat = sat
+        srf = ffSrf(len(lam), lam.ctypes.data_as(_dp), fwhm.ctypes.data_as(_dp))
+        atm = ffAtmosphere(len(hr), hr.ctypes.data_as(_dp), e.ctypes.data_as(_dp),
+                           tdn.ctypes.data_as(_dp), tup.ctypes.data_as(_dp), ratm.ctypes.data_as(_dp),
+                           ssph.ctypes.data_as(_dp), float(a.cos_sza),
+                           sat.ctypes.data_as(_fp) if sat is not None else None)
+        h = C.c_void_p()
+        _check(lib().ff_scene_create(C.byref(srf), C.byref(atm), C.byref(h)), "ff_scene_create")
+        self.handle = h
+        self.n_bands = int(lib().ff_scene_n_bands(h))
+
+    def band_tables(self) -> np.ndarray:
+        out = np.empty((self.n_bands, TABLE_COLS))
+        _check(lib().ff_scene_band_tables(self.handle, out.ctypes.data_as(_dp)), "ff_scene_band_tables")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ff_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def forward(scene: Scene, state, model: int = MODEL_LOGNORMAL_1, n_quad: int = 32,
+            jacobian: bool = False, stream=None):
+    """Model radiance [P, B] (and dL/dx [P, B, n]) at device states [P, n]
+    (float32 -> FP32 kernels, float64 -> FP64 kernels)."""
+    torch = _torch()
+    n = N_STATE[model]
+    assert state.is_cuda and state.dim() == 2 and state.shape[1] == n and state.is_contiguous()
+    prec = PRECISION_FP64 if state.dtype == torch.float64 else PRECISION_FP32
+    assert state.dtype in (torch.float32, torch.float64)
+    P = state.shape[0]
+    L = torch.empty((P, scene.n_bands), dtype=state.dtype, device=state.device)
+    J = torch.empty((P, scene.n_bands, n), dtype=state.dtype, device=state.device) if jacobian else None
+    _check(lib().ff_forward(scene.handle, model, prec, n_quad, _ptr(state), P, _ptr(L), _ptr(J),
+                            _stream_handle(stream)), "ff_forward")
+    return (L, J) if jacobian else L
+
+
+@dataclass
+class Outputs:
+    state: object
+    cov: object
+    moments: object
+    rrr: object
+    iters: object
+    status: object
+    state_f64: object | None = None
+
+    def to_c(self) -> ffOutputs:
+        return ffOutputs(_ptr(self.state), _ptr(self.cov), _ptr(self.moments), _ptr(self.rrr),
+                         _ptr(self.iters), _ptr(self.status), _ptr(self.state_f64))
+
+    def numpy(self) -> dict:
+        d = {k: getattr(self, k) for k in ("state", "cov", "moments", "rrr", "iters", "status", "state_f64")}
+        return {k: (None if v is None else v.cpu().numpy()) for k, v in d.items()}
+
+
+def allocate_outputs(P: int, model: int, device, state_f64: bool = False) -> Outputs:
+    torch = _torch()
+    n = N_STATE[model]
+    return Outputs(state=torch.empty((P, n), dtype=torch.float32, device=device),
+                   cov=torch.empty((P, n * (n + 1) // 2), dtype=torch.float32, device=device),
+                   moments=torch.empty((P, 2), dtype=torch.float32, device=device),
+                   rrr=torch.empty(P, dtype=torch.float32, device=device),
+                   iters=torch.empty(P, dtype=torch.int32, device=device),
+                   status=torch.empty(P, dtype=torch.int32, device=device),
+                   state_f64=torch.empty((P, n), dtype=torch.float64, device=device) if state_f64 else None)
+
+
+def retrieve(scene: Scene, radiance, prior: Prior | None = None, z0=None, options: ffOptions | None = None,
+             outputs: Outputs | None = None, evals=None, stream=None, state_f64: bool = False) -> Outputs:
+    """Levenberg-Marquardt retrieval of every pixel of radiance [P, B] float32 (device)."""
+    torch = _torch()
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    options = options or default_options()
+    assert radiance.is_cuda and radiance.dtype == torch.float32 and radiance.is_contiguous()
+    assert radiance.dim() == 2 and radiance.shape[1] == scene.n_bands
+    P = radiance.shape[0]
+    if z0 is not None:
+        assert z0.is_cuda and z0.dtype == torch.float32 and z0.is_contiguous()
+        assert tuple(z0.shape) == (P, N_STATE[prior.model])
+    out = outputs or allocate_outputs(P, prior.model, radiance.device, state_f64)
+    pc = prior.to_c()
+    oc = out.to_c()
+    _check(lib().ff_retrieve_scene(scene.handle, _ptr(radiance), P, C.byref(pc), _ptr(z0),
+                                   C.byref(options), C.byref(oc), _ptr(evals), _stream_handle(stream)),
+           "ff_retrieve_scene")
+    return out
+
+
+def retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None, options: ffOptions | None = None,
+                   outputs=None, evals=None, stream=None) -> list:
+    """One launch sequence over a ragged batch of scenes (same band count)."""
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    options = options or default_options()
+    ns = len(scenes)
+    outs = outputs or [allocate_outputs(r.shape[0], prior.model, r.device) for r in radiances]
+    sc = (C.c_void_p * ns)(*[s.handle.value for s in scenes])
+    rd = (C.c_void_p * ns)(*[r.data_ptr() for r in radiances])
+    Ps = (C.c_int64 * ns)(*[r.shape[0] for r in radiances])
+    z0p = None
+    if z0s is not None:
+        z0p = (C.c_void_p * ns)(*[0 if z is None else z.data_ptr() for z in z0s])
+    oc = (ffOutputs * ns)(*[o.to_c() for o in outs])
+    pc = prior.to_c()
+    _check(lib().ff_retrieve_batch(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
+                                   _stream_handle(stream)), "ff_retrieve_batch")
+    return outs

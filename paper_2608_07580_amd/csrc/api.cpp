@@ -1,0 +1,206 @@
+// C-ABI entry points of firefit: argument validation, defaults, errors.
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "ff_internal.hpp"
+
+namespace ff {
+
+static thread_local std::string g_last_error;
+
+ff_status set_error(ff_status code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+ff_status clear_error()
+{
+    g_last_error.clear();
+    return FF_OK;
+}
+
+ff_status hip_error(hipError_t e, const char* what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return FF_ENOMEM;
+    return FF_EDEVICE;
+}
+
+int n_state(int model)
+{
+    return model == FF_MODEL_LOGNORMAL_1 ? 5 : (model == FF_MODEL_LOGNORMAL_2 ? 8 : -1);
+}
+
+static ff_status check_prior(const ff_prior* prior)
+{
+    if (!prior) return set_error(FF_EINVAL, "prior is NULL");
+    const int n = n_state(prior->model);
+    if (n < 0) return set_error(FF_EINVAL, "unknown model");
+    for (int j = 0; j < n; ++j) {
+        if (!std::isfinite(prior->lo[j]) || !std::isfinite(prior->hi[j]) || !(prior->hi[j] > prior->lo[j]))
+            return set_error(FF_EINVAL, "prior box needs finite lo < hi for every state variable");
+        if (!std::isfinite(prior->x0[j])) return set_error(FF_EINVAL, "prior x0 is not finite");
+    }
+    // the lognormal mean and s.d. must stay positive over the whole box
+    const int pos[2][4] = {{1, 2, -1, -1}, {2, 3, 4, 5}};
+    for (int k = 0; k < 4; ++k) {
+        const int j = pos[prior->model - 1][k];
+        if (j >= 0 && !(prior->lo[j] > 0.0))
+            return set_error(FF_EINVAL, "temperature mean and spread bounds must be positive");
+    }
+    return FF_OK;
+}
+
+static ff_status check_options(const ff_options* o)
+{
+    if (!o) return set_error(FF_EINVAL, "options is NULL");
+    if (o->max_iter < 0 || o->max_iter > 100000) return set_error(FF_EINVAL, "max_iter out of range");
+    if (o->precision != FF_PRECISION_FP32 && o->precision != FF_PRECISION_FP64)
+        return set_error(FF_EINVAL, "unknown precision");
+    if (o->schedule != FF_SCHEDULE_PERSISTENT && o->schedule != FF_SCHEDULE_STATIC)
+        return set_error(FF_EINVAL, "unknown schedule");
+    if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 256 || o->block_size % 64 != 0))
+        return set_error(FF_EINVAL, "block_size must be 64, 128, 192 or 256");
+    if (o->blocks_per_cu < 0) return set_error(FF_EINVAL, "blocks_per_cu < 0");
+    if (!(o->xtol >= 0) || !(o->ftol >= 0) || !(o->gtol >= 0) || !(o->kappa >= 0) || !(o->tau > 0))
+        return set_error(FF_EINVAL, "tolerances must be >= 0 and tau > 0");
+    return FF_OK;
+}
+
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" const char* ff_version(void) { return "firefit 0.1 (gfx950)"; }
+
+extern "C" const char* ff_status_string(ff_status s)
+{
+    switch (s) {
+    case FF_OK: return "ok";
+    case FF_EINVAL: return "invalid argument";
+    case FF_EDEVICE: return "device error";
+    case FF_ENOMEM: return "out of memory";
+    case FF_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char* ff_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void ff_options_default(ff_options* o)
+{
+    if (!o) return;
+    o->max_iter = 50;
+    o->precision = FF_PRECISION_FP32;
+    o->n_quad = 32;
+    o->schedule = FF_SCHEDULE_PERSISTENT;
+    o->block_size = 256;
+    o->blocks_per_cu = 0;
+    o->fallback = 1;
+    o->reserved = 0;
+    o->xtol = 1e-6;
+    o->ftol = 1e-10;
+    o->gtol = 1e-10;
+    o->kappa = 1e-5;
+    o->tau = 1e-3;
+}
+
+extern "C" ff_status ff_prior_default(int32_t model, ff_prior* p)
+{
+    if (!p) return set_error(FF_EINVAL, "ff_prior_default: NULL prior");
+    for (int j = 0; j < FF_MAX_STATE; ++j) { p->lo[j] = 0.0; p->hi[j] = 1.0; p->x0[j] = 0.5; }
+    p->model = model;
+    if (model == FF_MODEL_LOGNORMAL_1) {
+        const double lo[5] = {0.0, 350.0, 1.0, -0.2, -5e-4};
+        const double hi[5] = {0.5, 2200.0, 500.0, 1.0, 5e-4};
+        const double x0[5] = {0.01, 1000.0, 150.0, 0.2, 0.0};
+        for (int j = 0; j < 5; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
+    } else if (model == FF_MODEL_LOGNORMAL_2) {
+        const double lo[8] = {0.0, 0.0, 350.0, 1.0, 900.0, 1.0, -0.2, -5e-4};
+        const double hi[8] = {0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 5e-4};
+        const double x0[8] = {0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.0};
+        for (int j = 0; j < 8; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
+    } else {
+        return set_error(FF_EINVAL, "ff_prior_default: unknown model");
+    }
+    return clear_error();
+}
+
+extern "C" ff_status ff_gauss_hermite(int32_t q, double* x, double* w)
+{
+    if (!x || !w) return set_error(FF_EINVAL, "ff_gauss_hermite: NULL output");
+    if (q < 1 || q > 64) return set_error(FF_EINVAL, "ff_gauss_hermite: q must be in [1, 64]");
+    if (!gauss_hermite(q, x, w)) return set_error(FF_EDEVICE, "ff_gauss_hermite: root bracketing failed");
+    return clear_error();
+}
+
+extern "C" ff_status ff_forward(const ff_scene* scene, int32_t model, int32_t precision, int32_t n_quad,
+                                const void* state_dev, int64_t P, void* radiance_dev, void* jac_dev,
+                                void* stream)
+{
+    if (!scene) return set_error(FF_EINVAL, "ff_forward: scene is NULL");
+    if (n_state(model) < 0) return set_error(FF_EINVAL, "ff_forward: unknown model");
+    if (precision != FF_PRECISION_FP32 && precision != FF_PRECISION_FP64)
+        return set_error(FF_EINVAL, "ff_forward: unknown precision");
+    if (P < 0) return set_error(FF_EINVAL, "ff_forward: P < 0");
+    if (P == 0) return clear_error();
+    if (!state_dev || !radiance_dev) return set_error(FF_EINVAL, "ff_forward: NULL state or radiance");
+    return dispatch_forward(precision, model, n_quad, scene, state_dev, P, radiance_dev, jac_dev,
+                            (hipStream_t)stream);
+}
+
+extern "C" ff_status ff_retrieve_batch(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                       const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                       const float* const* z0_dev, const ff_options* opts,
+                                       const ff_outputs* outs, unsigned long long* evals_dev,
+                                       void* stream)
+{
+    if (n_scenes < 0) return set_error(FF_EINVAL, "ff_retrieve_batch: n_scenes < 0");
+    if (n_scenes == 0) return clear_error();
+    if (!scenes || !radiance_dev || !P || !outs) return set_error(FF_EINVAL, "ff_retrieve_batch: NULL array");
+    ff_status s = check_prior(prior);
+    if (s != FF_OK) return s;
+    s = check_options(opts);
+    if (s != FF_OK) return s;
+    int B = -1;
+    for (int i = 0; i < n_scenes; ++i) {
+        if (!scenes[i]) return set_error(FF_EINVAL, "ff_retrieve_batch: NULL scene");
+        if (P[i] < 0) return set_error(FF_EINVAL, "ff_retrieve_batch: P < 0");
+        if (B < 0) B = scenes[i]->n_bands;
+        if (scenes[i]->n_bands != B) return set_error(FF_EINVAL, "ff_retrieve_batch: scenes differ in band count");
+        if (P[i] > 0 && !radiance_dev[i]) return set_error(FF_EINVAL, "ff_retrieve_batch: NULL radiance");
+    }
+    BatchSpec bs{scenes, radiance_dev, P, n_scenes, prior, z0_dev, opts, outs, evals_dev, (hipStream_t)stream};
+    return dispatch_lm(opts->precision, prior->model, opts->n_quad, bs);
+}
+
+extern "C" ff_status ff_retrieve_scene(const ff_scene* scene, const float* radiance_dev, int64_t P,
+                                       const ff_prior* prior, const float* z0_dev, const ff_options* opts,
+                                       const ff_outputs* out, unsigned long long* evals_dev, void* stream)
+{
+    if (!scene || !out) return set_error(FF_EINVAL, "ff_retrieve_scene: NULL scene or outputs");
+    const float* const rads[1] = {radiance_dev};
+    const float* const z0s[1] = {z0_dev};
+    const ff_scene* const scs[1] = {scene};
+    const int64_t Ps[1] = {P};
+    return ff_retrieve_batch(scs, rads, Ps, 1, prior, z0s, opts, out, evals_dev, stream);
+}
+
+extern "C" ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,
+                                 const ff_atmosphere* atm, const ff_prior* prior, const float* z0_dev,
+                                 const ff_options* opts, const ff_outputs* out, void* stream)
+{
+    if (srf == nullptr || atm == nullptr) return set_error(FF_EINVAL, "ff_retrieve: NULL srf/atmosphere");
+    ff_scene* sc = nullptr;
+    ff_status s = ff_scene_create(srf, atm, &sc);
+    if (s != FF_OK) return s;
+    s = ff_retrieve_scene(sc, radiance_dev, P, prior, z0_dev, opts, out, nullptr, stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    ff_scene_destroy(sc);
+    if (s != FF_OK) return s;
+    if (e != hipSuccess) return hip_error(e, "ff_retrieve: stream synchronize");
+    return clear_error();
+}

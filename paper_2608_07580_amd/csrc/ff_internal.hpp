@@ -1,0 +1,90 @@
+// Internal declarations of the firefit HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "firefit.h"
+
+namespace ff {
+
+// ---- errors ---------------------------------------------------------------
+ff_status set_error(ff_status code, const std::string& msg);
+ff_status clear_error();
+ff_status hip_error(hipError_t e, const char* what);
+
+#define FF_HIP_TRY(expr)                                   \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) return ff::hip_error(_e, #expr); \
+    } while (0)
+
+// ---- physical constants (exact SI values) ----------------------------------
+constexpr double kPlanck = 6.62607015e-34;
+constexpr double kLight = 299792458.0;
+constexpr double kBoltzmann = 1.380649e-23;
+constexpr double kLambdaRefNm = 1440.0;   // reference wavelength of the reflectance slope
+
+// ---- per-band table layout: row of FF_TABLE_COLS values per band -----------
+// 0..6 are documented in firefit.h; 7..10 are derived constants of the
+// range-scaled Planck evaluation:
+//   a2 = c2 / lambda * log2(e)  [K]  so that exp(-c2/(lambda T)) = 2^(-a2 / T)
+//   cb = c1 / lambda^5 per nm    [W m^-2 sr^-1 nm^-1]
+//   cj = cb * ln 2               (T dB/dT = cj * x2 e / (1 - e)^2 with x2 = a2 / T)
+//   dl = lambda - 1440 nm
+enum TableCol : int {
+    COL_LAMBDA = 0, COL_K = 1, COL_TAU2 = 2, COL_TUP = 3, COL_RATM = 4, COL_S = 5, COL_LSAT = 6,
+    COL_A2 = 7, COL_CB = 8, COL_CJ = 9, COL_DLAM = 10, COL_PAD = 11
+};
+static_assert(FF_TABLE_COLS == 12, "table layout");
+
+}  // namespace ff
+
+// Scene handle: per-band tables in device memory, FP32 and FP64 copies.
+struct ff_scene {
+    int32_t n_bands = 0;
+    int device = 0;
+    float* table_f32 = nullptr;   // [B][12]
+    double* table_f64 = nullptr;  // [B][12]
+};
+
+namespace ff {
+
+// Gauss-Hermite rule computed on the host (nodes by bracketing + Newton on
+// the orthonormal Hermite recurrence, weights 1 / (q p_{q-1}(x)^2)).
+bool gauss_hermite(int q, double* x, double* w);
+
+// Quadrature weights used by the kernels for the lognormal temperature
+// integral: w_hat = w / sqrt(pi), s = sqrt(2) x, v_hat = s * w_hat.
+template <typename R, int Q>
+struct Quad {
+    R w[Q];
+    R v[Q];
+    R s[Q];
+};
+bool make_quad_f32(int q, float* w, float* v, float* s);
+bool make_quad_f64(int q, double* w, double* v, double* s);
+
+int n_state(int model);
+
+// One retrieval launch sequence over a ragged batch of scenes.
+struct BatchSpec {
+    const ff_scene* const* scenes;
+    const float* const* radiance;
+    const int64_t* P;
+    int n_scenes;
+    const ff_prior* prior;
+    const float* const* z0;
+    const ff_options* opts;
+    const ff_outputs* outs;
+    unsigned long long* evals;
+    hipStream_t stream;
+};
+
+ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs);
+ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, const void* state,
+                           int64_t P, void* L, void* J, hipStream_t stream);
+
+}  // namespace ff

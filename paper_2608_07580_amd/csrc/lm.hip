@@ -1,0 +1,867 @@
+// Per-pixel Levenberg-Marquardt retrieval kernel and forward-model kernel.
+//
+// Work mapping: one lane owns one pixel for its whole solve.  Every round
+// of the kernel's loop each lane runs one model evaluation (the initial
+// point of a fresh pixel or the trial point of its current LM step), so the
+// dominant work -- B x Q Planck evaluations per lane -- is executed by all
+// lanes in lock-step with no cross-lane traffic; the damped step, tests and
+// epilogue are per-lane FP64 scalar code.  In the persistent schedule a
+// lane whose pixel has finished pulls the next pixel from a device queue
+// (one wave-aggregated atomic per refill), so uneven convergence does not
+// leave lanes idle until the queue drains.
+//
+// Loss, coordinates and solver (Keely et al. Sec. 2.5): r = m (L_obs - L(x(z))),
+// F = r.r (eq. loss), z = 2 (x - lo)/(hi - lo) - 1 clipped to [-1, 1]
+// (eq. affine).  The damped Gauss-Newton (Levenberg-Marquardt) iteration
+// replaces the paper's Adam: (A + mu diag(d)) delta = -g on the free
+// variables (a variable at a bound whose gradient points out of the box is
+// held), z_t = clip(z + delta), gain-ratio acceptance and damping update.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "physics.hpp"
+
+namespace ff {
+
+constexpr int kMaxScenesPerLaunch = 16;
+constexpr int kMaxSolveTries = 64;
+
+struct SceneDev {
+    const float* radiance;
+    const void* table;
+    int64_t P;
+    int64_t offset;
+    const float* z0;
+    float* state;
+    float* cov;
+    float* moments;
+    float* rrr;
+    int32_t* iters;
+    uint32_t* status;
+    double* state64;
+};
+
+// Launch descriptor, kept in device memory (written by a one-thread fill
+// kernel on the launch stream).  The kernel reads its fields through a
+// laundered pointer where they are used, so loop-invariant values are
+// re-fetched by scalar loads instead of occupying registers for the whole
+// persistent loop.
+template <typename R, int Q>
+struct LmDesc {
+    SceneDev sc[kMaxScenesPerLaunch];
+    int n_scenes;
+    int B;
+    int64_t total;
+    unsigned long long* queue;     // queue head of this pass
+    unsigned long long* evals;     // += model evaluations (may be null)
+    int64_t* fb_items;             // items to re-solve from the default start
+    unsigned long long* fb_count;  // number of fb_items
+    int pass;                      // 0: main pass, 1: fallback pass over fb_items
+    int schedule;
+    int max_iter;
+    int fallback;
+    double xtol, ftol, gtol, kappa, tau;
+    double lo[FF_MAX_STATE], hi[FF_MAX_STATE], zdef[FF_MAX_STATE];
+};
+
+// Hide a pointer's value from the optimiser: loads through the result are
+// not hoisted across this point (the pointer stays in SGPRs, no code).
+template <typename T>
+__device__ __forceinline__ const T* launder(const T* p)
+{
+#ifdef FF_LAUNDER
+    asm volatile("" : "+s"(p));
+#endif
+    return p;
+}
+
+namespace {
+
+// upper-triangle row-major index of (i, j), i <= j: the output packing
+__device__ __forceinline__ int upper(int n, int i, int j) { return i * n - i * (i - 1) / 2 + (j - i); }
+
+template <typename R, int Q>
+__device__ __forceinline__ int scene_of(const LmDesc<R, Q>* p, int64_t item)
+{
+    int s = 0;
+    const int ns = p->n_scenes;
+    for (int i = 1; i < ns; ++i)
+        if (item >= p->sc[i].offset) s = i;
+    return s;
+}
+
+// In-place Cholesky M = C C^T of a packed lower-triangular SPD matrix; the
+// diagonal is stored as 1 / C_jj so the triangular solves only multiply.
+// Returns false if a pivot is not strictly positive.
+template <int N>
+__device__ __forceinline__ bool cholesky_packed(double (&m)[N * (N + 1) / 2])
+{
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double dj = m[tri(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dj -= m[tri(j, k)] * m[tri(j, k)];
+        ok = ok && dj > 0.0;
+        const double dd = dj > 0.0 ? dj : 1.0;
+        double inv = __builtin_amdgcn_rsq(dd);
+        inv = inv * (1.5 - 0.5 * dd * inv * inv);   // one Newton step: full FP64 accuracy
+        m[tri(j, j)] = inv;
+#pragma unroll
+        for (int i = j + 1; i < N; ++i) {
+            double v = m[tri(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= m[tri(i, k)] * m[tri(j, k)];
+            m[tri(i, j)] = v * inv;
+        }
+    }
+    return ok;
+}
+
+// Solve C C^T x = rhs with the factor of cholesky_packed.
+template <int N>
+__device__ __forceinline__ void cholesky_solve(const double (&c)[N * (N + 1) / 2], const double (&rhs)[N],
+                                               double (&x)[N])
+{
+    double y[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double v = rhs[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= c[tri(i, k)] * y[k];
+        y[i] = v * c[tri(i, i)];
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        double v = y[i];
+#pragma unroll
+        for (int k = i + 1; k < N; ++k) v -= c[tri(k, i)] * x[k];
+        x[i] = v * c[tri(i, i)];
+    }
+}
+
+// Projected-gradient test: max over free j of |g_j| / sqrt(A_jj F) <= gtol.
+template <typename R, int N>
+__device__ __forceinline__ bool gradient_small(const R (&z)[N], const R (&A)[N * (N + 1) / 2],
+                                               const R (&g)[N], double F, double gtol)
+{
+    if (!(F > 0.0)) return true;
+    bool small = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double gj = (double)g[j], ajj = (double)A[tri(j, j)];
+        const bool act = ((double)z[j] <= -1.0 && gj > 0.0) || ((double)z[j] >= 1.0 && gj < 0.0);
+        if (!act && ajj > 0.0 && fabs(gj) > gtol * sqrt(ajj * F)) small = false;
+    }
+    return small;
+}
+
+// One model evaluation at physical state x: basis Gram matrix G = sum_b u u^T,
+// h = sum_b u r_b and F = sum_b r_b^2 over unmasked bands, then the normal
+// equations in z: A = D M G M^T D, g = J^T r = -D M h (D = diag((hi-lo)/2)).
+template <typename R, int MODEL, int Q>
+__device__ __forceinline__ R evaluate(const LmDesc<R, Q>* descp, const float* __restrict__ rad,
+                                      const R* __restrict__ tab, const double (&x)[ModelDims<MODEL>::N],
+                                      R (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
+                                      R (&g)[ModelDims<MODEL>::N])
+{
+    using PM = PixelModel<R, MODEL, Q>;
+    constexpr int N = PM::N;
+    constexpr int NT = N * (N + 1) / 2;
+    const int B = launder(descp)->B;
+    PM pm;
+    pm.setup(x);
+    R G[NT], h[N], F = (R)0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) G[i] = (R)0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) h[i] = (R)0;
+
+    for (int b0 = 0; b0 < B; b0 += 4) {
+        // four radiance values per lane per load group: one cache line
+        // serves the group, so a wave fetches each of its 64 rows once
+        float l0 = rad[b0];
+        float l1 = b0 + 1 < B ? rad[b0 + 1] : 0.f;
+        float l2 = b0 + 2 < B ? rad[b0 + 2] : 0.f;
+        float l3 = b0 + 3 < B ? rad[b0 + 3] : 0.f;
+#pragma unroll 1
+        for (int j = 0; j < 4; ++j) {
+            const int b = b0 + j;
+            if (b >= B) break;
+            const float lob = l0;
+            l0 = l1;
+            l1 = l2;
+            l2 = l3;
+            // quadrature weights are re-read (scalar loads) every band
+            const int o = opaque_zero();
+            const BandRow<R> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
+            R ub[N];
+            const R lm = pm.band(row, o, ub);
+            const bool msk = (R)lob < row.lsat;
+            const R r = msk ? (R)lob - lm : (R)0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) ub[i] = msk ? ub[i] : (R)0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                h[i] += ub[i] * r;
+#pragma unroll
+                for (int k = 0; k <= i; ++k) G[tri(i, k)] += ub[i] * ub[k];
+            }
+            F += r * r;
+        }
+    }
+
+    const LmDesc<R, Q>* D = launder(descp);
+    double c1[N], c2[N];
+    PM::coefficients(x, c1, c2);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double dzi = 0.5 * (D->hi[i] - D->lo[i]);
+        const int a1 = PM::s1[i], a2 = PM::s2[i];
+        double gi = c1[i] * (double)h[a1];
+        if (a2 >= 0) gi += c2[i] * (double)h[a2];
+        g[i] = (R)(-dzi * gi);
+#pragma unroll
+        for (int k = 0; k <= i; ++k) {
+            const double dzk = 0.5 * (D->hi[k] - D->lo[k]);
+            const int b1 = PM::s1[k], b2 = PM::s2[k];
+            double v = c1[i] * c1[k] * (double)G[tri(a1, b1)];
+            if (b2 >= 0) v += c1[i] * c2[k] * (double)G[tri(a1, b2)];
+            if (a2 >= 0) v += c2[i] * c1[k] * (double)G[tri(a2, b1)];
+            if (a2 >= 0 && b2 >= 0) v += c2[i] * c2[k] * (double)G[tri(a2, b2)];
+            A[tri(i, k)] = (R)(dzi * dzk * v);
+        }
+    }
+    return F;
+}
+
+// Outputs of one pixel (all pointers may be null).
+struct OutPtrs {
+    float* state;
+    float* cov;
+    float* moments;
+    float* rrr;
+    int32_t* iters;
+    uint32_t* status;
+    double* state64;
+};
+
+__device__ __forceinline__ OutPtrs out_ptrs(const SceneDev& d)
+{
+    return OutPtrs{d.state, d.cov, d.moments, d.rrr, d.iters, d.status, d.state64};
+}
+
+template <int N>
+__device__ inline void write_nan(const OutPtrs& o, int64_t pix)
+{
+    constexpr int NT = N * (N + 1) / 2;
+    const float qn = __builtin_nanf("");
+    if (o.state) for (int j = 0; j < N; ++j) o.state[pix * N + j] = qn;
+    if (o.state64) for (int j = 0; j < N; ++j) o.state64[pix * N + j] = __builtin_nan("");
+    if (o.cov) for (int j = 0; j < NT; ++j) o.cov[pix * NT + j] = qn;
+    if (o.moments) { o.moments[2 * pix] = qn; o.moments[2 * pix + 1] = qn; }
+}
+
+template <typename R, int MODEL, int Q>
+__global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
+{
+    using PM = PixelModel<R, MODEL, Q>;
+    constexpr int N = PM::N;
+    constexpr int NT = N * (N + 1) / 2;
+    const int lane = threadIdx.x & 63;
+
+    // ---- per-lane pixel state ----
+    bool has = false, exhausted = false, warm = false, static_taken = false;
+    int64_t item = -1, pix = 0;
+    int sidx = 0;
+    const float* rad = nullptr;
+    const R* tab = nullptr;
+    double lnorm2 = 0.0, amax = 1.0;
+    int nvalid = 0;
+    R z[N], zt[N], A[NT], g[N], d[N];
+    R F = (R)0;
+    double mu = 0.0, nu = 2.0, pred = 0.0;
+    int it = 0, phase = 0;
+    unsigned st = 0;
+    unsigned long long nevals = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) { z[j] = zt[j] = g[j] = d[j] = (R)0; }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) A[j] = (R)0;
+
+    int64_t total;
+    {
+        const LmDesc<R, Q>* D = launder(descp);
+        total = D->total;
+        if (D->pass == 1) total = (int64_t)__atomic_load_n(D->fb_count, __ATOMIC_RELAXED);
+    }
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+
+    for (;;) {
+        // ------------------------------------------------------------ refill
+        for (;;) {
+            const LmDesc<R, Q>* D = launder(descp);
+            const bool is_static = D->schedule == FF_SCHEDULE_STATIC;
+            const bool need = !has && !exhausted;
+            int64_t my = -1;
+            if (is_static) {
+                if (need) {
+                    if (!static_taken) { my = gtid; static_taken = true; }
+                    else exhausted = true;
+                }
+            } else {
+                const unsigned long long mask = __ballot(need);
+                if (mask == 0ull) break;
+                const int cnt = __popcll(mask);
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(D->queue, (unsigned long long)cnt);
+                const unsigned lo32 = __builtin_amdgcn_readlane((unsigned)(base & 0xffffffffull), leader);
+                const unsigned hi32 = __builtin_amdgcn_readlane((unsigned)(base >> 32), leader);
+                base = ((unsigned long long)hi32 << 32) | lo32;
+                const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+                if (need) my = (int64_t)(base + below);
+            }
+            if (need && my >= 0) {
+                if (my >= total) {
+                    exhausted = true;
+                } else {
+                    item = D->pass == 1 ? D->fb_items[my] : my;
+                    sidx = scene_of(D, item);
+                    const SceneDev& sd = D->sc[sidx];
+                    pix = item - sd.offset;
+                    const int B = D->B;
+                    rad = sd.radiance + pix * B;
+                    tab = reinterpret_cast<const R*>(sd.table);
+                    bool fin = true;
+                    nvalid = 0;
+                    lnorm2 = 0.0;
+                    for (int b = 0; b < B; ++b) {
+                        const float v = rad[b];
+                        fin = fin && isfinite(v);
+                        if ((R)v < tab[(size_t)b * FF_TABLE_COLS + COL_LSAT]) {
+                            ++nvalid;
+                            lnorm2 += (double)v * (double)v;
+                        }
+                    }
+                    it = 0;
+                    phase = 0;
+                    st = 0;
+                    warm = false;
+                    if (!fin || nvalid <= N) {
+                        const OutPtrs o = out_ptrs(sd);
+                        write_nan<N>(o, pix);
+                        if (o.rrr) o.rrr[pix] = __builtin_nanf("");
+                        if (o.iters) o.iters[pix] = 0;
+                        if (o.status) o.status[pix] = !fin ? FF_ST_NONFINITE_INPUT : FF_ST_NO_DOF;
+                    } else {
+                        const float* z0 = sd.z0;
+                        warm = D->pass == 0 && z0 != nullptr;
+#pragma unroll
+                        for (int j = 0; j < N; ++j) {
+                            double zz = warm ? (double)z0[pix * N + j] : D->zdef[j];
+                            zz = isfinite(zz) ? zz : D->zdef[j];
+                            z[j] = (R)fmin(1.0, fmax(-1.0, zz));
+                        }
+                        if (warm) st |= FF_ST_WARM_START;
+                        has = true;
+                    }
+                }
+            }
+            if (is_static) break;
+        }
+        if (__ballot(has) == 0ull) break;
+        if (has) {
+            // ---------------------------------------------- one evaluation
+            double xe[N];
+            {
+                const LmDesc<R, Q>* D = launder(descp);
+#pragma unroll
+                for (int j = 0; j < N; ++j)
+                    xe[j] = D->lo[j] + 0.5 * (D->hi[j] - D->lo[j]) * ((double)(phase == 0 ? z[j] : zt[j]) + 1.0);
+            }
+            R At[NT], gt[N];
+            const R Fe = evaluate<R, MODEL, Q>(descp, rad, tab, xe, At, gt);
+            ++nevals;
+
+            // -------------------------------------------- LM bookkeeping
+            const LmDesc<R, Q>* D = launder(descp);
+            bool done = false, need_step = false;
+            if (phase == 0) {
+                F = Fe;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) A[j] = At[j];
+#pragma unroll
+                for (int j = 0; j < N; ++j) g[j] = gt[j];
+                if (!isfinite((double)Fe)) {
+                    st |= FF_ST_NONFINITE_INPUT;
+                    done = true;
+                } else if (gradient_small<R, N>(z, A, g, (double)F, D->gtol)) {
+                    st |= FF_ST_CONVERGED_GTOL;
+                    done = true;
+                } else {
+                    amax = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) amax = fmax(amax, (double)A[tri(j, j)]);
+                    if (!(amax > 0.0)) amax = 1.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) d[j] = (R)fmax((double)A[tri(j, j)], 1e-12 * amax);
+                    mu = D->tau * amax;
+                    nu = 2.0;
+                    phase = 1;
+                    need_step = true;
+                }
+            } else {
+                ++it;
+                const double rho = ((double)F - (double)Fe) / pred;
+                if (isfinite((double)Fe) && (rho > 0.0 || pred <= D->kappa * (double)F)) {
+                    const double fold = (double)F;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) { z[j] = zt[j]; g[j] = gt[j]; }
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) A[j] = At[j];
+                    F = Fe;
+                    const double rc = fmin(fmax(rho, 0.0), 1.0);
+                    const double t = 2.0 * rc - 1.0;
+                    mu *= fmax(1.0 / 3.0, 1.0 - t * t * t);
+                    nu = 2.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) d[j] = (R)fmax((double)d[j], (double)A[tri(j, j)]);
+                    if (pred <= D->ftol * fold) {
+                        st |= FF_ST_CONVERGED_FTOL;
+                        done = true;
+                    } else if (gradient_small<R, N>(z, A, g, (double)F, D->gtol)) {
+                        st |= FF_ST_CONVERGED_GTOL;
+                        done = true;
+                    }
+                } else {
+                    mu *= nu;
+                    nu *= 2.0;
+                }
+                need_step = !done;
+            }
+
+            // ------------------------------------------- next damped step
+            if (need_step) {
+                if (it >= D->max_iter) {
+                    st |= FF_ST_MAX_ITER;
+                    done = true;
+                } else {
+                    const double xtol = D->xtol;
+                    int tries = 0;
+                    for (;;) {
+                        // keep the FP64 widening of the stored state inside the retry
+                        // loop (hoisting it would hold ~2x the state in registers)
+#pragma unroll
+                        for (int j = 0; j < NT; ++j) asm volatile("" : "+v"(A[j]));
+#pragma unroll
+                        for (int j = 0; j < N; ++j) asm volatile("" : "+v"(g[j]), "+v"(z[j]), "+v"(d[j]));
+                        if (++tries > kMaxSolveTries || mu > 1e30 * amax) {
+                            st |= FF_ST_DAMPING_OVERFLOW;
+                            done = true;
+                            break;
+                        }
+                        bool act[N];
+                        double m[NT], rhs[N], delta[N];
+#pragma unroll
+                        for (int j = 0; j < N; ++j) {
+                            const double gj = (double)g[j], zj = (double)z[j];
+                            act[j] = (zj <= -1.0 && gj > 0.0) || (zj >= 1.0 && gj < 0.0);
+                            rhs[j] = act[j] ? 0.0 : -gj;
+                        }
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+#pragma unroll
+                            for (int k = 0; k < i; ++k)
+                                m[tri(i, k)] = (act[i] || act[k]) ? 0.0 : (double)A[tri(i, k)];
+                            m[tri(i, i)] = act[i] ? 1.0 : (double)A[tri(i, i)] + mu * (double)d[i];
+                        }
+                        if (!cholesky_packed<N>(m)) {
+                            mu *= nu;
+                            nu *= 2.0;
+                            continue;
+                        }
+                        cholesky_solve<N>(m, rhs, delta);
+                        double hstep[N], hmax = 0.0;
+#pragma unroll
+                        for (int j = 0; j < N; ++j) {
+                            const R zz = (R)fmin(1.0, fmax(-1.0, (double)z[j] + delta[j]));
+                            zt[j] = zz;
+                            hstep[j] = (double)zz - (double)z[j];
+                            hmax = fmax(hmax, fabs(hstep[j]));
+                        }
+                        if (hmax <= xtol) {
+                            st |= FF_ST_CONVERGED_XTOL;
+                            done = true;
+                            break;
+                        }
+                        double hg = 0.0, hah = 0.0;
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+                            hg += hstep[i] * (double)g[i];
+                            double row = 0.0;
+#pragma unroll
+                            for (int k = 0; k < N; ++k) row += (double)A[tri(i, k)] * hstep[k];
+                            hah += hstep[i] * row;
+                        }
+                        pred = -(2.0 * hg + hah);
+                        if (pred > 0.0) break;
+                        mu *= nu;
+                        nu *= 2.0;
+                    }
+                }
+            }
+
+            if (done) {
+                // --------------------------------------------------- epilogue
+                has = false;
+                const OutPtrs o = out_ptrs(D->sc[sidx]);
+                const bool valid = !(st & FF_ST_NONFINITE_INPUT);
+                double x[N];
+                bool bound = false;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    x[j] = D->lo[j] + 0.5 * (D->hi[j] - D->lo[j]) * ((double)z[j] + 1.0);
+                    bound = bound || (double)z[j] <= -1.0 || (double)z[j] >= 1.0;
+                }
+                if (valid && bound) st |= FF_ST_AT_BOUND;
+                const double rrr_new = valid && lnorm2 > 0.0 ? sqrt((double)F / lnorm2) : __builtin_nan("");
+                int it_out = it;
+                bool write = true;
+                if (D->pass == 1) {
+                    // fallback from the default start: kept if it converged or fits better
+                    const float old_rrr = o.rrr ? o.rrr[pix] : __builtin_nanf("");
+                    write = (st & FF_ST_CONVERGED) != 0 || !(rrr_new >= (double)old_rrr);
+                    it_out = (o.iters ? o.iters[pix] : 0) + 1 + it;
+                    if (write) st |= FF_ST_USED_FALLBACK;
+                    else if (o.iters) o.iters[pix] = it_out;
+                } else if (warm && D->fallback && !(st & FF_ST_CONVERGED)) {
+                    const unsigned long long slot = atomicAdd(D->fb_count, 1ull);
+                    D->fb_items[slot] = item;
+                }
+                if (write) {
+                    if (valid) {
+                        // Gauss-Newton covariance sigma^2 A^-1 (sigma^2 = F / (N_valid - n))
+                        // in z, scaled to x; variables whose Jacobian column is identically
+                        // zero are unidentified and get NaN rows/columns.
+                        bool keep[N];
+                        double cm[NT];
+                        bool any_drop = false;
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+                            keep[i] = (double)A[tri(i, i)] > 0.0;
+                            any_drop = any_drop || !keep[i];
+                        }
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+#pragma unroll
+                            for (int k = 0; k < i; ++k)
+                                cm[tri(i, k)] = (keep[i] && keep[k]) ? (double)A[tri(i, k)] : 0.0;
+                            cm[tri(i, i)] = keep[i] ? (double)A[tri(i, i)] : 1.0;
+                        }
+                        const bool ok = cholesky_packed<N>(cm);
+                        if (any_drop || !ok) st |= FF_ST_COV_SINGULAR;
+                        const double s2 = (double)F / (double)(nvalid - N);
+                        if (o.cov) {
+                            for (int c = 0; c < N; ++c) {
+                                double e[N], col[N];
+#pragma unroll
+                                for (int i = 0; i < N; ++i) { e[i] = i == c ? 1.0 : 0.0; col[i] = 0.0; }
+                                if (ok) cholesky_solve<N>(cm, e, col);
+                                bool keepc = false;
+#pragma unroll
+                                for (int i = 0; i < N; ++i) keepc = keepc || (i == c && keep[i]);
+                                const double dc = D->hi[c] - D->lo[c];
+#pragma unroll
+                                for (int i = 0; i < N; ++i) {
+                                    if (i <= c) {
+                                        const double v = (ok && keep[i] && keepc)
+                                            ? s2 * col[i] * 0.25 * (D->hi[i] - D->lo[i]) * dc
+                                            : __builtin_nan("");
+                                        o.cov[pix * NT + upper(N, i, c)] = (float)v;
+                                    }
+                                }
+                            }
+                        }
+                        double et, sd;
+                        PM::moments(x, et, sd);
+                        if (o.moments) { o.moments[2 * pix] = (float)et; o.moments[2 * pix + 1] = (float)sd; }
+                        if (o.state) for (int j = 0; j < N; ++j) o.state[pix * N + j] = (float)x[j];
+                        if (o.state64) for (int j = 0; j < N; ++j) o.state64[pix * N + j] = x[j];
+                    } else {
+                        write_nan<N>(o, pix);
+                    }
+                    if (o.rrr) o.rrr[pix] = (float)rrr_new;
+                    if (o.iters) o.iters[pix] = it_out;
+                    if (o.status) o.status[pix] = st;
+                }
+            }
+        }
+    }
+
+    // one atomic per wave for the evaluation count
+    unsigned long long* evals = launder(descp)->evals;
+    if (evals) {
+        unsigned long long v = nevals;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffull), off);
+            const unsigned hi = __shfl_xor((unsigned)(v >> 32), off);
+            v += ((unsigned long long)hi << 32) | lo;
+        }
+        if (lane == 0 && v) atomicAdd(evals, v);
+    }
+}
+
+// Forward model and dL/dx at P states, one lane per pixel.
+template <typename R, int MODEL, int Q>
+__global__ void __launch_bounds__(256)
+forward_kernel(const R* __restrict__ tab, int B, const R* __restrict__ state, int64_t P,
+               R* __restrict__ L, R* __restrict__ J)
+{
+    using PM = PixelModel<R, MODEL, Q>;
+    constexpr int N = PM::N;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) x[j] = (double)state[p * N + j];
+    PM pm;
+    pm.setup(x);
+    double c1[N], c2[N];
+    PM::coefficients(x, c1, c2);
+    for (int b = 0; b < B; ++b) {
+        const BandRow<R> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
+        R ub[N];
+        const R lm = pm.band(row, opaque_zero(), ub);
+        L[p * B + b] = lm;
+        if (J) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double v = c1[i] * (double)ub[PM::s1[i]];
+                if (PM::s2[i] >= 0) v += c2[i] * (double)ub[PM::s2[i]];
+                J[(p * B + b) * N + i] = (R)v;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void fill_struct(const T v, T* __restrict__ out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = v;
+}
+
+__global__ void zero_u64(unsigned long long* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------- host side
+template <typename R, int Q>
+const Quad<R, Q>* cached_quad()
+{
+    static Quad<R, Q> q;
+    static bool ok = false;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        if constexpr (sizeof(R) == 4) ok = make_quad_f32(Q, q.w, q.v, q.s);
+        else ok = make_quad_f64(Q, q.w, q.v, q.s);
+    });
+    return ok ? &q : nullptr;
+}
+
+}  // namespace
+
+
+// Fill the constant-memory quadrature rule of (R, Q) on a device once.
+template <typename R, int Q>
+static bool ensure_quad(int dev)
+{
+    static std::mutex mtx;
+    static bool done[64] = {};
+    if (dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lock(mtx);
+    if (!done[dev]) {
+        const Quad<R, Q>* host = cached_quad<R, Q>();
+        if (!host) return false;
+        const void* sym = reinterpret_cast<const void*>(&c_quad<R, Q>);
+        if (hipMemcpyToSymbol(sym, host, sizeof(Quad<R, Q>), 0, hipMemcpyHostToDevice) != hipSuccess)
+            return false;
+        done[dev] = true;
+    }
+    return true;
+}
+
+template <typename R, int MODEL, int Q>
+static ff_status launch_lm(const BatchSpec& bs)
+{
+    const ff_options& o = *bs.opts;
+    const int block = o.block_size > 0 ? o.block_size : 256;
+    int dev = 0;
+    FF_HIP_TRY(hipGetDevice(&dev));
+    if (!ensure_quad<R, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
+    int n_cu = 0;
+    FF_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    int occ = 0;
+    FF_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lm_kernel<R, MODEL, Q>, block, 0));
+    if (occ < 1) occ = 1;
+    const int per_cu = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
+
+    const int n_chunks = (bs.n_scenes + kMaxScenesPerLaunch - 1) / kMaxScenesPerLaunch;
+    int64_t max_chunk_total = 0;
+    bool any_warm = false;
+    for (int c = 0; c < n_chunks; ++c) {
+        int64_t t = 0;
+        for (int s = c * kMaxScenesPerLaunch; s < std::min(bs.n_scenes, (c + 1) * kMaxScenesPerLaunch); ++s) {
+            t += bs.P[s];
+            if (bs.z0 && bs.z0[s] && bs.P[s] > 0) any_warm = true;
+        }
+        max_chunk_total = std::max(max_chunk_total, t);
+    }
+    if (max_chunk_total == 0) return clear_error();
+    const bool fallback = any_warm && o.fallback != 0;
+
+    // stream-ordered scratch: per chunk 4 counters and 2 descriptors (one
+    // per pass), then the fallback item list
+    using Desc = LmDesc<R, Q>;
+    const size_t desc_bytes = (sizeof(Desc) + 255) / 256 * 256;
+    const size_t n_ctr = 4 * (size_t)n_chunks;
+    const size_t ctr_bytes = (n_ctr * sizeof(unsigned long long) + 255) / 256 * 256;
+    const size_t bytes = ctr_bytes + 2 * (size_t)n_chunks * desc_bytes +
+                         (fallback ? (size_t)max_chunk_total * sizeof(int64_t) : 0);
+    char* scratch = nullptr;
+    FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&scratch), bytes, bs.stream));
+    auto* ctr = reinterpret_cast<unsigned long long*>(scratch);
+    char* descs = scratch + ctr_bytes;
+    int64_t* fb_items = fallback ? reinterpret_cast<int64_t*>(descs + 2 * (size_t)n_chunks * desc_bytes) : nullptr;
+    hipLaunchKernelGGL(zero_u64, dim3((unsigned)((n_ctr + 255) / 256)), dim3(256), 0, bs.stream, ctr, (int)n_ctr);
+    hipError_t e = hipGetLastError();
+
+    for (int c = 0; c < n_chunks && e == hipSuccess; ++c) {
+        Desc prm{};
+        int64_t off = 0;
+        int ns = 0;
+        for (int s = c * kMaxScenesPerLaunch; s < std::min(bs.n_scenes, (c + 1) * kMaxScenesPerLaunch); ++s, ++ns) {
+            SceneDev& d = prm.sc[ns];
+            const ff_outputs& out = bs.outs[s];
+            d.radiance = bs.radiance[s];
+            d.table = sizeof(R) == 4 ? (const void*)bs.scenes[s]->table_f32 : (const void*)bs.scenes[s]->table_f64;
+            d.P = bs.P[s];
+            d.offset = off;
+            d.z0 = bs.z0 ? bs.z0[s] : nullptr;
+            d.state = out.state;
+            d.cov = out.cov_packed;
+            d.moments = out.moments;
+            d.rrr = out.rrr;
+            d.iters = out.iters;
+            d.status = out.status;
+            d.state64 = out.state_f64;
+            off += bs.P[s];
+        }
+        for (int s = ns; s < kMaxScenesPerLaunch; ++s) prm.sc[s].offset = INT64_MAX;
+        if (off == 0) continue;
+        prm.n_scenes = ns;
+        prm.B = bs.scenes[0]->n_bands;
+        prm.total = off;
+        prm.evals = bs.evals;
+        prm.fb_items = fb_items;
+        prm.fb_count = ctr + 4 * c + 2;
+        prm.max_iter = o.max_iter;
+        prm.fallback = fallback ? 1 : 0;
+        prm.xtol = o.xtol;
+        prm.ftol = o.ftol;
+        prm.gtol = o.gtol;
+        prm.kappa = o.kappa;
+        prm.tau = o.tau;
+        const int n = ModelDims<MODEL>::N;
+        for (int j = 0; j < FF_MAX_STATE; ++j) {
+            prm.lo[j] = j < n ? bs.prior->lo[j] : 0.0;
+            prm.hi[j] = j < n ? bs.prior->hi[j] : 1.0;
+            prm.zdef[j] = j < n ? 2.0 * (bs.prior->x0[j] - bs.prior->lo[j]) / (bs.prior->hi[j] - bs.prior->lo[j]) - 1.0 : 0.0;
+        }
+        const int64_t grid_static = (off + block - 1) / block;
+        const int64_t grid_pers = std::min<int64_t>((int64_t)n_cu * per_cu, grid_static);
+        for (int pass = 0; pass < (fallback ? 2 : 1) && e == hipSuccess; ++pass) {
+            prm.pass = pass;
+            prm.queue = ctr + 4 * c + pass;
+            prm.schedule = o.schedule;
+            int64_t grid = o.schedule == FF_SCHEDULE_STATIC ? grid_static : grid_pers;
+            if (pass == 1) {
+                // the fallback pass pulls from the queue: its size is on the device
+                prm.schedule = FF_SCHEDULE_PERSISTENT;
+                grid = grid_pers;
+            }
+            if (grid > 0x7fffffff) {
+                e = hipErrorInvalidValue;
+                break;
+            }
+            Desc* dptr = reinterpret_cast<Desc*>(descs + (2 * (size_t)c + pass) * desc_bytes);
+            hipLaunchKernelGGL(fill_struct<Desc>, dim3(1), dim3(64), 0, bs.stream, prm, dptr);
+            e = hipGetLastError();
+            if (e != hipSuccess) break;
+            hipLaunchKernelGGL((lm_kernel<R, MODEL, Q>), dim3((unsigned)grid), dim3(block), 0, bs.stream,
+                               (const Desc*)dptr);
+            e = hipGetLastError();
+        }
+    }
+    hipError_t e2 = hipFreeAsync(scratch, bs.stream);
+    if (e != hipSuccess) return hip_error(e, "lm_kernel launch");
+    if (e2 != hipSuccess) return hip_error(e2, "hipFreeAsync");
+    return clear_error();
+}
+
+template <typename R, int MODEL, int Q>
+static ff_status launch_forward(const ff_scene* sc, const void* state, int64_t P, void* L, void* J,
+                                hipStream_t stream)
+{
+    if (P == 0) return clear_error();
+    int dev = 0;
+    FF_HIP_TRY(hipGetDevice(&dev));
+    if (!ensure_quad<R, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
+    const int block = 256;
+    const int64_t grid = (P + block - 1) / block;
+    if (grid > 0x7fffffff) return set_error(FF_EINVAL, "ff_forward: P too large");
+    const R* tab = sizeof(R) == 4 ? (const R*)(const void*)sc->table_f32 : (const R*)(const void*)sc->table_f64;
+    hipLaunchKernelGGL((forward_kernel<R, MODEL, Q>), dim3((unsigned)grid), dim3(block), 0, stream, tab,
+                       sc->n_bands, (const R*)state, P, (R*)L, (R*)J);
+    FF_HIP_TRY(hipGetLastError());
+    return clear_error();
+}
+
+// ---------------------------------------------------------------- dispatch
+#define FF_DISPATCH_Q(FN, R, MODEL, q, ...)                         \
+    switch (q) {                                                    \
+    case 16: return FN<R, MODEL, 16>(__VA_ARGS__);                  \
+    case 24: return FN<R, MODEL, 24>(__VA_ARGS__);                  \
+    case 32: return FN<R, MODEL, 32>(__VA_ARGS__);                  \
+    default: return set_error(FF_EUNSUPPORTED, "unsupported quadrature order for FP32 (16, 24, 32)"); \
+    }
+
+ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs)
+{
+    if (precision == FF_PRECISION_FP32) {
+        if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_Q(launch_lm, float, FF_MODEL_LOGNORMAL_1, q, bs) }
+        FF_DISPATCH_Q(launch_lm, float, FF_MODEL_LOGNORMAL_2, q, bs)
+    }
+    if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
+    if (model == FF_MODEL_LOGNORMAL_1) return launch_lm<double, FF_MODEL_LOGNORMAL_1, 32>(bs);
+    return launch_lm<double, FF_MODEL_LOGNORMAL_2, 32>(bs);
+}
+
+ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, const void* state, int64_t P,
+                           void* L, void* J, hipStream_t stream)
+{
+    if (precision == FF_PRECISION_FP32) {
+        if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_Q(launch_forward, float, FF_MODEL_LOGNORMAL_1, q, sc, state, P, L, J, stream) }
+        FF_DISPATCH_Q(launch_forward, float, FF_MODEL_LOGNORMAL_2, q, sc, state, P, L, J, stream)
+    }
+    if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
+    if (model == FF_MODEL_LOGNORMAL_1) return launch_forward<double, FF_MODEL_LOGNORMAL_1, 32>(sc, state, P, L, J, stream);
+    return launch_forward<double, FF_MODEL_LOGNORMAL_2, 32>(sc, state, P, L, J, stream);
+}
+
+}  // namespace ff

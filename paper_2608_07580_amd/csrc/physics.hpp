@@ -1,0 +1,293 @@
+// Device-side forward model of the fire-temperature inversion (Keely et al.,
+// Sec. 2.2): solar term (eq. solar), thermal term (eq. thermal) with a
+// lognormal (or two-lognormal mixture) sub-pixel temperature density
+// integrated by Gauss-Hermite quadrature in log T, and the per-band basis
+// from which the Jacobian follows.
+//
+// Range-scaled Planck: with x2 = a2 / T (a2 = c2 / lambda * log2 e) and
+// e = 2^(-x2) in (0, 1],
+//   B       = cb * e / (1 - e)                 (cb = c1 lambda^-5 per nm)
+//   T dB/dT = cj * x2 * e / (1 - e)^2          (cj = cb ln 2)
+// so no exponential of a positive argument is ever formed: x2 runs from
+// ~0.07 (hottest quadrature node, longest band) to ~4e4 (coldest node,
+// shortest band), where e underflows to 0 and the node contributes 0.
+#pragma once
+
+#include "ff_internal.hpp"
+
+#ifndef FF_NODE_GROUP
+#define FF_NODE_GROUP 8
+#endif
+
+namespace ff {
+
+template <int MODEL> struct ModelDims;
+template <> struct ModelDims<FF_MODEL_LOGNORMAL_1> { static constexpr int N = 5; static constexpr int C = 1; };
+template <> struct ModelDims<FF_MODEL_LOGNORMAL_2> { static constexpr int N = 8; static constexpr int C = 2; };
+
+// Quadrature rule of order Q in constant memory (filled once per device by
+// the host before the first launch).  Kernels index it with a laundered zero
+// offset so each use is a scalar load at the point of use.
+template <typename R, int Q>
+__constant__ Quad<R, Q> c_quad;
+
+__device__ __forceinline__ int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
+// packed lower triangle, (i, j) with j <= i
+__host__ __device__ constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+// Lognormal of mean m and s.d. s: log T ~ N(mu, sig^2), sig^2 = ln(1 + s^2/m^2),
+// mu = ln m - sig^2 / 2; and d(mu, sig)/d(m, s).
+struct LogNormal {
+    double mu, sig, dmu_dm, dmu_ds, dsig_dm, dsig_ds;
+};
+
+__device__ inline LogNormal lognormal(double m, double s)
+{
+    LogNormal r;
+    const double q = m * m + s * s;
+    const double sig2 = log1p(s * s / (m * m));
+    r.sig = sqrt(sig2);
+    r.mu = log(m) - 0.5 * sig2;
+    const double ds2_dm = -2.0 * s * s / (m * q);
+    const double ds2_ds = 2.0 * s / q;
+    r.dmu_dm = 1.0 / m - 0.5 * ds2_dm;
+    r.dmu_ds = -0.5 * ds2_ds;
+    r.dsig_dm = ds2_dm / (2.0 * r.sig);
+    r.dsig_ds = ds2_ds / (2.0 * r.sig);
+    return r;
+}
+
+// Inverse node temperatures u_k = 1 / T_k = exp(-mu - sqrt2 x_k sig), formed
+// in FP64 and rounded once to R.
+template <typename R, int Q>
+__device__ inline void node_inverse_temperatures(const LogNormal& ln, R (&u)[Q])
+{
+    // one node at a time (each exponent depends, through an empty asm, on the
+    // previous node's result): interleaving Q FP64 exponentials would hold
+    // ~3Q registers in a prologue that runs once per evaluation
+    const int o = opaque_zero();
+    double mu = ln.mu;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        u[k] = (R)exp(-mu - (double)c_quad<R, Q>.s[k + o] * ln.sig);
+        asm volatile("" : "+v"(mu) : "v"(u[k]));
+    }
+}
+
+// Quadrature sums over the nodes of one component at one band:
+//   sI = sum_k w_k e/(1-e),  sM = sum_k w_k x2 e/(1-e)^2,  sS = sum_k v_k x2 e/(1-e)^2
+// (w_k = GH weight / sqrt(pi), v_k = sqrt2 x_k w_k).  Then
+//   I = cb sI,  dI/dmu = cj sM,  dI/dsig = cj sS.
+// FP32: 2 transcendental (exp2, rcp) + 8 VALU per node.
+template <int Q>
+__device__ __forceinline__ void thermal_sums(float a2, const float (&u)[Q], int o,
+                                             float& sI, float& sM, float& sS)
+{
+    // Nodes are processed in groups of kGroup.  An empty asm after each group
+    // makes the next group's exponent depend on this group's last reciprocal,
+    // so the compiler cannot hoist all Q exponentials ahead of the sums (which
+    // would keep ~2Q temporaries live); the FMA chains still overlap the
+    // next group's transcendentals.
+    constexpr int kGroup = FF_NODE_GROUP;
+    const Quad<float, Q>& qd = c_quad<float, Q>;
+    float i0 = 0.f, m0 = 0.f, s0 = 0.f;
+    float a = a2;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const float x = a * u[k];
+        const float e = __builtin_amdgcn_exp2f(-x);
+        const float r = __builtin_amdgcn_rcpf(1.0f - e);
+        const float q = e * r;
+        const float wk = qd.w[k + o], vk = qd.v[k + o];
+        i0 = __builtin_fmaf(wk, q, i0);
+        const float y = x * __builtin_fmaf(q, q, q);   // x q (1 + q) = x e / (1 - e)^2
+        m0 = __builtin_fmaf(wk, y, m0);
+        s0 = __builtin_fmaf(vk, y, s0);
+        if ((k + 1) % kGroup == 0) asm volatile("" : "+v"(a) : "v"(i0), "v"(m0), "v"(s0));
+    }
+    sI = i0;
+    sM = m0;
+    sS = s0;
+}
+
+template <int Q>
+__device__ __forceinline__ void thermal_sums(double a2, const double (&u)[Q], int o,
+                                             double& sI, double& sM, double& sS)
+{
+    const Quad<double, Q>& qd = c_quad<double, Q>;
+    double i0 = 0.0, m0 = 0.0, s0 = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < Q; ++k) {
+        const double x = a2 * u[k];
+        const double e = exp2(-x);
+        const double r = 1.0 / (1.0 - e);
+        const double q = e * r;
+        const double wk = qd.w[k + o], vk = qd.v[k + o];
+        i0 = fma(wk, q, i0);
+        const double y = x * fma(q, q, q);
+        m0 = fma(wk, y, m0);
+        s0 = fma(vk, y, s0);
+    }
+    sI = i0;
+    sM = m0;
+    sS = s0;
+}
+
+template <typename R> __device__ __forceinline__ R fast_rcp(R x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
+
+// One band row of the scene table (see TableCol).
+template <typename R>
+struct BandRow {
+    R K, tau2, tup, ratm, S, lsat, a2, cb, cj, dl;
+};
+
+__device__ __forceinline__ BandRow<float> load_row(const float* __restrict__ t)
+{
+    const float4 p0 = *reinterpret_cast<const float4*>(t);
+    const float4 p1 = *reinterpret_cast<const float4*>(t + 4);
+    const float4 p2 = *reinterpret_cast<const float4*>(t + 8);
+    BandRow<float> r;
+    r.K = p0.y; r.tau2 = p0.z; r.tup = p0.w;
+    r.ratm = p1.x; r.S = p1.y; r.lsat = p1.z; r.a2 = p1.w;
+    r.cb = p2.x; r.cj = p2.y; r.dl = p2.z;
+    return r;
+}
+
+__device__ __forceinline__ BandRow<double> load_row(const double* __restrict__ t)
+{
+    const double2 p0 = *reinterpret_cast<const double2*>(t);
+    const double2 p1 = *reinterpret_cast<const double2*>(t + 2);
+    const double2 p2 = *reinterpret_cast<const double2*>(t + 4);
+    const double2 p3 = *reinterpret_cast<const double2*>(t + 6);
+    const double2 p4 = *reinterpret_cast<const double2*>(t + 8);
+    const double2 p5 = *reinterpret_cast<const double2*>(t + 10);
+    BandRow<double> r;
+    r.K = p0.y; r.tau2 = p1.x; r.tup = p1.y;
+    r.ratm = p2.x; r.S = p2.y; r.lsat = p3.x; r.a2 = p3.y;
+    r.cb = p4.x; r.cj = p4.y; r.dl = p5.x;
+    (void)p5;
+    return r;
+}
+
+// Per-pixel constants of one model evaluation.
+template <typename R, int MODEL, int Q> struct PixelModel;
+
+template <typename R, int Q>
+struct PixelModel<R, FF_MODEL_LOGNORMAL_1, Q> {
+    static constexpr int N = 5;
+    R f, r0, r1;
+    R u[Q];
+    __device__ void setup(const double (&x)[N])
+    {
+        f = (R)x[0];
+        r0 = (R)x[3];
+        r1 = (R)x[4];
+        node_inverse_temperatures<R, Q>(lognormal(x[1], x[2]), u);
+    }
+    // Basis u_b (J row = -D M u_b) and model radiance at one band.
+    __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N]) const
+    {
+        R sI, sM, sS;
+        thermal_sums<Q>(t.a2, u, o, sI, sM, sS);
+        const R rho = r0 + r1 * t.dl;
+        const R rden = fast_rcp<R>((R)1 - t.S * rho);
+        const R ls = t.K * (t.ratm + t.tau2 * rho * rden);
+        ub[0] = t.tup * t.cb * sI;
+        ub[1] = t.tup * t.cj * sM;
+        ub[2] = t.tup * t.cj * sS;
+        ub[3] = t.K * t.tau2 * rden * rden;
+        ub[4] = ub[3] * t.dl;
+        return ls + f * ub[0];
+    }
+    // Coefficients of the physical Jacobian rows in the basis:
+    // dL/dx_i = c1_i u[s1_i] + c2_i u[s2_i].
+    static constexpr int s1[N] = {0, 1, 1, 3, 4};
+    static constexpr int s2[N] = {-1, 2, 2, -1, -1};
+    __device__ static void coefficients(const double (&x)[N], double (&c1)[N], double (&c2)[N])
+    {
+        const LogNormal l = lognormal(x[1], x[2]);
+        const double f = x[0];
+        c1[0] = 1.0; c2[0] = 0.0;
+        c1[1] = f * l.dmu_dm; c2[1] = f * l.dsig_dm;
+        c1[2] = f * l.dmu_ds; c2[2] = f * l.dsig_ds;
+        c1[3] = 1.0; c2[3] = 0.0;
+        c1[4] = 1.0; c2[4] = 0.0;
+    }
+    __device__ static void moments(const double (&x)[N], double& et, double& sd)
+    {
+        et = x[1];
+        sd = x[2];
+    }
+};
+
+template <typename R, int Q>
+struct PixelModel<R, FF_MODEL_LOGNORMAL_2, Q> {
+    static constexpr int N = 8;
+    R f, eta, r0, r1;
+    R us[Q], uh[Q];
+    __device__ void setup(const double (&x)[N])
+    {
+        f = (R)x[0];
+        eta = (R)x[1];
+        r0 = (R)x[6];
+        r1 = (R)x[7];
+        node_inverse_temperatures<R, Q>(lognormal(x[2], x[3]), us);
+        node_inverse_temperatures<R, Q>(lognormal(x[4], x[5]), uh);
+    }
+    __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N]) const
+    {
+        R sIs, sMs, sSs, sIh, sMh, sSh;
+        thermal_sums<Q>(t.a2, us, o, sIs, sMs, sSs);
+        thermal_sums<Q>(t.a2, uh, o, sIh, sMh, sSh);
+        const R rho = r0 + r1 * t.dl;
+        const R rden = fast_rcp<R>((R)1 - t.S * rho);
+        const R ls = t.K * (t.ratm + t.tau2 * rho * rden);
+        const R tb = t.tup * t.cb, tj = t.tup * t.cj;
+        const R is_ = tb * sIs, ih = tb * sIh;
+        ub[0] = is_ + eta * (ih - is_);   // tau_up (eta I_h + (1 - eta) I_s)
+        ub[1] = ih - is_;                  // tau_up (I_h - I_s)
+        ub[2] = tj * sMs;
+        ub[3] = tj * sSs;
+        ub[4] = tj * sMh;
+        ub[5] = tj * sSh;
+        ub[6] = t.K * t.tau2 * rden * rden;
+        ub[7] = ub[6] * t.dl;
+        return ls + f * ub[0];
+    }
+    static constexpr int s1[N] = {0, 1, 2, 2, 4, 4, 6, 7};
+    static constexpr int s2[N] = {-1, -1, 3, 3, 5, 5, -1, -1};
+    __device__ static void coefficients(const double (&x)[N], double (&c1)[N], double (&c2)[N])
+    {
+        const LogNormal ls = lognormal(x[2], x[3]);
+        const LogNormal lh = lognormal(x[4], x[5]);
+        const double f = x[0], eta = x[1];
+        const double fs = f * (1.0 - eta), fh = f * eta;
+        c1[0] = 1.0; c2[0] = 0.0;
+        c1[1] = f; c2[1] = 0.0;
+        c1[2] = fs * ls.dmu_dm; c2[2] = fs * ls.dsig_dm;
+        c1[3] = fs * ls.dmu_ds; c2[3] = fs * ls.dsig_ds;
+        c1[4] = fh * lh.dmu_dm; c2[4] = fh * lh.dsig_dm;
+        c1[5] = fh * lh.dmu_ds; c2[5] = fh * lh.dsig_ds;
+        c1[6] = 1.0; c2[6] = 0.0;
+        c1[7] = 1.0; c2[7] = 0.0;
+    }
+    // Sec. 2.2 moment matching: E[T] = eta m_h + (1 - eta) m_s,
+    // Var[T] = eta s_h^2 + (1 - eta) s_s^2 + eta (1 - eta)(m_h - m_s)^2.
+    __device__ static void moments(const double (&x)[N], double& et, double& sd)
+    {
+        const double eta = x[1], ms = x[2], ss = x[3], mh = x[4], sh = x[5];
+        et = eta * mh + (1.0 - eta) * ms;
+        const double dm = mh - ms;
+        sd = sqrt(eta * sh * sh + (1.0 - eta) * ss * ss + eta * (1.0 - eta) * dm * dm);
+    }
+};
+
+}  // namespace ff

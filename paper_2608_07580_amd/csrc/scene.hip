@@ -1,0 +1,167 @@
+// Scene setup: Gaussian spectral-response resampling of the high-resolution
+// atmosphere onto the instrument bands and the per-band constants of the
+// forward model (eq. solar, eq. thermal).  One workgroup per band, FP64.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ff_internal.hpp"
+
+namespace ff {
+namespace {
+
+constexpr int kSetupThreads = 256;
+
+// Per band b: weights w_j = exp(-(l_j - lambda_b)^2 / (2 sig_b^2)) on the
+// high-resolution samples within +-4 sig_b, normalised to sum 1; the
+// resampled value of a spectrum X is sum_j w_j X_j.
+__global__ void __launch_bounds__(kSetupThreads)
+srf_band_tables(int B, int H, const double* __restrict__ lam_b, const double* __restrict__ fwhm_b,
+                const double* __restrict__ hr_lam, const double* __restrict__ e_sol,
+                const double* __restrict__ t_dn, const double* __restrict__ t_up,
+                const double* __restrict__ r_atm, const double* __restrict__ s_sph,
+                const float* __restrict__ sat, double cos_sza,
+                double* __restrict__ tab64, float* __restrict__ tab32, int* __restrict__ bad)
+{
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const double lc = lam_b[b];
+    const double sig = fwhm_b[b] / (2.0 * sqrt(2.0 * log(2.0)));
+    double acc[6] = {0, 0, 0, 0, 0, 0};  // sum w, w E, w t_dn, w t_up, w rho_atm, w S
+    for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        const double d = hr_lam[j] - lc;
+        if (fabs(d) > 4.0 * sig) continue;
+        const double w = exp(-0.5 * (d / sig) * (d / sig));
+        acc[0] += w;
+        acc[1] += w * e_sol[j];
+        acc[2] += w * t_dn[j];
+        acc[3] += w * t_up[j];
+        acc[4] += w * r_atm[j];
+        acc[5] += w * s_sph[j];
+    }
+    __shared__ double red[6][kSetupThreads];
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int stride = kSetupThreads / 2; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + stride];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double sw = red[0][0];
+    if (!(sw > 0.0)) { bad[0] = 1; return; }
+    const double E = red[1][0] / sw, tdn = red[2][0] / sw, tup = red[3][0] / sw;
+    const double ratm = red[4][0] / sw, S = red[5][0] / sw;
+    const double c1 = 2.0 * kPlanck * kLight * kLight;   // W m^2 sr^-1
+    const double c2 = kPlanck * kLight / kBoltzmann;     // m K
+    const double lam_m = lc * 1e-9;
+    double row[FF_TABLE_COLS];
+    row[COL_LAMBDA] = lc;
+    row[COL_K] = E * cos_sza / M_PI;
+    row[COL_TAU2] = tdn * tup;
+    row[COL_TUP] = tup;
+    row[COL_RATM] = ratm;
+    row[COL_S] = S;
+    row[COL_LSAT] = sat ? (double)sat[b] : INFINITY;
+    row[COL_A2] = c2 / lam_m * M_LOG2E;
+    row[COL_CB] = c1 / (lam_m * lam_m * lam_m * lam_m * lam_m) * 1e-9;
+    row[COL_CJ] = row[COL_CB] * M_LN2;
+    row[COL_DLAM] = lc - kLambdaRefNm;
+    row[COL_PAD] = 0.0;
+    for (int c = 0; c < FF_TABLE_COLS; ++c) {
+        tab64[b * FF_TABLE_COLS + c] = row[c];
+        tab32[b * FF_TABLE_COLS + c] = (float)row[c];
+    }
+}
+
+}  // namespace
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm, ff_scene** out)
+{
+    if (!out) return set_error(FF_EINVAL, "ff_scene_create: out is NULL");
+    *out = nullptr;
+    if (!srf || !atm) return set_error(FF_EINVAL, "ff_scene_create: srf/atm is NULL");
+    if (srf->n_bands <= 0 || !srf->wavelength_nm || !srf->fwhm_nm)
+        return set_error(FF_EINVAL, "ff_scene_create: bad band description");
+    if (atm->n_hr <= 0 || !atm->lambda_nm || !atm->e_solar || !atm->tau_down || !atm->tau_up ||
+        !atm->rho_atm || !atm->s_sph)
+        return set_error(FF_EINVAL, "ff_scene_create: bad atmosphere description");
+    const int B = srf->n_bands, H = atm->n_hr;
+    for (int b = 0; b < B; ++b) {
+        if (!(srf->fwhm_nm[b] > 0.0) || !std::isfinite(srf->wavelength_nm[b]) ||
+            !(srf->wavelength_nm[b] > 0.0))
+            return set_error(FF_EINVAL, "ff_scene_create: non-positive FWHM or wavelength");
+    }
+    if (!std::isfinite(atm->cos_sza)) return set_error(FF_EINVAL, "ff_scene_create: cos_sza");
+
+    ff_scene* sc = new ff_scene();
+    sc->n_bands = B;
+    hipError_t e = hipGetDevice(&sc->device);
+    // staging: [lam_b, fwhm_b, hr_lam, E, tdn, tup, ratm, S] doubles + sat floats + bad flag
+    const size_t nd = 2 * (size_t)B + 6 * (size_t)H;
+    double* stage = nullptr;
+    float* sat_d = nullptr;
+    int* bad_d = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&stage, nd * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&sat_d, (size_t)B * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&bad_d, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&sc->table_f64, (size_t)B * FF_TABLE_COLS * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&sc->table_f32, (size_t)B * FF_TABLE_COLS * sizeof(float));
+    if (e == hipSuccess) {
+        std::vector<double> host(nd);
+        std::memcpy(&host[0], srf->wavelength_nm, B * sizeof(double));
+        std::memcpy(&host[B], srf->fwhm_nm, B * sizeof(double));
+        const double* src[6] = {atm->lambda_nm, atm->e_solar, atm->tau_down, atm->tau_up,
+                                atm->rho_atm, atm->s_sph};
+        for (int i = 0; i < 6; ++i) std::memcpy(&host[2 * B + (size_t)i * H], src[i], H * sizeof(double));
+        e = hipMemcpy(stage, host.data(), nd * sizeof(double), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && atm->sat_level)
+        e = hipMemcpy(sat_d, atm->sat_level, (size_t)B * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(bad_d, 0, sizeof(int));
+    if (e == hipSuccess) {
+        const double* s = stage;
+        hipLaunchKernelGGL(srf_band_tables, dim3(B), dim3(kSetupThreads), 0, 0, B, H, s, s + B,
+                           s + 2 * B, s + 2 * B + H, s + 2 * B + 2 * (size_t)H, s + 2 * B + 3 * (size_t)H,
+                           s + 2 * B + 4 * (size_t)H, s + 2 * B + 5 * (size_t)H,
+                           atm->sat_level ? sat_d : nullptr, atm->cos_sza, sc->table_f64,
+                           sc->table_f32, bad_d);
+        e = hipGetLastError();
+    }
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpy(&bad, bad_d, sizeof(int), hipMemcpyDeviceToHost);
+    hipFree(stage);
+    hipFree(sat_d);
+    hipFree(bad_d);
+    if (e != hipSuccess) {
+        ff_scene_destroy(sc);
+        return hip_error(e, "ff_scene_create");
+    }
+    if (bad) {
+        ff_scene_destroy(sc);
+        return set_error(FF_EINVAL, "ff_scene_create: a band's response window holds no high-resolution sample");
+    }
+    *out = sc;
+    return clear_error();
+}
+
+extern "C" void ff_scene_destroy(ff_scene* sc)
+{
+    if (!sc) return;
+    if (sc->table_f32) hipFree(sc->table_f32);
+    if (sc->table_f64) hipFree(sc->table_f64);
+    delete sc;
+}
+
+extern "C" int32_t ff_scene_n_bands(const ff_scene* sc) { return sc ? sc->n_bands : 0; }
+
+extern "C" ff_status ff_scene_band_tables(const ff_scene* sc, double* out_host)
+{
+    if (!sc || !out_host) return set_error(FF_EINVAL, "ff_scene_band_tables: NULL argument");
+    FF_HIP_TRY(hipMemcpy(out_host, sc->table_f64, (size_t)sc->n_bands * FF_TABLE_COLS * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    return clear_error();
+}

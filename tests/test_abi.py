@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every declared entry point; host-only
+entry points and argument validation work without a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2608_07580_amd as ff
+import scenegen
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "firefit.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ff_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ff.LIB_PATH):
+        from paper_2608_07580_amd import build
+        build.build()
+    return ff.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 14
+    assert set(names) == set(ff.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_status_strings(L):
+    assert "firefit" in ff.version()
+    assert L.ff_status_string(ff.FF_EINVAL).decode() == "invalid argument"
+
+
+def test_gauss_hermite_library_matches_oracle(L, oracle_mod):
+    """The library's rule (sign-change bracketing + Newton, weights from
+    p_{q-1}) against the oracle's (Golub-Welsch + Christoffel): two
+    independent algorithms for the same nodes and weights."""
+    for q in (8, 16, 24, 32, 48, 64):
+        x, w = ff.gauss_hermite(q)
+        xo, wo = oracle_mod.gauss_hermite(q)
+        np.testing.assert_allclose(x, xo, atol=2e-14)
+        np.testing.assert_allclose(w, wo, rtol=1e-12)
+
+
+def test_default_prior_and_options(L):
+    for model in (1, 2):
+        p = ff.default_prior(model)
+        lo, hi, x0 = scenegen.default_prior(model)
+        np.testing.assert_array_equal(p.lo, lo)
+        np.testing.assert_array_equal(p.hi, hi)
+        np.testing.assert_array_equal(p.x0, x0)
+    o = ff.default_options()
+    assert (o.max_iter, o.n_quad, o.precision) == (50, 32, ff.PRECISION_FP32)
+    with pytest.raises(ff.FirefitError):
+        ff.default_prior(7)
+
+
+def test_argument_errors_return_einval_before_any_launch(L):
+    # NULL scene / bad sizes: validated on the host
+    assert L.ff_forward(None, 1, 0, 32, None, 10, None, None, None) == ff.FF_EINVAL
+    assert L.ff_forward(None, 3, 0, 32, None, 10, None, None, None) == ff.FF_EINVAL
+    pr = ff.default_prior(1).to_c()
+    o = ff.default_options()
+    assert L.ff_retrieve_batch(None, None, None, -1, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_EINVAL
+    assert L.ff_retrieve_batch(None, None, None, 0, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_OK
+    assert L.ff_retrieve_scene(None, None, 0, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_EINVAL
+    assert "NULL" in ff.lib().ff_last_error().decode()
+    x = np.empty(4)
+    assert L.ff_gauss_hermite(0, x.ctypes.data_as(C.POINTER(C.c_double)), x.ctypes.data_as(C.POINTER(C.c_double))) == ff.FF_EINVAL
