@@ -1,0 +1,189 @@
+"""Benchmark: converged pixel retrievals per second at 284 bands on one MI355X.
+
+Workload (default): the clustered-fire scene, 1,234 cross-track x 2,048 lines =
+2,527,232 pixels x 284 bands float32 radiance (3 % fire pixels in smoothed
+blobs, the rest f = 0 background), synthetic and seeded.  One step = scene
+setup (band resampling) + Levenberg-Marquardt retrieval of every pixel
+(FP32 forward model / Jacobian / reductions, FP64 damped solves) with the
+radiance already resident in HBM.  With a trained warm-start network
+(--warmstart PATH) a step also runs the network and the fallback pass.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Roofline of the dominant kernel: FP32 VALU issue slots.  MI355X: 256 CUs x
+# 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s without packed
+# FP32 (packed FP32 is not used).  v_exp_f32 / v_rcp_f32 issue at half rate
+# (2 slots), everything else 1 slot.
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12
+
+
+def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> int:
+    """Algorithmic VALU slots of one model+Jacobian+reduction evaluation of one
+    pixel: per (band, node) 8 VALU + 2 transcendentals (2 slots each) = 12;
+    per band and component 5 slots of scaling plus 19 (n=5) / 49 (n=8) for the
+    solar term, basis, residual and the J^T J, J^T r, r.r accumulations."""
+    comps = 1 if model == 1 else 2
+    per_band = comps * (12 * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45)
+    return n_bands * per_band
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(args, dev):
+    import torch
+    import paper_2608_07580_amd as ff
+    import scenegen
+    atm = scenegen.make_atmosphere(1, 0)
+    t0 = time.time()
+    states, fire = scenegen.config1_states(args.lines, args.cross, scene=0)
+    P = states.shape[0]
+    scene = ff.Scene(atm)
+    B = scene.n_bands
+    lt = torch.empty((P, B), dtype=torch.float32, device=dev)
+    chunk = 1 << 18
+    for s in range(0, P, chunk):
+        st = torch.tensor(states[s:s + chunk], dtype=torch.float32, device=dev)
+        lt[s:s + chunk] = ff.forward(scene, st, 1)
+    noise = scenegen.noise_normals(1, 0, P, B)
+    rad = torch.empty_like(lt)
+    for s in range(0, P, chunk):
+        n = torch.from_numpy(noise[s:s + chunk]).to(dev)
+        rad[s:s + chunk] = lt[s:s + chunk] * (1.0 + n / args.snr)
+    del lt
+    torch.cuda.synchronize()
+    log(f"workload: {P} px x {B} bands, {fire.sum()} fire px, built in {time.time() - t0:.1f}s")
+    return atm, scene, states, fire, noise, rad
+
+
+def cpu_baseline(args, atm, states, noise):
+    """The FP64 oracle on a seeded subsample of the same scene, on this host."""
+    import oracle
+    import scenegen
+    P = states.shape[0]
+    idx = scenegen.subsample(1, 0, P, args.cpu_sample)
+    tab = oracle.band_tables(atm)
+    lt = oracle.forward(tab, states[idx], 1)
+    lobs = (lt * (1.0 + noise[idx].astype(np.float64) / args.snr)).astype(np.float32)
+    lo, hi, x0 = scenegen.default_prior(1)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.time()
+    r = oracle.retrieve(tab, lobs, 1, lo, hi, x0, nthreads=cores)
+    dt = time.time() - t0
+    conv = int(r.converged.sum())
+    return {"value": conv / dt, "unit": "converged retrievals/s", "cores": cores, "kind": "oracle",
+            "sample": f"seeded uniform subsample of {len(idx)} of the {P} scene pixels "
+                      f"({int((states[idx, 0] > 0).sum())} fire), FP64 LM from the default start, "
+                      f"{dt:.1f} s wall, {conv} converged, mean {r.iters.mean():.1f} iterations"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lines", type=int, default=2048)
+    ap.add_argument("--cross", type=int, default=1234)
+    ap.add_argument("--snr", type=float, default=300.0)
+    ap.add_argument("--n-quad", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2608_07580_amd as ff
+    dev = torch.device("cuda:0")
+    ff.lib()
+    atm, scene, states, fire, noise, rad = make_workload(args, dev)
+    P, B = rad.shape
+    prior = ff.default_prior(1)
+    opts = ff.default_options(n_quad=args.n_quad)
+    stream = torch.cuda.Stream(device=dev)
+    outs = ff.allocate_outputs(P, 1, dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    live = []   # scene tables must outlive the asynchronous launches that read them
+
+    def step():
+        sc = ff.Scene(atm)
+        ff.retrieve(sc, rad, prior, options=opts, outputs=outs, evals=evals, stream=stream)
+        live.append(sc)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        evals.zero_()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.time()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+    for sc in live:
+        sc.close()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    n_evals = int(evals.item()) / args.steps
+    st = outs.status.cpu().numpy().astype(np.int64)
+    conv = int(((st & ff.ST_CONVERGED) != 0).sum())
+    iters = outs.iters.cpu().numpy()
+    value = conv / (ms * 1e-3)
+    spe = slots_per_eval(B, args.n_quad)
+    achieved = n_evals * spe / (ms * 1e-3)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": "converged pixel retrievals/sec @284 bands, plain LM vs NN warm start, % roofline",
+        "value": value, "unit": "converged retrievals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"clustered-fire scene {args.cross} x {args.lines} px x {B} bands, "
+                               f"3% fire, SNR {args.snr:g}, plain LM from the default start",
+                   "pixels": P, "bands": B, "n_quad": args.n_quad, "precision": "fp32-bulk/fp64-solve",
+                   "start": "default (plain LM)"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "op": "FP32 VALU issue slot per lane (transcendental = 2)",
+                     "ops_per_eval": spe, "evals_per_step": n_evals},
+        "plain_lm": {"converged": conv, "pixels": P, "converged_per_s": value,
+                     "mean_iters": float(iters.mean()), "p99_iters": float(np.percentile(iters, 99)),
+                     "evals_per_pixel": n_evals / P, "wall_s_per_step": wall / args.steps},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args, atm, states, noise)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

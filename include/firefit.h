@@ -70,6 +70,11 @@ typedef int32_t ff_status;
 #define FF_PRECISION_FP32 0
 #define FF_PRECISION_FP64 1
 
+/* Accumulation of the per-band sums J^T J, J^T r, r.r on the FP32 path
+ * (the FP64 path always accumulates in FP64). */
+#define FF_ACCUMULATE_FP32 0
+#define FF_ACCUMULATE_FP64 1
+
 /* Work distribution of the retrieval kernel. */
 #define FF_SCHEDULE_PERSISTENT 0   /* resident waves pull pixels from a device queue; a lane refills as its pixel converges */
 #define FF_SCHEDULE_STATIC 1       /* one pixel per lane, one launch covers all pixels */
@@ -83,8 +88,8 @@ typedef int32_t ff_status;
 #define FF_ST_DAMPING_OVERFLOW 32u
 #define FF_ST_COV_SINGULAR 64u     /* some covariance rows are NaN (unidentified variables) */
 #define FF_ST_AT_BOUND 128u        /* some z_j = +-1 at the end */
-#define FF_ST_USED_FALLBACK 256u   /* warm start failed, result is from the default start */
-#define FF_ST_WARM_START 512u      /* solve started from the per-pixel start z0 */
+#define FF_ST_USED_FALLBACK 256u   /* the solve from z0 failed; the result is from the default start x0 */
+#define FF_ST_WARM_START 512u      /* a per-pixel start z0 was used (see FF_ST_USED_FALLBACK) */
 #define FF_ST_NO_DOF 1024u         /* fewer unmasked bands than n + 1: no solve */
 #define FF_ST_CONVERGED (FF_ST_CONVERGED_GTOL | FF_ST_CONVERGED_XTOL | FF_ST_CONVERGED_FTOL)
 
@@ -131,17 +136,17 @@ typedef struct ff_prior {
 typedef struct ff_options {
     int32_t max_iter;      /* LM model evaluations after the first (default 50) */
     int32_t precision;     /* FF_PRECISION_* (default FP32) */
-    int32_t n_quad;        /* Gauss-Hermite order: 8, 12, 16, 20, 24 or 32 (default 32); FP64 supports 32 */
+    int32_t n_quad;        /* Gauss-Hermite order: 16, 24 or 32 (default 32); FP64 supports 32 */
     int32_t schedule;      /* FF_SCHEDULE_* (default persistent) */
-    int32_t block_size;    /* threads per workgroup, multiple of 64, <= 1024 (0 = default 256) */
+    int32_t block_size;    /* threads per workgroup: 64, 128, 192 or 256 (0 = default 256) */
     int32_t blocks_per_cu; /* persistent grid: workgroups per CU (0 = occupancy limit) */
     int32_t fallback;      /* with a per-pixel start: re-solve failed pixels from x0 (default 1) */
-    int32_t reserved;
+    int32_t accumulate;    /* FF_ACCUMULATE_* for the FP32 path (default FP32) */
     double xtol;           /* default 1e-6 (z units) */
     double ftol;           /* default 1e-10 */
     double gtol;           /* default 1e-10 */
     double kappa;          /* accept a step whose predicted reduction is <= kappa F (default 1e-5) */
-    double tau;            /* initial damping = tau * max diag(J^T J) (default 1e-3) */
+    double tau;            /* initial damping = tau * max diag(J^T J) (default 1e-6) */
 } ff_options;
 
 /* Outputs, device arrays owned by the caller (any pointer may be NULL to

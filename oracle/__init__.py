@@ -73,7 +73,7 @@ def lib():
         L.orc_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
                                    C.c_int, dp, dp, dp, dp, C.c_long, fp,
                                    C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
-                                   C.c_int,
+                                   C.c_double, C.c_int,
                                    dp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_uint)]
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -234,6 +234,7 @@ class LMOptions:
     ftol: float = 1e-10
     gtol: float = 1e-10
     kappa: float = 1e-5
+    tau: float = 1e-6      # initial damping mu_0 = tau * max diag(J^T J)
 
 
 @dataclass
@@ -271,7 +272,7 @@ def retrieve(tab: Tables, lobs, model: int, lo, hi, x0, z0=None, q: int = 32,
                             _dp(tab.ratm), _dp(tab.S), _fp(lsat), q, _dp(gx), _dp(gw),
                             model, _dp(lo), _dp(hi), _dp(x0), _dp(z0c), P, _fp(lobs),
                             opts.max_iter, opts.xtol, opts.ftol, opts.gtol, opts.kappa,
-                            nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),
+                            opts.tau, nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),
                             _dp(out.rrr), out.iters.ctypes.data_as(C.POINTER(C.c_int)),
                             out.status.ctypes.data_as(C.POINTER(C.c_uint)))
     if rc != 0:

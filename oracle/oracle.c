@@ -300,7 +300,7 @@ static int gradient_small(int n, const double* z, const double* A, const double*
 
 typedef struct {
     int max_iter;
-    double xtol, ftol, gtol, kappa;
+    double xtol, ftol, gtol, kappa, tau;
 } lmopt_t;
 
 /* Levenberg-Marquardt from z (in/out).  Returns status bits; *iters counts
@@ -321,7 +321,7 @@ static unsigned lm_solve(const problem_t* pb, const lmopt_t* o, double* z,
     for (int j = 0; j < n; ++j) amax = fmax(amax, A[j * n + j]);
     if (!(amax > 0.0)) amax = 1.0;
     for (int j = 0; j < n; ++j) d[j] = fmax(A[j * n + j], 1e-12 * amax);
-    double mu = 1e-3 * amax, nu = 2.0;
+    double mu = o->tau * amax, nu = 2.0;
 
     for (;;) {
         if (*iters >= o->max_iter) { st = ST_MAXITER; break; }
@@ -452,7 +452,7 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
                  int model, const double* lo, const double* hi, const double* x0,
                  const double* z0, long P, const float* lobs,
                  int max_iter, double xtol, double ftol, double gtol, double kappa,
-                 int nthreads,
+                 double tau, int nthreads,
                  double* state, double* cov, double* moments, double* rrr,
                  int* iters, unsigned* status)
 {
@@ -460,7 +460,8 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
     if (n < 0 || Q <= 0 || Q > QMAX || B <= 0 || P < 0) return -1;
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
     scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
-    lmopt_t o = {max_iter, xtol, ftol, gtol, kappa};
+    lmopt_t o = {max_iter, xtol, ftol, gtol, kappa, tau};
+    if (!(tau > 0.0)) return -1;
     const int ncov = n * (n + 1) / 2;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);

@@ -23,6 +23,7 @@ FF_OK, FF_EINVAL, FF_EDEVICE, FF_ENOMEM, FF_EUNSUPPORTED = 0, -1, -2, -3, -4
 MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2 = 1, 2
 PRECISION_FP32, PRECISION_FP64 = 0, 1
 SCHEDULE_PERSISTENT, SCHEDULE_STATIC = 0, 1
+ACCUMULATE_FP32, ACCUMULATE_FP64 = 0, 1
 MAX_STATE = 8
 TABLE_COLS = 12
 
@@ -69,7 +70,7 @@ class ffPrior(C.Structure):
 class ffOptions(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("precision", C.c_int32), ("n_quad", C.c_int32),
                 ("schedule", C.c_int32), ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("fallback", C.c_int32), ("reserved", C.c_int32), ("xtol", C.c_double),
+                ("fallback", C.c_int32), ("accumulate", C.c_int32), ("xtol", C.c_double),
                 ("ftol", C.c_double), ("gtol", C.c_double), ("kappa", C.c_double),
                 ("tau", C.c_double)]
 

@@ -160,8 +160,8 @@ __device__ __forceinline__ bool gradient_small(const R (&z)[N], const R (&A)[N *
 // One model evaluation at physical state x: basis Gram matrix G = sum_b u u^T,
 // h = sum_b u r_b and F = sum_b r_b^2 over unmasked bands, then the normal
 // equations in z: A = D M G M^T D, g = J^T r = -D M h (D = diag((hi-lo)/2)).
-template <typename R, int MODEL, int Q>
-__device__ __forceinline__ R evaluate(const LmDesc<R, Q>* descp, const float* __restrict__ rad,
+template <typename R, typename ACC, int MODEL, int Q>
+__device__ __forceinline__ double evaluate(const LmDesc<R, Q>* descp, const float* __restrict__ rad,
                                       const R* __restrict__ tab, const double (&x)[ModelDims<MODEL>::N],
                                       R (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
                                       R (&g)[ModelDims<MODEL>::N])
@@ -172,11 +172,11 @@ __device__ __forceinline__ R evaluate(const LmDesc<R, Q>* descp, const float* __
     const int B = launder(descp)->B;
     PM pm;
     pm.setup(x);
-    R G[NT], h[N], F = (R)0;
+    ACC G[NT], h[N], F = (ACC)0;
 #pragma unroll
-    for (int i = 0; i < NT; ++i) G[i] = (R)0;
+    for (int i = 0; i < NT; ++i) G[i] = (ACC)0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) h[i] = (R)0;
+    for (int i = 0; i < N; ++i) h[i] = (ACC)0;
 
     for (int b0 = 0; b0 < B; b0 += 4) {
         // four radiance values per lane per load group: one cache line
@@ -199,14 +199,15 @@ __device__ __forceinline__ R evaluate(const LmDesc<R, Q>* descp, const float* __
             R ub[N];
             const R lm = pm.band(row, o, ub);
             const bool msk = (R)lob < row.lsat;
-            const R r = msk ? (R)lob - lm : (R)0;
+            const ACC r = msk ? (ACC)((R)lob - lm) : (ACC)0;
+            ACC ua[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) ub[i] = msk ? ub[i] : (R)0;
+            for (int i = 0; i < N; ++i) ua[i] = msk ? (ACC)ub[i] : (ACC)0;
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                h[i] += ub[i] * r;
+                h[i] += ua[i] * r;
 #pragma unroll
-                for (int k = 0; k <= i; ++k) G[tri(i, k)] += ub[i] * ub[k];
+                for (int k = 0; k <= i; ++k) G[tri(i, k)] += ua[i] * ua[k];
             }
             F += r * r;
         }
@@ -263,7 +264,7 @@ __device__ inline void write_nan(const OutPtrs& o, int64_t pix)
     if (o.moments) { o.moments[2 * pix] = qn; o.moments[2 * pix + 1] = qn; }
 }
 
-template <typename R, int MODEL, int Q>
+template <typename R, typename ACC, int MODEL, int Q>
 __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
 {
     using PM = PixelModel<R, MODEL, Q>;
@@ -280,7 +281,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
     double lnorm2 = 0.0, amax = 1.0;
     int nvalid = 0;
     R z[N], zt[N], A[NT], g[N], d[N];
-    R F = (R)0;
+    double F = 0.0;
     double mu = 0.0, nu = 2.0, pred = 0.0;
     int it = 0, phase = 0;
     unsigned st = 0;
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     xe[j] = D->lo[j] + 0.5 * (D->hi[j] - D->lo[j]) * ((double)(phase == 0 ? z[j] : zt[j]) + 1.0);
             }
             R At[NT], gt[N];
-            const R Fe = evaluate<R, MODEL, Q>(descp, rad, tab, xe, At, gt);
+            const double Fe = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, xe, At, gt);
             ++nevals;
 
             // -------------------------------------------- LM bookkeeping
@@ -395,10 +396,10 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                 for (int j = 0; j < NT; ++j) A[j] = At[j];
 #pragma unroll
                 for (int j = 0; j < N; ++j) g[j] = gt[j];
-                if (!isfinite((double)Fe)) {
+                if (!isfinite(Fe)) {
                     st |= FF_ST_NONFINITE_INPUT;
                     done = true;
-                } else if (gradient_small<R, N>(z, A, g, (double)F, D->gtol)) {
+                } else if (gradient_small<R, N>(z, A, g, F, D->gtol)) {
                     st |= FF_ST_CONVERGED_GTOL;
                     done = true;
                 } else {
@@ -415,9 +416,9 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                 }
             } else {
                 ++it;
-                const double rho = ((double)F - (double)Fe) / pred;
-                if (isfinite((double)Fe) && (rho > 0.0 || pred <= D->kappa * (double)F)) {
-                    const double fold = (double)F;
+                const double rho = (F - Fe) / pred;
+                if (isfinite(Fe) && (rho > 0.0 || pred <= D->kappa * F)) {
+                    const double fold = F;
 #pragma unroll
                     for (int j = 0; j < N; ++j) { z[j] = zt[j]; g[j] = gt[j]; }
 #pragma unroll
@@ -432,7 +433,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     if (pred <= D->ftol * fold) {
                         st |= FF_ST_CONVERGED_FTOL;
                         done = true;
-                    } else if (gradient_small<R, N>(z, A, g, (double)F, D->gtol)) {
+                    } else if (gradient_small<R, N>(z, A, g, F, D->gtol)) {
                         st |= FF_ST_CONVERGED_GTOL;
                         done = true;
                     }
@@ -527,7 +528,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     bound = bound || (double)z[j] <= -1.0 || (double)z[j] >= 1.0;
                 }
                 if (valid && bound) st |= FF_ST_AT_BOUND;
-                const double rrr_new = valid && lnorm2 > 0.0 ? sqrt((double)F / lnorm2) : __builtin_nan("");
+                const double rrr_new = valid && lnorm2 > 0.0 ? sqrt(F / lnorm2) : __builtin_nan("");
                 int it_out = it;
                 bool write = true;
                 if (D->pass == 1) {
@@ -535,7 +536,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     const float old_rrr = o.rrr ? o.rrr[pix] : __builtin_nanf("");
                     write = (st & FF_ST_CONVERGED) != 0 || !(rrr_new >= (double)old_rrr);
                     it_out = (o.iters ? o.iters[pix] : 0) + 1 + it;
-                    if (write) st |= FF_ST_USED_FALLBACK;
+                    if (write) st |= FF_ST_USED_FALLBACK | FF_ST_WARM_START;
                     else if (o.iters) o.iters[pix] = it_out;
                 } else if (warm && D->fallback && !(st & FF_ST_CONVERGED)) {
                     const unsigned long long slot = atomicAdd(D->fb_count, 1ull);
@@ -563,7 +564,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                         }
                         const bool ok = cholesky_packed<N>(cm);
                         if (any_drop || !ok) st |= FF_ST_COV_SINGULAR;
-                        const double s2 = (double)F / (double)(nvalid - N);
+                        const double s2 = F / (double)(nvalid - N);
                         if (o.cov) {
                             for (int c = 0; c < N; ++c) {
                                 double e[N], col[N];
@@ -696,7 +697,7 @@ static bool ensure_quad(int dev)
     return true;
 }
 
-template <typename R, int MODEL, int Q>
+template <typename R, typename ACC, int MODEL, int Q>
 static ff_status launch_lm(const BatchSpec& bs)
 {
     const ff_options& o = *bs.opts;
@@ -707,7 +708,7 @@ static ff_status launch_lm(const BatchSpec& bs)
     int n_cu = 0;
     FF_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     int occ = 0;
-    FF_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lm_kernel<R, MODEL, Q>, block, 0));
+    FF_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lm_kernel<R, ACC, MODEL, Q>, block, 0));
     if (occ < 1) occ = 1;
     const int per_cu = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
 
@@ -803,7 +804,7 @@ static ff_status launch_lm(const BatchSpec& bs)
             hipLaunchKernelGGL(fill_struct<Desc>, dim3(1), dim3(64), 0, bs.stream, prm, dptr);
             e = hipGetLastError();
             if (e != hipSuccess) break;
-            hipLaunchKernelGGL((lm_kernel<R, MODEL, Q>), dim3((unsigned)grid), dim3(block), 0, bs.stream,
+            hipLaunchKernelGGL((lm_kernel<R, ACC, MODEL, Q>), dim3((unsigned)grid), dim3(block), 0, bs.stream,
                                (const Desc*)dptr);
             e = hipGetLastError();
         }
@@ -833,31 +834,44 @@ static ff_status launch_forward(const ff_scene* sc, const void* state, int64_t P
 }
 
 // ---------------------------------------------------------------- dispatch
-#define FF_DISPATCH_Q(FN, R, MODEL, q, ...)                         \
+#define FF_DISPATCH_Q(FN, q, ...)                                       \
     switch (q) {                                                    \
-    case 16: return FN<R, MODEL, 16>(__VA_ARGS__);                  \
-    case 24: return FN<R, MODEL, 24>(__VA_ARGS__);                  \
-    case 32: return FN<R, MODEL, 32>(__VA_ARGS__);                  \
+    case 16: return FN<__VA_ARGS__, 16>(bs);                        \
+    case 24: return FN<__VA_ARGS__, 24>(bs);                        \
+    case 32: return FN<__VA_ARGS__, 32>(bs);                        \
     default: return set_error(FF_EUNSUPPORTED, "unsupported quadrature order for FP32 (16, 24, 32)"); \
     }
 
 ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs)
 {
+    const bool acc64 = bs.opts->accumulate == FF_ACCUMULATE_FP64;
     if (precision == FF_PRECISION_FP32) {
-        if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_Q(launch_lm, float, FF_MODEL_LOGNORMAL_1, q, bs) }
-        FF_DISPATCH_Q(launch_lm, float, FF_MODEL_LOGNORMAL_2, q, bs)
+        if (model == FF_MODEL_LOGNORMAL_1) {
+            if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_LOGNORMAL_1) }
+            FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_LOGNORMAL_1)
+        }
+        if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_LOGNORMAL_2) }
+        FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_LOGNORMAL_2)
     }
     if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
-    if (model == FF_MODEL_LOGNORMAL_1) return launch_lm<double, FF_MODEL_LOGNORMAL_1, 32>(bs);
-    return launch_lm<double, FF_MODEL_LOGNORMAL_2, 32>(bs);
+    if (model == FF_MODEL_LOGNORMAL_1) return launch_lm<double, double, FF_MODEL_LOGNORMAL_1, 32>(bs);
+    return launch_lm<double, double, FF_MODEL_LOGNORMAL_2, 32>(bs);
 }
+
+#define FF_DISPATCH_FWD(q, ...)                                      \
+    switch (q) {                                                    \
+    case 16: return launch_forward<__VA_ARGS__, 16>(sc, state, P, L, J, stream); \
+    case 24: return launch_forward<__VA_ARGS__, 24>(sc, state, P, L, J, stream); \
+    case 32: return launch_forward<__VA_ARGS__, 32>(sc, state, P, L, J, stream); \
+    default: return set_error(FF_EUNSUPPORTED, "unsupported quadrature order for FP32 (16, 24, 32)"); \
+    }
 
 ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, const void* state, int64_t P,
                            void* L, void* J, hipStream_t stream)
 {
     if (precision == FF_PRECISION_FP32) {
-        if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_Q(launch_forward, float, FF_MODEL_LOGNORMAL_1, q, sc, state, P, L, J, stream) }
-        FF_DISPATCH_Q(launch_forward, float, FF_MODEL_LOGNORMAL_2, q, sc, state, P, L, J, stream)
+        if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_1) }
+        FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_2)
     }
     if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_forward<double, FF_MODEL_LOGNORMAL_1, 32>(sc, state, P, L, J, stream);
