@@ -234,6 +234,86 @@ ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,
                       const ff_atmosphere* atm, const ff_prior* prior, const float* z0_dev,
                       const ff_options* opts, const ff_outputs* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A multilayer perceptron maps a radiance spectrum to a
+ * starting state z0 for the LM solve (which always refines it and falls
+ * back to the default start when the solve from z0 fails).  Layers:
+ * n_in -> h1 -> h2 -> h3 -> n_out, GELU (tanh form, Hendrycks & Gimpel 2016)
+ * after each hidden layer and tanh on the output, so z0 lies in (-1, 1).
+ * Input features: u_b = (ln max(L_b, floor) - mean_b) * inv_std_b.
+ * Weights: FP32 master copy; BF16 copies feed the matrix-core (MFMA) GEMMs,
+ * which accumulate in FP32.  Training: mean squared error in z, Adam
+ * (Kingma & Ba; the paper's Sec. 2.5 update with beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8).
+ * Parameter vector layout (ff_mlp_get_params / ff_mlp_set_params):
+ *   W1 [h1][n_in], b1 [h1], W2 [h2][h1], b2 [h2], W3 [h3][h2], b3 [h3],
+ *   W4 [n_out][h3], b4 [n_out]   (row-major, out x in).
+ * ------------------------------------------------------------------------ */
+typedef struct ff_mlp ff_mlp;
+
+/* Create a network on the current device with weights drawn from a seeded
+ * counter-based generator (He-normal for hidden layers, zero biases) and
+ * identity normalisation.  n_in <= 1024, hidden sizes multiples of 64 and
+ * <= 1024, n_out <= 16.  Synchronous. */
+ff_status ff_mlp_create(int32_t n_in, int32_t h1, int32_t h2, int32_t h3, int32_t n_out,
+                        uint64_t seed, ff_mlp** out);
+void ff_mlp_destroy(ff_mlp* mlp);
+int64_t ff_mlp_n_params(const ff_mlp* mlp);
+
+/* Copy the FP32 parameter vector to/from host memory [ff_mlp_n_params]
+ * (set also refreshes the BF16 copies and clears the Adam state).
+ * Synchronous. */
+ff_status ff_mlp_get_params(const ff_mlp* mlp, float* params_host);
+ff_status ff_mlp_set_params(ff_mlp* mlp, const float* params_host);
+
+/* Feature normalisation: host arrays [n_in] and the radiance floor.
+ * Synchronous. */
+ff_status ff_mlp_set_normalization(ff_mlp* mlp, const float* mean_host, const float* inv_std_host,
+                                   float floor);
+ff_status ff_mlp_get_normalization(const ff_mlp* mlp, float* mean_host, float* inv_std_host, float* floor);
+
+/* Set the normalisation from P spectra radiance_dev [P][n_in] (per-band
+ * mean and 1/s.d. of ln max(L, floor)).  Asynchronous on stream. */
+ff_status ff_mlp_fit_normalization(ff_mlp* mlp, const float* radiance_dev, int64_t P, float floor,
+                                   void* stream);
+
+/* Warm start: z0_dev [P][n_out] = network(radiance_dev [P][n_in]).
+ * Asynchronous on stream; internal activations are processed in chunks. */
+ff_status ff_mlp_infer(const ff_mlp* mlp, const float* radiance_dev, int64_t P, float* z0_dev,
+                       void* stream);
+
+/* Loss and gradient of one batch: loss_dev[0] = mean over the batch and
+ * outputs of (z - target)^2, grads_dev [ff_mlp_n_params] (either may be
+ * NULL).  target_dev [P][n_out].  P <= 65536.  Asynchronous on stream. */
+ff_status ff_mlp_gradients(ff_mlp* mlp, const float* radiance_dev, const float* target_dev, int64_t P,
+                           double* loss_dev, float* grads_dev, void* stream);
+
+/* One Adam step on one batch (gradients as above, then the update with
+ * learning rate lr).  loss_dev may be NULL.  Asynchronous on stream. */
+ff_status ff_mlp_train_step(ff_mlp* mlp, const float* radiance_dev, const float* target_dev, int64_t P,
+                            float lr, double* loss_dev, void* stream);
+
+/* Training data: P spectra of the one-component model for the scene, with
+ * states drawn from a Philox4x32-10 counter generator keyed by seed
+ * (sample g = offset + p): f ~ logU[1e-4, 0.3], m ~ U[600, 1400] K,
+ * s ~ U[50, 300] K, rho0 ~ U[0.05, 0.4], rho1 ~ U[-1e-4, 1e-4] /nm; a
+ * fraction bg_fraction of samples has f = 0 (background, target m, s = x0).
+ * Noise sigma = L / snr (snr <= 0: none) from Box-Muller pairs.  Writes
+ * radiance_dev [P][n_bands], target_z_dev [P][5] (z of the state in prior's
+ * box, clipped to [-1, 1]) and optionally state_dev [P][5] (physical).
+ * Asynchronous on stream. */
+ff_status ff_mlp_generate(const ff_scene* scene, const ff_prior* prior, uint64_t seed, uint64_t offset,
+                          int64_t P, double snr, double bg_fraction, float* radiance_dev,
+                          float* target_z_dev, float* state_dev, void* stream);
+
+/* Train for `steps` Adam steps of `batch` fresh generated spectra each
+ * (sample offset advances by batch per step); the learning rate decays by
+ * cosine from lr to lr_final.  loss_history_dev [steps] or NULL.
+ * Asynchronous on stream. */
+ff_status ff_mlp_train(ff_mlp* mlp, const ff_scene* scene, const ff_prior* prior, int64_t steps,
+                       int32_t batch, uint64_t seed, double snr, double bg_fraction, float lr,
+                       float lr_final, double* loss_history_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

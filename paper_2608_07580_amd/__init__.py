@@ -38,7 +38,11 @@ N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8}
 EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_default",
            "ff_prior_default", "ff_gauss_hermite", "ff_scene_create", "ff_scene_destroy",
            "ff_scene_n_bands", "ff_scene_band_tables", "ff_forward", "ff_retrieve_scene",
-           "ff_retrieve_batch", "ff_retrieve")
+           "ff_retrieve_batch", "ff_retrieve",
+           "ff_mlp_create", "ff_mlp_destroy", "ff_mlp_n_params", "ff_mlp_get_params",
+           "ff_mlp_set_params", "ff_mlp_set_normalization", "ff_mlp_get_normalization",
+           "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
+           "ff_mlp_generate", "ff_mlp_train")
 
 
 class FirefitError(RuntimeError):
@@ -115,8 +119,29 @@ def lib():
         L.ff_retrieve.argtypes = [C.c_void_p, C.c_int64, C.POINTER(ffSrf), C.POINTER(ffAtmosphere),
                                   C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
                                   C.POINTER(ffOutputs), C.c_void_p]
+        vp = C.c_void_p
+        L.ff_mlp_create.argtypes = [C.c_int32] * 5 + [C.c_uint64, C.POINTER(vp)]
+        L.ff_mlp_destroy.argtypes = [vp]
+        L.ff_mlp_destroy.restype = None
+        L.ff_mlp_n_params.argtypes = [vp]
+        L.ff_mlp_n_params.restype = C.c_int64
+        L.ff_mlp_get_params.argtypes = [vp, _fp]
+        L.ff_mlp_set_params.argtypes = [vp, _fp]
+        L.ff_mlp_set_normalization.argtypes = [vp, _fp, _fp, C.c_float]
+        L.ff_mlp_get_normalization.argtypes = [vp, _fp, _fp, _fp]
+        L.ff_mlp_fit_normalization.argtypes = [vp, vp, C.c_int64, C.c_float, vp]
+        L.ff_mlp_infer.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.ff_mlp_gradients.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
+        L.ff_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, vp, vp]
+        L.ff_mlp_generate.argtypes = [vp, C.POINTER(ffPrior), C.c_uint64, C.c_uint64, C.c_int64, C.c_double,
+                                      C.c_double, vp, vp, vp, vp]
+        L.ff_mlp_train.argtypes = [vp, vp, C.POINTER(ffPrior), C.c_int64, C.c_int32, C.c_uint64, C.c_double,
+                                   C.c_double, C.c_float, C.c_float, vp, vp]
         for name in ("ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
-                     "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default"):
+                     "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default",
+                     "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
+                     "ff_mlp_get_normalization", "ff_mlp_fit_normalization", "ff_mlp_infer",
+                     "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -314,3 +339,117 @@ def retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None, opti
     _check(lib().ff_retrieve_batch(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
                                    _stream_handle(stream)), "ff_retrieve_batch")
     return outs
+
+
+# ----------------------------------------------------------------------------
+# learned warm start
+# ----------------------------------------------------------------------------
+def generate(scene: Scene, prior: Prior, seed: int, offset: int, P: int, snr: float = 300.0,
+             bg_fraction: float = 0.0, device=None, stream=None, states: bool = False):
+    """Training spectra of the one-component model (ff_mlp_generate)."""
+    torch = _torch()
+    device = device or torch.device("cuda:0")
+    rad = torch.empty((P, scene.n_bands), dtype=torch.float32, device=device)
+    tgt = torch.empty((P, 5), dtype=torch.float32, device=device)
+    st = torch.empty((P, 5), dtype=torch.float32, device=device) if states else None
+    pc = prior.to_c()
+    _check(lib().ff_mlp_generate(scene.handle, C.byref(pc), seed, offset, P, snr, bg_fraction, _ptr(rad),
+                                 _ptr(tgt), _ptr(st), _stream_handle(stream)), "ff_mlp_generate")
+    return (rad, tgt, st) if states else (rad, tgt)
+
+
+class WarmStart:
+    """The warm-start network (ff_mlp) on the current device."""
+
+    def __init__(self, n_in: int = 284, hidden=(512, 512, 256), n_out: int = 5, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().ff_mlp_create(n_in, hidden[0], hidden[1], hidden[2], n_out, seed, C.byref(h)), "ff_mlp_create")
+        self.handle = h
+        self.sizes = (n_in, hidden[0], hidden[1], hidden[2], n_out)
+        self.n_params = int(lib().ff_mlp_n_params(h))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ff_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.n_params, np.float32)
+        _check(lib().ff_mlp_get_params(self.handle, p.ctypes.data_as(_fp)), "ff_mlp_get_params")
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.shape == (self.n_params,)
+        _check(lib().ff_mlp_set_params(self.handle, p.ctypes.data_as(_fp)), "ff_mlp_set_params")
+
+    def set_normalization(self, mean, inv_std, floor: float):
+        mean = np.ascontiguousarray(mean, np.float32)
+        inv_std = np.ascontiguousarray(inv_std, np.float32)
+        _check(lib().ff_mlp_set_normalization(self.handle, mean.ctypes.data_as(_fp), inv_std.ctypes.data_as(_fp),
+                                              floor), "ff_mlp_set_normalization")
+
+    def get_normalization(self):
+        n = self.sizes[0]
+        mean = np.empty(n, np.float32)
+        inv = np.empty(n, np.float32)
+        fl = np.empty(1, np.float32)
+        _check(lib().ff_mlp_get_normalization(self.handle, mean.ctypes.data_as(_fp), inv.ctypes.data_as(_fp),
+                                              fl.ctypes.data_as(_fp)), "ff_mlp_get_normalization")
+        return mean, inv, float(fl[0])
+
+    def fit_normalization(self, radiance, floor: float = 1e-6, stream=None):
+        _check(lib().ff_mlp_fit_normalization(self.handle, _ptr(radiance), radiance.shape[0], floor,
+                                              _stream_handle(stream)), "ff_mlp_fit_normalization")
+
+    def infer(self, radiance, stream=None):
+        torch = _torch()
+        z0 = torch.empty((radiance.shape[0], self.sizes[4]), dtype=torch.float32, device=radiance.device)
+        _check(lib().ff_mlp_infer(self.handle, _ptr(radiance), radiance.shape[0], _ptr(z0), _stream_handle(stream)),
+               "ff_mlp_infer")
+        return z0
+
+    def gradients(self, radiance, target, stream=None):
+        torch = _torch()
+        loss = torch.zeros(1, dtype=torch.float64, device=radiance.device)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=radiance.device)
+        _check(lib().ff_mlp_gradients(self.handle, _ptr(radiance), _ptr(target), radiance.shape[0], _ptr(loss),
+                                      _ptr(g), _stream_handle(stream)), "ff_mlp_gradients")
+        return loss, g
+
+    def train_step(self, radiance, target, lr: float, stream=None):
+        torch = _torch()
+        loss = torch.zeros(1, dtype=torch.float64, device=radiance.device)
+        _check(lib().ff_mlp_train_step(self.handle, _ptr(radiance), _ptr(target), radiance.shape[0], lr, _ptr(loss),
+                                       _stream_handle(stream)), "ff_mlp_train_step")
+        return loss
+
+    def train(self, scene: Scene, prior: Prior, steps: int, batch: int = 2048, seed: int = 1, snr: float = 300.0,
+              bg_fraction: float = 0.0, lr: float = 1e-3, lr_final: float = 1e-5, stream=None, device=None):
+        torch = _torch()
+        device = device or torch.device("cuda:0")
+        hist = torch.zeros(steps, dtype=torch.float64, device=device)
+        pc = prior.to_c()
+        _check(lib().ff_mlp_train(self.handle, scene.handle, C.byref(pc), steps, batch, seed, snr, bg_fraction, lr,
+                                  lr_final, _ptr(hist), _stream_handle(stream)), "ff_mlp_train")
+        return hist
+
+    def save(self, path: str):
+        mean, inv, fl = self.get_normalization()
+        np.savez(path, params=self.get_params(), mean=mean, inv_std=inv, floor=np.float32(fl),
+                 sizes=np.array(self.sizes))
+
+    @classmethod
+    def load(cls, path: str):
+        d = np.load(path, allow_pickle=False)
+        sz = [int(x) for x in d["sizes"]]
+        w = cls(sz[0], tuple(sz[1:4]), sz[4])
+        w.set_params(d["params"])
+        w.set_normalization(d["mean"], d["inv_std"], float(d["floor"]))
+        return w

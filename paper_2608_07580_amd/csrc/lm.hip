@@ -8,7 +8,10 @@
 // epilogue are per-lane FP64 scalar code.  In the persistent schedule a
 // lane whose pixel has finished pulls the next pixel from a device queue
 // (one wave-aggregated atomic per refill), so uneven convergence does not
-// leave lanes idle until the queue drains.
+// leave lanes idle until the queue drains.  A pixel whose solve from a
+// per-pixel start fails is re-solved from the default start by the same
+// lane at once, so the fallback overlaps the rest of the queue instead of
+// forming a second, sparsely occupied launch.
 //
 // Loss, coordinates and solver (Keely et al. Sec. 2.5): r = m (L_obs - L(x(z))),
 // F = r.r (eq. loss), z = 2 (x - lo)/(hi - lo) - 1 clipped to [-1, 1]
@@ -53,11 +56,8 @@ struct LmDesc {
     int n_scenes;
     int B;
     int64_t total;
-    unsigned long long* queue;     // queue head of this pass
+    unsigned long long* queue;     // queue head
     unsigned long long* evals;     // += model evaluations (may be null)
-    int64_t* fb_items;             // items to re-solve from the default start
-    unsigned long long* fb_count;  // number of fb_items
-    int pass;                      // 0: main pass, 1: fallback pass over fb_items
     int schedule;
     int max_iter;
     int fallback;
@@ -274,6 +274,9 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
 
     // ---- per-lane pixel state ----
     bool has = false, exhausted = false, warm = false, static_taken = false;
+    bool fbmode = false;        // re-solving a failed warm start from the default start
+    int it_prev = 0;            // iterations of the failed warm-started solve
+    float rrr_prev = 0.f;       // its relative residual
     int64_t item = -1, pix = 0;
     int sidx = 0;
     const float* rad = nullptr;
@@ -291,12 +294,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
 #pragma unroll
     for (int j = 0; j < NT; ++j) A[j] = (R)0;
 
-    int64_t total;
-    {
-        const LmDesc<R, Q>* D = launder(descp);
-        total = D->total;
-        if (D->pass == 1) total = (int64_t)__atomic_load_n(D->fb_count, __ATOMIC_RELAXED);
-    }
+    const int64_t total = launder(descp)->total;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 
     for (;;) {
@@ -329,7 +327,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                 if (my >= total) {
                     exhausted = true;
                 } else {
-                    item = D->pass == 1 ? D->fb_items[my] : my;
+                    item = my;
                     sidx = scene_of(D, item);
                     const SceneDev& sd = D->sc[sidx];
                     pix = item - sd.offset;
@@ -351,6 +349,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     phase = 0;
                     st = 0;
                     warm = false;
+                    fbmode = false;
                     if (!fin || nvalid <= N) {
                         const OutPtrs o = out_ptrs(sd);
                         write_nan<N>(o, pix);
@@ -359,7 +358,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                         if (o.status) o.status[pix] = !fin ? FF_ST_NONFINITE_INPUT : FF_ST_NO_DOF;
                     } else {
                         const float* z0 = sd.z0;
-                        warm = D->pass == 0 && z0 != nullptr;
+                        warm = z0 != nullptr;
 #pragma unroll
                         for (int j = 0; j < N; ++j) {
                             double zz = warm ? (double)z0[pix * N + j] : D->zdef[j];
@@ -530,17 +529,17 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                 if (valid && bound) st |= FF_ST_AT_BOUND;
                 const double rrr_new = valid && lnorm2 > 0.0 ? sqrt(F / lnorm2) : __builtin_nan("");
                 int it_out = it;
-                bool write = true;
-                if (D->pass == 1) {
+                bool write = true, restart = false;
+                if (fbmode) {
                     // fallback from the default start: kept if it converged or fits better
-                    const float old_rrr = o.rrr ? o.rrr[pix] : __builtin_nanf("");
-                    write = (st & FF_ST_CONVERGED) != 0 || !(rrr_new >= (double)old_rrr);
-                    it_out = (o.iters ? o.iters[pix] : 0) + 1 + it;
+                    write = (st & FF_ST_CONVERGED) != 0 || !(rrr_new >= (double)rrr_prev);
+                    it_out = it_prev + 1 + it;
                     if (write) st |= FF_ST_USED_FALLBACK | FF_ST_WARM_START;
                     else if (o.iters) o.iters[pix] = it_out;
                 } else if (warm && D->fallback && !(st & FF_ST_CONVERGED)) {
-                    const unsigned long long slot = atomicAdd(D->fb_count, 1ull);
-                    D->fb_items[slot] = item;
+                    // the warm-started result is written now and the same lane
+                    // re-solves the pixel from the default start right away
+                    restart = true;
                 }
                 if (write) {
                     if (valid) {
@@ -597,6 +596,18 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     if (o.rrr) o.rrr[pix] = (float)rrr_new;
                     if (o.iters) o.iters[pix] = it_out;
                     if (o.status) o.status[pix] = st;
+                }
+                if (restart) {
+                    has = true;
+                    fbmode = true;
+                    warm = false;
+                    it_prev = it;
+                    rrr_prev = (float)rrr_new;
+                    it = 0;
+                    phase = 0;
+                    st = 0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) z[j] = (R)fmin(1.0, fmax(-1.0, D->zdef[j]));
                 }
             }
         }
@@ -661,41 +672,8 @@ __global__ void zero_u64(unsigned long long* p, int n)
     if (i < n) p[i] = 0ull;
 }
 
-// ---------------------------------------------------------------- host side
-template <typename R, int Q>
-const Quad<R, Q>* cached_quad()
-{
-    static Quad<R, Q> q;
-    static bool ok = false;
-    static std::once_flag once;
-    std::call_once(once, [] {
-        if constexpr (sizeof(R) == 4) ok = make_quad_f32(Q, q.w, q.v, q.s);
-        else ok = make_quad_f64(Q, q.w, q.v, q.s);
-    });
-    return ok ? &q : nullptr;
-}
-
 }  // namespace
 
-
-// Fill the constant-memory quadrature rule of (R, Q) on a device once.
-template <typename R, int Q>
-static bool ensure_quad(int dev)
-{
-    static std::mutex mtx;
-    static bool done[64] = {};
-    if (dev < 0 || dev >= 64) return false;
-    std::lock_guard<std::mutex> lock(mtx);
-    if (!done[dev]) {
-        const Quad<R, Q>* host = cached_quad<R, Q>();
-        if (!host) return false;
-        const void* sym = reinterpret_cast<const void*>(&c_quad<R, Q>);
-        if (hipMemcpyToSymbol(sym, host, sizeof(Quad<R, Q>), 0, hipMemcpyHostToDevice) != hipSuccess)
-            return false;
-        done[dev] = true;
-    }
-    return true;
-}
 
 template <typename R, typename ACC, int MODEL, int Q>
 static ff_status launch_lm(const BatchSpec& bs)
@@ -726,19 +704,16 @@ static ff_status launch_lm(const BatchSpec& bs)
     if (max_chunk_total == 0) return clear_error();
     const bool fallback = any_warm && o.fallback != 0;
 
-    // stream-ordered scratch: per chunk 4 counters and 2 descriptors (one
-    // per pass), then the fallback item list
+    // stream-ordered scratch: per chunk one queue counter and one descriptor
     using Desc = LmDesc<R, Q>;
     const size_t desc_bytes = (sizeof(Desc) + 255) / 256 * 256;
-    const size_t n_ctr = 4 * (size_t)n_chunks;
+    const size_t n_ctr = (size_t)n_chunks;
     const size_t ctr_bytes = (n_ctr * sizeof(unsigned long long) + 255) / 256 * 256;
-    const size_t bytes = ctr_bytes + 2 * (size_t)n_chunks * desc_bytes +
-                         (fallback ? (size_t)max_chunk_total * sizeof(int64_t) : 0);
+    const size_t bytes = ctr_bytes + (size_t)n_chunks * desc_bytes;
     char* scratch = nullptr;
     FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&scratch), bytes, bs.stream));
     auto* ctr = reinterpret_cast<unsigned long long*>(scratch);
     char* descs = scratch + ctr_bytes;
-    int64_t* fb_items = fallback ? reinterpret_cast<int64_t*>(descs + 2 * (size_t)n_chunks * desc_bytes) : nullptr;
     hipLaunchKernelGGL(zero_u64, dim3((unsigned)((n_ctr + 255) / 256)), dim3(256), 0, bs.stream, ctr, (int)n_ctr);
     hipError_t e = hipGetLastError();
 
@@ -769,8 +744,6 @@ static ff_status launch_lm(const BatchSpec& bs)
         prm.B = bs.scenes[0]->n_bands;
         prm.total = off;
         prm.evals = bs.evals;
-        prm.fb_items = fb_items;
-        prm.fb_count = ctr + 4 * c + 2;
         prm.max_iter = o.max_iter;
         prm.fallback = fallback ? 1 : 0;
         prm.xtol = o.xtol;
@@ -786,28 +759,20 @@ static ff_status launch_lm(const BatchSpec& bs)
         }
         const int64_t grid_static = (off + block - 1) / block;
         const int64_t grid_pers = std::min<int64_t>((int64_t)n_cu * per_cu, grid_static);
-        for (int pass = 0; pass < (fallback ? 2 : 1) && e == hipSuccess; ++pass) {
-            prm.pass = pass;
-            prm.queue = ctr + 4 * c + pass;
-            prm.schedule = o.schedule;
-            int64_t grid = o.schedule == FF_SCHEDULE_STATIC ? grid_static : grid_pers;
-            if (pass == 1) {
-                // the fallback pass pulls from the queue: its size is on the device
-                prm.schedule = FF_SCHEDULE_PERSISTENT;
-                grid = grid_pers;
-            }
-            if (grid > 0x7fffffff) {
-                e = hipErrorInvalidValue;
-                break;
-            }
-            Desc* dptr = reinterpret_cast<Desc*>(descs + (2 * (size_t)c + pass) * desc_bytes);
-            hipLaunchKernelGGL(fill_struct<Desc>, dim3(1), dim3(64), 0, bs.stream, prm, dptr);
-            e = hipGetLastError();
-            if (e != hipSuccess) break;
-            hipLaunchKernelGGL((lm_kernel<R, ACC, MODEL, Q>), dim3((unsigned)grid), dim3(block), 0, bs.stream,
-                               (const Desc*)dptr);
-            e = hipGetLastError();
+        prm.queue = ctr + c;
+        prm.schedule = o.schedule;
+        const int64_t grid = o.schedule == FF_SCHEDULE_STATIC ? grid_static : grid_pers;
+        if (grid > 0x7fffffff) {
+            e = hipErrorInvalidValue;
+            break;
         }
+        Desc* dptr = reinterpret_cast<Desc*>(descs + (size_t)c * desc_bytes);
+        hipLaunchKernelGGL(fill_struct<Desc>, dim3(1), dim3(64), 0, bs.stream, prm, dptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL((lm_kernel<R, ACC, MODEL, Q>), dim3((unsigned)grid), dim3(block), 0, bs.stream,
+                           (const Desc*)dptr);
+        e = hipGetLastError();
     }
     hipError_t e2 = hipFreeAsync(scratch, bs.stream);
     if (e != hipSuccess) return hip_error(e, "lm_kernel launch");

@@ -1,0 +1,797 @@
+// Learned warm start: a multilayer perceptron mapping a radiance spectrum to
+// a starting state z0 of the Levenberg-Marquardt solve.
+//
+//  * bf16 matrix-core GEMM (v_mfma_f32_16x16x32_bf16, FP32 accumulation)
+//    with LDS-staged 64x64x32 tiles, used for the forward pass, the
+//    backward data pass and the weight gradients, with fused epilogues
+//    (bias + GELU, GELU-derivative gating, FP32 store);
+//  * feature, loss/output, column-sum and Adam kernels;
+//  * a training-data generator: Philox4x32-10 counter-based draws (Salmon,
+//    Moraes, Dror & Shaw 2011) of one-component states, the forward model of
+//    physics.hpp and Box-Muller noise.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "physics.hpp"
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+namespace ff {
+
+// ---------------------------------------------------------------- Philox
+struct U32x4 {
+    uint32_t v[4];
+};
+
+// Philox4x32-10: 10 rounds of (hi, lo) = M * c multiplies with a Weyl key
+// schedule.  Constants from the published definition.
+__host__ __device__ inline U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1)
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t p0 = (uint64_t)M0 * c0;
+        const uint64_t p1 = (uint64_t)M1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    return U32x4{{c0, c1, c2, c3}};
+}
+
+// uniform in (0, 1): the top 24 bits, centred in their cell
+__host__ __device__ inline double u01(uint32_t x) { return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+namespace {
+
+constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
+constexpr int kGemmThreads = 256;
+
+enum : int { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_GELU = 2, EPI_F32 = 3, EPI_FWD_GELU_NOH = 4 };
+
+struct EpiArgs {
+    const float* bias;
+    float* outf;
+    int ldof;
+    __bf16* outb;
+    int ldob;
+    const float* hprev;
+    int ldh;
+};
+
+__device__ __forceinline__ float gelu_t(float x, float& dgelu)
+{
+    const float c = 0.7978845608028654f;  // sqrt(2 / pi)
+    const float a = 0.044715f;
+    const float t = tanhf(c * (x + a * x * x * x));
+    dgelu = 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * a * x * x);
+    return 0.5f * x * (1.0f + t);
+}
+
+// C[m][n] = sum_k Aop[m][k] Bop[k][n];  Aop = TA ? A[k][m] : A[m][k],
+// Bop = TB ? B[n][k] : B[k][n] (lda/ldb = row strides of the stored arrays).
+// Loads: m < Ml, n < Nl, k < K (8-element chunks along the contiguous
+// dimension, whose extent must be a multiple of 8); stores: m < M, n < N.
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(kGemmThreads)
+gemm_bf16(int M, int N, int Ml, int Nl, int K, const __bf16* __restrict__ A, int lda,
+          const __bf16* __restrict__ B, int ldb, EpiArgs ep)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[kBM][kBK + kPad];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[kBN][kBK + kPad];
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    float4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    const bf16x8_t zero8 = {};
+
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        // ---- A tile -> As[m][k]
+        if (!TA) {
+            const int r = t >> 2, kc = (t & 3) * 8;
+            const int m = m0 + r, k = k0 + kc;
+            bf16x8_t v = zero8;
+            if (m < Ml && k < K) v = *reinterpret_cast<const bf16x8_t*>(A + (size_t)m * lda + k);
+            *reinterpret_cast<bf16x8_t*>(&As[r][kc]) = v;
+        } else {
+            const int kr = t >> 3, mc = (t & 7) * 8;
+            const int k = k0 + kr, m = m0 + mc;
+            bf16x8_t v = zero8;
+            if (k < K && m < Ml) v = *reinterpret_cast<const bf16x8_t*>(A + (size_t)k * lda + m);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) As[mc + e][kr] = v[e];
+        }
+        // ---- B tile -> Bs[n][k]
+        if (TB) {
+            const int r = t >> 2, kc = (t & 3) * 8;
+            const int n = n0 + r, k = k0 + kc;
+            bf16x8_t v = zero8;
+            if (n < Nl && k < K) v = *reinterpret_cast<const bf16x8_t*>(B + (size_t)n * ldb + k);
+            *reinterpret_cast<bf16x8_t*>(&Bs[r][kc]) = v;
+        } else {
+            const int kr = t >> 3, nc = (t & 7) * 8;
+            const int k = k0 + kr, n = n0 + nc;
+            bf16x8_t v = zero8;
+            if (k < K && n < Nl) v = *reinterpret_cast<const bf16x8_t*>(B + (size_t)k * ldb + n);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Bs[nc + e][kr] = v[e];
+        }
+        __syncthreads();
+        bf16x8_t a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            a[i] = *reinterpret_cast<const bf16x8_t*>(&As[wm * 32 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            b[j] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn * 32 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+
+    // ---- epilogue: lane holds D[4*(lane/16) + e][lane % 16] of each 16x16 tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+            if (n >= N) continue;
+            const float bias = (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_NOH || EPI == EPI_FWD_LINEAR) ? ep.bias[n] : 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + e;
+                if (m >= M) continue;
+                const float v = acc[i][j][e];
+                if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_NOH) {
+                    const float h = v + bias;
+                    float dg;
+                    const float g = gelu_t(h, dg);
+                    if (EPI == EPI_FWD_GELU) ep.outf[(size_t)m * ep.ldof + n] = h;
+                    ep.outb[(size_t)m * ep.ldob + n] = (__bf16)g;
+                } else if (EPI == EPI_FWD_LINEAR) {
+                    ep.outf[(size_t)m * ep.ldof + n] = v + bias;
+                } else if (EPI == EPI_BWD_GELU) {
+                    float dg;
+                    gelu_t(ep.hprev[(size_t)m * ep.ldh + n], dg);
+                    ep.outb[(size_t)m * ep.ldob + n] = (__bf16)(v * dg);
+                } else {
+                    ep.outf[(size_t)m * ep.ldof + n] = v;
+                }
+            }
+        }
+    }
+}
+
+// u_b = (ln max(L_b, floor) - mean_b) * inv_std_b, zero-padded to kin columns
+__global__ void features_kernel(const float* __restrict__ L, int64_t P, int n_in, int kin,
+                                const float* __restrict__ mean, const float* __restrict__ inv_std,
+                                float floor_v, __bf16* __restrict__ X)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = P * kin;
+    if (i >= total) return;
+    const int64_t p = i / kin;
+    const int b = (int)(i - p * kin);
+    float u = 0.f;
+    if (b < n_in) {
+        const float v = L[p * n_in + b];
+        const float lv = logf(fmaxf(v, floor_v));
+        u = (lv - mean[b]) * inv_std[b];
+    }
+    X[i] = (__bf16)u;
+}
+
+// z = tanh(y); loss += (z - t)^2; dY = d loss_mean / dy = scale (z - t)(1 - z^2)
+// as bf16 (16 columns, zero beyond n_out)
+__global__ void loss_kernel(const float* __restrict__ Y, const float* __restrict__ target, int64_t P,
+                            int n_out, __bf16* __restrict__ dY, double* __restrict__ loss)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float part = 0.f;
+    if (p < P) {
+        const float scale = 2.0f / ((float)P * (float)n_out);
+        for (int j = 0; j < 16; ++j) {
+            float d = 0.f;
+            if (j < n_out) {
+                const float y = Y[p * 16 + j];
+                const float z = tanhf(y);
+                const float diff = z - target[p * n_out + j];
+                part += diff * diff;
+                d = scale * diff * (1.0f - z * z);
+            }
+            dY[p * 16 + j] = (__bf16)d;
+        }
+    }
+    __shared__ float red[256];
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss) atomicAdd(loss, (double)red[0] / ((double)P * n_out));
+}
+
+__global__ void output_kernel(const float* __restrict__ Y, int64_t P, int n_out, float* __restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * n_out) return;
+    const int64_t p = i / n_out;
+    const int j = (int)(i - p * n_out);
+    z[i] = tanhf(Y[p * 16 + j]);
+}
+
+// out[n] = sum_m D[m][n] for n < N (bias gradients)
+__global__ void colsum_kernel(const __bf16* __restrict__ D, int64_t M, int N, int ld, float* __restrict__ out)
+{
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int grp = threadIdx.x >> 6;
+    float s = 0.f;
+    if (col < N)
+        for (int64_t m = grp; m < M; m += 4) s += (float)D[m * ld + col];
+    __shared__ float red[4][64];
+    red[grp][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (grp == 0 && col < N)
+        out[col] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+struct LayerMap {
+    int64_t off_w[4], off_b[4], off_wb[4];
+    int in_dim[4], out_dim[4], in_pad[4];
+};
+
+// Adam (m, v moments, bias-corrected) on the FP32 master weights, then the
+// BF16 copy of each weight into its padded matrix.
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            float bc1, float bc2, __bf16* __restrict__ wb, LayerMap map)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int64_t nw = (int64_t)map.out_dim[l] * map.in_dim[l];
+        if (i >= map.off_w[l] && i < map.off_w[l] + nw) {
+            const int64_t r = (i - map.off_w[l]) / map.in_dim[l];
+            const int64_t c = (i - map.off_w[l]) - r * map.in_dim[l];
+            wb[map.off_wb[l] + r * map.in_pad[l] + c] = (__bf16)pi;
+        }
+    }
+}
+
+__global__ void refresh_bf16_kernel(const float* __restrict__ p, int64_t n, __bf16* __restrict__ wb, LayerMap map)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int64_t nw = (int64_t)map.out_dim[l] * map.in_dim[l];
+        if (i >= map.off_w[l] && i < map.off_w[l] + nw) {
+            const int64_t r = (i - map.off_w[l]) / map.in_dim[l];
+            const int64_t c = (i - map.off_w[l]) - r * map.in_dim[l];
+            wb[map.off_wb[l] + r * map.in_pad[l] + c] = (__bf16)p[i];
+        }
+    }
+}
+
+// per band: mean and 1/s.d. of ln max(L, floor) over P spectra
+__global__ void fit_norm_kernel(const float* __restrict__ L, int64_t P, int B, float floor_v,
+                                float* __restrict__ mean, float* __restrict__ inv_std)
+{
+    const int b = blockIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+        const double v = log((double)fmaxf(L[p * B + b], floor_v));
+        s1 += v;
+        s2 += v * v;
+    }
+    __shared__ double r1[256], r2[256];
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu = r1[0] / (double)P;
+        const double var = fmax(r2[0] / (double)P - mu * mu, 1e-12);
+        mean[b] = (float)mu;
+        inv_std[b] = (float)(1.0 / sqrt(var));
+    }
+}
+
+struct GenArgs {
+    double lo[5], hi[5], x0[5];
+    uint32_t k0, k1;
+    uint64_t offset;
+    double snr;
+    double bg;
+};
+
+// Training spectra: one lane per sample (one-component model, FP32 forward).
+template <int Q>
+__global__ void __launch_bounds__(256)
+generate_kernel(const float* __restrict__ tab, int B, int64_t P, GenArgs ga, float* __restrict__ rad,
+                float* __restrict__ target, float* __restrict__ state)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const uint64_t g = ga.offset + (uint64_t)p;
+    const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
+    const U32x4 r0 = philox4x32_10(glo, ghi, 0u, 0u, ga.k0, ga.k1);
+    const U32x4 r1 = philox4x32_10(glo, ghi, 1u, 0u, ga.k0, ga.k1);
+    const double lf0 = log(1e-4), lf1 = log(0.3);
+    double x[5];
+    x[0] = exp(lf0 + (lf1 - lf0) * u01(r0.v[0]));
+    x[1] = 600.0 + 800.0 * u01(r0.v[1]);
+    x[2] = 50.0 + 250.0 * u01(r0.v[2]);
+    x[3] = 0.05 + 0.35 * u01(r0.v[3]);
+    x[4] = -1e-4 + 2e-4 * u01(r1.v[0]);
+    if (u01(r1.v[1]) < ga.bg) {
+        x[0] = 0.0;
+        x[1] = ga.x0[1];
+        x[2] = ga.x0[2];
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const double z = 2.0 * (x[j] - ga.lo[j]) / (ga.hi[j] - ga.lo[j]) - 1.0;
+        target[p * 5 + j] = (float)fmin(1.0, fmax(-1.0, z));
+        if (state) state[p * 5 + j] = (float)x[j];
+    }
+    PixelModel<float, FF_MODEL_LOGNORMAL_1, Q> pm;
+    pm.setup(x);
+    const bool noisy = ga.snr > 0.0;
+    const float inv_snr = noisy ? (float)(1.0 / ga.snr) : 0.f;
+    float nz[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < B; ++b) {
+        if (noisy && (b & 3) == 0) {
+            // four normals per Philox block: Box-Muller on (x0, x1) and (x2, x3)
+            const U32x4 rn = philox4x32_10(glo, ghi, 2u + (uint32_t)(b >> 2), 0u, ga.k0, ga.k1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float ua = (float)u01(rn.v[2 * h]), ub = (float)u01(rn.v[2 * h + 1]);
+                const float rr = sqrtf(-2.0f * logf(ua));
+                float sn, cs;
+                sincosf(6.283185307179586f * ub, &sn, &cs);
+                nz[2 * h] = rr * cs;
+                nz[2 * h + 1] = rr * sn;
+            }
+        }
+        const BandRow<float> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
+        float ub[5];
+        const float lt = pm.band(row, opaque_zero(), ub);
+        rad[p * B + b] = noisy ? lt * (1.0f + nz[b & 3] * inv_snr) : lt;
+    }
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__global__ void zero_f64(double* p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
+}
+
+}  // namespace
+}  // namespace ff
+
+using namespace ff;
+
+struct ff_mlp {
+    int device = 0;
+    int n_in = 0, h[3] = {0, 0, 0}, n_out = 0, kin = 0;
+    int64_t n_params = 0, n_wb = 0;
+    LayerMap map{};
+    float* params = nullptr;
+    float* grads = nullptr;
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    __bf16* wb = nullptr;
+    float* mean = nullptr;
+    float* inv_std = nullptr;
+    float floor_v = 1e-6f;
+    int64_t step = 0;
+    int64_t ws_rows = 0;
+    __bf16* X = nullptr;
+    float* H[3] = {nullptr, nullptr, nullptr};
+    __bf16* A[3] = {nullptr, nullptr, nullptr};
+    float* Y = nullptr;
+    __bf16* dY = nullptr;
+    __bf16* dH[3] = {nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+void free_ws(ff_mlp* m)
+{
+    hipFree(m->X);
+    for (int i = 0; i < 3; ++i) { hipFree(m->H[i]); hipFree(m->A[i]); hipFree(m->dH[i]); }
+    hipFree(m->Y);
+    hipFree(m->dY);
+    m->X = nullptr; m->Y = nullptr; m->dY = nullptr;
+    for (int i = 0; i < 3; ++i) { m->H[i] = nullptr; m->A[i] = nullptr; m->dH[i] = nullptr; }
+    m->ws_rows = 0;
+}
+
+// Activation workspace for up to `rows` rows (grown on demand; the caller's
+// stream is synchronised first so no launch still reads the old buffers).
+ff_status ensure_ws(ff_mlp* m, int64_t rows, hipStream_t stream)
+{
+    if (rows <= m->ws_rows) return FF_OK;
+    FF_HIP_TRY(hipStreamSynchronize(stream));
+    free_ws(m);
+    const int64_t R = cdiv(rows, 64) * 64;
+    hipError_t e = hipMalloc(&m->X, (size_t)R * m->kin * sizeof(__bf16));
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        e = hipMalloc(&m->H[i], (size_t)R * m->h[i] * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&m->A[i], (size_t)R * m->h[i] * sizeof(__bf16));
+        if (e == hipSuccess) e = hipMalloc(&m->dH[i], (size_t)R * m->h[i] * sizeof(__bf16));
+    }
+    if (e == hipSuccess) e = hipMalloc(&m->Y, (size_t)R * 16 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->dY, (size_t)R * 16 * sizeof(__bf16));
+    if (e != hipSuccess) {
+        free_ws(m);
+        return hip_error(e, "mlp workspace");
+    }
+    m->ws_rows = R;
+    return FF_OK;
+}
+
+template <bool TA, bool TB, int EPI>
+void gemm(int M, int N, int Ml, int Nl, int K, const __bf16* A, int lda, const __bf16* B, int ldb,
+          const EpiArgs& ep, hipStream_t s)
+{
+    dim3 grid((unsigned)cdiv(N, kBN), (unsigned)cdiv(M, kBM));
+    hipLaunchKernelGGL((gemm_bf16<TA, TB, EPI>), grid, dim3(kGemmThreads), 0, s, M, N, Ml, Nl, K, A, lda, B, ldb, ep);
+}
+
+// forward pass of R rows of features already in m->X; keep_h: store the
+// pre-activations for the backward pass
+void forward_rows(const ff_mlp* m, int64_t R, bool keep_h, hipStream_t s)
+{
+    const int r = (int)R;
+    for (int l = 0; l < 3; ++l) {
+        const __bf16* in = l == 0 ? m->X : m->A[l - 1];
+        const int kin = m->map.in_pad[l];
+        EpiArgs ep{m->params + m->map.off_b[l], m->H[l], m->h[l], m->A[l], m->h[l], nullptr, 0};
+        if (keep_h)
+            gemm<false, true, EPI_FWD_GELU>(r, m->h[l], r, m->h[l], kin, in, kin, m->wb + m->map.off_wb[l], kin, ep, s);
+        else
+            gemm<false, true, EPI_FWD_GELU_NOH>(r, m->h[l], r, m->h[l], kin, in, kin, m->wb + m->map.off_wb[l], kin, ep, s);
+    }
+    EpiArgs ep{m->params + m->map.off_b[3], m->Y, 16, nullptr, 0, nullptr, 0};
+    gemm<false, true, EPI_FWD_LINEAR>(r, m->n_out, r, 16, m->h[2], m->A[2], m->h[2], m->wb + m->map.off_wb[3],
+                                      m->h[2], ep, s);
+}
+
+// backward pass of R rows: dY in m->dY -> all gradients into m->grads
+void backward_rows(ff_mlp* m, int64_t R, hipStream_t s)
+{
+    const int r = (int)R;
+    const int h1 = m->h[0], h2 = m->h[1], h3 = m->h[2];
+    float* gw = m->grads;
+    const LayerMap& mp = m->map;
+    // output layer
+    gemm<true, false, EPI_F32>(m->n_out, h3, 16, h3, r, m->dY, 16, m->A[2], h3,
+                               EpiArgs{nullptr, gw + mp.off_w[3], h3, nullptr, 0, nullptr, 0}, s);
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cdiv(m->n_out, 64)), dim3(256), 0, s, m->dY, R, m->n_out, 16,
+                       gw + mp.off_b[3]);
+    gemm<false, false, EPI_BWD_GELU>(r, h3, r, h3, 16, m->dY, 16, m->wb + mp.off_wb[3], h3,
+                                     EpiArgs{nullptr, nullptr, 0, m->dH[2], h3, m->H[2], h3}, s);
+    // hidden layers 3, 2, 1
+    const int hs[3] = {h1, h2, h3};
+    for (int l = 2; l >= 0; --l) {
+        const int nout = hs[l];
+        const int nin = l == 0 ? m->n_in : hs[l - 1];
+        const int nin_pad = mp.in_pad[l];
+        const __bf16* xin = l == 0 ? m->X : m->A[l - 1];
+        gemm<true, false, EPI_F32>(nout, nin, nout, nin_pad, r, m->dH[l], nout, xin, nin_pad,
+                                   EpiArgs{nullptr, gw + mp.off_w[l], nin, nullptr, 0, nullptr, 0}, s);
+        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cdiv(nout, 64)), dim3(256), 0, s, m->dH[l], R, nout, nout,
+                           gw + mp.off_b[l]);
+        if (l > 0)
+            gemm<false, false, EPI_BWD_GELU>(r, nin, r, nin, nout, m->dH[l], nout, m->wb + mp.off_wb[l], nin_pad,
+                                             EpiArgs{nullptr, nullptr, 0, m->dH[l - 1], nin, m->H[l - 1], nin}, s);
+    }
+}
+
+ff_status check_mlp(const ff_mlp* m, const char* what)
+{
+    if (!m) return set_error(FF_EINVAL, std::string(what) + ": NULL network");
+    return FF_OK;
+}
+
+}  // namespace
+
+extern "C" ff_status ff_mlp_create(int32_t n_in, int32_t h1, int32_t h2, int32_t h3, int32_t n_out, uint64_t seed,
+                                   ff_mlp** out)
+{
+    if (!out) return set_error(FF_EINVAL, "ff_mlp_create: out is NULL");
+    *out = nullptr;
+    const int hs[3] = {h1, h2, h3};
+    if (n_in < 1 || n_in > 1024 || n_out < 1 || n_out > 16)
+        return set_error(FF_EINVAL, "ff_mlp_create: need 1 <= n_in <= 1024 and 1 <= n_out <= 16");
+    for (int i = 0; i < 3; ++i)
+        if (hs[i] < 64 || hs[i] > 1024 || hs[i] % 64)
+            return set_error(FF_EINVAL, "ff_mlp_create: hidden sizes must be multiples of 64 in [64, 1024]");
+    ff_mlp* m = new ff_mlp();
+    hipGetDevice(&m->device);
+    m->n_in = n_in;
+    m->n_out = n_out;
+    for (int i = 0; i < 3; ++i) m->h[i] = hs[i];
+    m->kin = (int)cdiv(n_in, 32) * 32;
+    const int ins[4] = {n_in, h1, h2, h3}, outs[4] = {h1, h2, h3, n_out};
+    const int inp[4] = {m->kin, h1, h2, h3}, outp[4] = {h1, h2, h3, 16};
+    int64_t off = 0, offb = 0;
+    for (int l = 0; l < 4; ++l) {
+        m->map.in_dim[l] = ins[l];
+        m->map.out_dim[l] = outs[l];
+        m->map.in_pad[l] = inp[l];
+        m->map.off_w[l] = off;
+        off += (int64_t)outs[l] * ins[l];
+        m->map.off_b[l] = off;
+        off += outs[l];
+        m->map.off_wb[l] = offb;
+        offb += (int64_t)outp[l] * inp[l];
+    }
+    m->n_params = off;
+    m->n_wb = offb;
+    // He-normal weights from Philox normals keyed by the seed; zero biases;
+    // the output layer scaled by 0.1 so the initial z0 is near the box centre
+    std::vector<float> p((size_t)off, 0.f);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int l = 0; l < 4; ++l) {
+        const double sd = std::sqrt(2.0 / ins[l]) * (l == 3 ? 0.1 : 1.0);
+        const int64_t nw = (int64_t)outs[l] * ins[l];
+        for (int64_t i = 0; i < nw; i += 2) {
+            const U32x4 r = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), (uint32_t)l, 7u, k0, k1);
+            const double rr = std::sqrt(-2.0 * std::log(u01(r.v[0])));
+            const double th = 6.283185307179586 * u01(r.v[1]);
+            p[(size_t)(m->map.off_w[l] + i)] = (float)(sd * rr * std::cos(th));
+            if (i + 1 < nw) p[(size_t)(m->map.off_w[l] + i + 1)] = (float)(sd * rr * std::sin(th));
+        }
+    }
+    std::vector<float> zeros_in((size_t)n_in, 0.f), ones_in((size_t)n_in, 1.f);
+    hipError_t e = hipMalloc(&m->params, off * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->grads, off * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->adam_m, off * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->adam_v, off * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->wb, offb * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMalloc(&m->mean, n_in * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->inv_std, n_in * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(m->wb, 0, offb * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMemcpy(m->mean, zeros_in.data(), n_in * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->inv_std, ones_in.data(), n_in * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ff_mlp_destroy(m);
+        return hip_error(e, "ff_mlp_create");
+    }
+    *out = m;
+    ff_status s = ff_mlp_set_params(m, p.data());
+    if (s != FF_OK) {
+        ff_mlp_destroy(m);
+        *out = nullptr;
+        return s;
+    }
+    return clear_error();
+}
+
+extern "C" void ff_mlp_destroy(ff_mlp* m)
+{
+    if (!m) return;
+    free_ws(m);
+    hipFree(m->params);
+    hipFree(m->grads);
+    hipFree(m->adam_m);
+    hipFree(m->adam_v);
+    hipFree(m->wb);
+    hipFree(m->mean);
+    hipFree(m->inv_std);
+    delete m;
+}
+
+extern "C" int64_t ff_mlp_n_params(const ff_mlp* m) { return m ? m->n_params : 0; }
+
+extern "C" ff_status ff_mlp_get_params(const ff_mlp* m, float* host)
+{
+    if (check_mlp(m, "ff_mlp_get_params") || !host) return set_error(FF_EINVAL, "ff_mlp_get_params: NULL argument");
+    FF_HIP_TRY(hipMemcpy(host, m->params, m->n_params * sizeof(float), hipMemcpyDeviceToHost));
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_set_params(ff_mlp* m, const float* host)
+{
+    if (check_mlp(m, "ff_mlp_set_params") || !host) return set_error(FF_EINVAL, "ff_mlp_set_params: NULL argument");
+    FF_HIP_TRY(hipMemcpy(m->params, host, m->n_params * sizeof(float), hipMemcpyHostToDevice));
+    FF_HIP_TRY(hipMemset(m->adam_m, 0, m->n_params * sizeof(float)));
+    FF_HIP_TRY(hipMemset(m->adam_v, 0, m->n_params * sizeof(float)));
+    m->step = 0;
+    hipLaunchKernelGGL(refresh_bf16_kernel, dim3((unsigned)cdiv(m->n_params, 256)), dim3(256), 0, 0, m->params,
+                       m->n_params, m->wb, m->map);
+    FF_HIP_TRY(hipGetLastError());
+    FF_HIP_TRY(hipDeviceSynchronize());
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_set_normalization(ff_mlp* m, const float* mean, const float* inv_std, float floor_v)
+{
+    if (check_mlp(m, "ff_mlp_set_normalization") || !mean || !inv_std)
+        return set_error(FF_EINVAL, "ff_mlp_set_normalization: NULL argument");
+    if (!(floor_v > 0.f)) return set_error(FF_EINVAL, "ff_mlp_set_normalization: floor must be > 0");
+    FF_HIP_TRY(hipMemcpy(m->mean, mean, m->n_in * sizeof(float), hipMemcpyHostToDevice));
+    FF_HIP_TRY(hipMemcpy(m->inv_std, inv_std, m->n_in * sizeof(float), hipMemcpyHostToDevice));
+    m->floor_v = floor_v;
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_get_normalization(const ff_mlp* m, float* mean, float* inv_std, float* floor_v)
+{
+    if (check_mlp(m, "ff_mlp_get_normalization") || !mean || !inv_std || !floor_v)
+        return set_error(FF_EINVAL, "ff_mlp_get_normalization: NULL argument");
+    FF_HIP_TRY(hipMemcpy(mean, m->mean, m->n_in * sizeof(float), hipMemcpyDeviceToHost));
+    FF_HIP_TRY(hipMemcpy(inv_std, m->inv_std, m->n_in * sizeof(float), hipMemcpyDeviceToHost));
+    *floor_v = m->floor_v;
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_fit_normalization(ff_mlp* m, const float* rad, int64_t P, float floor_v, void* stream)
+{
+    if (check_mlp(m, "ff_mlp_fit_normalization") || !rad || P <= 0 || !(floor_v > 0.f))
+        return set_error(FF_EINVAL, "ff_mlp_fit_normalization: bad argument");
+    m->floor_v = floor_v;
+    hipLaunchKernelGGL(fit_norm_kernel, dim3(m->n_in), dim3(256), 0, (hipStream_t)stream, rad, P, m->n_in, floor_v,
+                       m->mean, m->inv_std);
+    FF_HIP_TRY(hipGetLastError());
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_infer(const ff_mlp* mc, const float* rad, int64_t P, float* z0, void* stream)
+{
+    if (check_mlp(mc, "ff_mlp_infer")) return FF_EINVAL;
+    if (P < 0) return set_error(FF_EINVAL, "ff_mlp_infer: P < 0");
+    if (P == 0) return clear_error();
+    if (!rad || !z0) return set_error(FF_EINVAL, "ff_mlp_infer: NULL buffer");
+    ff_mlp* m = const_cast<ff_mlp*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t chunk = std::min<int64_t>(P, 1 << 18);
+    ff_status st = ensure_ws(m, chunk, s);
+    if (st != FF_OK) return st;
+    for (int64_t p0 = 0; p0 < P; p0 += chunk) {
+        const int64_t R = std::min(chunk, P - p0);
+        hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(R * m->kin, 256)), dim3(256), 0, s, rad + p0 * m->n_in, R,
+                           m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
+        forward_rows(m, R, false, s);
+        hipLaunchKernelGGL(output_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y, R, m->n_out,
+                           z0 + p0 * m->n_out);
+    }
+    FF_HIP_TRY(hipGetLastError());
+    return clear_error();
+}
+
+static ff_status grads_impl(ff_mlp* m, const float* rad, const float* target, int64_t P, double* loss,
+                            hipStream_t s)
+{
+    ff_status st = ensure_ws(m, P, s);
+    if (st != FF_OK) return st;
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(P * m->kin, 256)), dim3(256), 0, s, rad, P, m->n_in, m->kin,
+                       m->mean, m->inv_std, m->floor_v, m->X);
+    forward_rows(m, P, true, s);
+    if (loss) hipLaunchKernelGGL(zero_f64, dim3(1), dim3(64), 0, s, loss);
+    hipLaunchKernelGGL(loss_kernel, dim3((unsigned)cdiv(P, 256)), dim3(256), 0, s, m->Y, target, P, m->n_out, m->dY,
+                       loss);
+    backward_rows(m, P, s);
+    FF_HIP_TRY(hipGetLastError());
+    return FF_OK;
+}
+
+extern "C" ff_status ff_mlp_gradients(ff_mlp* m, const float* rad, const float* target, int64_t P, double* loss,
+                                      float* grads, void* stream)
+{
+    if (check_mlp(m, "ff_mlp_gradients")) return FF_EINVAL;
+    if (P <= 0 || P > 65536 || !rad || !target) return set_error(FF_EINVAL, "ff_mlp_gradients: bad batch");
+    hipStream_t s = (hipStream_t)stream;
+    ff_status st = grads_impl(m, rad, target, P, loss, s);
+    if (st != FF_OK) return st;
+    if (grads) FF_HIP_TRY(hipMemcpyAsync(grads, m->grads, m->n_params * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_train_step(ff_mlp* m, const float* rad, const float* target, int64_t P, float lr,
+                                       double* loss, void* stream)
+{
+    if (check_mlp(m, "ff_mlp_train_step")) return FF_EINVAL;
+    if (P <= 0 || P > 65536 || !rad || !target || !(lr >= 0.f))
+        return set_error(FF_EINVAL, "ff_mlp_train_step: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    ff_status st = grads_impl(m, rad, target, P, loss, s);
+    if (st != FF_OK) return st;
+    m->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)m->step));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)m->step));
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)cdiv(m->n_params, 256)), dim3(256), 0, s, m->params, m->grads,
+                       m->adam_m, m->adam_v, m->n_params, lr, b1, b2, eps, bc1, bc2, m->wb, m->map);
+    FF_HIP_TRY(hipGetLastError());
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_generate(const ff_scene* sc, const ff_prior* prior, uint64_t seed, uint64_t offset,
+                                     int64_t P, double snr, double bg, float* rad, float* target, float* state,
+                                     void* stream)
+{
+    if (!sc || !prior || prior->model != FF_MODEL_LOGNORMAL_1)
+        return set_error(FF_EINVAL, "ff_mlp_generate: needs a scene and a one-component prior");
+    if (P < 0 || !(bg >= 0.0 && bg <= 1.0)) return set_error(FF_EINVAL, "ff_mlp_generate: bad P or bg_fraction");
+    if (P == 0) return clear_error();
+    if (!rad || !target) return set_error(FF_EINVAL, "ff_mlp_generate: NULL output");
+    GenArgs ga{};
+    for (int j = 0; j < 5; ++j) {
+        ga.lo[j] = prior->lo[j];
+        ga.hi[j] = prior->hi[j];
+        ga.x0[j] = prior->x0[j];
+        if (!(ga.hi[j] > ga.lo[j])) return set_error(FF_EINVAL, "ff_mlp_generate: prior box");
+    }
+    ga.k0 = (uint32_t)seed;
+    ga.k1 = (uint32_t)(seed >> 32);
+    ga.offset = offset;
+    ga.snr = snr;
+    ga.bg = bg;
+    int dev = 0;
+    FF_HIP_TRY(hipGetDevice(&dev));
+    if (!ensure_quad<float, 32>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
+    hipLaunchKernelGGL(generate_kernel<32>, dim3((unsigned)cdiv(P, 256)), dim3(256), 0, (hipStream_t)stream,
+                       sc->table_f32, sc->n_bands, P, ga, rad, target, state);
+    FF_HIP_TRY(hipGetLastError());
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_train(ff_mlp* m, const ff_scene* sc, const ff_prior* prior, int64_t steps, int32_t batch,
+                                  uint64_t seed, double snr, double bg, float lr, float lr_final,
+                                  double* loss_hist, void* stream)
+{
+    if (check_mlp(m, "ff_mlp_train")) return FF_EINVAL;
+    if (!sc || sc->n_bands != m->n_in) return set_error(FF_EINVAL, "ff_mlp_train: scene band count != n_in");
+    if (steps < 0 || batch <= 0 || batch > 65536) return set_error(FF_EINVAL, "ff_mlp_train: bad steps/batch");
+    hipStream_t s = (hipStream_t)stream;
+    float* rad = nullptr;
+    float* tgt = nullptr;
+    FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&rad), (size_t)batch * m->n_in * sizeof(float), s));
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tgt), (size_t)batch * 5 * sizeof(float), s);
+    ff_status st = e == hipSuccess ? FF_OK : hip_error(e, "ff_mlp_train");
+    for (int64_t i = 0; i < steps && st == FF_OK; ++i) {
+        const double c = steps > 1 ? 0.5 * (1.0 + std::cos(M_PI * (double)i / (double)(steps - 1))) : 1.0;
+        const float lr_i = (float)(lr_final + (lr - lr_final) * c);
+        st = ff_mlp_generate(sc, prior, seed, (uint64_t)i * (uint64_t)batch, batch, snr, bg, rad, tgt, nullptr, s);
+        if (st == FF_OK) st = ff_mlp_train_step(m, rad, tgt, batch, lr_i, loss_hist ? loss_hist + i : nullptr, s);
+    }
+    hipFreeAsync(rad, s);
+    hipFreeAsync(tgt, s);
+    if (st != FF_OK) return st;
+    return clear_error();
+}

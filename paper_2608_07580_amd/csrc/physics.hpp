@@ -13,6 +13,8 @@
 // shortest band), where e underflows to 0 and the node contributes 0.
 #pragma once
 
+#include <mutex>
+
 #include "ff_internal.hpp"
 
 #ifndef FF_NODE_GROUP
@@ -28,8 +30,11 @@ template <> struct ModelDims<FF_MODEL_LOGNORMAL_2> { static constexpr int N = 8;
 // Quadrature rule of order Q in constant memory (filled once per device by
 // the host before the first launch).  Kernels index it with a laundered zero
 // offset so each use is a scalar load at the point of use.
+// (internal linkage: one instance per translation unit, see ensure_quad)
+namespace {
 template <typename R, int Q>
 __constant__ Quad<R, Q> c_quad;
+}
 
 __device__ __forceinline__ int opaque_zero()
 {
@@ -290,4 +295,43 @@ struct PixelModel<R, FF_MODEL_LOGNORMAL_2, Q> {
     }
 };
 
+// ---------------------------------------------------------------- host side
+// The quadrature rule (computed once per process) and its copy into this
+// translation unit's constant memory on each device.  Internal linkage: with
+// separate device code objects per translation unit, each unit owns its own
+// c_quad instances and must fill them itself.
+namespace {
+
+template <typename R, int Q>
+const Quad<R, Q>* cached_quad()
+{
+    static Quad<R, Q> q;
+    static bool ok = false;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        if constexpr (sizeof(R) == 4) ok = make_quad_f32(Q, q.w, q.v, q.s);
+        else ok = make_quad_f64(Q, q.w, q.v, q.s);
+    });
+    return ok ? &q : nullptr;
+}
+
+template <typename R, int Q>
+bool ensure_quad(int dev)
+{
+    static std::mutex mtx;
+    static bool done[64] = {};
+    if (dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lock(mtx);
+    if (!done[dev]) {
+        const Quad<R, Q>* host = cached_quad<R, Q>();
+        if (!host) return false;
+        const void* sym = reinterpret_cast<const void*>(&c_quad<R, Q>);
+        if (hipMemcpyToSymbol(sym, host, sizeof(Quad<R, Q>), 0, hipMemcpyHostToDevice) != hipSuccess)
+            return false;
+        done[dev] = true;
+    }
+    return true;
+}
+
+}  // namespace
 }  // namespace ff
