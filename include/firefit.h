@@ -142,8 +142,11 @@ typedef struct ff_options {
     int32_t blocks_per_cu; /* persistent grid: workgroups per CU (0 = occupancy limit) */
     int32_t fallback;      /* with a per-pixel start: re-solve failed pixels from x0 (default 1) */
     int32_t accumulate;    /* FF_ACCUMULATE_* for the FP32 path (default FP32) */
+    int32_t lanes_per_pixel; /* lanes that share one pixel's evaluation: 1, 2, 4, 8, 16, 32 or 64
+                              (0 = default 1); more lanes shorten each pixel's latency at a
+                              small replicated cost (results differ only in summation order) */
     double xtol;           /* default 1e-6 (z units) */
-    double ftol;           /* default 1e-10 */
+    double ftol;           /* default 1e-8 */
     double gtol;           /* default 1e-10 */
     double kappa;          /* accept a step whose predicted reduction is <= kappa F (default 1e-5) */
     double tau;            /* initial damping = tau * max diag(J^T J) (default 1e-6) */

@@ -231,7 +231,7 @@ def forward(tab: Tables, state, model: int, q: int = 32, jacobian: bool = False,
 class LMOptions:
     max_iter: int = 50
     xtol: float = 1e-6
-    ftol: float = 1e-10
+    ftol: float = 1e-8     # relative decrease ~ 3e-6 in chi^2 at SNR 300 (noise-level stop)
     gtol: float = 1e-10
     kappa: float = 1e-5
     tau: float = 1e-6      # initial damping mu_0 = tau * max diag(J^T J)

@@ -65,6 +65,8 @@ static ff_status check_options(const ff_options* o)
     if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 256 || o->block_size % 64 != 0))
         return set_error(FF_EINVAL, "block_size must be 64, 128, 192 or 256");
     if (o->blocks_per_cu < 0) return set_error(FF_EINVAL, "blocks_per_cu < 0");
+    if (o->lanes_per_pixel < 0 || o->lanes_per_pixel > 64 || (o->lanes_per_pixel & (o->lanes_per_pixel - 1)) != 0)
+        return set_error(FF_EINVAL, "lanes_per_pixel must be 0 or a power of two <= 64");
     if (o->accumulate != FF_ACCUMULATE_FP32 && o->accumulate != FF_ACCUMULATE_FP64)
         return set_error(FF_EINVAL, "unknown accumulate mode");
     if (!(o->xtol >= 0) || !(o->ftol >= 0) || !(o->gtol >= 0) || !(o->kappa >= 0) || !(o->tau > 0))
@@ -101,10 +103,11 @@ extern "C" void ff_options_default(ff_options* o)
     o->schedule = FF_SCHEDULE_PERSISTENT;
     o->block_size = 256;
     o->blocks_per_cu = 0;
+    o->lanes_per_pixel = 1;
     o->fallback = 1;
     o->accumulate = FF_ACCUMULATE_FP32;
     o->xtol = 1e-6;
-    o->ftol = 1e-10;
+    o->ftol = 1e-8;
     o->gtol = 1e-10;
     o->kappa = 1e-5;
     o->tau = 1e-6;

@@ -57,6 +57,7 @@ struct LmDesc {
     int B;
     int64_t total;
     unsigned long long* queue;     // queue head
+    int lpp;                       // lanes per pixel (power of two, <= 64)
     unsigned long long* evals;     // += model evaluations (may be null)
     int schedule;
     int max_iter;
@@ -157,14 +158,37 @@ __device__ __forceinline__ bool gradient_small(const R (&z)[N], const R (&A)[N *
     return small;
 }
 
+// Sum over the L lanes of a pixel's group (aligned, L a power of two) by an
+// xor butterfly: every lane of the group ends with the same bits, since each
+// level adds the same two partial sums (a + b == b + a in IEEE arithmetic).
+__device__ __forceinline__ float group_sum(float v, int L)
+{
+    for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ double group_sum(double v, int L)
+{
+    for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ int group_sum(int v, int L)
+{
+    for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // One model evaluation at physical state x: basis Gram matrix G = sum_b u u^T,
 // h = sum_b u r_b and F = sum_b r_b^2 over unmasked bands, then the normal
 // equations in z: A = D M G M^T D, g = J^T r = -D M h (D = diag((hi-lo)/2)).
+// The L lanes of a pixel's group take bands sub, sub + L, ... and their
+// partial sums are combined across the group before the normal equations.
 template <typename R, typename ACC, int MODEL, int Q>
 __device__ __forceinline__ double evaluate(const LmDesc<R, Q>* descp, const float* __restrict__ rad,
                                       const R* __restrict__ tab, const double (&x)[ModelDims<MODEL>::N],
                                       R (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
-                                      R (&g)[ModelDims<MODEL>::N])
+                                      R (&g)[ModelDims<MODEL>::N], int sub, int L)
 {
     using PM = PixelModel<R, MODEL, Q>;
     constexpr int N = PM::N;
@@ -178,16 +202,17 @@ __device__ __forceinline__ double evaluate(const LmDesc<R, Q>* descp, const floa
 #pragma unroll
     for (int i = 0; i < N; ++i) h[i] = (ACC)0;
 
-    for (int b0 = 0; b0 < B; b0 += 4) {
-        // four radiance values per lane per load group: one cache line
-        // serves the group, so a wave fetches each of its 64 rows once
+    for (int b0 = sub; b0 < B; b0 += 4 * L) {
+        // four radiance values per lane per load group (bands b0 + jL): with
+        // one lane per pixel they share a cache line, with L lanes the group
+        // reads L consecutive values per load
         float l0 = rad[b0];
-        float l1 = b0 + 1 < B ? rad[b0 + 1] : 0.f;
-        float l2 = b0 + 2 < B ? rad[b0 + 2] : 0.f;
-        float l3 = b0 + 3 < B ? rad[b0 + 3] : 0.f;
+        float l1 = b0 + L < B ? rad[b0 + L] : 0.f;
+        float l2 = b0 + 2 * L < B ? rad[b0 + 2 * L] : 0.f;
+        float l3 = b0 + 3 * L < B ? rad[b0 + 3 * L] : 0.f;
 #pragma unroll 1
         for (int j = 0; j < 4; ++j) {
-            const int b = b0 + j;
+            const int b = b0 + j * L;
             if (b >= B) break;
             const float lob = l0;
             l0 = l1;
@@ -211,6 +236,13 @@ __device__ __forceinline__ double evaluate(const LmDesc<R, Q>* descp, const floa
             }
             F += r * r;
         }
+    }
+    if (L > 1) {
+#pragma unroll
+        for (int i = 0; i < NT; ++i) G[i] = group_sum(G[i], L);
+#pragma unroll
+        for (int i = 0; i < N; ++i) h[i] = group_sum(h[i], L);
+        F = group_sum(F, L);
     }
 
     const LmDesc<R, Q>* D = launder(descp);
@@ -271,8 +303,11 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
     constexpr int N = PM::N;
     constexpr int NT = N * (N + 1) / 2;
     const int lane = threadIdx.x & 63;
+    const int L = launder(descp)->lpp;        // lanes per pixel
+    const int sub = lane & (L - 1);           // this lane's index in its group
+    const bool head = sub == 0;               // the group's writer
 
-    // ---- per-lane pixel state ----
+    // ---- per-lane pixel state (identical on the L lanes of a group) ----
     bool has = false, exhausted = false, warm = false, static_taken = false;
     bool fbmode = false;        // re-solving a failed warm start from the default start
     int it_prev = 0;            // iterations of the failed warm-started solve
@@ -306,12 +341,15 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
             int64_t my = -1;
             if (is_static) {
                 if (need) {
-                    if (!static_taken) { my = gtid; static_taken = true; }
+                    if (!static_taken) { my = gtid / L; static_taken = true; }
                     else exhausted = true;
                 }
             } else {
-                const unsigned long long mask = __ballot(need);
-                if (mask == 0ull) break;
+                // one queue slot per group that needs a pixel: the group heads
+                // take consecutive slots with one atomic per wave, then each
+                // head hands its slot to the rest of its group
+                if (__ballot(need) == 0ull) break;
+                const unsigned long long mask = __ballot(need && head);
                 const int cnt = __popcll(mask);
                 const int leader = __ffsll((long long)mask) - 1;
                 unsigned long long base = 0;
@@ -321,7 +359,11 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                 base = ((unsigned long long)hi32 << 32) | lo32;
                 const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                           __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-                if (need) my = (int64_t)(base + below);
+                const unsigned long long mine = base + below;
+                const int src = lane - sub;
+                const unsigned mlo = (unsigned)__shfl((int)(unsigned)(mine & 0xffffffffull), src);
+                const unsigned mhi = (unsigned)__shfl((int)(unsigned)(mine >> 32), src);
+                if (need) my = (int64_t)(((unsigned long long)mhi << 32) | mlo);
             }
             if (need && my >= 0) {
                 if (my >= total) {
@@ -334,28 +376,36 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     const int B = D->B;
                     rad = sd.radiance + pix * B;
                     tab = reinterpret_cast<const R*>(sd.table);
-                    bool fin = true;
+                    int nonfin = 0;
                     nvalid = 0;
                     lnorm2 = 0.0;
-                    for (int b = 0; b < B; ++b) {
+                    for (int b = sub; b < B; b += L) {
                         const float v = rad[b];
-                        fin = fin && isfinite(v);
+                        nonfin += isfinite(v) ? 0 : 1;
                         if ((R)v < tab[(size_t)b * FF_TABLE_COLS + COL_LSAT]) {
                             ++nvalid;
                             lnorm2 += (double)v * (double)v;
                         }
                     }
+                    if (L > 1) {
+                        nonfin = group_sum(nonfin, L);
+                        nvalid = group_sum(nvalid, L);
+                        lnorm2 = group_sum(lnorm2, L);
+                    }
+                    const bool fin = nonfin == 0;
                     it = 0;
                     phase = 0;
                     st = 0;
                     warm = false;
                     fbmode = false;
                     if (!fin || nvalid <= N) {
-                        const OutPtrs o = out_ptrs(sd);
-                        write_nan<N>(o, pix);
-                        if (o.rrr) o.rrr[pix] = __builtin_nanf("");
-                        if (o.iters) o.iters[pix] = 0;
-                        if (o.status) o.status[pix] = !fin ? FF_ST_NONFINITE_INPUT : FF_ST_NO_DOF;
+                        if (head) {
+                            const OutPtrs o = out_ptrs(sd);
+                            write_nan<N>(o, pix);
+                            if (o.rrr) o.rrr[pix] = __builtin_nanf("");
+                            if (o.iters) o.iters[pix] = 0;
+                            if (o.status) o.status[pix] = !fin ? FF_ST_NONFINITE_INPUT : FF_ST_NO_DOF;
+                        }
                     } else {
                         const float* z0 = sd.z0;
                         warm = z0 != nullptr;
@@ -383,8 +433,8 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     xe[j] = D->lo[j] + 0.5 * (D->hi[j] - D->lo[j]) * ((double)(phase == 0 ? z[j] : zt[j]) + 1.0);
             }
             R At[NT], gt[N];
-            const double Fe = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, xe, At, gt);
-            ++nevals;
+            const double Fe = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, xe, At, gt, sub, L);
+            nevals += head ? 1 : 0;
 
             // -------------------------------------------- LM bookkeeping
             const LmDesc<R, Q>* D = launder(descp);
@@ -535,13 +585,13 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     write = (st & FF_ST_CONVERGED) != 0 || !(rrr_new >= (double)rrr_prev);
                     it_out = it_prev + 1 + it;
                     if (write) st |= FF_ST_USED_FALLBACK | FF_ST_WARM_START;
-                    else if (o.iters) o.iters[pix] = it_out;
+                    else if (o.iters && head) o.iters[pix] = it_out;
                 } else if (warm && D->fallback && !(st & FF_ST_CONVERGED)) {
                     // the warm-started result is written now and the same lane
                     // re-solves the pixel from the default start right away
                     restart = true;
                 }
-                if (write) {
+                if (write && head) {
                     if (valid) {
                         // Gauss-Newton covariance sigma^2 A^-1 (sigma^2 = F / (N_valid - n))
                         // in z, scaled to x; variables whose Jacobian column is identically
@@ -680,6 +730,7 @@ static ff_status launch_lm(const BatchSpec& bs)
 {
     const ff_options& o = *bs.opts;
     const int block = o.block_size > 0 ? o.block_size : 256;
+    const int lpp = o.lanes_per_pixel > 0 ? o.lanes_per_pixel : 1;
     int dev = 0;
     FF_HIP_TRY(hipGetDevice(&dev));
     if (!ensure_quad<R, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
@@ -757,9 +808,10 @@ static ff_status launch_lm(const BatchSpec& bs)
             prm.hi[j] = j < n ? bs.prior->hi[j] : 1.0;
             prm.zdef[j] = j < n ? 2.0 * (bs.prior->x0[j] - bs.prior->lo[j]) / (bs.prior->hi[j] - bs.prior->lo[j]) - 1.0 : 0.0;
         }
-        const int64_t grid_static = (off + block - 1) / block;
+        const int64_t grid_static = (off * lpp + block - 1) / block;
         const int64_t grid_pers = std::min<int64_t>((int64_t)n_cu * per_cu, grid_static);
         prm.queue = ctr + c;
+        prm.lpp = lpp;
         prm.schedule = o.schedule;
         const int64_t grid = o.schedule == FF_SCHEDULE_STATIC ? grid_static : grid_pers;
         if (grid > 0x7fffffff) {

@@ -60,6 +60,7 @@ def test_default_prior_and_options(L):
         np.testing.assert_array_equal(p.x0, x0)
     o = ff.default_options()
     assert (o.max_iter, o.n_quad, o.precision) == (50, 32, ff.PRECISION_FP32)
+    assert (o.lanes_per_pixel, o.fallback, o.ftol) == (1, 1, 1e-8)
     with pytest.raises(ff.FirefitError):
         ff.default_prior(7)
 

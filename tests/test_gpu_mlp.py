@@ -238,13 +238,13 @@ def test_warm_start_gain_fire_pixels(world, dev, trained):
 
 def test_warm_start_wall_time(world, dev, trained):
     """Network inference plus warm-started LM (fallback on) takes less wall
-    time than the plain LM on a batch that keeps every lane busy for many
-    pixels (each lane of the persistent grid drains about eight)."""
+    time than the plain LM on a batch of the headline scene's size, where
+    each lane of the persistent grid drains about twenty pixels."""
     tab, scene, prior = world
     net, _ = trained
     X = scenegen.config0_states(4096, scene=5)
     rad = torch.from_numpy(noisy_spectra(tab, X, 1, 0, 5)).to(dev)
-    big = rad.repeat(256, 1).contiguous()                    # 1,048,576 pixels
+    big = rad.repeat(640, 1).contiguous()                    # 2,621,440 pixels
     t = {}
     for name in ("plain", "warm", "plain", "warm"):
         torch.cuda.synchronize()
@@ -253,7 +253,7 @@ def test_warm_start_wall_time(world, dev, trained):
         ff.retrieve(scene, big, prior, z0=zz)
         torch.cuda.synchronize()
         t[name] = time.perf_counter() - t0
-    print(f"\n  1,048,576 px: plain {t['plain'] * 1e3:.1f} ms, warm (network + LM) {t['warm'] * 1e3:.1f} ms")
+    print(f"\n  2,621,440 px: plain {t['plain'] * 1e3:.1f} ms, warm (network + LM) {t['warm'] * 1e3:.1f} ms")
     assert t["warm"] < 0.8 * t["plain"]
 
 
@@ -291,5 +291,5 @@ def test_warm_start_on_clustered_fire_scene(dev):
     # accuracy on the fire pixels against the oracle from the default start
     sel = np.flatnonzero(isf)[:1500]
     ref = oracle.retrieve(tab, lobs[sel], 1, lo, hi, x0)
-    sub = {k: v[sel] for k, v in warm.items()}
+    sub = {k: v[sel] for k, v in warm.items() if v is not None}
     assert_parity(sub, ref, min_same=0.97, label="warm start, clustered-fire scene")

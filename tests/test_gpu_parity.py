@@ -114,10 +114,11 @@ def test_forward_lower_quadrature_order(world, dev, q):
     assert rel.max() <= (2e-5 if q == 24 else 2e-4), rel.max()
 
 
-def test_retrieve_fp64_parity(world, dev, cfg0):
+@pytest.mark.parametrize("lpp", [1, 8])
+def test_retrieve_fp64_parity(world, dev, cfg0, lpp):
     X, lobs, ref = cfg0
     atm, tab, scene, prior = world
-    r = _run(scene, lobs, prior, dev, precision=ff.PRECISION_FP64)
+    r = _run(scene, lobs, prior, dev, precision=ff.PRECISION_FP64, lanes_per_pixel=lpp)
     conv = (r["status"].astype(np.int64) & CONVERGED) != 0
     assert (conv == ref.converged).mean() >= 0.995
     both = conv & ref.converged
@@ -140,21 +141,23 @@ def test_retrieve_fp64_parity(world, dev, cfg0):
     np.testing.assert_allclose(corr_g, corr_r, atol=1e-4)
 
 
-@pytest.mark.parametrize("acc", [ff.ACCUMULATE_FP32, ff.ACCUMULATE_FP64])
-def test_retrieve_fp32_parity(world, dev, cfg0, acc):
+@pytest.mark.parametrize("acc,lpp", [(ff.ACCUMULATE_FP32, 1), (ff.ACCUMULATE_FP64, 1), (ff.ACCUMULATE_FP32, 2),
+                                     (ff.ACCUMULATE_FP32, 4), (ff.ACCUMULATE_FP32, 16), (ff.ACCUMULATE_FP64, 64)])
+def test_retrieve_fp32_parity(world, dev, cfg0, acc, lpp):
     X, lobs, ref = cfg0
     atm, tab, scene, prior = world
-    r = _run(scene, lobs, prior, dev, accumulate=acc)
-    rep = assert_parity(r, ref, min_t=700, label=f"acc {acc}")
+    r = _run(scene, lobs, prior, dev, accumulate=acc, lanes_per_pixel=lpp)
+    rep = assert_parity(r, ref, min_t=700, label=f"acc {acc} lanes/pixel {lpp}")
     assert rep["both"] >= 0.95 * len(X)
 
 
-def test_schedules_and_block_sizes_are_bitwise_identical(world, dev, cfg0):
+@pytest.mark.parametrize("lpp", [1, 4])
+def test_schedules_and_block_sizes_are_bitwise_identical(world, dev, cfg0, lpp):
     X, lobs, ref = cfg0
     atm, tab, scene, prior = world
-    base = _run(scene, lobs, prior, dev)
+    base = _run(scene, lobs, prior, dev, lanes_per_pixel=lpp)
     for kw in [dict(schedule=ff.SCHEDULE_STATIC), dict(block_size=64), dict(block_size=128, blocks_per_cu=1)]:
-        r = _run(scene, lobs, prior, dev, **kw)
+        r = _run(scene, lobs, prior, dev, lanes_per_pixel=lpp, **kw)
         for k in ("state", "cov", "moments", "rrr", "iters", "status"):
             np.testing.assert_array_equal(r[k], base[k], err_msg=f"{kw} {k}")
 
@@ -172,31 +175,34 @@ def test_noise_free_recovery_fp32(world, dev):
     assert np.abs(r["state"][conv, 0] - X[conv, 0]).max() <= 1e-4
 
 
-def test_edge_cases(world, dev, cfg0):
+@pytest.mark.parametrize("lpp", [1, 16])
+def test_edge_cases(world, dev, cfg0, lpp):
     X, lobs, ref = cfg0
     atm, tab, scene, prior = world
     # empty batch
-    r = _run(scene, lobs[:0], prior, dev)
+    r = _run(scene, lobs[:0], prior, dev, lanes_per_pixel=lpp)
     assert r["state"].shape == (0, 5)
+    with pytest.raises(ff.FirefitError):
+        _run(scene, lobs[:4], prior, dev, lanes_per_pixel=3)
     # one pixel and a ragged count equal the corresponding rows of the full run
-    full = _run(scene, lobs[:130], prior, dev)
-    one = _run(scene, lobs[17:18], prior, dev)
+    full = _run(scene, lobs[:130], prior, dev, lanes_per_pixel=lpp)
+    one = _run(scene, lobs[17:18], prior, dev, lanes_per_pixel=lpp)
     for k in ("state", "rrr", "iters", "status"):
         np.testing.assert_array_equal(one[k][0], full[k][17])
-    rag = _run(scene, lobs[:65], prior, dev)
+    rag = _run(scene, lobs[:65], prior, dev, lanes_per_pixel=lpp)
     np.testing.assert_array_equal(rag["state"], full["state"][:65])
     # non-finite input
     bad = lobs[:3].copy()
     bad[1, 100] = np.nan
     bad[2, 0] = np.inf
-    r = _run(scene, bad, prior, dev)
+    r = _run(scene, bad, prior, dev, lanes_per_pixel=lpp)
     assert r["status"][1] == ff.ST_NONFINITE_INPUT and r["status"][2] == ff.ST_NONFINITE_INPUT
     assert np.isnan(r["state"][1:]).all() and np.isnan(r["rrr"][1:]).all() and (r["iters"][1:] == 0).all()
     np.testing.assert_array_equal(r["state"][0], full["state"][0])
     # no iterations allowed: the default start is returned with MAX_ITER
     # (FP32 path: z is held in float, so x0 round-trips to ~1 ulp of z)
     for prec, tol in ((ff.PRECISION_FP64, 1e-14), (ff.PRECISION_FP32, 1e-6)):
-        r = _run(scene, lobs[:8], prior, dev, max_iter=0, precision=prec)
+        r = _run(scene, lobs[:8], prior, dev, max_iter=0, precision=prec, lanes_per_pixel=lpp)
         assert np.all((r["status"] & ff.ST_MAX_ITER) != 0) and np.all(r["iters"] == 0)
         np.testing.assert_allclose(r["state_f64"], np.tile(prior.x0, (8, 1)), rtol=tol, atol=1e-12)
 
@@ -246,7 +252,8 @@ def test_batch_equals_single_scene_runs(dev):
             np.testing.assert_array_equal(o[k], s1[k])
 
 
-def test_warm_start_and_fallback(world, dev, cfg0):
+@pytest.mark.parametrize("lpp", [1, 4])
+def test_warm_start_and_fallback(world, dev, cfg0, lpp):
     """A per-pixel start z0: pixels that converge from it keep that result;
     pixels that do not are solved again from x0 and take that result when it
     converged or fits better (USED_FALLBACK), iterations summing both runs."""
@@ -263,7 +270,8 @@ def test_warm_start_and_fallback(world, dev, cfg0):
     ref_cold = oracle.retrieve(tab, lobs[:P], 1, lo, hi, prior.x0, opts=oracle.LMOptions(max_iter=12))
     out = ff.retrieve(scene, torch.from_numpy(lobs[:P]).to(dev), prior,
                       z0=torch.tensor(z0, dtype=torch.float32, device=dev),
-                      options=ff.default_options(precision=ff.PRECISION_FP64, **opts), state_f64=True)
+                      options=ff.default_options(precision=ff.PRECISION_FP64, lanes_per_pixel=lpp, **opts),
+                      state_f64=True)
     torch.cuda.synchronize()
     r = out.numpy()
     st = r["status"].astype(np.int64)
