@@ -138,6 +138,20 @@ def run_leg(args, atm, rad, stream, net):
     P = rad.shape[0]
     prior = ff.default_prior(1)
     opts = ff.default_options(n_quad=args.n_quad)
+    tuned = None
+    if not args.no_tune:
+        # launch shape from the tuner's table (tuned on this batch on a miss)
+        sc = ff.Scene(atm)
+        z0 = net.infer(rad, stream=stream) if net is not None else None
+        with torch.cuda.stream(stream):
+            opts, tms = ff.tune([sc], [rad], prior, z0s=None if z0 is None else [z0], options=opts,
+                                cache_path=args.tune_cache, stream=stream)
+        torch.cuda.synchronize()
+        sc.close()
+        del z0
+        tuned = {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size,
+                 "blocks_per_cu": opts.blocks_per_cu, "schedule": opts.schedule, "tuned_ms": tms}
+        log(f"tuned launch: {tuned}")
     outs = ff.allocate_outputs(P, 1, rad.device)
     evals = torch.zeros(1, dtype=torch.int64, device=rad.device)
     live = []      # scene tables must outlive the asynchronous launches that read them
@@ -182,7 +196,7 @@ def run_leg(args, atm, rad, stream, net):
            "lm_kernel_ms": lm_ms, "wall_s_per_step": wall / args.steps,
            "evals_per_pixel": int(evals.item()) / args.steps / P,
            "mean_iters": float(it.mean()), "p99_iters": float(np.percentile(it, 99)),
-           "max_iters": int(it.max())}
+           "max_iters": int(it.max()), "launch": tuned}
     if net is not None:
         leg["fallback_rate"] = float(((st & ff.ST_USED_FALLBACK) != 0).mean())
     return leg, res, int(evals.item()) / args.steps
@@ -204,6 +218,9 @@ def main():
     ap.add_argument("--bg-fraction", type=float, default=0.3)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the tuner's")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2608_07580_amd", "tuning.json"),
+                    help="autotuner table (read, and written on a miss)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")

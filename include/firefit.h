@@ -231,6 +231,24 @@ ff_status ff_retrieve_batch(const ff_scene* const* scenes, const float* const* r
                             const float* const* z0_dev, const ff_options* opts,
                             const ff_outputs* outs, unsigned long long* evals_dev, void* stream);
 
+/* Launch-shape autotuner.  Times ff_retrieve_batch on the given batch
+ * (writing its results to outs) for candidate lanes_per_pixel (1..64),
+ * block_size (64, 128, 256), blocks_per_cu (occupancy limit or 1) and
+ * schedule, one dimension at a time starting from *opts, and writes the
+ * fastest into *opts (other fields untouched; n_quad is never changed, since
+ * it changes the model).  cache_path: JSON table of earlier choices keyed by
+ * device architecture, band count, model, precision, accumulation, n_quad,
+ * start kind (z0 given or not) and floor(log2(total pixels)); a hit is
+ * applied without timing, a new choice is stored (NULL: no table).
+ * flags: FF_TUNE_IGNORE_CACHE re-tunes and overwrites the entry.  best_ms
+ * (may be NULL) receives the chosen configuration's time.  Synchronous
+ * (waits on stream between candidates). */
+#define FF_TUNE_IGNORE_CACHE 1
+ff_status ff_tune(const ff_scene* const* scenes, const float* const* radiance_dev, const int64_t* P,
+                  int32_t n_scenes, const ff_prior* prior, const float* const* z0_dev, ff_options* opts,
+                  const ff_outputs* outs, const char* cache_path, int32_t flags, double* best_ms,
+                  void* stream);
+
 /* One-shot form: builds a scene from srf/atm, retrieves, destroys the scene.
  * Synchronous (waits for stream). */
 ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,

@@ -38,7 +38,7 @@ N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8}
 EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_default",
            "ff_prior_default", "ff_gauss_hermite", "ff_scene_create", "ff_scene_destroy",
            "ff_scene_n_bands", "ff_scene_band_tables", "ff_forward", "ff_retrieve_scene",
-           "ff_retrieve_batch", "ff_retrieve",
+           "ff_retrieve_batch", "ff_retrieve", "ff_tune",
            "ff_mlp_create", "ff_mlp_destroy", "ff_mlp_n_params", "ff_mlp_get_params",
            "ff_mlp_set_params", "ff_mlp_set_normalization", "ff_mlp_get_normalization",
            "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
@@ -120,6 +120,9 @@ def lib():
         L.ff_retrieve.argtypes = [C.c_void_p, C.c_int64, C.POINTER(ffSrf), C.POINTER(ffAtmosphere),
                                   C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
                                   C.POINTER(ffOutputs), C.c_void_p]
+        L.ff_tune.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_int32,
+                              C.POINTER(ffPrior), C.POINTER(C.c_void_p), C.POINTER(ffOptions),
+                              C.POINTER(ffOutputs), C.c_char_p, C.c_int32, _dp, C.c_void_p]
         vp = C.c_void_p
         L.ff_mlp_create.argtypes = [C.c_int32] * 5 + [C.c_uint64, C.POINTER(vp)]
         L.ff_mlp_destroy.argtypes = [vp]
@@ -139,7 +142,7 @@ def lib():
         L.ff_mlp_train.argtypes = [vp, vp, C.POINTER(ffPrior), C.c_int64, C.c_int32, C.c_uint64, C.c_double,
                                    C.c_double, C.c_float, C.c_float, vp, vp]
         for name in ("ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
-                     "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default",
+                     "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
                      "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
                      "ff_mlp_get_normalization", "ff_mlp_fit_normalization", "ff_mlp_infer",
                      "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train"):
@@ -340,6 +343,37 @@ def retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None, opti
     _check(lib().ff_retrieve_batch(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
                                    _stream_handle(stream)), "ff_retrieve_batch")
     return outs
+
+
+TUNE_IGNORE_CACHE = 1
+
+
+def tune(scenes, radiances, prior: Prior | None = None, z0s=None, options: ffOptions | None = None,
+         cache_path: str | None = None, retune: bool = False, stream=None):
+    """Launch-shape autotuner (ff_tune) on a batch: returns (options, best_ms).
+
+    `scenes`/`radiances`/`z0s` are lists (one scene: lists of one).  The
+    chosen lanes per pixel, workgroup size, workgroups per CU and schedule
+    are written into a copy of `options`; with `cache_path` the choice is
+    read from / stored in that JSON table."""
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    opts = ffOptions()
+    C.memmove(C.byref(opts), C.byref(options or default_options()), C.sizeof(ffOptions))
+    ns = len(scenes)
+    outs = [allocate_outputs(r.shape[0], prior.model, r.device) for r in radiances]
+    sc = (C.c_void_p * ns)(*[s.handle.value for s in scenes])
+    rd = (C.c_void_p * ns)(*[r.data_ptr() for r in radiances])
+    Ps = (C.c_int64 * ns)(*[r.shape[0] for r in radiances])
+    z0p = None
+    if z0s is not None:
+        z0p = (C.c_void_p * ns)(*[0 if z is None else z.data_ptr() for z in z0s])
+    oc = (ffOutputs * ns)(*[o.to_c() for o in outs])
+    pc = prior.to_c()
+    ms = C.c_double(0.0)
+    _check(lib().ff_tune(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(opts), oc,
+                         None if cache_path is None else os.fsencode(cache_path),
+                         TUNE_IGNORE_CACHE if retune else 0, C.byref(ms), _stream_handle(stream)), "ff_tune")
+    return opts, ms.value
 
 
 # ----------------------------------------------------------------------------

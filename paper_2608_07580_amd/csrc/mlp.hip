@@ -75,6 +75,27 @@ __device__ __forceinline__ float gelu_t(float x, float& dgelu)
     return 0.5f * x * (1.0f + t);
 }
 
+// Store one accumulator element through the epilogue EPI.
+template <int EPI>
+__device__ __forceinline__ void epilogue_store(int m, int n, float v, const EpiArgs& ep)
+{
+    if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_NOH) {
+        const float h = v + ep.bias[n];
+        float dg;
+        const float g = gelu_t(h, dg);
+        if (EPI == EPI_FWD_GELU) ep.outf[(size_t)m * ep.ldof + n] = h;
+        ep.outb[(size_t)m * ep.ldob + n] = (__bf16)g;
+    } else if (EPI == EPI_FWD_LINEAR) {
+        ep.outf[(size_t)m * ep.ldof + n] = v + ep.bias[n];
+    } else if (EPI == EPI_BWD_GELU) {
+        float dg;
+        gelu_t(ep.hprev[(size_t)m * ep.ldh + n], dg);
+        ep.outb[(size_t)m * ep.ldob + n] = (__bf16)(v * dg);
+    } else {
+        ep.outf[(size_t)m * ep.ldof + n] = v;
+    }
+}
+
 // C[m][n] = sum_k Aop[m][k] Bop[k][n];  Aop = TA ? A[k][m] : A[m][k],
 // Bop = TB ? B[n][k] : B[k][n] (lda/ldb = row strides of the stored arrays).
 // Loads: m < Ml, n < Nl, k < K (8-element chunks along the contiguous
@@ -151,47 +172,113 @@ gemm_bf16(int M, int N, int Ml, int Nl, int K, const __bf16* __restrict__ A, int
         for (int j = 0; j < 2; ++j) {
             const int n = n0 + wn * 32 + j * 16 + (lane & 15);
             if (n >= N) continue;
-            const float bias = (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_NOH || EPI == EPI_FWD_LINEAR) ? ep.bias[n] : 0.f;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + e;
-                if (m >= M) continue;
-                const float v = acc[i][j][e];
-                if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_NOH) {
-                    const float h = v + bias;
-                    float dg;
-                    const float g = gelu_t(h, dg);
-                    if (EPI == EPI_FWD_GELU) ep.outf[(size_t)m * ep.ldof + n] = h;
-                    ep.outb[(size_t)m * ep.ldob + n] = (__bf16)g;
-                } else if (EPI == EPI_FWD_LINEAR) {
-                    ep.outf[(size_t)m * ep.ldof + n] = v + bias;
-                } else if (EPI == EPI_BWD_GELU) {
-                    float dg;
-                    gelu_t(ep.hprev[(size_t)m * ep.ldh + n], dg);
-                    ep.outb[(size_t)m * ep.ldob + n] = (__bf16)(v * dg);
-                } else {
-                    ep.outf[(size_t)m * ep.ldof + n] = v;
-                }
+                if (m < M) epilogue_store<EPI>(m, n, acc[i][j][e], ep);
+            }
+        }
+    }
+}
+
+// Forward-pass GEMM C[m][n] = sum_k A[m][k] B[n][k] (both operands contiguous
+// in k) for large row counts: 128x128 output tile per workgroup of four
+// waves (64x64 each, 4x4 MFMA 16x16x32 accumulators), k advanced 32 at a
+// time through double-buffered LDS with one barrier per step; the next k
+// slice is fetched into registers while the current one feeds the matrix
+// cores.  (A 64-wide k step measured slower: its LDS and registers halve
+// the workgroups resident per CU.)  Requires N % 128 == 0 and K % 8 == 0;
+// rows m >= Ml read as zero, rows m >= M are not stored.
+constexpr int kFM = 128, kFN = 128;
+
+template <int EPI>
+__global__ void __launch_bounds__(kGemmThreads)
+gemm_nt_128(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, const __bf16* __restrict__ B,
+            int ldb, EpiArgs ep)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][kFM][kBK + kPad];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][kFN][kBK + kPad];
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * kFM, n0 = blockIdx.x * kFN;
+    const int lr = t >> 2, lk = (t & 3) * 8;     // this thread's load rows lr, lr + 64 and k chunk
+    const bf16x8_t zero8 = {};
+    float4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+    bf16x8_t ra[2], rb[2];
+    auto fetch = [&](int k0) {
+        const int k = k0 + lk;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int m = m0 + lr + 64 * h;
+            const int n = n0 + lr + 64 * h;
+            ra[h] = (m < Ml && k < K) ? *reinterpret_cast<const bf16x8_t*>(A + (size_t)m * lda + k) : zero8;
+            rb[h] = (n < N && k < K) ? *reinterpret_cast<const bf16x8_t*>(B + (size_t)n * ldb + k) : zero8;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<bf16x8_t*>(&As[buf][lr + 64 * h][lk]) = ra[h];
+            *reinterpret_cast<bf16x8_t*>(&Bs[buf][lr + 64 * h][lk]) = rb[h];
+        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        const bool more = k0 + kBK < K;
+        if (more) fetch(k0 + kBK);
+        bf16x8_t a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a[i] = *reinterpret_cast<const bf16x8_t*>(&As[cur][wm * 64 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            b[j] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][wn * 64 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more) stash(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + e;
+                if (m < M) epilogue_store<EPI>(m, n, acc[i][j][e], ep);
             }
         }
     }
 }
 
 // u_b = (ln max(L_b, floor) - mean_b) * inv_std_b, zero-padded to kin columns
-__global__ void features_kernel(const float* __restrict__ L, int64_t P, int n_in, int kin,
+// (one element per thread; P * kin < 2^31)
+__global__ void features_kernel(const float* __restrict__ L, int P, int n_in, int kin,
                                 const float* __restrict__ mean, const float* __restrict__ inv_std,
                                 float floor_v, __bf16* __restrict__ X)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = P * kin;
-    if (i >= total) return;
-    const int64_t p = i / kin;
-    const int b = (int)(i - p * kin);
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (unsigned)P * (unsigned)kin) return;
+    const unsigned p = i / (unsigned)kin;
+    const int b = (int)(i - p * (unsigned)kin);
     float u = 0.f;
     if (b < n_in) {
-        const float v = L[p * n_in + b];
-        const float lv = logf(fmaxf(v, floor_v));
-        u = (lv - mean[b]) * inv_std[b];
+        const float v = L[(size_t)p * n_in + b];
+        u = (logf(fmaxf(v, floor_v)) - mean[b]) * inv_std[b];
     }
     X[i] = (__bf16)u;
 }
@@ -471,6 +558,14 @@ void gemm(int M, int N, int Ml, int Nl, int K, const __bf16* A, int lda, const _
     hipLaunchKernelGGL((gemm_bf16<TA, TB, EPI>), grid, dim3(kGemmThreads), 0, s, M, N, Ml, Nl, K, A, lda, B, ldb, ep);
 }
 
+template <int EPI>
+void gemm_fwd(int M, int N, int K, const __bf16* A, int lda, const __bf16* B, int ldb, const EpiArgs& ep,
+              hipStream_t s)
+{
+    dim3 grid((unsigned)(N / kFN), (unsigned)cdiv(M, kFM));
+    hipLaunchKernelGGL((gemm_nt_128<EPI>), grid, dim3(kGemmThreads), 0, s, M, N, M, K, A, lda, B, ldb, ep);
+}
+
 // forward pass of R rows of features already in m->X; keep_h: store the
 // pre-activations for the backward pass
 void forward_rows(const ff_mlp* m, int64_t R, bool keep_h, hipStream_t s)
@@ -480,7 +575,11 @@ void forward_rows(const ff_mlp* m, int64_t R, bool keep_h, hipStream_t s)
         const __bf16* in = l == 0 ? m->X : m->A[l - 1];
         const int kin = m->map.in_pad[l];
         EpiArgs ep{m->params + m->map.off_b[l], m->H[l], m->h[l], m->A[l], m->h[l], nullptr, 0};
-        if (keep_h)
+        const __bf16* w = m->wb + m->map.off_wb[l];
+        if (m->h[l] % kFN == 0) {
+            if (keep_h) gemm_fwd<EPI_FWD_GELU>(r, m->h[l], kin, in, kin, w, kin, ep, s);
+            else gemm_fwd<EPI_FWD_GELU_NOH>(r, m->h[l], kin, in, kin, w, kin, ep, s);
+        } else if (keep_h)
             gemm<false, true, EPI_FWD_GELU>(r, m->h[l], r, m->h[l], kin, in, kin, m->wb + m->map.off_wb[l], kin, ep, s);
         else
             gemm<false, true, EPI_FWD_GELU_NOH>(r, m->h[l], r, m->h[l], kin, in, kin, m->wb + m->map.off_wb[l], kin, ep, s);
@@ -684,8 +783,8 @@ extern "C" ff_status ff_mlp_infer(const ff_mlp* mc, const float* rad, int64_t P,
     if (st != FF_OK) return st;
     for (int64_t p0 = 0; p0 < P; p0 += chunk) {
         const int64_t R = std::min(chunk, P - p0);
-        hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(R * m->kin, 256)), dim3(256), 0, s, rad + p0 * m->n_in, R,
-                           m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
+        hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(R * m->kin, 256)), dim3(256), 0, s,
+                           rad + p0 * m->n_in, (int)R, m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
         forward_rows(m, R, false, s);
         hipLaunchKernelGGL(output_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y, R, m->n_out,
                            z0 + p0 * m->n_out);
@@ -699,8 +798,8 @@ static ff_status grads_impl(ff_mlp* m, const float* rad, const float* target, in
 {
     ff_status st = ensure_ws(m, P, s);
     if (st != FF_OK) return st;
-    hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(P * m->kin, 256)), dim3(256), 0, s, rad, P, m->n_in, m->kin,
-                       m->mean, m->inv_std, m->floor_v, m->X);
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(P * m->kin, 256)), dim3(256), 0, s, rad, (int)P,
+                       m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
     forward_rows(m, P, true, s);
     if (loss) hipLaunchKernelGGL(zero_f64, dim3(1), dim3(64), 0, s, loss);
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)cdiv(P, 256)), dim3(256), 0, s, m->Y, target, P, m->n_out, m->dY,

@@ -13,10 +13,13 @@ the oracle's own Gauss-Newton posterior at its solution:
     leaves f undetermined; at f = 0 the temperature columns of the Jacobian
     vanish, the linearisation cannot see that branch, and a large f at the
     lower temperature bound fits the same spectrum equally well);
-  * FP32 and FP64 trajectories can take different accept/reject decisions
-    and end in different local minima of the same loss; a pixel reaches
-    the oracle's minimum when the relative radiance residuals agree to 1e-5.
-    That share is reported and bounded, and states are compared on it.
+  * FP32 and FP64 trajectories (or solves from different starts) can take
+    different accept/reject decisions and end in different local minima of
+    the same loss, some of nearly equal cost (the area-temperature
+    degeneracy); a pixel reaches the oracle's minimum when the relative
+    radiance residuals agree to 1e-5 and every identified variable lies
+    within 3 posterior s.d. of the oracle's value.  That share is reported
+    and bounded, and states are compared on it.
 """
 import numpy as np
 
@@ -74,16 +77,23 @@ def f_comparable(gpu, ref, model=1):
     return both & (sd_f <= SD_F_MAX) & full_rank
 
 
-def same_minimum(gpu, ref, tol=1e-5):
+BASIN_SD = 3.0
+
+
+def same_minimum(gpu, ref, tol=1e-5, model=1):
     gst = gpu["status"].astype(np.int64)
     both = ((gst & CONVERGED) != 0) & ref.converged
-    return both & (np.abs(gpu["rrr"] - ref.rrr) <= tol)
+    n = oracle.n_state(model)
+    sd = np.sqrt(np.abs(np.diagonal(oracle.unpack_cov(ref.cov, n), axis1=1, axis2=2)))
+    near = np.abs(gpu["state"][:, :n] - ref.state) <= BASIN_SD * sd
+    near |= ~np.isfinite(sd)                 # unidentified variables are not compared
+    return both & (np.abs(gpu["rrr"] - ref.rrr) <= tol) & near.all(axis=1)
 
 
 def parity_report(gpu, ref, model=1):
     """Dict of the parity statistics used by the tests."""
     both, ok = identifiable(gpu, ref, model)
-    same = same_minimum(gpu, ref)
+    same = same_minimum(gpu, ref, model=model)
     t_ok = ok & same
     f_ok = f_comparable(gpu, ref, model) & same
     dT = np.abs(gpu["moments"][:, 0] - ref.moments[:, 0])

@@ -77,3 +77,11 @@ def test_argument_errors_return_einval_before_any_launch(L):
     assert "NULL" in ff.lib().ff_last_error().decode()
     x = np.empty(4)
     assert L.ff_gauss_hermite(0, x.ctypes.data_as(C.POINTER(C.c_double)), x.ctypes.data_as(C.POINTER(C.c_double))) == ff.FF_EINVAL
+
+
+def test_tune_rejects_bad_arguments_on_the_host(L):
+    pr = ff.default_prior(1).to_c()
+    o = ff.default_options()
+    ms = C.c_double(0)
+    assert L.ff_tune(None, None, None, 0, C.byref(pr), None, C.byref(o), None, None, 0, C.byref(ms), None) == ff.FF_EINVAL
+    assert L.ff_tune(None, None, None, 1, None, None, C.byref(o), None, None, 0, C.byref(ms), None) == ff.FF_EINVAL
