@@ -335,6 +335,40 @@ ff_status ff_mlp_train(ff_mlp* mlp, const ff_scene* scene, const ff_prior* prior
                        int32_t batch, uint64_t seed, double snr, double bg_fraction, float lr,
                        float lr_final, double* loss_history_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Graph-captured pipeline.  The launch sequence of one batch shape --
+ * network inference of z0 for every scene (when mlp is not NULL), then the
+ * retrieval with fallback -- recorded once into a HIP graph and replayed by
+ * one graph launch.  The graph binds every pointer given here (radiance,
+ * outputs, evals counter, scene tables, network weights): rewrite the
+ * radiance buffers in place between launches; results land in outs.  z0
+ * lives in a buffer the pipeline owns (ff_pipeline_z0).
+ * Create waits for stream, runs the sequence once eagerly (results
+ * written, evals incremented) so that every workspace reaches its size
+ * outside capture, then records it (thread-local capture) on a stream the
+ * pipeline owns -- so its scratch is never shared or regrown -- and
+ * instantiates the graph.  Synchronous.  The network's workspace stays
+ * valid for the graph while the pipeline exists (a larger eager use keeps
+ * the old buffers alive instead of freeing them); destroy pipelines before
+ * their network.  Launch: asynchronous on stream (may be NULL).  Replays of
+ * one pipeline must not overlap each other or run concurrently with other
+ * uses of the same network (they share buffers).
+ * ------------------------------------------------------------------------ */
+typedef struct ff_pipeline ff_pipeline;
+ff_status ff_pipeline_create(const ff_scene* const* scenes, const float* const* radiance_dev,
+                             const int64_t* P, int32_t n_scenes, const ff_prior* prior, const ff_mlp* mlp,
+                             const ff_options* opts, const ff_outputs* outs, unsigned long long* evals_dev,
+                             void* stream, ff_pipeline** out);
+ff_status ff_pipeline_launch(ff_pipeline* pipeline, void* stream);
+const float* ff_pipeline_z0(const ff_pipeline* pipeline);   /* [sum P][n], scene after scene */
+void ff_pipeline_destroy(ff_pipeline* pipeline);
+
+/* Retrieval launches use a library-owned scratch buffer per (device,
+ * stream) that only grows (so that repeated calls allocate nothing and can
+ * be captured); this frees them all after synchronizing their streams.
+ * Call only when no library work is in flight. */
+ff_status ff_release_scratch(void);
+
 #ifdef __cplusplus
 }
 #endif

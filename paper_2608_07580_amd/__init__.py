@@ -42,7 +42,8 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_create", "ff_mlp_destroy", "ff_mlp_n_params", "ff_mlp_get_params",
            "ff_mlp_set_params", "ff_mlp_set_normalization", "ff_mlp_get_normalization",
            "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
-           "ff_mlp_generate", "ff_mlp_train")
+           "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
+           "ff_pipeline_destroy", "ff_release_scratch")
 
 
 class FirefitError(RuntimeError):
@@ -141,7 +142,16 @@ def lib():
                                       C.c_double, vp, vp, vp, vp]
         L.ff_mlp_train.argtypes = [vp, vp, C.POINTER(ffPrior), C.c_int64, C.c_int32, C.c_uint64, C.c_double,
                                    C.c_double, C.c_float, C.c_float, vp, vp]
-        for name in ("ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
+        L.ff_pipeline_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32,
+                                         C.POINTER(ffPrior), vp, C.POINTER(ffOptions), C.POINTER(ffOutputs), vp, vp,
+                                         C.POINTER(vp)]
+        L.ff_pipeline_launch.argtypes = [vp, vp]
+        L.ff_pipeline_z0.argtypes = [vp]
+        L.ff_pipeline_z0.restype = vp
+        L.ff_pipeline_destroy.argtypes = [vp]
+        L.ff_pipeline_destroy.restype = None
+        for name in ("ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
+                     "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
                      "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
                      "ff_mlp_get_normalization", "ff_mlp_fit_normalization", "ff_mlp_infer",
@@ -454,6 +464,7 @@ class WarmStart:
         torch = _torch()
         loss = torch.zeros(1, dtype=torch.float64, device=radiance.device)
         g = torch.empty(self.n_params, dtype=torch.float32, device=radiance.device)
+        self._pending = (loss, g)
         _check(lib().ff_mlp_gradients(self.handle, _ptr(radiance), _ptr(target), radiance.shape[0], _ptr(loss),
                                       _ptr(g), _stream_handle(stream)), "ff_mlp_gradients")
         return loss, g
@@ -461,6 +472,7 @@ class WarmStart:
     def train_step(self, radiance, target, lr: float, stream=None):
         torch = _torch()
         loss = torch.zeros(1, dtype=torch.float64, device=radiance.device)
+        self._pending = loss
         _check(lib().ff_mlp_train_step(self.handle, _ptr(radiance), _ptr(target), radiance.shape[0], lr, _ptr(loss),
                                        _stream_handle(stream)), "ff_mlp_train_step")
         return loss
@@ -473,6 +485,10 @@ class WarmStart:
         pc = prior.to_c()
         _check(lib().ff_mlp_train(self.handle, scene.handle, C.byref(pc), steps, batch, seed, snr, bg_fraction, lr,
                                   lr_final, _ptr(hist), _stream_handle(stream)), "ff_mlp_train")
+        # the kernels still write hist after this returns: keep it alive even
+        # if the caller drops it (its block must not be handed out to a
+        # tensor used on another stream meanwhile)
+        self._pending = hist
         return hist
 
     def save(self, path: str):
@@ -488,3 +504,45 @@ class WarmStart:
         w.set_params(d["params"])
         w.set_normalization(d["mean"], d["inv_std"], float(d["floor"]))
         return w
+
+
+class Pipeline:
+    """Graph-captured (warm start +) retrieval of one batch (ff_pipeline_*).
+
+    The graph binds the radiance tensors, outputs and network given here;
+    rewrite the radiance tensors in place (``rad.copy_(new)``) and call
+    ``launch()`` again.  ``outputs`` is a list of Outputs, one per scene."""
+
+    def __init__(self, scenes, radiances, prior: Prior | None = None, net: "WarmStart | None" = None,
+                 options: ffOptions | None = None, evals=None, stream=None):
+        torch = _torch()
+        self.prior = prior or default_prior(MODEL_LOGNORMAL_1)
+        self.options = options or default_options()
+        self.scenes, self.radiances, self.net, self.evals = list(scenes), list(radiances), net, evals
+        ns = len(self.scenes)
+        self.outputs = [allocate_outputs(r.shape[0], self.prior.model, r.device) for r in self.radiances]
+        sc = (C.c_void_p * ns)(*[s.handle.value for s in self.scenes])
+        rd = (C.c_void_p * ns)(*[r.data_ptr() for r in self.radiances])
+        Ps = (C.c_int64 * ns)(*[r.shape[0] for r in self.radiances])
+        oc = (ffOutputs * ns)(*[o.to_c() for o in self.outputs])
+        pc = self.prior.to_c()
+        self.stream = stream or torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().ff_pipeline_create(sc, rd, Ps, ns, C.byref(pc), None if net is None else net.handle,
+                                        C.byref(self.options), oc, _ptr(evals), _stream_handle(self.stream),
+                                        C.byref(h)), "ff_pipeline_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().ff_pipeline_launch(self.handle, _stream_handle(stream or self.stream)), "ff_pipeline_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ff_pipeline_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -84,6 +84,17 @@ struct BatchSpec {
 };
 
 ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs);
+
+// Library-owned, grow-only scratch per (device, stream); growth is refused
+// while the stream is being captured into a graph.
+ff_status stream_scratch(hipStream_t stream, size_t bytes, void** out);
+bool stream_capturing(hipStream_t stream);
+
+// Input and output widths of a warm-start network; pin/unpin its activation
+// workspace (while pinned, a grown workspace keeps the old buffers alive for
+// the graphs that bind them).
+void mlp_dims(const ff_mlp* m, int* n_in, int* n_out);
+void mlp_pin(const ff_mlp* m, int delta);
 ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, const void* state,
                            int64_t P, void* L, void* J, hipStream_t stream);
 

@@ -755,14 +755,17 @@ static ff_status launch_lm(const BatchSpec& bs)
     if (max_chunk_total == 0) return clear_error();
     const bool fallback = any_warm && o.fallback != 0;
 
-    // stream-ordered scratch: per chunk one queue counter and one descriptor
+    // the stream's scratch: per chunk one queue counter and one descriptor
     using Desc = LmDesc<R, Q>;
     const size_t desc_bytes = (sizeof(Desc) + 255) / 256 * 256;
     const size_t n_ctr = (size_t)n_chunks;
     const size_t ctr_bytes = (n_ctr * sizeof(unsigned long long) + 255) / 256 * 256;
     const size_t bytes = ctr_bytes + (size_t)n_chunks * desc_bytes;
     char* scratch = nullptr;
-    FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&scratch), bytes, bs.stream));
+    {
+        const ff_status st = stream_scratch(bs.stream, bytes, reinterpret_cast<void**>(&scratch));
+        if (st != FF_OK) return st;
+    }
     auto* ctr = reinterpret_cast<unsigned long long*>(scratch);
     char* descs = scratch + ctr_bytes;
     hipLaunchKernelGGL(zero_u64, dim3((unsigned)((n_ctr + 255) / 256)), dim3(256), 0, bs.stream, ctr, (int)n_ctr);
@@ -826,9 +829,7 @@ static ff_status launch_lm(const BatchSpec& bs)
                            (const Desc*)dptr);
         e = hipGetLastError();
     }
-    hipError_t e2 = hipFreeAsync(scratch, bs.stream);
     if (e != hipSuccess) return hip_error(e, "lm_kernel launch");
-    if (e2 != hipSuccess) return hip_error(e2, "hipFreeAsync");
     return clear_error();
 }
 

@@ -511,16 +511,23 @@ struct ff_mlp {
     float* Y = nullptr;
     __bf16* dY = nullptr;
     __bf16* dH[3] = {nullptr, nullptr, nullptr};
+    int pins = 0;                     // graphs that bind the workspace (see ff_pipeline_create)
+    std::vector<void*> retired;       // workspace buffers replaced while pinned, freed at destroy
 };
 
 namespace {
 
+// Drop the activation workspace: freed, or -- while a captured graph binds
+// it -- kept until the network is destroyed.
 void free_ws(ff_mlp* m)
 {
-    hipFree(m->X);
-    for (int i = 0; i < 3; ++i) { hipFree(m->H[i]); hipFree(m->A[i]); hipFree(m->dH[i]); }
-    hipFree(m->Y);
-    hipFree(m->dY);
+    void* bufs[12] = {m->X, m->H[0], m->H[1], m->H[2], m->A[0], m->A[1], m->A[2],
+                      m->dH[0], m->dH[1], m->dH[2], m->Y, m->dY};
+    for (void* b : bufs) {
+        if (!b) continue;
+        if (m->pins > 0) m->retired.push_back(b);
+        else (void)hipFree(b);
+    }
     m->X = nullptr; m->Y = nullptr; m->dY = nullptr;
     for (int i = 0; i < 3; ++i) { m->H[i] = nullptr; m->A[i] = nullptr; m->dH[i] = nullptr; }
     m->ws_rows = 0;
@@ -531,6 +538,9 @@ void free_ws(ff_mlp* m)
 ff_status ensure_ws(ff_mlp* m, int64_t rows, hipStream_t stream)
 {
     if (rows <= m->ws_rows) return FF_OK;
+    if (stream_capturing(stream))
+        return set_error(FF_EINVAL, "network workspace must grow outside graph capture: run the same call "
+                                    "once before capturing it");
     FF_HIP_TRY(hipStreamSynchronize(stream));
     free_ws(m);
     const int64_t R = cdiv(rows, 64) * 64;
@@ -704,7 +714,9 @@ extern "C" ff_status ff_mlp_create(int32_t n_in, int32_t h1, int32_t h2, int32_t
 extern "C" void ff_mlp_destroy(ff_mlp* m)
 {
     if (!m) return;
+    m->pins = 0;
     free_ws(m);
+    for (void* b : m->retired) (void)hipFree(b);
     hipFree(m->params);
     hipFree(m->grads);
     hipFree(m->adam_m);
@@ -769,6 +781,19 @@ extern "C" ff_status ff_mlp_fit_normalization(ff_mlp* m, const float* rad, int64
     FF_HIP_TRY(hipGetLastError());
     return clear_error();
 }
+
+namespace ff {
+void mlp_dims(const ff_mlp* m, int* n_in, int* n_out)
+{
+    *n_in = m ? m->n_in : 0;
+    *n_out = m ? m->n_out : 0;
+}
+
+void mlp_pin(const ff_mlp* m, int delta)
+{
+    if (m) const_cast<ff_mlp*>(m)->pins += delta;
+}
+}  // namespace ff
 
 extern "C" ff_status ff_mlp_infer(const ff_mlp* mc, const float* rad, int64_t P, float* z0, void* stream)
 {

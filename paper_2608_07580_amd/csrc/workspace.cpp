@@ -1,0 +1,83 @@
+// Library-owned scratch memory: one grow-only device buffer per (device,
+// stream).  Launches ordered on one stream reuse it safely (the next launch
+// sequence starts after the previous one's kernels in stream order), so a
+// launch sequence needs no allocation once its stream's buffer is large
+// enough -- which is what lets it be recorded into a HIP graph.  Growing
+// synchronizes the stream first and is refused while the stream is being
+// captured.  Buffers are held until ff_release_scratch or process exit.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "ff_internal.hpp"
+
+namespace ff {
+namespace {
+
+struct Buf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+std::mutex g_mutex;
+std::map<std::pair<int, hipStream_t>, Buf>& table()
+{
+    static auto* t = new std::map<std::pair<int, hipStream_t>, Buf>();   // never destroyed: no HIP calls at exit
+    return *t;
+}
+
+}  // namespace
+
+bool stream_capturing(hipStream_t stream)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+ff_status stream_scratch(hipStream_t stream, size_t bytes, void** out)
+{
+    int dev = 0;
+    FF_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mutex);
+    Buf& b = table()[{dev, stream}];
+    if (b.bytes >= bytes) {
+        *out = b.ptr;
+        return FF_OK;
+    }
+    if (stream_capturing(stream))
+        return set_error(FF_EINVAL, "scratch must grow outside graph capture: run the same call once on this "
+                                    "stream before capturing it");
+    FF_HIP_TRY(hipStreamSynchronize(stream));
+    if (b.ptr) {
+        FF_HIP_TRY(hipFree(b.ptr));
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    const size_t n = (bytes + 4095) / 4096 * 4096;
+    FF_HIP_TRY(hipMalloc(&b.ptr, n));
+    b.bytes = n;
+    *out = b.ptr;
+    return FF_OK;
+}
+
+}  // namespace ff
+
+extern "C" ff_status ff_release_scratch(void)
+{
+    std::lock_guard<std::mutex> lk(ff::g_mutex);
+    for (auto& kv : ff::table()) {
+        if (kv.second.ptr) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(kv.first.first);
+            (void)hipStreamSynchronize(kv.first.second);
+            (void)hipFree(kv.second.ptr);
+            (void)hipSetDevice(cur);
+        }
+    }
+    ff::table().clear();
+    return ff::clear_error();
+}

@@ -1,0 +1,102 @@
+"""Graph-captured pipeline (ff_pipeline_*): every replay equals the eager
+launch sequence bitwise, also after the radiance buffers are rewritten in
+place, with eager library work and synchronisations between replays."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from _helpers import noisy_spectra
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2608_07580_amd as ff  # noqa: E402
+
+KEYS = ("state", "cov", "moments", "rrr", "iters", "status")
+
+
+def _batch(dev, sizes=(70, 1, 333)):
+    scenes, rads = [], []
+    for s, P in enumerate(sizes):
+        atm = scenegen.make_atmosphere(4, s)
+        tab = oracle.band_tables(atm)
+        X = scenegen.config0_states(P, scene=10 + s)
+        scenes.append(ff.Scene(atm))
+        rads.append(torch.from_numpy(noisy_spectra(tab, X, 1, 4, s)).to(dev))
+    return scenes, rads
+
+
+def _same(outs, ref):
+    for o, r in zip(outs, ref):
+        o, r = o.numpy(), r.numpy()
+        for k in KEYS:
+            np.testing.assert_array_equal(o[k], r[k], err_msg=k)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_pipeline_replays_match_eager(warm):
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    scenes, rads = _batch(dev)
+    prior = ff.default_prior(1)
+    opts = ff.default_options(lanes_per_pixel=4)
+    net = None
+    if warm:
+        net = ff.WarmStart(seed=1)
+        net.fit_normalization(ff.generate(scenes[0], prior, 9, 0, 4096)[0])
+        net.train(scenes[0], prior, steps=200, batch=1024, seed=2)
+        torch.cuda.synchronize()          # training runs on the default stream
+    stream = torch.cuda.Stream(device=dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def eager():
+        with torch.cuda.stream(stream):
+            z0s = [net.infer(r, stream=stream) for r in rads] if warm else None
+            outs = ff.retrieve_batch(scenes, rads, prior, z0s=z0s, options=opts, stream=stream)
+        torch.cuda.synchronize()
+        return outs
+
+    pipe = ff.Pipeline(scenes, rads, prior, net=net, options=opts, evals=evals, stream=stream)
+    torch.cuda.synchronize()
+    ref = eager()
+    _same(pipe.outputs, ref)                      # the eager pass inside create
+    n0 = evals.item()
+    assert n0 > 0
+    for rep in range(3):
+        for o in pipe.outputs:                    # clear the outputs with a fill kernel
+            for t in (o.state, o.cov, o.moments, o.rrr):
+                t.fill_(-7.0)
+        torch.cuda.synchronize()
+        pipe.launch()
+        torch.cuda.synchronize()
+        _same(pipe.outputs, ref)
+        eager()                                   # eager library work between replays
+    assert evals.item() == 4 * n0                 # create + three replays
+    # serving pattern: new spectra written into the bound buffers
+    with torch.no_grad():
+        rads[0].mul_(1.01)
+        rads[2].copy_(torch.flip(rads[2], dims=[0]))
+    torch.cuda.synchronize()
+    ref2 = eager()
+    pipe.launch()
+    torch.cuda.synchronize()
+    _same(pipe.outputs, ref2)
+    assert not np.array_equal(ref2[0].numpy()["state"], ref[0].numpy()["state"])
+    pipe.close()
+
+
+def test_pipeline_argument_checks():
+    dev = torch.device("cuda:0")
+    scenes, rads = _batch(dev, sizes=(8,))
+    net = ff.WarmStart(n_in=100, seed=1)                    # inputs != 284 bands
+    with pytest.raises(ff.FirefitError):
+        ff.Pipeline(scenes, rads, ff.default_prior(1), net=net)
+    # the default (null) stream is fine for create and launch
+    pipe = ff.Pipeline(scenes, rads, ff.default_prior(1), stream=torch.cuda.default_stream(dev))
+    ref = pipe.outputs[0].numpy()
+    pipe.launch()
+    torch.cuda.synchronize()
+    for k in KEYS:
+        np.testing.assert_array_equal(pipe.outputs[0].numpy()[k], ref[k])
+    pipe.close()
