@@ -337,9 +337,10 @@ ff_status ff_mlp_train(ff_mlp* mlp, const ff_scene* scene, const ff_prior* prior
 
 /* ------------------------------------------------------------------------
  * Graph-captured pipeline.  The launch sequence of one batch shape --
- * network inference of z0 for every scene (when mlp is not NULL), then the
- * retrieval with fallback -- recorded once into a HIP graph and replayed by
- * one graph launch.  The graph binds every pointer given here (radiance,
+ * network inference of z0 for every scene that has a network (mlps: NULL,
+ * or n_scenes entries, each NULL for the default start), then the retrieval
+ * with fallback -- recorded once into a HIP graph and replayed by one graph
+ * launch.  The graph binds every pointer given here (radiance,
  * outputs, evals counter, scene tables, network weights): rewrite the
  * radiance buffers in place between launches; results land in outs.  z0
  * lives in a buffer the pipeline owns (ff_pipeline_z0).
@@ -350,13 +351,13 @@ ff_status ff_mlp_train(ff_mlp* mlp, const ff_scene* scene, const ff_prior* prior
  * instantiates the graph.  Synchronous.  The network's workspace stays
  * valid for the graph while the pipeline exists (a larger eager use keeps
  * the old buffers alive instead of freeing them); destroy pipelines before
- * their network.  Launch: asynchronous on stream (may be NULL).  Replays of
+ * their networks.  Launch: asynchronous on stream (may be NULL).  Replays of
  * one pipeline must not overlap each other or run concurrently with other
  * uses of the same network (they share buffers).
  * ------------------------------------------------------------------------ */
 typedef struct ff_pipeline ff_pipeline;
 ff_status ff_pipeline_create(const ff_scene* const* scenes, const float* const* radiance_dev,
-                             const int64_t* P, int32_t n_scenes, const ff_prior* prior, const ff_mlp* mlp,
+                             const int64_t* P, int32_t n_scenes, const ff_prior* prior, const ff_mlp* const* mlps,
                              const ff_options* opts, const ff_outputs* outs, unsigned long long* evals_dev,
                              void* stream, ff_pipeline** out);
 ff_status ff_pipeline_launch(ff_pipeline* pipeline, void* stream);

@@ -143,8 +143,8 @@ def lib():
         L.ff_mlp_train.argtypes = [vp, vp, C.POINTER(ffPrior), C.c_int64, C.c_int32, C.c_uint64, C.c_double,
                                    C.c_double, C.c_float, C.c_float, vp, vp]
         L.ff_pipeline_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32,
-                                         C.POINTER(ffPrior), vp, C.POINTER(ffOptions), C.POINTER(ffOutputs), vp, vp,
-                                         C.POINTER(vp)]
+                                         C.POINTER(ffPrior), C.POINTER(vp), C.POINTER(ffOptions),
+                                         C.POINTER(ffOutputs), vp, vp, C.POINTER(vp)]
         L.ff_pipeline_launch.argtypes = [vp, vp]
         L.ff_pipeline_z0.argtypes = [vp]
         L.ff_pipeline_z0.restype = vp
@@ -509,17 +509,20 @@ class WarmStart:
 class Pipeline:
     """Graph-captured (warm start +) retrieval of one batch (ff_pipeline_*).
 
-    The graph binds the radiance tensors, outputs and network given here;
+    The graph binds the radiance tensors, outputs and networks given here;
     rewrite the radiance tensors in place (``rad.copy_(new)``) and call
-    ``launch()`` again.  ``outputs`` is a list of Outputs, one per scene."""
+    ``launch()`` again.  ``outputs`` is a list of Outputs, one per scene.
+    ``net``: one WarmStart for every scene, or a list (entries may be None)."""
 
-    def __init__(self, scenes, radiances, prior: Prior | None = None, net: "WarmStart | None" = None,
+    def __init__(self, scenes, radiances, prior: Prior | None = None, net=None,
                  options: ffOptions | None = None, evals=None, stream=None):
         torch = _torch()
         self.prior = prior or default_prior(MODEL_LOGNORMAL_1)
         self.options = options or default_options()
-        self.scenes, self.radiances, self.net, self.evals = list(scenes), list(radiances), net, evals
+        self.scenes, self.radiances, self.evals = list(scenes), list(radiances), evals
         ns = len(self.scenes)
+        self.nets = list(net) if isinstance(net, (list, tuple)) else [net] * ns
+        assert len(self.nets) == ns
         self.outputs = [allocate_outputs(r.shape[0], self.prior.model, r.device) for r in self.radiances]
         sc = (C.c_void_p * ns)(*[s.handle.value for s in self.scenes])
         rd = (C.c_void_p * ns)(*[r.data_ptr() for r in self.radiances])
@@ -528,7 +531,10 @@ class Pipeline:
         pc = self.prior.to_c()
         self.stream = stream or torch.cuda.current_stream()
         h = C.c_void_p()
-        _check(lib().ff_pipeline_create(sc, rd, Ps, ns, C.byref(pc), None if net is None else net.handle,
+        nets = None
+        if any(n is not None for n in self.nets):
+            nets = (C.c_void_p * ns)(*[None if n is None else n.handle.value for n in self.nets])
+        _check(lib().ff_pipeline_create(sc, rd, Ps, ns, C.byref(pc), nets,
                                         C.byref(self.options), oc, _ptr(evals), _stream_handle(self.stream),
                                         C.byref(h)), "ff_pipeline_create")
         self.handle = h

@@ -5,6 +5,7 @@
 // a serving loop rewrites the radiance buffers in place and relaunches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "ff_internal.hpp"
@@ -17,7 +18,7 @@ struct ff_pipeline {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float* z0 = nullptr;
-    const ff_mlp* mlp = nullptr;      // pinned while the graph exists
+    std::vector<const ff_mlp*> pinned;   // networks whose workspace the graph binds
 };
 
 namespace {
@@ -30,7 +31,7 @@ void release(ff_pipeline* p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->z0) (void)hipFree(p->z0);
     if (p->capture) (void)hipStreamDestroy(p->capture);
-    if (p->mlp) mlp_pin(p->mlp, -1);
+    for (const ff_mlp* m : p->pinned) mlp_pin(m, -1);
     delete p;
 }
 
@@ -38,7 +39,7 @@ void release(ff_pipeline* p)
 
 extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const float* const* radiance_dev,
                                         const int64_t* P, int32_t n_scenes, const ff_prior* prior,
-                                        const ff_mlp* mlp, const ff_options* opts, const ff_outputs* outs,
+                                        const ff_mlp* const* mlps, const ff_options* opts, const ff_outputs* outs,
                                         unsigned long long* evals_dev, void* stream, ff_pipeline** out)
 {
     if (!out) return set_error(FF_EINVAL, "ff_pipeline_create: NULL out");
@@ -54,13 +55,15 @@ extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const flo
         off[i] = total;
         total += P[i];
     }
-    if (mlp) {
+    bool any_net = false;
+    for (int i = 0; mlps && i < n_scenes; ++i) {
+        if (!mlps[i]) continue;
+        any_net = true;
         int n_in = 0, n_out = 0;
-        mlp_dims(mlp, &n_in, &n_out);
+        mlp_dims(mlps[i], &n_in, &n_out);
         if (n_out != n) return set_error(FF_EINVAL, "ff_pipeline_create: network outputs != state size");
-        for (int i = 0; i < n_scenes; ++i)
-            if (scenes[i] && scenes[i]->n_bands != n_in)
-                return set_error(FF_EINVAL, "ff_pipeline_create: network inputs != band count");
+        if (!scenes[i] || scenes[i]->n_bands != n_in)
+            return set_error(FF_EINVAL, "ff_pipeline_create: network inputs != band count");
     }
     auto* p = new ff_pipeline();
     {
@@ -76,11 +79,12 @@ extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const flo
     }
     hipStream_t s = p->capture;
     void* cs = (void*)s;
-    if (mlp) {
-        p->mlp = mlp;
-        mlp_pin(mlp, +1);
+    for (int i = 0; mlps && i < n_scenes; ++i) {
+        if (!mlps[i] || std::find(p->pinned.begin(), p->pinned.end(), mlps[i]) != p->pinned.end()) continue;
+        p->pinned.push_back(mlps[i]);
+        mlp_pin(mlps[i], +1);
     }
-    if (mlp && total > 0) {
+    if (any_net && total > 0) {
         const hipError_t e = hipMalloc(&p->z0, (size_t)total * n * sizeof(float));
         if (e != hipSuccess) {
             release(p);
@@ -88,18 +92,16 @@ extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const flo
         }
     }
     std::vector<const float*> z0s(n_scenes, nullptr);
-    for (int i = 0; i < n_scenes; ++i) z0s[i] = p->z0 ? p->z0 + off[i] * n : nullptr;
+    for (int i = 0; i < n_scenes; ++i) z0s[i] = (p->z0 && mlps && mlps[i]) ? p->z0 + off[i] * n : nullptr;
 
     auto run = [&]() -> ff_status {
-        if (mlp) {
-            for (int i = 0; i < n_scenes; ++i) {
-                if (P[i] == 0) continue;
-                const ff_status st = ff_mlp_infer(mlp, radiance_dev[i], P[i], const_cast<float*>(z0s[i]), cs);
-                if (st != FF_OK) return st;
-            }
+        for (int i = 0; any_net && i < n_scenes; ++i) {
+            if (P[i] == 0 || !z0s[i]) continue;
+            const ff_status st = ff_mlp_infer(mlps[i], radiance_dev[i], P[i], const_cast<float*>(z0s[i]), cs);
+            if (st != FF_OK) return st;
         }
-        return ff_retrieve_batch(scenes, radiance_dev, P, n_scenes, prior, mlp ? z0s.data() : nullptr, opts, outs,
-                                 evals_dev, cs);
+        return ff_retrieve_batch(scenes, radiance_dev, P, n_scenes, prior, any_net ? z0s.data() : nullptr, opts,
+                                 outs, evals_dev, cs);
     };
     // one eager pass sizes every workspace outside capture
     ff_status st = run();

@@ -248,3 +248,48 @@ def ragged_scene_sizes(n_scenes: int = 16, lo: int = 10_000, hi: int = 2_500_000
                        cfg: int = 4) -> np.ndarray:
     """Pixel counts of a ragged multi-scene batch, log-uniform in [lo, hi]."""
     return log_uniform_int(rng_for(cfg, 0, STREAM_PARAMS), lo, hi, n_scenes)
+
+
+# ----------------------------------------------------------------------------
+# Ragged multi-scene batch: 16 scenes, pixel counts log-uniform in
+# [10k, 2.5M]; four atmospheres (one per flight line, scene s uses s % 4);
+# the four smallest scenes are coarse-resolution versions of a 15x finer
+# truth (each coarse pixel is the footprint of 15 x 15 fine pixels, so its
+# temperature distribution is a sub-pixel mixture of the fine-scale draws).
+# ----------------------------------------------------------------------------
+RAGGED_BLOCK = 15
+RAGGED_ATMOSPHERES = 4
+
+
+def config4_layout(n_scenes: int = 16, n_block_averaged: int = 4) -> list[dict]:
+    """Per-scene shape: rows x cols coarse pixels (near-square, rows*cols <=
+    the drawn count), atmosphere id and block size (1 or RAGGED_BLOCK)."""
+    sizes = ragged_scene_sizes(n_scenes)
+    smallest = set(np.argsort(sizes, kind="stable")[:n_block_averaged].tolist())
+    out = []
+    for s, p in enumerate(sizes.tolist()):
+        cols = max(1, int(math.isqrt(int(p))))
+        rows = max(1, int(p) // cols)
+        out.append({"scene": s, "rows": rows, "cols": cols, "pixels": rows * cols,
+                    "atmosphere": s % RAGGED_ATMOSPHERES,
+                    "block": RAGGED_BLOCK if s in smallest else 1})
+    return out
+
+
+def config4_states(spec: dict, fire_fraction: float = 0.03) -> tuple[np.ndarray, np.ndarray]:
+    """Truth of one ragged-batch scene at its finest resolution: (states
+    [rows*block * cols*block, 5], fire mask) in row-major order of the fine
+    grid, clustered fire blobs as in the clustered-fire scene."""
+    r, c = spec["rows"] * spec["block"], spec["cols"] * spec["block"]
+    states = draw_states_lognormal1(rng_for(4, spec["scene"], STREAM_PARAMS), r * c)
+    mask = fire_mask_blobs(rng_for(4, spec["scene"], STREAM_MASK), r, c, fire_fraction).ravel()
+    states[~mask, 0] = 0.0
+    return states, mask
+
+
+def block_footprints(rows: int, cols: int, block: int) -> np.ndarray:
+    """Index map [rows*cols, block*block]: the fine pixels (row-major on the
+    fine grid of rows*block x cols*block) inside each coarse pixel."""
+    fr = np.arange(rows)[:, None, None, None] * block + np.arange(block)[None, None, :, None]
+    fc = np.arange(cols)[None, :, None, None] * block + np.arange(block)[None, None, None, :]
+    return (fr * (cols * block) + fc).reshape(rows * cols, block * block)

@@ -34,7 +34,7 @@ def _same(outs, ref):
             np.testing.assert_array_equal(o[k], r[k], err_msg=k)
 
 
-@pytest.mark.parametrize("warm", [False, True])
+@pytest.mark.parametrize("warm", [False, True, "mixed"])
 def test_pipeline_replays_match_eager(warm):
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
@@ -49,15 +49,18 @@ def test_pipeline_replays_match_eager(warm):
         torch.cuda.synchronize()          # training runs on the default stream
     stream = torch.cuda.Stream(device=dev)
     evals = torch.zeros(1, dtype=torch.int64, device=dev)
+    # one network per scene; "mixed": the middle scene starts from x0
+    nets = None if not warm else [net, None if warm == "mixed" else net, net]
 
     def eager():
         with torch.cuda.stream(stream):
-            z0s = [net.infer(r, stream=stream) for r in rads] if warm else None
+            z0s = None if nets is None else [None if n is None else n.infer(r, stream=stream)
+                                             for n, r in zip(nets, rads)]
             outs = ff.retrieve_batch(scenes, rads, prior, z0s=z0s, options=opts, stream=stream)
         torch.cuda.synchronize()
         return outs
 
-    pipe = ff.Pipeline(scenes, rads, prior, net=net, options=opts, evals=evals, stream=stream)
+    pipe = ff.Pipeline(scenes, rads, prior, net=nets, options=opts, evals=evals, stream=stream)
     torch.cuda.synchronize()
     ref = eager()
     _same(pipe.outputs, ref)                      # the eager pass inside create

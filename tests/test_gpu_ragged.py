@@ -1,0 +1,63 @@
+"""Ragged multi-scene batches with a footprint-averaged (sub-pixel mixture)
+scene: one launch over all scenes matches the oracle per scene, with the
+batch solved in one graph replay equal to the eager batch."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from _helpers import assert_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2608_07580_amd as ff  # noqa: E402
+
+SPECS = [
+    {"scene": 21, "rows": 6, "cols": 9, "pixels": 54, "atmosphere": 0, "block": 15},   # 15x15 footprints
+    {"scene": 22, "rows": 20, "cols": 31, "pixels": 620, "atmosphere": 1, "block": 1},
+    {"scene": 23, "rows": 1, "cols": 3, "pixels": 3, "atmosphere": 2, "block": 1},
+]
+
+
+def _scene_inputs(spec):
+    atm = scenegen.make_atmosphere(4, spec["atmosphere"])
+    tab = oracle.band_tables(atm)
+    states, mask = scenegen.config4_states(spec, fire_fraction=0.3)
+    L = oracle.forward(tab, states, 1)
+    if spec["block"] > 1:
+        idx = scenegen.block_footprints(spec["rows"], spec["cols"], spec["block"])
+        L = L[idx].mean(axis=1)                    # the footprint average of the fine radiance
+        mask = mask[idx].any(axis=1)
+    noise = scenegen.noise_normals(4, spec["scene"], L.shape[0], tab.B)
+    lobs = (L * (1.0 + noise / 300.0)).astype(np.float32)
+    return atm, tab, lobs, mask
+
+
+def test_ragged_batch_with_footprint_averaged_scene():
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    lo, hi, x0 = scenegen.default_prior(1)
+    prior = ff.Prior(1, lo, hi, x0)
+    inputs = [_scene_inputs(s) for s in SPECS]
+    scenes = [ff.Scene(atm) for atm, _, _, _ in inputs]
+    rads = [torch.from_numpy(lobs).to(dev) for _, _, lobs, _ in inputs]
+    opts = ff.default_options(lanes_per_pixel=4)
+    outs = ff.retrieve_batch(scenes, rads, prior, options=opts)
+    torch.cuda.synchronize()
+    for spec, (atm, tab, lobs, mask), o in zip(SPECS, inputs, outs):
+        ref = oracle.retrieve(tab, lobs, 1, lo, hi, x0)
+        g = o.numpy()
+        if spec["block"] > 1:
+            print(f"\n  footprint-averaged scene: {mask.sum()} of {len(mask)} coarse px hold fire; "
+                  f"oracle converged {ref.converged.mean():.3f}")
+        assert_parity(g, ref, min_same=0.95, min_t=0, label=f"scene {spec['scene']} block {spec['block']}")
+    # one graph replay of the same batch equals the eager batch
+    stream = torch.cuda.Stream(device=dev)
+    pipe = ff.Pipeline(scenes, rads, prior, options=opts, stream=stream)
+    pipe.launch()
+    torch.cuda.synchronize()
+    for o, e in zip(pipe.outputs, outs):
+        for k in ("state", "rrr", "iters", "status"):
+            np.testing.assert_array_equal(o.numpy()[k], e.numpy()[k])
+    pipe.close()
