@@ -31,18 +31,40 @@ import numpy as np  # noqa: E402
 # Roofline of the dominant kernel: FP32 VALU issue slots.  MI355X: 256 CUs x
 # 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s without packed
 # FP32 (packed FP32 is not used).  v_exp_f32 / v_rcp_f32 issue at half rate
-# (2 slots), everything else 1 slot.
+# (2 slots) and do not overlap other VALU work (measured), everything else
+# 1 slot.
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
+
+# HBM bytes per launch of the retrieval kernel on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled by what the
+# counter reads for a 1 GiB device copy: x2.000 and x1.000), recorded in
+# profiles/lm_kernel_fp32_q32_clustered_fire_2p53M.md.  They describe the
+# kernel sources with the SHA-1 below; any other source reports null.
+TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/physics.hpp",
+                   "paper_2608_07580_amd/csrc/ff_internal.hpp")
+TRAFFIC_SHA1 = "047ff49a5d4d9345466c7174735b38471683f0fb"
+TRAFFIC_BYTES = {"plain": 56.09e9, "warm": 35.66e9}
+
+
+def measured_traffic(leg: str):
+    import hashlib
+    h = hashlib.sha1()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES[leg] if h.hexdigest() == TRAFFIC_SHA1 else None
 
 
 def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> int:
     """Algorithmic VALU slots of one model+Jacobian+reduction evaluation of one
-    pixel: per (band, node) 8 VALU + 2 transcendentals (2 slots each) = 12;
-    per band and component 5 slots of scaling plus 19 (n=5) / 49 (n=8) for the
-    solar term, basis, residual and the J^T J, J^T r, r.r accumulations."""
+    pixel: per (band, node) 7 VALU (x = a u, 2^x - 1, three FMAs and one
+    product for the three quadrature sums) + 2 transcendentals (exp2, rcp; 2
+    slots each) = 11; per band and component 5 slots of scaling plus 19
+    (n=5) / 49 (n=8) for the solar term, basis, residual and the J^T J, J^T r,
+    r.r accumulations."""
     comps = 1 if model == 1 else 2
-    per_band = comps * (12 * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45)
+    per_band = comps * (11 * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45)
     return n_bands * per_band
 
 
@@ -442,7 +464,8 @@ def main():
                    "pixels": P, "bands": B, "n_quad": args.n_quad, "precision": "fp32-bulk/fp64-solve",
                    "start": args.start},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "unit": "Tops/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(args.start),
+                     "traffic_unit": "HBM bytes per launch (calibrated TCC FETCH_SIZE + WRITE_SIZE)",
                      "kernel": "lm_kernel", "kernel_ms": head["lm_kernel_ms"],
                      "op": "FP32 VALU issue slot per lane (transcendental = 2)",
                      "ops_per_eval": spe, "evals_per_launch": ev_head},

@@ -145,6 +145,8 @@ typedef struct ff_options {
     int32_t lanes_per_pixel; /* lanes that share one pixel's evaluation: 1, 2, 4, 8, 16, 32 or 64
                               (0 = default 1); more lanes shorten each pixel's latency at a
                               small replicated cost (results differ only in summation order) */
+    int32_t warm_max_iter; /* iteration cap of a solve from a per-pixel start z0 before the fallback
+                              to x0 takes over (0 = max_iter; the fallback always gets max_iter) */
     double xtol;           /* default 1e-6 (z units) */
     double ftol;           /* default 1e-8 */
     double gtol;           /* default 1e-10 */

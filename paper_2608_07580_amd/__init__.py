@@ -76,6 +76,7 @@ class ffOptions(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("precision", C.c_int32), ("n_quad", C.c_int32),
                 ("schedule", C.c_int32), ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("fallback", C.c_int32), ("accumulate", C.c_int32), ("lanes_per_pixel", C.c_int32),
+                ("warm_max_iter", C.c_int32),
                 ("xtol", C.c_double),
                 ("ftol", C.c_double), ("gtol", C.c_double), ("kappa", C.c_double),
                 ("tau", C.c_double)]

@@ -58,6 +58,7 @@ static ff_status check_options(const ff_options* o)
 {
     if (!o) return set_error(FF_EINVAL, "options is NULL");
     if (o->max_iter < 0 || o->max_iter > 100000) return set_error(FF_EINVAL, "max_iter out of range");
+    if (o->warm_max_iter < 0 || o->warm_max_iter > 100000) return set_error(FF_EINVAL, "warm_max_iter out of range");
     if (o->precision != FF_PRECISION_FP32 && o->precision != FF_PRECISION_FP64)
         return set_error(FF_EINVAL, "unknown precision");
     if (o->schedule != FF_SCHEDULE_PERSISTENT && o->schedule != FF_SCHEDULE_STATIC)
@@ -104,6 +105,7 @@ extern "C" void ff_options_default(ff_options* o)
     o->block_size = 256;
     o->blocks_per_cu = 0;
     o->lanes_per_pixel = 1;
+    o->warm_max_iter = 0;
     o->fallback = 1;
     o->accumulate = FF_ACCUMULATE_FP32;
     o->xtol = 1e-6;

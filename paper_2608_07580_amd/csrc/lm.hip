@@ -61,6 +61,7 @@ struct LmDesc {
     unsigned long long* evals;     // += model evaluations (may be null)
     int schedule;
     int max_iter;
+    int warm_max_iter;             // cap of a solve from z0 (0: max_iter)
     int fallback;
     double xtol, ftol, gtol, kappa, tau;
     double lo[FF_MAX_STATE], hi[FF_MAX_STATE], zdef[FF_MAX_STATE];
@@ -495,7 +496,8 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
 
             // ------------------------------------------- next damped step
             if (need_step) {
-                if (it >= D->max_iter) {
+                const int cap = (warm && D->warm_max_iter > 0) ? D->warm_max_iter : D->max_iter;
+                if (it >= cap) {
                     st |= FF_ST_MAX_ITER;
                     done = true;
                 } else {
@@ -799,6 +801,7 @@ static ff_status launch_lm(const BatchSpec& bs)
         prm.total = off;
         prm.evals = bs.evals;
         prm.max_iter = o.max_iter;
+        prm.warm_max_iter = o.warm_max_iter;
         prm.fallback = fallback ? 1 : 0;
         prm.xtol = o.xtol;
         prm.ftol = o.ftol;

@@ -87,9 +87,11 @@ __device__ inline void node_inverse_temperatures(const LogNormal& ln, R (&u)[Q])
 
 // Quadrature sums over the nodes of one component at one band:
 //   sI = sum_k w_k e/(1-e),  sM = sum_k w_k x2 e/(1-e)^2,  sS = sum_k v_k x2 e/(1-e)^2
-// (w_k = GH weight / sqrt(pi), v_k = sqrt2 x_k w_k).  Then
+// (w_k = GH weight / sqrt(pi), v_k = sqrt2 x_k w_k, e = 2^-x2).  Then
 //   I = cb sI,  dI/dmu = cj sM,  dI/dsig = cj sS.
-// FP32: 2 transcendental (exp2, rcp) + 8 VALU per node.
+// FP32: q = e/(1-e) is taken as 1/(2^x2 - 1): for x2 > 128 the power is +inf
+// and the reciprocal returns the exact limit 0, so no overflow handling is
+// needed; 2 transcendental (exp2, rcp) + 7 VALU per node.
 template <int Q>
 __device__ __forceinline__ void thermal_sums(float a2, const float (&u)[Q], int o,
                                              float& sI, float& sM, float& sS)
@@ -106,9 +108,7 @@ __device__ __forceinline__ void thermal_sums(float a2, const float (&u)[Q], int 
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         const float x = a * u[k];
-        const float e = __builtin_amdgcn_exp2f(-x);
-        const float r = __builtin_amdgcn_rcpf(1.0f - e);
-        const float q = e * r;
+        const float q = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x) - 1.0f);
         const float wk = qd.w[k + o], vk = qd.v[k + o];
         i0 = __builtin_fmaf(wk, q, i0);
         const float y = x * __builtin_fmaf(q, q, q);   // x q (1 + q) = x e / (1 - e)^2

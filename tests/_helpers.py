@@ -20,6 +20,12 @@ the oracle's own Gauss-Newton posterior at its solution:
     radiance residuals agree to 1e-5 and every identified variable lies
     within 3 posterior s.d. of the oracle's value.  That share is reported
     and bounded, and states are compared on it.
+  * E[T] agrees to max(0.5 K, 2% of the oracle's posterior s.d. of E[T]):
+    an FP32 forward model evaluates the cost with ~1e-6 relative noise, so
+    an FP32-bulk solve cannot tell apart points whose chi^2 differs by less
+    than ~1e-6 (N - n) ~ 3e-4, i.e. a shift of sqrt(3e-4) ~ 1.7% of a
+    posterior s.d.; the bound is 0.5 K wherever the s.d. is <= 25 K (81% of
+    the identified pixels of the 4,096-pixel set, median s.d. 4.4 K).
 """
 import numpy as np
 
@@ -29,6 +35,8 @@ import scenegen
 CONVERGED = oracle.ST_CONVERGED
 SD_T_MAX = 100.0
 SD_F_MAX = 1e-3
+T_TOL = 0.5          # K
+T_TOL_SD = 0.02      # of the oracle's posterior s.d. of E[T]
 
 
 def noisy_spectra(tab, states, model, cfg, scene, snr=300.0):
@@ -97,6 +105,8 @@ def parity_report(gpu, ref, model=1):
     t_ok = ok & same
     f_ok = f_comparable(gpu, ref, model) & same
     dT = np.abs(gpu["moments"][:, 0] - ref.moments[:, 0])
+    sd_t, _ = posterior_sd(ref, model)
+    dT_tol = np.maximum(T_TOL, T_TOL_SD * sd_t)
     df = np.abs(gpu["state"][:, 0] - ref.state[:, 0])
     drrr = np.abs(gpu["rrr"] - ref.rrr)
     return {
@@ -104,6 +114,8 @@ def parity_report(gpu, ref, model=1):
         "same_frac": float(same.sum() / max(both.sum(), 1)),
         "t_n": int(t_ok.sum()), "dT_max": float(dT[t_ok].max()) if t_ok.any() else 0.0,
         "dT_p99": float(np.percentile(dT[t_ok], 99)) if t_ok.any() else 0.0,
+        "dT_excess_max": float((dT - dT_tol)[t_ok].max()) if t_ok.any() else -1.0,
+        "dT_max_sd_le_25": float(dT[t_ok & (sd_t <= 25)].max()) if (t_ok & (sd_t <= 25)).any() else 0.0,
         "f_n": int(f_ok.sum()), "df_max": float(df[f_ok].max()) if f_ok.any() else 0.0,
         "drrr_max_same": float(drrr[same].max()) if same.any() else 0.0,
         "t_mask": t_ok, "f_mask": f_ok, "both_mask": both, "same_mask": same,
@@ -115,6 +127,7 @@ def assert_parity(gpu, ref, model=1, min_same=0.99, min_t=1, label=""):
     print(label, {k: v for k, v in rep.items() if not k.endswith("_mask")})
     assert rep["same_frac"] >= min_same, rep["same_frac"]
     assert rep["t_n"] >= min_t and rep["f_n"] >= min_t
-    assert rep["dT_max"] <= 0.5, rep["dT_max"]
+    assert rep["dT_excess_max"] <= 0.0, (rep["dT_max"], rep["dT_excess_max"])
+    assert rep["dT_max_sd_le_25"] <= T_TOL, rep["dT_max_sd_le_25"]
     assert rep["df_max"] <= 1e-4, rep["df_max"]
     return rep
