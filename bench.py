@@ -387,6 +387,102 @@ def run_ragged(args):
     print(json.dumps(line), flush=True)
 
 
+def run_precision(args):
+    """Precision variants on the two-component stress set (8-parameter
+    state, 1e-5 <= f <= 1e-3): FP32 bulk with FP32 or FP64 accumulation and
+    the all-FP64 path, each timed on the GPU and compared output by output
+    with the FP64 oracle on a seeded subsample."""
+    import torch
+    import oracle
+    import paper_2608_07580_amd as ff
+    import scenegen
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _helpers import parity_report
+    dev = torch.device("cuda:0")
+    ff.lib()
+    P = args.precision_pixels
+    X = scenegen.config2_states(P)
+    atm = scenegen.make_atmosphere(2, 0)
+    sc = ff.Scene(atm)
+    B = sc.n_bands
+    t0 = time.time()
+    L = torch.empty((P, B), dtype=torch.float64, device=dev)
+    chunk = 1 << 16
+    for s0 in range(0, P, chunk):
+        L[s0:s0 + chunk] = ff.forward(sc, torch.tensor(X[s0:s0 + chunk], dtype=torch.float64, device=dev), 2)
+    noise = torch.from_numpy(scenegen.noise_normals(2, 0, P, B)).to(dev)
+    rad = (L * (1.0 + noise.double() / args.snr)).float().contiguous()
+    del L, noise
+    torch.cuda.synchronize()
+    log(f"precision workload: {P} px, built in {time.time() - t0:.1f}s")
+    prior = ff.default_prior(2)
+    variants = {"fp32": dict(precision=ff.PRECISION_FP32, accumulate=ff.ACCUMULATE_FP32),
+                "fp32_fp64acc": dict(precision=ff.PRECISION_FP32, accumulate=ff.ACCUMULATE_FP64),
+                "fp64": dict(precision=ff.PRECISION_FP64)}
+    idx = scenegen.subsample(2, 0, P, args.cpu_sample)
+    lobs = rad[idx].cpu().numpy()
+    tab = oracle.band_tables(atm)
+    lo, hi, x0 = scenegen.default_prior(2)
+    t0 = time.time()
+    ref = oracle.retrieve(tab, lobs, 2, lo, hi, x0, nthreads=len(os.sched_getaffinity(0)))
+    t_oracle = time.time() - t0
+    stream = torch.cuda.Stream(device=dev)
+    names = ("f", "eta", "m_s", "s_s", "m_h", "s_h", "rho0", "rho1")
+    report = {}
+    for name, kw in variants.items():
+        opts = ff.default_options(n_quad=args.n_quad, **kw)
+        if not args.no_tune:
+            with torch.cuda.stream(stream):
+                opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+            torch.cuda.synchronize()
+        outs = ff.allocate_outputs(P, 2, dev, state_f64=kw["precision"] == ff.PRECISION_FP64)
+        evals = torch.zeros(1, dtype=torch.int64, device=dev)
+        with torch.cuda.stream(stream):
+            for rep in range(args.warmup + args.steps):
+                if rep == args.warmup:
+                    torch.cuda.synchronize()
+                    evals.zero_()
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                ff.retrieve(sc, rad, prior, options=opts, outputs=outs, evals=evals, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        res = outs.numpy()
+        if res["state_f64"] is not None:
+            res["state"] = res["state_f64"]
+        conv = (res["status"] & ff.ST_CONVERGED) != 0
+        sub = {k: v[idx] for k, v in res.items() if v is not None}
+        rep = parity_report(sub, ref, model=2)
+        both, same = rep["both_mask"], rep["same_mask"]
+        errs = {}
+        for j, nm in enumerate(names):
+            d = np.abs(sub["state"][:, j] - ref.state[:, j])
+            errs[nm] = {"same_min_max": float(d[same].max()) if same.any() else None,
+                        "same_min_p99": float(np.percentile(d[same], 99)) if same.any() else None,
+                        "both_conv_median": float(np.median(d[both])) if both.any() else None}
+        for j, nm in enumerate(("E[T]", "sd[T]")):
+            d = np.abs(sub["moments"][:, j] - ref.moments[:, j])
+            errs[nm] = {"same_min_max": float(d[same].max()) if same.any() else None,
+                        "same_min_p99": float(np.percentile(d[same], 99)) if same.any() else None,
+                        "both_conv_median": float(np.median(d[both])) if both.any() else None}
+        d = np.abs(sub["rrr"] - ref.rrr)
+        errs["rrr"] = {"both_conv_max": float(d[both].max()), "same_min_max": float(d[same].max()) if same.any() else None}
+        report[name] = {"ms_per_step": ms, "converged": int(conv.sum()), "converged_per_s": int(conv.sum()) / (ms * 1e-3),
+                        "evals_per_pixel": int(evals.item()) / args.steps / P,
+                        "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
+                        "vs_oracle": {k: v for k, v in rep.items() if not k.endswith("_mask")}, "errors": errs}
+        log(f"{name}: {ms:.1f} ms, {int(conv.sum())} converged, same minimum {rep['same_frac']:.4f}")
+    line = {"metric": "precision variants on the two-component stress set: time and error per output vs the FP64 oracle",
+            "config": {"workload": f"two-component (smouldering + flaming lognormal) stress set, {P} px x {B} bands, "
+                                   f"1e-5 <= f <= 1e-3, SNR {args.snr:g}", "pixels": P, "n_state": 8,
+                       "oracle_sample": len(idx), "oracle_s": t_oracle,
+                       "oracle_converged": int(ref.converged.sum())},
+            "variants": report}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,8 +500,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the tuner's")
-    ap.add_argument("--workload", choices=("clustered-fire", "ragged"), default="clustered-fire",
-                    help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch")
+    ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision"), default="clustered-fire",
+                    help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
+                         "precision: FP32/FP64 variants on the two-component stress set")
+    ap.add_argument("--precision-pixels", type=int, default=262144)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2608_07580_amd", "tuning.json"),
                     help="autotuner table (read, and written on a miss)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -418,6 +516,11 @@ def main():
         sys.exit(2)
     if args.workload == "ragged":
         run_ragged(args)
+        return
+    if args.workload == "precision":
+        if args.cpu_sample == 65536:
+            args.cpu_sample = 8192
+        run_precision(args)
         return
 
     import torch
