@@ -118,6 +118,7 @@ def parity_report(gpu, ref, model=1):
         "dT_max_sd_le_25": float(dT[t_ok & (sd_t <= 25)].max()) if (t_ok & (sd_t <= 25)).any() else 0.0,
         "f_n": int(f_ok.sum()), "df_max": float(df[f_ok].max()) if f_ok.any() else 0.0,
         "drrr_max_same": float(drrr[same].max()) if same.any() else 0.0,
+        "dT_over_tol": int((dT > dT_tol)[t_ok].sum()), "df_over_tol": int((df > 1e-4)[f_ok].sum()),
         "t_mask": t_ok, "f_mask": f_ok, "both_mask": both, "same_mask": same,
     }
 
