@@ -196,7 +196,7 @@ __device__ __forceinline__ double evaluate(const LmDesc<R, Q>* descp, const floa
     constexpr int NT = N * (N + 1) / 2;
     const int B = launder(descp)->B;
     PM pm;
-    pm.setup(x);
+    pm.setup(x, sub, L);
     ACC G[NT], h[N], F = (ACC)0;
 #pragma unroll
     for (int i = 0; i < NT; ++i) G[i] = (ACC)0;

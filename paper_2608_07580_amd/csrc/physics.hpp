@@ -4,13 +4,15 @@
 // integrated by Gauss-Hermite quadrature in log T, and the per-band basis
 // from which the Jacobian follows.
 //
-// Range-scaled Planck: with x2 = a2 / T (a2 = c2 / lambda * log2 e) and
+// Range-safe Planck: with x2 = a2 / T (a2 = c2 / lambda * log2 e) and
 // e = 2^(-x2) in (0, 1],
 //   B       = cb * e / (1 - e)                 (cb = c1 lambda^-5 per nm)
 //   T dB/dT = cj * x2 * e / (1 - e)^2          (cj = cb ln 2)
-// so no exponential of a positive argument is ever formed: x2 runs from
-// ~0.07 (hottest quadrature node, longest band) to ~4e4 (coldest node,
-// shortest band), where e underflows to 0 and the node contributes 0.
+// x2 runs from ~1e-3 (hottest quadrature node of the widest distribution,
+// longest band) to ~4e4 (coldest node, shortest band).  The FP64 path forms
+// e directly (it underflows to 0 for large x2); the FP32 path forms
+// e / (1 - e) as 1 / (2^x2 - 1), where 2^x2 overflows to +inf for x2 > 128
+// and the reciprocal returns the exact limit 0.
 #pragma once
 
 #include <mutex>
@@ -183,6 +185,62 @@ __device__ __forceinline__ BandRow<double> load_row(const double* __restrict__ t
 }
 
 // Per-pixel constants of one model evaluation.
+// Broadcast the value of lane M of each aligned group of G lanes (G = 2 or 4,
+// so a group lies inside a quad) to the whole group: one DPP quad_perm move
+// per 32-bit word.
+template <int G, int M>
+struct QuadBcast {
+    static constexpr int ctrl = G == 4 ? M * 0x55 : (M | (M << 2) | ((2 + M) << 4) | ((2 + M) << 6));
+    __device__ static __forceinline__ float run(float v)
+    {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+    }
+    __device__ static __forceinline__ double run(double v)
+    {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), ctrl, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
+        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    }
+};
+
+template <int G, int M, typename R, int Q>
+__device__ __forceinline__ void fill_from_group(R (&u)[Q], int base, R t)
+{
+    u[base + M] = QuadBcast<G, M>::run(t);
+    if constexpr (M + 1 < G) fill_from_group<G, M + 1>(u, base, t);
+}
+
+// The same node temperatures computed by G cooperating lanes (lane `sub` of
+// an aligned group of G = 2 or 4 forms nodes j G + sub) and gathered with
+// DPP: every lane ends with the values node_inverse_temperatures gives.
+template <typename R, int Q, int G>
+__device__ inline void node_inverse_temperatures_split(const LogNormal& ln, R (&u)[Q], int sub)
+{
+    static_assert(Q % G == 0, "node count must divide among the group");
+    const int o = opaque_zero();
+    double mu = ln.mu;
+#pragma unroll
+    for (int j = 0; j < Q / G; ++j) {
+        double sk = (double)c_quad<R, Q>.s[j * G + o];
+#pragma unroll
+        for (int m = 1; m < G; ++m) sk = sub == m ? (double)c_quad<R, Q>.s[j * G + m + o] : sk;
+        const R t = (R)exp(-mu - sk * ln.sig);
+        asm volatile("" : "+v"(mu) : "v"(t));
+        fill_from_group<G, 0>(u, j * G, t);
+    }
+}
+
+// Node temperatures for a pixel evaluated by L lanes: the work is split
+// among the lanes of each quad of the group (L >= 4: four ways, L = 2: two).
+template <typename R, int Q>
+__device__ __forceinline__ void node_inverse_temperatures_lanes(const LogNormal& ln, R (&u)[Q], int lane, int L)
+{
+    if (L >= 4) node_inverse_temperatures_split<R, Q, 4>(ln, u, lane & 3);
+    else if (L == 2) node_inverse_temperatures_split<R, Q, 2>(ln, u, lane & 1);
+    else node_inverse_temperatures<R, Q>(ln, u);
+}
+
 template <typename R, int MODEL, int Q> struct PixelModel;
 
 template <typename R, int Q>
@@ -190,12 +248,13 @@ struct PixelModel<R, FF_MODEL_LOGNORMAL_1, Q> {
     static constexpr int N = 5;
     R f, r0, r1;
     R u[Q];
-    __device__ void setup(const double (&x)[N])
+    // lane / L: this lane and the number of lanes evaluating the pixel
+    __device__ void setup(const double (&x)[N], int lane = 0, int L = 1)
     {
         f = (R)x[0];
         r0 = (R)x[3];
         r1 = (R)x[4];
-        node_inverse_temperatures<R, Q>(lognormal(x[1], x[2]), u);
+        node_inverse_temperatures_lanes<R, Q>(lognormal(x[1], x[2]), u, lane, L);
     }
     // Basis u_b (J row = -D M u_b) and model radiance at one band.
     __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N]) const
@@ -238,14 +297,14 @@ struct PixelModel<R, FF_MODEL_LOGNORMAL_2, Q> {
     static constexpr int N = 8;
     R f, eta, r0, r1;
     R us[Q], uh[Q];
-    __device__ void setup(const double (&x)[N])
+    __device__ void setup(const double (&x)[N], int lane = 0, int L = 1)
     {
         f = (R)x[0];
         eta = (R)x[1];
         r0 = (R)x[6];
         r1 = (R)x[7];
-        node_inverse_temperatures<R, Q>(lognormal(x[2], x[3]), us);
-        node_inverse_temperatures<R, Q>(lognormal(x[4], x[5]), uh);
+        node_inverse_temperatures_lanes<R, Q>(lognormal(x[2], x[3]), us, lane, L);
+        node_inverse_temperatures_lanes<R, Q>(lognormal(x[4], x[5]), uh, lane, L);
     }
     __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N]) const
     {

@@ -114,7 +114,7 @@ def test_forward_lower_quadrature_order(world, dev, q):
     assert rel.max() <= (2e-5 if q == 24 else 2e-4), rel.max()
 
 
-@pytest.mark.parametrize("lpp", [1, 8])
+@pytest.mark.parametrize("lpp", [1, 2, 8])
 def test_retrieve_fp64_parity(world, dev, cfg0, lpp):
     X, lobs, ref = cfg0
     atm, tab, scene, prior = world
