@@ -17,6 +17,7 @@
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 namespace ff {
 
@@ -66,13 +67,32 @@ struct EpiArgs {
     int ldh;
 };
 
+// GELU in its tanh form, evaluated as x * sigmoid(2u) (equal to
+// 0.5 x (1 + tanh u) with u = sqrt(2/pi) (x + 0.044715 x^3)): one exp2 and one
+// reciprocal; for large |u| the power saturates to 0 or +inf and the
+// reciprocal to 1 or 0, the exact limits.  With r = sigmoid(2u):
+// 1 + tanh u = 2 r and 1 - tanh^2 u = 4 r (1 - r).
+__device__ __forceinline__ float gelu_r(float x, float& x2)
+{
+    const float c2 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;   // -2 sqrt(2/pi) log2 e
+    x2 = x * x;
+    const float u = x * __builtin_fmaf(0.044715f, x2, 1.0f);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(c2 * u));
+}
+
 __device__ __forceinline__ float gelu_t(float x, float& dgelu)
 {
-    const float c = 0.7978845608028654f;  // sqrt(2 / pi)
-    const float a = 0.044715f;
-    const float t = tanhf(c * (x + a * x * x * x));
-    dgelu = 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * a * x * x);
-    return 0.5f * x * (1.0f + t);
+    float x2;
+    const float r = gelu_r(x, x2);
+    const float c = 0.7978845608028654f;   // sqrt(2 / pi)
+    dgelu = r + 2.0f * x * r * (1.0f - r) * c * __builtin_fmaf(3.0f * 0.044715f, x2, 1.0f);
+    return x * r;
+}
+
+__device__ __forceinline__ float gelu_only(float x)
+{
+    float x2;
+    return x * gelu_r(x, x2);
 }
 
 // Store one accumulator element through the epilogue EPI.
@@ -81,8 +101,7 @@ __device__ __forceinline__ void epilogue_store(int m, int n, float v, const EpiA
 {
     if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_GELU_NOH) {
         const float h = v + ep.bias[n];
-        float dg;
-        const float g = gelu_t(h, dg);
+        const float g = gelu_only(h);
         if (EPI == EPI_FWD_GELU) ep.outf[(size_t)m * ep.ldof + n] = h;
         ep.outb[(size_t)m * ep.ldob + n] = (__bf16)g;
     } else if (EPI == EPI_FWD_LINEAR) {
@@ -265,8 +284,160 @@ gemm_nt_128(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, 
     }
 }
 
+// Forward-pass GEMM with direct-to-LDS loads (global_load_lds_dwordx4):
+// 128x128 tile, four waves of 64x64 each as 2x2 v_mfma_f32_32x32x16_bf16
+// tiles (on gfx950 the 32x32x16 form sustains twice the rate of 16x16x32,
+// measured 2.3 vs 1.3 PFLOP/s, and reads half the operand bytes per flop);
+// each k slice
+// (32 wide) is copied by the load unit straight into LDS without passing
+// through registers, three slices in flight (ring of three LDS stages, one
+// barrier per slice).  A wave's load writes 1 KB of LDS at M0 + 16 * lane,
+// i.e. 16 rows of 64 B; lane L takes row L / 4 of its block and 16-byte
+// chunk (L % 4) ^ ((row >> 1) & 3), so the chunks of a row are stored
+// swizzled and the 16-byte operand reads of 8 consecutive rows hit disjoint
+// banks.  Rows m >= Ml load row Ml - 1 (in bounds; their results are not
+// stored).  Requires N % 128 == 0, K % 32 == 0, Ml >= 1.
+// XCD-aware tile order: the grid is 1-D and the hardware hands consecutive
+// workgroup ids to the 8 XCDs in turn, so id g works on tile
+// (g % 8) * per_xcd + g / 8 -- each XCD takes a contiguous run of tiles
+// (all column tiles of its row blocks), and an activation row block is
+// fetched into one L2 instead of four.
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+constexpr int kLdsStages = 3;
+constexpr int kXcds = 8;   // XCDs of an MI355X
+
+template <int VM>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    // s_waitcnt with vmcnt = VM and the other counters at their maximum
+    __builtin_amdgcn_s_waitcnt((VM & 0xF) | ((VM >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(kGemmThreads)
+gemm_nt_lds(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, const __bf16* __restrict__ B,
+            int ldb, EpiArgs ep)
+{
+    // one LDS object per stage, so the compiler can tell a stage being read
+    // from the stages whose loads are still in flight
+    __shared__ __attribute__((aligned(1024))) __bf16 A0[kFM * 32], A1[kFM * 32], A2[kFM * 32];
+    __shared__ __attribute__((aligned(1024))) __bf16 B0[kFN * 32], B1[kFN * 32], B2[kFN * 32];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 1, wn = w & 1;
+    const int n_tiles_n = N / kFN;
+    const int n_tiles = n_tiles_n * ((M + kFM - 1) / kFM);
+    const int per_xcd = (n_tiles + kXcds - 1) / kXcds;
+    const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+    if (tile >= n_tiles) return;
+    const int m0 = (tile / n_tiles_n) * kFM, n0 = (tile % n_tiles_n) * kFN;
+    const __bf16* ga[2];
+    const __bf16* gb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = 32 * w + 16 * h + (lane >> 2);
+        const int c = (lane & 3) ^ ((r >> 1) & 3);
+        const int m = min(m0 + r, Ml - 1);
+        ga[h] = A + (size_t)m * lda + 8 * c;
+        gb[h] = B + (size_t)(n0 + r) * ldb + 8 * c;
+    }
+    auto issue = [&](__bf16* as, __bf16* bs, int k0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row0 = 32 * w + 16 * h;
+            __builtin_amdgcn_global_load_lds((const void*)(ga[h] + k0), (lds_ptr_t)(as + row0 * 32), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(gb[h] + k0), (lds_ptr_t)(bs + row0 * 32), 16, 0, 0);
+        }
+    };
+    // 32x32x16 operand layout: lane l holds row (A) / column (B) l % 32 and
+    // k = 8 (l / 32) + 0..7 of a 16-wide k half; result element e of lane l
+    // is D[8 (e / 4) + 4 (l / 32) + e % 4][l % 32]
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+    int ao[4], bo[4];   // element offsets of this lane's operand chunks inside a stage: [tile * 2 + k half]
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) {
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh) {
+            const int ra = wm * 64 + ti * 32 + (lane & 31);
+            const int rb = wn * 64 + ti * 32 + (lane & 31);
+            const int c = 2 * kh + (lane >> 5);
+            ao[ti * 2 + kh] = ra * 32 + ((c ^ ((ra >> 1) & 3)) * 8);
+            bo[ti * 2 + kh] = rb * 32 + ((c ^ ((rb >> 1) & 3)) * 8);
+        }
+    }
+    auto compute = [&](const __bf16* as, const __bf16* bs) {
+        // The eight operand reads are issued (and waited for) in one asm
+        // block: the slice they read is complete by the caller's vmcnt wait
+        // and barrier, while the compiler, unable to tell LDS stages apart,
+        // would otherwise wait for every load still in flight.
+        typedef __attribute__((address_space(3))) const __bf16* lds_cptr_t;
+        const unsigned la = (unsigned)(uintptr_t)(lds_cptr_t)as, lb = (unsigned)(uintptr_t)(lds_cptr_t)bs;
+        bf16x8_t a[4], b[4];
+        asm volatile(
+            "ds_read_b128 %0, %8\n\t"
+            "ds_read_b128 %1, %9\n\t"
+            "ds_read_b128 %2, %10\n\t"
+            "ds_read_b128 %3, %11\n\t"
+            "ds_read_b128 %4, %12\n\t"
+            "ds_read_b128 %5, %13\n\t"
+            "ds_read_b128 %6, %14\n\t"
+            "ds_read_b128 %7, %15\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=v"(a[0]), "=v"(a[1]), "=v"(a[2]), "=v"(a[3]), "=v"(b[0]), "=v"(b[1]), "=v"(b[2]), "=v"(b[3])
+            : "v"(la + 2u * ao[0]), "v"(la + 2u * ao[1]), "v"(la + 2u * ao[2]), "v"(la + 2u * ao[3]),
+              "v"(lb + 2u * bo[0]), "v"(lb + 2u * bo[1]), "v"(lb + 2u * bo[2]), "v"(lb + 2u * bo[3])
+            : "memory");
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ti * 2 + kh], b[tj * 2 + kh],
+                                                                           acc[ti][tj], 0, 0, 0);
+    };
+    // slice kt lives in stage kt % 3; at step kt: wait for slice kt, barrier
+    // (everyone is done with slice kt - 1, whose stage slice kt + 2 reuses),
+    // issue slice kt + 2, compute slice kt
+    auto step = [&](int kt, int KT, __bf16* as, __bf16* bs, __bf16* an, __bf16* bn) {
+        if (kt + 1 < KT) wait_vmcnt<4>();
+        else wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        if (kt + 2 < KT) issue(an, bn, (kt + 2) * 32);
+        compute(as, bs);
+    };
+    const int KT = K / 32;
+    issue(A0, B0, 0);
+    if (KT > 1) issue(A1, B1, 32);
+    for (int kt = 0; kt < KT; kt += 3) {
+        step(kt, KT, A0, B0, A2, B2);
+        if (kt + 1 < KT) step(kt + 1, KT, A1, B1, A0, B0);
+        if (kt + 2 < KT) step(kt + 2, KT, A2, B2, A1, B1);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) {
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+            const int n = n0 + wn * 64 + tj * 32 + (lane & 31);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int m = m0 + wm * 64 + ti * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                if (m < M) epilogue_store<EPI>(m, n, acc[ti][tj][e], ep);
+            }
+        }
+    }
+}
+
 // u_b = (ln max(L_b, floor) - mean_b) * inv_std_b, zero-padded to kin columns
-// (one element per thread; P * kin < 2^31)
+// (one element per thread; P * kin < 2^31).  ln from the hardware log2
+// (v_log_f32, ~1 ulp): the feature is rounded to BF16 (8 significant bits).
 __global__ void features_kernel(const float* __restrict__ L, int P, int n_in, int kin,
                                 const float* __restrict__ mean, const float* __restrict__ inv_std,
                                 float floor_v, __bf16* __restrict__ X)
@@ -278,7 +449,7 @@ __global__ void features_kernel(const float* __restrict__ L, int P, int n_in, in
     float u = 0.f;
     if (b < n_in) {
         const float v = L[(size_t)p * n_in + b];
-        u = (logf(fmaxf(v, floor_v)) - mean[b]) * inv_std[b];
+        u = (__builtin_amdgcn_logf(fmaxf(v, floor_v)) * 0.6931471805599453f - mean[b]) * inv_std[b];
     }
     X[i] = (__bf16)u;
 }
@@ -573,7 +744,13 @@ void gemm_fwd(int M, int N, int K, const __bf16* A, int lda, const __bf16* B, in
               hipStream_t s)
 {
     dim3 grid((unsigned)(N / kFN), (unsigned)cdiv(M, kFM));
-    hipLaunchKernelGGL((gemm_nt_128<EPI>), grid, dim3(kGemmThreads), 0, s, M, N, M, K, A, lda, B, ldb, ep);
+    if (K % 32 == 0 && M >= 1) {
+        const int64_t tiles = (int64_t)(N / kFN) * cdiv(M, kFM);
+        const unsigned blocks = (unsigned)(cdiv(tiles, kXcds) * kXcds);
+        hipLaunchKernelGGL((gemm_nt_lds<EPI>), dim3(blocks), dim3(kGemmThreads), 0, s, M, N, M, K, A, lda, B, ldb,
+                           ep);
+    } else
+        hipLaunchKernelGGL((gemm_nt_128<EPI>), grid, dim3(kGemmThreads), 0, s, M, N, M, K, A, lda, B, ldb, ep);
 }
 
 // forward pass of R rows of features already in m->X; keep_h: store the
