@@ -219,8 +219,12 @@ ff_status ff_forward(const ff_scene* scene, int32_t model, int32_t precision, in
  * from prior->x0.  With z0_dev and opts->fallback, pixels whose solve from
  * z0 does not converge are solved again from x0 (FF_ST_USED_FALLBACK).
  * evals_dev: optional uint64 counter that receives += the number of model
- * evaluations performed (NULL to skip).  Asynchronous on stream; internal
- * queue counters are allocated stream-ordered. */
+ * evaluations performed (NULL to skip).  Asynchronous on stream.  The
+ * queue counter and launch descriptor live in a library-owned scratch
+ * buffer per (device, stream), allocated on the first call on that stream
+ * (which synchronizes it) and reused by later calls, so calls ordered on one
+ * stream allocate nothing; calls on one stream must be ordered (they share
+ * that buffer).  See ff_release_scratch. */
 ff_status ff_retrieve_scene(const ff_scene* scene, const float* radiance_dev, int64_t P,
                             const ff_prior* prior, const float* z0_dev, const ff_options* opts,
                             const ff_outputs* out, unsigned long long* evals_dev, void* stream);
@@ -368,8 +372,10 @@ void ff_pipeline_destroy(ff_pipeline* pipeline);
 
 /* Retrieval launches use a library-owned scratch buffer per (device,
  * stream) that only grows (so that repeated calls allocate nothing and can
- * be captured); this frees them all after synchronizing their streams.
- * Call only when no library work is in flight. */
+ * be captured); this frees them all after synchronizing each device that
+ * holds one.  Call only when no library work is in flight.  Destroy a
+ * stream only after its retrieval work has completed: a new stream that
+ * receives the same handle reuses the buffer. */
 ff_status ff_release_scratch(void);
 
 #ifdef __cplusplus

@@ -89,6 +89,7 @@ ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs);
 // while the stream is being captured into a graph.
 ff_status stream_scratch(hipStream_t stream, size_t bytes, void** out);
 bool stream_capturing(hipStream_t stream);
+void release_stream_scratch(hipStream_t stream);
 
 // Input and output widths of a warm-start network; pin/unpin its activation
 // workspace (while pinned, a grown workspace keeps the old buffers alive for

@@ -744,17 +744,13 @@ static ff_status launch_lm(const BatchSpec& bs)
     const int per_cu = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
 
     const int n_chunks = (bs.n_scenes + kMaxScenesPerLaunch - 1) / kMaxScenesPerLaunch;
-    int64_t max_chunk_total = 0;
+    int64_t total = 0;
     bool any_warm = false;
-    for (int c = 0; c < n_chunks; ++c) {
-        int64_t t = 0;
-        for (int s = c * kMaxScenesPerLaunch; s < std::min(bs.n_scenes, (c + 1) * kMaxScenesPerLaunch); ++s) {
-            t += bs.P[s];
-            if (bs.z0 && bs.z0[s] && bs.P[s] > 0) any_warm = true;
-        }
-        max_chunk_total = std::max(max_chunk_total, t);
+    for (int s = 0; s < bs.n_scenes; ++s) {
+        total += bs.P[s];
+        if (bs.z0 && bs.z0[s] && bs.P[s] > 0) any_warm = true;
     }
-    if (max_chunk_total == 0) return clear_error();
+    if (total == 0) return clear_error();
     const bool fallback = any_warm && o.fallback != 0;
 
     // the stream's scratch: per chunk one queue counter and one descriptor

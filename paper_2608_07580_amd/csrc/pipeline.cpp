@@ -30,7 +30,10 @@ void release(ff_pipeline* p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->z0) (void)hipFree(p->z0);
-    if (p->capture) (void)hipStreamDestroy(p->capture);
+    if (p->capture) {
+        release_stream_scratch(p->capture);
+        (void)hipStreamDestroy(p->capture);
+    }
     for (const ff_mlp* m : p->pinned) mlp_pin(m, -1);
     delete p;
 }

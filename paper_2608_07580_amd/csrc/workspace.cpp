@@ -4,10 +4,12 @@
 // launch sequence needs no allocation once its stream's buffer is large
 // enough -- which is what lets it be recorded into a HIP graph.  Growing
 // synchronizes the stream first and is refused while the stream is being
-// captured.  Buffers are held until ff_release_scratch or process exit.
+// captured.  Buffers are held until ff_release_scratch or process exit
+// (a pipeline frees the buffer of its private stream when destroyed).
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <set>
 #include <mutex>
 #include <utility>
 
@@ -65,19 +67,44 @@ ff_status stream_scratch(hipStream_t stream, size_t bytes, void** out)
 
 }  // namespace ff
 
+namespace ff {
+
+// Drop the buffer of one stream (the stream must still exist: it is
+// synchronized first).  Used by objects that own a private stream.
+void release_stream_scratch(hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_mutex);
+    auto it = table().find({dev, stream});
+    if (it == table().end()) return;
+    (void)hipStreamSynchronize(stream);
+    if (it->second.ptr) (void)hipFree(it->second.ptr);
+    table().erase(it);
+}
+
+}  // namespace ff
+
 extern "C" ff_status ff_release_scratch(void)
 {
     std::lock_guard<std::mutex> lk(ff::g_mutex);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    // no stream handle is touched (some may have been destroyed): each device
+    // that holds buffers is synchronized as a whole, then the buffers freed
+    std::set<int> devices;
+    for (const auto& kv : ff::table()) devices.insert(kv.first.first);
+    for (int d : devices) {
+        (void)hipSetDevice(d);
+        (void)hipDeviceSynchronize();
+    }
     for (auto& kv : ff::table()) {
         if (kv.second.ptr) {
-            int cur = 0;
-            (void)hipGetDevice(&cur);
             (void)hipSetDevice(kv.first.first);
-            (void)hipStreamSynchronize(kv.first.second);
             (void)hipFree(kv.second.ptr);
-            (void)hipSetDevice(cur);
         }
     }
     ff::table().clear();
+    (void)hipSetDevice(cur);
     return ff::clear_error();
 }

@@ -103,3 +103,18 @@ def test_pipeline_argument_checks():
     for k in KEYS:
         np.testing.assert_array_equal(pipe.outputs[0].numpy()[k], ref[k])
     pipe.close()
+
+
+def test_release_scratch_then_retrieve_again():
+    """ff_release_scratch frees the per-stream buffers; the next call on the
+    same stream allocates afresh and gives the same result."""
+    dev = torch.device("cuda:0")
+    scenes, rads = _batch(dev, sizes=(40,))
+    stream = torch.cuda.Stream(device=dev)
+    a = ff.retrieve(scenes[0], rads[0], ff.default_prior(1), stream=stream)
+    torch.cuda.synchronize()
+    assert ff.lib().ff_release_scratch() == ff.FF_OK
+    b = ff.retrieve(scenes[0], rads[0], ff.default_prior(1), stream=stream)
+    torch.cuda.synchronize()
+    for k in KEYS:
+        np.testing.assert_array_equal(a.numpy()[k], b.numpy()[k])
