@@ -75,6 +75,12 @@ def lib():
                                    C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_int,
                                    dp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_uint)]
+        L.orc_adam_retrieve.restype = C.c_int
+        L.orc_adam_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
+                                        C.c_int, dp, dp, dp, dp, C.c_long, fp,
+                                        C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_uint), dp, dp,
+                                        dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
+                                        dp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_uint)]
         L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -277,6 +283,106 @@ def retrieve(tab: Tables, lobs, model: int, lo, hi, x0, z0=None, q: int = 32,
                             out.status.ctypes.data_as(C.POINTER(C.c_uint)))
     if rc != 0:
         raise ValueError("orc_retrieve: bad arguments")
+    return out
+
+
+@dataclass
+class AdamStage:
+    """One stage of the paper's optimiser (Sec. 2.5): ``steps`` Adam updates of
+    the variables in ``free`` (indices) at learning rate ``lr``; the gradient is
+    scaled to at most ``clip`` in global norm (<= 0: no clip); variable j's loss
+    runs over the used bands with window[j][0] <= lambda <= window[j][1] nm;
+    ``zset`` maps a variable to the z it takes when the stage starts."""
+    steps: int
+    lr: float
+    free: tuple
+    window: dict            # j -> (lo_nm, hi_nm) for the free variables
+    clip: float = 1.0
+    zset: dict | None = None
+
+
+ADAM_BETA1, ADAM_BETA2, ADAM_EPS = 0.9, 0.999, 1e-8     # eq. (adam) defaults
+
+
+# Sec. 2.5: band windows of the two stages (nm).  Stage 1 fits over the
+# whole VSWIR range; in stage 2 the flaming component's variables see
+# [900, 1800], the smouldering component's [1500, 2500], and the variables
+# shared by both (f, eta) the union of the two.
+OMEGA_1 = (350.0, 2500.0)
+OMEGA_HOT = (900.0, 1800.0)
+OMEGA_SMOL = (1500.0, 2500.0)
+OMEGA_2 = (900.0, 2500.0)
+ADAM_CLIP = 1.0     # maximum global gradient norm (the printed value is lost)
+
+
+def paper_stages(model: int, lo, hi, x0, clip: float = ADAM_CLIP):
+    """The two Adam stages of Sec. 2.5 on this model's state.
+
+    Stage 1 (30 steps, lr 0.03, window OMEGA_1) fits the reflectance, the
+    thermal fraction f and one temperature with the spread held at its lower
+    bound (a near-delta distribution: the single temperature of stage 1);
+    for the two-component model that temperature is the flaming mean with
+    eta held at 1.  Stage 2 (100 steps, lr 0.015) holds the reflectance and
+    fits f and the temperature distribution, whose spreads (and eta) restart
+    from the prior start x0; the one-component model's f, m, s use OMEGA_2,
+    the two-component model's flaming (m_h, s_h) and smouldering (m_s, s_s)
+    variables their own windows."""
+    z0 = x_to_z(np.asarray(x0, np.float64), np.asarray(lo, np.float64), np.asarray(hi, np.float64))
+    if model == 1:
+        s1 = AdamStage(30, 0.03, (0, 1, 3, 4), {j: OMEGA_1 for j in (0, 1, 3, 4)}, clip, {2: -1.0})
+        s2 = AdamStage(100, 0.015, (0, 1, 2), {j: OMEGA_2 for j in (0, 1, 2)}, clip, {2: float(z0[2])})
+    elif model == 2:
+        s1 = AdamStage(30, 0.03, (0, 4, 6, 7), {j: OMEGA_1 for j in (0, 4, 6, 7)}, clip,
+                       {1: 1.0, 5: -1.0})
+        win = {0: OMEGA_2, 1: OMEGA_2, 2: OMEGA_SMOL, 3: OMEGA_SMOL, 4: OMEGA_HOT, 5: OMEGA_HOT}
+        s2 = AdamStage(100, 0.015, (0, 1, 2, 3, 4, 5), win, clip,
+                       {1: float(z0[1]), 3: float(z0[3]), 5: float(z0[5])})
+    else:
+        raise ValueError(f"unknown model {model}")
+    return [s1, s2]
+
+
+def adam_retrieve(tab: Tables, lobs, model: int, lo, hi, x0, stages, z0=None, q: int = 32,
+                  beta1: float = ADAM_BETA1, beta2: float = ADAM_BETA2, eps: float = ADAM_EPS,
+                  nthreads: int = 0) -> Result:
+    """FP64 staged-Adam retrieval (Sec. 2.5, eq. adam) of every pixel of lobs
+    [P, B]; outputs as ``retrieve`` (iters = Adam steps taken)."""
+    n = n_state(model)
+    lobs = np.ascontiguousarray(lobs, dtype=np.float32)
+    P = lobs.shape[0]
+    assert lobs.shape[1] == tab.B
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    x0 = np.ascontiguousarray(x0, np.float64)
+    z0c = None if z0 is None else np.ascontiguousarray(z0, np.float64).reshape(P, n)
+    k = len(stages)
+    steps = np.array([s.steps for s in stages], np.int32)
+    free = np.array([sum(1 << j for j in s.free) for s in stages], np.uint32)
+    lr = np.array([s.lr for s in stages], np.float64)
+    clip = np.array([s.clip for s in stages], np.float64)
+    wlo = np.zeros((max(k, 1), n))
+    whi = np.zeros((max(k, 1), n))
+    zset = np.full((max(k, 1), n), np.nan)
+    for i, s in enumerate(stages):
+        for j in s.free:
+            wlo[i, j], whi[i, j] = s.window[j]
+        for j, v in (s.zset or {}).items():
+            zset[i, j] = v
+    gx, gw = gauss_hermite(q)
+    out = Result(state=np.empty((P, n)), cov=np.empty((P, n * (n + 1) // 2)),
+                 moments=np.empty((P, 2)), rrr=np.empty(P),
+                 iters=np.empty(P, np.int32), status=np.empty(P, np.uint32))
+    lsat = None if tab.lsat is None else np.ascontiguousarray(tab.lsat, np.float32)
+    rc = lib().orc_adam_retrieve(
+        tab.B, _dp(tab.lam), _dp(tab.K), _dp(tab.tau2), _dp(tab.tup), _dp(tab.ratm), _dp(tab.S),
+        _fp(lsat), q, _dp(gx), _dp(gw), model, _dp(lo), _dp(hi), _dp(x0), _dp(z0c), P,
+        _fp(lobs), k, steps.ctypes.data_as(C.POINTER(C.c_int)),
+        free.ctypes.data_as(C.POINTER(C.c_uint)), _dp(lr), _dp(clip), _dp(wlo), _dp(whi),
+        _dp(zset), beta1, beta2, eps, nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),
+        _dp(out.rrr), out.iters.ctypes.data_as(C.POINTER(C.c_int)),
+        out.status.ctypes.data_as(C.POINTER(C.c_uint)))
+    if rc != 0:
+        raise ValueError("orc_adam_retrieve: bad arguments")
     return out
 
 

@@ -21,10 +21,13 @@
  *   - the masked least-squares loss (Sec. 2.5, eq. loss) minimised in the
  *     normalised coordinate z of eq. (affine) with z clipped to [-1, 1]
  *     after every update (Sec. 2.5)
- *   - a Levenberg-Marquardt solve (the paper uses Adam; the damped
- *     Gauss-Newton scheme here follows Madsen, Nielsen & Tingleff 2004 with
- *     Marquardt diagonal scaling, gain-ratio damping updates and an active
- *     set for variables held at a bound)
+ *   - a Levenberg-Marquardt solve (the damped Gauss-Newton scheme follows
+ *     Madsen, Nielsen & Tingleff 2004 with Marquardt diagonal scaling,
+ *     gain-ratio damping updates and an active set for variables held at a
+ *     bound)
+ *   - the paper's own solver: staged Adam (Sec. 2.5, eq. adam; Kingma & Ba
+ *     2015) on the windowed loss, with a global-norm gradient clip, the
+ *     z-clip after every update and per-stage free variables and windows
  *   - the Gauss-Newton state covariance at convergence, and the
  *     moment-matched E[T], sigma[T] of the temperature mixture (Sec. 2.2,
  *     mixture moments).
@@ -441,6 +444,62 @@ static void moments_of(int model, const double* x, double* et, double* sdt)
     *sdt = sqrt(var);
 }
 
+/* Saturation mask of one pixel (a band is used iff L_obs < L_sat), the
+ * number of used bands and the squared norm of their radiance.  Returns 0 if
+ * some radiance is not finite. */
+static int pixel_bands(int B, const float* lp, const float* lsat, unsigned char* mask,
+                       int* nvalid, double* lnorm2)
+{
+    int fin = 1;
+    *nvalid = 0;
+    *lnorm2 = 0.0;
+    for (int b = 0; b < B; ++b) {
+        if (!isfinite(lp[b])) fin = 0;
+        mask[b] = lsat ? (lp[b] < lsat[b]) : 1;
+        if (mask[b]) { ++*nvalid; *lnorm2 += (double)lp[b] * (double)lp[b]; }
+    }
+    return fin;
+}
+
+/* Starting z of one pixel: z0 if given, else x0 mapped by eq. (affine);
+ * clipped to [-1, 1]. */
+static void start_z(int n, const double* lo, const double* hi, const double* x0,
+                    const double* z0p, double* z)
+{
+    for (int j = 0; j < n; ++j) {
+        const double zz = z0p ? z0p[j] : 2.0 * (x0[j] - lo[j]) / (hi[j] - lo[j]) - 1.0;
+        z[j] = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
+    }
+}
+
+/* Outputs of pixel p from its final z, J^T J (A) and loss F over all used
+ * bands; st carries the status bits so far. */
+static void write_pixel(int model, int n, long p, unsigned st, const double* z, const double* A,
+                        double F, int nvalid, double lnorm2, const double* lo, const double* hi,
+                        double* state, double* cov, double* moments, double* rrr,
+                        unsigned* status)
+{
+    const int ncov = n * (n + 1) / 2;
+    double* cv = cov + p * ncov;
+    if (st & (ST_NONFINITE | ST_NODOF)) {
+        for (int j = 0; j < n; ++j) state[p * n + j] = NAN;
+        for (int j = 0; j < ncov; ++j) cv[j] = NAN;
+        moments[2 * p] = moments[2 * p + 1] = NAN;
+        rrr[p] = NAN;
+    } else {
+        double x[NMAX];
+        for (int j = 0; j < n; ++j) {
+            x[j] = lo[j] + 0.5 * (hi[j] - lo[j]) * (z[j] + 1.0);
+            state[p * n + j] = x[j];
+            if (z[j] <= -1.0 || z[j] >= 1.0) st |= ST_ATBOUND;
+        }
+        st |= covariance(n, A, F, nvalid, lo, hi, cv);
+        moments_of(model, x, &moments[2 * p], &moments[2 * p + 1]);
+        rrr[p] = lnorm2 > 0.0 ? sqrt(F / lnorm2) : NAN;
+    }
+    status[p] = st;
+}
+
 /* Retrieve P pixels.  lobs is [P][B] float32 (widened to double).
  * lsat: [B] saturation levels or NULL.  z0: [P][n] starting z or NULL
  * (then x0 is mapped to z for every pixel).  Outputs are double:
@@ -462,7 +521,6 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
     scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
     lmopt_t o = {max_iter, xtol, ftol, gtol, kappa, tau};
     if (!(tau > 0.0)) return -1;
-    const int ncov = n * (n + 1) / 2;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -471,44 +529,169 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
         const float* lp = lobs + p * B;
         unsigned char* mask = (unsigned char*)malloc(B);
         unsigned st = 0;
-        int nvalid = 0, finite_in = 1;
-        double lnorm2 = 0.0;
-        for (int b = 0; b < B; ++b) {
-            if (!isfinite(lp[b])) finite_in = 0;
-            mask[b] = lsat ? (lp[b] < lsat[b]) : 1;
-            if (mask[b]) { ++nvalid; lnorm2 += (double)lp[b] * (double)lp[b]; }
-        }
-        double z[NMAX], x[NMAX], A[NMAX * NMAX], g[NMAX], F = NAN;
+        int nvalid;
+        double lnorm2;
+        const int finite_in = pixel_bands(B, lp, lsat, mask, &nvalid, &lnorm2);
+        double z[NMAX], A[NMAX * NMAX], g[NMAX], F = NAN;
         int it = 0;
         if (!finite_in) st = ST_NONFINITE;
         else if (nvalid <= n) st = ST_NODOF;
         if (!st) {
-            for (int j = 0; j < n; ++j) {
-                double zz = z0 ? z0[p * n + j]
-                               : 2.0 * (x0[j] - lo[j]) / (hi[j] - lo[j]) - 1.0;
-                z[j] = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
-            }
+            start_z(n, lo, hi, x0, z0 ? z0 + p * n : 0, z);
             problem_t pb = {&sc, model, n, lo, hi, lp, mask};
             st = lm_solve(&pb, &o, z, A, g, &F, &it);
         }
-        double* cv = cov + p * ncov;
-        if (st & (ST_NONFINITE | ST_NODOF)) {
-            for (int j = 0; j < n; ++j) state[p * n + j] = NAN;
-            for (int j = 0; j < ncov; ++j) cv[j] = NAN;
-            moments[2 * p] = moments[2 * p + 1] = NAN;
-            rrr[p] = NAN;
-        } else {
-            for (int j = 0; j < n; ++j) {
-                x[j] = lo[j] + 0.5 * (hi[j] - lo[j]) * (z[j] + 1.0);
-                state[p * n + j] = x[j];
-                if (z[j] <= -1.0 || z[j] >= 1.0) st |= ST_ATBOUND;
-            }
-            st |= covariance(n, A, F, nvalid, lo, hi, cv);
-            moments_of(model, x, &moments[2 * p], &moments[2 * p + 1]);
-            rrr[p] = lnorm2 > 0.0 ? sqrt(F / lnorm2) : NAN;
-        }
+        write_pixel(model, n, p, st, z, A, F, nvalid, lnorm2, lo, hi, state, cov, moments, rrr,
+                    status);
         iters[p] = it;
-        status[p] = st;
+        free(mask);
+    }
+    return 0;
+}
+
+/* ---- the paper's solver: staged Adam (Sec. 2.5) ---------------------------- */
+typedef struct {
+    int steps;
+    unsigned free_mask;        /* bit j set: z_j is a variable of this stage */
+    double lr;                 /* learning rate in z */
+    double clip;               /* maximum global norm of the gradient (<= 0: none) */
+    const double *wlo, *whi;   /* [n] band window (nm, inclusive) of each variable's loss */
+    const double* zset;        /* [n] NaN: z_j carried over; else z_j at the stage start */
+} adam_stage_t;
+
+static double clamp1(double v) { return v < -1.0 ? -1.0 : (v > 1.0 ? 1.0 : v); }
+
+/* Gradient of the windowed loss (eq. loss) with respect to each free z_j,
+ * taken over the used bands inside variable j's window:
+ *   G_j = d/dz_j sum_b (L_obs,b - L_b(x(z)))^2
+ *       = -2 sum_b (L_obs,b - L_b) dL_b/dx_j (hi_j - lo_j)/2.
+ * Held variables get G_j = 0.  Returns 0 if some G_j is not finite. */
+static int windowed_gradient(const problem_t* pb, const adam_stage_t* s, const double* z,
+                             double* G)
+{
+    const int n = pb->n;
+    double x[NMAX];
+    z_to_x(pb, z, x);
+    for (int j = 0; j < n; ++j) G[j] = 0.0;
+    for (int b = 0; b < pb->sc->B; ++b) {
+        if (!pb->mask[b]) continue;
+        const double lam = pb->sc->lam[b];
+        int in[NMAX], any = 0;
+        for (int j = 0; j < n; ++j) {
+            in[j] = ((s->free_mask >> j) & 1u) && lam >= s->wlo[j] && lam <= s->whi[j];
+            any |= in[j];
+        }
+        if (!any) continue;
+        double dl[NMAX];
+        const double r = (double)pb->lobs[b] - model_band(pb->sc, b, pb->model, x, dl);
+        for (int j = 0; j < n; ++j)
+            if (in[j]) G[j] += -2.0 * r * dl[j] * 0.5 * (pb->hi[j] - pb->lo[j]);
+    }
+    for (int j = 0; j < n; ++j)
+        if (!isfinite(G[j])) return 0;
+    return 1;
+}
+
+/* Adam (eq. adam) through the stages in order, from z (in/out).  Each stage
+ * starts a fresh optimiser (t = 1, m = v = 0) on its free variables; the
+ * gradient is scaled down to the stage's maximum global norm when it is
+ * longer, and z is clipped to [-1, 1] after every update.  Returns the number
+ * of steps taken, or -1 when a gradient is not finite. */
+static int adam_solve(const problem_t* pb, int nst, const adam_stage_t* stages, double beta1,
+                      double beta2, double eps, double* z)
+{
+    const int n = pb->n;
+    int steps = 0;
+    for (int k = 0; k < nst; ++k) {
+        const adam_stage_t* s = &stages[k];
+        double m[NMAX], v[NMAX], G[NMAX];
+        for (int j = 0; j < n; ++j) {
+            m[j] = v[j] = 0.0;
+            if (!isnan(s->zset[j])) z[j] = clamp1(s->zset[j]);
+        }
+        for (int t = 1; t <= s->steps; ++t) {
+            if (!windowed_gradient(pb, s, z, G)) return -1;
+            double norm2 = 0.0;
+            for (int j = 0; j < n; ++j) norm2 += G[j] * G[j];
+            const double norm = sqrt(norm2);
+            if (s->clip > 0.0 && norm > s->clip)
+                for (int j = 0; j < n; ++j) G[j] *= s->clip / norm;
+            const double bc1 = 1.0 - pow(beta1, t), bc2 = 1.0 - pow(beta2, t);
+            for (int j = 0; j < n; ++j) {
+                if (!((s->free_mask >> j) & 1u)) continue;
+                m[j] = beta1 * m[j] + (1.0 - beta1) * G[j];
+                v[j] = beta2 * v[j] + (1.0 - beta2) * G[j] * G[j];
+                const double mhat = m[j] / bc1, vhat = v[j] / bc2;
+                z[j] = clamp1(z[j] - s->lr * mhat / (sqrt(vhat) + eps));
+            }
+            ++steps;
+        }
+    }
+    return steps;
+}
+
+/* Staged-Adam retrieval of P pixels; inputs and outputs as orc_retrieve.
+ * Stage k: steps[k], free[k] (bit mask), lr[k], clip[k], and [n_stages][n]
+ * arrays wlo, whi (window of each variable's loss, nm) and zset (NaN: carry
+ * over).  iters = Adam steps taken.  The covariance, moments and relative
+ * residual are those of the final z over all used bands. */
+int orc_adam_retrieve(int B, const double* lam, const double* K, const double* tau2,
+                      const double* tup, const double* ratm, const double* S,
+                      const float* lsat, int Q, const double* gx, const double* gw,
+                      int model, const double* lo, const double* hi, const double* x0,
+                      const double* z0, long P, const float* lobs,
+                      int n_stages, const int* steps, const unsigned* free_mask,
+                      const double* lr, const double* clip, const double* wlo,
+                      const double* whi, const double* zset,
+                      double beta1, double beta2, double eps, int nthreads,
+                      double* state, double* cov, double* moments, double* rrr,
+                      int* iters, unsigned* status)
+{
+    const int n = n_of_model(model);
+    if (n < 0 || Q <= 0 || Q > QMAX || B <= 0 || P < 0 || n_stages < 0 || n_stages > 16) return -1;
+    for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
+    adam_stage_t st[16];
+    for (int k = 0; k < n_stages; ++k) {
+        if (steps[k] < 0 || !(lr[k] > 0.0)) return -1;
+        st[k].steps = steps[k];
+        st[k].free_mask = free_mask[k];
+        st[k].lr = lr[k];
+        st[k].clip = clip[k];
+        st[k].wlo = wlo + k * n;
+        st[k].whi = whi + k * n;
+        st[k].zset = zset + k * n;
+    }
+    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (long p = 0; p < P; ++p) {
+        const float* lp = lobs + p * B;
+        unsigned char* mask = (unsigned char*)malloc(B);
+        unsigned s = 0;
+        int nvalid;
+        double lnorm2;
+        const int finite_in = pixel_bands(B, lp, lsat, mask, &nvalid, &lnorm2);
+        double z[NMAX], A[NMAX * NMAX], g[NMAX], F = NAN;
+        int it = 0;
+        if (!finite_in) s = ST_NONFINITE;
+        else if (nvalid <= n) s = ST_NODOF;
+        if (!s) {
+            start_z(n, lo, hi, x0, z0 ? z0 + p * n : 0, z);
+            problem_t pb = {&sc, model, n, lo, hi, lp, mask};
+            it = adam_solve(&pb, n_stages, st, beta1, beta2, eps, z);
+            if (it < 0) {
+                s = ST_NONFINITE;
+                it = 0;
+            } else {
+                F = evaluate(&pb, z, A, g);
+                if (!isfinite(F)) s = ST_NONFINITE;
+            }
+        }
+        write_pixel(model, n, p, s, z, A, F, nvalid, lnorm2, lo, hi, state, cov, moments, rrr,
+                    status);
+        iters[p] = it;
         free(mask);
     }
     return 0;
