@@ -41,8 +41,8 @@ HBM_PEAK = 8.0e12
 # counter reads for a 1 GiB device copy: x2.000 and x1.000), recorded in
 # profiles/lm_kernel_fp32_q32_clustered_fire_2p53M.md.  They describe the
 # kernel sources with the SHA-1 below; any other source reports null.
-TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/physics.hpp",
-                   "paper_2608_07580_amd/csrc/ff_internal.hpp")
+TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
+                   "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
 TRAFFIC_SHA1 = "5a2887324622c32d821e0ef47ed386133ef339c1"
 TRAFFIC_BYTES = {"plain": 56.13e9, "warm": 35.86e9}
 
@@ -483,6 +483,125 @@ def run_precision(args):
     print(json.dumps(line), flush=True)
 
 
+def adam_slots_per_pixel(lam, stages, n_bands: int, n_quad: int) -> int:
+    """Algorithmic VALU slots of one pixel's staged-Adam solve (one component):
+    per step and band inside the union of the free variables' windows, the
+    thermal quadrature (11 per node + 5), 19 for the solar term, basis and
+    residual, and 12 for the windowed gradient sums (7 products into the
+    per-variable sums, 5 window selects); then one full evaluation with the
+    normal equations for the outputs (slots_per_eval)."""
+    per_band = 11 * n_quad + 5 + 19 + 12
+    total = 0
+    for st in stages:
+        lo = min(st["window"][j][0] for j in st["free"])
+        hi = max(st["window"][j][1] for j in st["free"])
+        nb = int(((lam >= lo) & (lam <= hi)).sum())
+        total += st["steps"] * nb * per_band
+    return total + slots_per_eval(n_bands, n_quad)
+
+
+def run_solvers(args):
+    """The paper's own solver against LM on the clustered-fire scene: the
+    two-stage Adam schedule of Sec. 2.5 (130 fixed steps) and the plain LM
+    from the same default start, each timed on the GPU, with accuracy against
+    the true states and, on a seeded subsample, the FP64 oracle's staged Adam
+    and LM for the same statistics."""
+    import torch
+    import oracle
+    import paper_2608_07580_amd as ff
+    import scenegen
+    dev = torch.device("cuda:0")
+    ff.lib()
+    atm, scene, states, fire, noise, rad = make_workload(args, dev)
+    P, B = rad.shape
+    prior = ff.default_prior(1)
+    stream = torch.cuda.Stream(device=dev)
+    lam = scene.band_tables()[:, 0]
+
+    def accuracy(state, moments, rrr, X):
+        f = X[:, 0] > 1e-3
+        eT = np.abs(moments[f, 0] - X[f, 1])
+        ef = np.abs(state[:, 0] - X[:, 0])
+        return {"fire_px": int(f.sum()), "dT_fire_median_K": float(np.median(eT)),
+                "dT_fire_p90_K": float(np.percentile(eT, 90)), "df_median": float(np.median(ef)),
+                "df_p90": float(np.percentile(ef, 90)), "rrr_median": float(np.median(rrr)),
+                "rrr_p90": float(np.percentile(rrr, 90))}
+
+    def timed(launch):
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                launch()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                launch()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    # LM from the default start, tuned launch shape
+    opts = ff.default_options(n_quad=args.n_quad)
+    if not args.no_tune:
+        with torch.cuda.stream(stream):
+            opts, _ = ff.tune([scene], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+        torch.cuda.synchronize()
+    out_lm = ff.allocate_outputs(P, 1, dev)
+    ms_lm = timed(lambda: ff.retrieve(scene, rad, prior, options=opts, outputs=out_lm, stream=stream))
+    r_lm = out_lm.numpy()
+    conv = (r_lm["status"] & ff.ST_CONVERGED) != 0
+    log(f"LM: {ms_lm:.1f} ms, {int(conv.sum())} converged")
+
+    # the paper's staged Adam
+    aopt = ff.adam_options(prior, n_quad=args.n_quad, lanes_per_pixel=args.adam_lpp)
+    stages = [dict(steps=aopt.stage[k].steps, lr=aopt.stage[k].lr,
+                   free=[j for j in range(5) if (aopt.stage[k].free_mask >> j) & 1],
+                   window={j: (aopt.stage[k].window_lo_nm[j], aopt.stage[k].window_hi_nm[j]) for j in range(5)})
+              for k in range(aopt.n_stages)]
+    out_ad = ff.allocate_outputs(P, 1, dev)
+    ms_ad = timed(lambda: ff.adam_retrieve(scene, rad, prior, options=aopt, outputs=out_ad, stream=stream))
+    r_ad = out_ad.numpy()
+    log(f"Adam: {ms_ad:.1f} ms")
+    spp = adam_slots_per_pixel(lam, stages, B, args.n_quad)
+    achieved = P * spp / (ms_ad * 1e-3)
+
+    # oracle on a seeded subsample: both solvers, same statistics
+    idx = scenegen.subsample(1, 0, P, args.solver_sample)
+    tab = oracle.band_tables(atm)
+    lobs = rad[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    lo, hi, x0 = scenegen.default_prior(1)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.time()
+    o_lm = oracle.retrieve(tab, lobs, 1, lo, hi, x0, nthreads=cores)
+    t_olm = time.time() - t0
+    t0 = time.time()
+    o_ad = oracle.adam_retrieve(tab, lobs, 1, lo, hi, x0, oracle.paper_stages(1, lo, hi, x0), nthreads=cores)
+    t_oad = time.time() - t0
+    X = states
+    line = {
+        "metric": "the paper's two-stage Adam vs LM on the clustered-fire scene: solved pixels/s and accuracy",
+        "config": {"workload": f"clustered-fire scene {args.cross} x {args.lines} px x {B} bands, 3% fire, "
+                               f"SNR {args.snr:g}; both solvers from the default start",
+                   "pixels": P, "bands": B, "n_quad": args.n_quad},
+        "lm": {"ms_per_step": ms_lm, "pixels_per_s": P / (ms_lm * 1e-3), "converged": int(conv.sum()),
+               "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
+               "accuracy": accuracy(r_lm["state"], r_lm["moments"], r_lm["rrr"], X)},
+        "adam": {"ms_per_step": ms_ad, "pixels_per_s": P / (ms_ad * 1e-3), "steps_per_pixel": 130,
+                 "lanes_per_pixel": args.adam_lpp,
+                 "accuracy": accuracy(r_ad["state"], r_ad["moments"], r_ad["rrr"], X),
+                 "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                              "unit": "Tops/s", "frac": achieved / PEAK_SLOTS, "kernel": "adam_kernel",
+                              "ops_per_pixel": spp}},
+        "oracle_sample": {"pixels": len(idx), "cores": cores, "lm_s": t_olm, "adam_s": t_oad,
+                          "lm": accuracy(o_lm.state, o_lm.moments, o_lm.rrr, X[idx]),
+                          "adam": accuracy(o_ad.state, o_ad.moments, o_ad.rrr, X[idx]),
+                          "gpu_lm": accuracy(r_lm["state"][idx], r_lm["moments"][idx], r_lm["rrr"][idx], X[idx]),
+                          "gpu_adam": accuracy(r_ad["state"][idx], r_ad["moments"][idx], r_ad["rrr"][idx], X[idx])},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,9 +619,13 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the tuner's")
-    ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision"), default="clustered-fire",
+    ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers"),
+                    default="clustered-fire",
                     help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
-                         "precision: FP32/FP64 variants on the two-component stress set")
+                         "precision: FP32/FP64 variants on the two-component stress set; "
+                         "solvers: the paper's two-stage Adam vs LM on the clustered-fire scene")
+    ap.add_argument("--adam-lpp", type=int, default=1, help="lanes per pixel of the Adam kernel")
+    ap.add_argument("--solver-sample", type=int, default=4096, help="oracle subsample of the solvers workload")
     ap.add_argument("--precision-pixels", type=int, default=262144)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2608_07580_amd", "tuning.json"),
                     help="autotuner table (read, and written on a miss)")
@@ -516,6 +639,9 @@ def main():
         sys.exit(2)
     if args.workload == "ragged":
         run_ragged(args)
+        return
+    if args.workload == "solvers":
+        run_solvers(args)
         return
     if args.workload == "precision":
         if args.cpu_sample == 65536:

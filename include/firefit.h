@@ -262,6 +262,70 @@ ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,
                       const ff_options* opts, const ff_outputs* out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's own solver: staged Adam (Keely et al. Sec. 2.5, eq. adam;
+ * Kingma & Ba 2015) on the windowed loss of eq. (loss) in the z coordinate of
+ * eq. (affine).  Each stage runs a fresh optimiser (t = 1, m = v = 0) for a
+ * fixed number of steps on its free variables; the others are held.  Step t:
+ *   g   = gradient of the loss in z, where variable j's component sums over
+ *         the unsaturated bands with window_lo_nm[j] <= lambda <= window_hi_nm[j]
+ *         (g_j = -2 sum_b r_b dL_b/dz_j, r = L_obs - L);
+ *   g  *= clip_norm / ||g||  when ||g|| > clip_norm > 0 (norm over free j);
+ *   m   = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2;
+ *   z_j = clip(z_j - lr (m_j / (1 - beta1^t)) / (sqrt(v_j / (1 - beta2^t)) + eps), -1, 1).
+ * Every pixel takes the same number of steps (no convergence test). */
+#define FF_MAX_ADAM_STAGES 4
+
+typedef struct ff_adam_stage {
+    int32_t steps;                     /* Adam steps of this stage (>= 0) */
+    uint32_t free_mask;                /* bit j set: state variable j is updated */
+    double lr;                         /* learning rate in z (> 0) */
+    double clip_norm;                  /* maximum global gradient norm; <= 0: no clip */
+    double window_lo_nm[FF_MAX_STATE]; /* band window of each free variable's gradient */
+    double window_hi_nm[FF_MAX_STATE];
+    double z_start[FF_MAX_STATE];      /* NaN: carried over; else z_j is set to it
+                                          (clipped to [-1, 1]) when the stage starts */
+} ff_adam_stage;
+
+typedef struct ff_adam_options {
+    int32_t n_stages;        /* 0 .. FF_MAX_ADAM_STAGES */
+    int32_t precision;       /* FF_PRECISION_* (default FP32) */
+    int32_t accumulate;      /* FF_ACCUMULATE_* for the FP32 path (default FP32) */
+    int32_t n_quad;          /* Gauss-Hermite order: 16, 24, 32 (default 32); FP64: 32 */
+    int32_t block_size;      /* 64, 128, 192 or 256 (0 = 256) */
+    int32_t lanes_per_pixel; /* power of two <= 64 (0 = 1) */
+    double beta1, beta2, eps;          /* eq. (adam) defaults 0.9, 0.999, 1e-8 */
+    ff_adam_stage stage[FF_MAX_ADAM_STAGES];
+} ff_adam_options;
+
+/* The paper's two stages for prior->model, start values taken from prior.
+ * Stage 1: 30 steps, lr 0.03, window [350, 2500] nm, frees f, one
+ * temperature and the reflectance (rho0, rho1) with the temperature spread
+ * at its lower bound -- the single temperature of the first stage (two-
+ * component model: the flaming mean, with eta at 1).  Stage 2: 100 steps,
+ * lr 0.015, holds the reflectance and frees f and the temperature
+ * distribution, spreads (and eta) restarting from x0; windows [900, 1800] nm
+ * for the flaming component, [1500, 2500] nm for the smouldering one and
+ * their union [900, 2500] nm for f, eta and the one-component model's
+ * variables.  clip_norm 1.0 (the paper's value is not legible).  FF_EINVAL
+ * for a NULL argument or an invalid prior.  Host only. */
+ff_status ff_adam_options_default(const ff_prior* prior, ff_adam_options* opts);
+
+/* Staged-Adam retrieval of a ragged batch (arguments as ff_retrieve_batch,
+ * options from ff_adam_options).  Start: z0_dev[s] per pixel, or prior->x0.
+ * Outputs as ff_retrieve_batch at the final z over all unsaturated bands;
+ * iters = Adam steps taken; status carries FF_ST_NONFINITE_INPUT (radiance
+ * or a gradient not finite), FF_ST_NO_DOF, FF_ST_AT_BOUND, FF_ST_COV_SINGULAR
+ * and FF_ST_WARM_START, never a convergence bit.  evals_dev receives += the
+ * model evaluations (steps + 1 per solved pixel).  Asynchronous on stream;
+ * the per-stream scratch of ff_retrieve_batch holds the launch descriptor
+ * and the per-stage band lists. */
+ff_status ff_adam_retrieve_batch(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                 const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                 const float* const* z0_dev, const ff_adam_options* opts,
+                                 const ff_outputs* outs, unsigned long long* evals_dev,
+                                 void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned warm start.  A multilayer perceptron maps a radiance spectrum to a
  * starting state z0 for the LM solve (which always refines it and falls
  * back to the default start when the solve from z0 fails).  Layers:

@@ -43,7 +43,7 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_set_params", "ff_mlp_set_normalization", "ff_mlp_get_normalization",
            "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
-           "ff_pipeline_destroy", "ff_release_scratch")
+           "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch")
 
 
 class FirefitError(RuntimeError):
@@ -80,6 +80,22 @@ class ffOptions(C.Structure):
                 ("xtol", C.c_double),
                 ("ftol", C.c_double), ("gtol", C.c_double), ("kappa", C.c_double),
                 ("tau", C.c_double)]
+
+
+MAX_ADAM_STAGES = 4
+
+
+class ffAdamStage(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("free_mask", C.c_uint32), ("lr", C.c_double), ("clip_norm", C.c_double),
+                ("window_lo_nm", C.c_double * MAX_STATE), ("window_hi_nm", C.c_double * MAX_STATE),
+                ("z_start", C.c_double * MAX_STATE)]
+
+
+class ffAdamOptions(C.Structure):
+    _fields_ = [("n_stages", C.c_int32), ("precision", C.c_int32), ("accumulate", C.c_int32),
+                ("n_quad", C.c_int32), ("block_size", C.c_int32), ("lanes_per_pixel", C.c_int32),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("stage", ffAdamStage * MAX_ADAM_STAGES)]
 
 
 class ffOutputs(C.Structure):
@@ -151,7 +167,13 @@ def lib():
         L.ff_pipeline_z0.restype = vp
         L.ff_pipeline_destroy.argtypes = [vp]
         L.ff_pipeline_destroy.restype = None
-        for name in ("ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
+        L.ff_adam_options_default.argtypes = [C.POINTER(ffPrior), C.POINTER(ffAdamOptions)]
+        L.ff_adam_retrieve_batch.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                             C.POINTER(C.c_int64), C.c_int32, C.POINTER(ffPrior),
+                                             C.POINTER(C.c_void_p), C.POINTER(ffAdamOptions),
+                                             C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
+        for name in ("ff_adam_options_default", "ff_adam_retrieve_batch",
+                     "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
                      "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
@@ -354,6 +376,82 @@ def retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None, opti
     _check(lib().ff_retrieve_batch(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
                                    _stream_handle(stream)), "ff_retrieve_batch")
     return outs
+
+
+def adam_options(prior: Prior | None = None, **kw) -> ffAdamOptions:
+    """The paper's two-stage Adam schedule for `prior` (ff_adam_options_default);
+    keyword arguments override top-level fields."""
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    o = ffAdamOptions()
+    pc = prior.to_c()
+    _check(lib().ff_adam_options_default(C.byref(pc), C.byref(o)), "ff_adam_options_default")
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def set_adam_stages(opts: ffAdamOptions, stages) -> ffAdamOptions:
+    """Replace the stages of `opts`.  Each stage is a mapping with keys
+    steps, lr, free (variable indices), window ({j: (lo_nm, hi_nm)}), and
+    optionally clip (default 1.0) and zset ({j: z at the stage start})."""
+    if len(stages) > MAX_ADAM_STAGES:
+        raise ValueError(f"at most {MAX_ADAM_STAGES} stages")
+    opts.n_stages = len(stages)
+    for k in range(MAX_ADAM_STAGES):
+        st = ffAdamStage()
+        for j in range(MAX_STATE):
+            st.z_start[j] = float("nan")
+        if k < len(stages):
+            d = stages[k]
+            st.steps = int(d["steps"])
+            st.lr = float(d["lr"])
+            st.clip_norm = float(d.get("clip", 1.0))
+            for j in d["free"]:
+                st.free_mask |= 1 << j
+                st.window_lo_nm[j], st.window_hi_nm[j] = d["window"][j]
+            for j, v in (d.get("zset") or {}).items():
+                st.z_start[j] = float(v)
+        opts.stage[k] = st
+    return opts
+
+
+def adam_retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None,
+                        options: ffAdamOptions | None = None, outputs=None, evals=None, stream=None) -> list:
+    """The paper's staged-Adam solver over a ragged batch (ff_adam_retrieve_batch)."""
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    options = options or adam_options(prior)
+    ns = len(scenes)
+    outs = outputs or [allocate_outputs(r.shape[0], prior.model, r.device) for r in radiances]
+    sc = (C.c_void_p * ns)(*[s.handle.value for s in scenes])
+    rd = (C.c_void_p * ns)(*[r.data_ptr() for r in radiances])
+    Ps = (C.c_int64 * ns)(*[r.shape[0] for r in radiances])
+    z0p = None
+    if z0s is not None:
+        z0p = (C.c_void_p * ns)(*[0 if z is None else z.data_ptr() for z in z0s])
+    oc = (ffOutputs * ns)(*[o.to_c() for o in outs])
+    pc = prior.to_c()
+    _check(lib().ff_adam_retrieve_batch(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
+                                        _stream_handle(stream)), "ff_adam_retrieve_batch")
+    return outs
+
+
+def adam_retrieve(scene: Scene, radiance, prior: Prior | None = None, z0=None,
+                  options: ffAdamOptions | None = None, outputs: Outputs | None = None, evals=None,
+                  stream=None, state_f64: bool = False) -> Outputs:
+    """The paper's staged-Adam solver on every pixel of radiance [P, B] float32 (device)."""
+    torch = _torch()
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    assert radiance.is_cuda and radiance.dtype == torch.float32 and radiance.is_contiguous()
+    assert radiance.dim() == 2 and radiance.shape[1] == scene.n_bands
+    P = radiance.shape[0]
+    if z0 is not None:
+        assert z0.is_cuda and z0.dtype == torch.float32 and z0.is_contiguous()
+        assert tuple(z0.shape) == (P, N_STATE[prior.model])
+    out = outputs or allocate_outputs(P, prior.model, radiance.device, state_f64)
+    return adam_retrieve_batch([scene], [radiance], prior, None if z0 is None else [z0], options, [out],
+                               evals, stream)[0]
 
 
 TUNE_IGNORE_CACHE = 1

@@ -75,6 +75,38 @@ static ff_status check_options(const ff_options* o)
     return FF_OK;
 }
 
+static ff_status check_adam_options(const ff_adam_options* o, int n)
+{
+    if (!o) return set_error(FF_EINVAL, "adam options is NULL");
+    if (o->n_stages < 0 || o->n_stages > FF_MAX_ADAM_STAGES) return set_error(FF_EINVAL, "n_stages out of range");
+    if (o->precision != FF_PRECISION_FP32 && o->precision != FF_PRECISION_FP64)
+        return set_error(FF_EINVAL, "unknown precision");
+    if (o->accumulate != FF_ACCUMULATE_FP32 && o->accumulate != FF_ACCUMULATE_FP64)
+        return set_error(FF_EINVAL, "unknown accumulate mode");
+    if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 256 || o->block_size % 64 != 0))
+        return set_error(FF_EINVAL, "block_size must be 64, 128, 192 or 256");
+    if (o->lanes_per_pixel < 0 || o->lanes_per_pixel > 64 || (o->lanes_per_pixel & (o->lanes_per_pixel - 1)) != 0)
+        return set_error(FF_EINVAL, "lanes_per_pixel must be 0 or a power of two <= 64");
+    if (!(o->beta1 >= 0.0 && o->beta1 < 1.0) || !(o->beta2 >= 0.0 && o->beta2 < 1.0) ||
+        !(o->eps > 0.0) || !std::isfinite(o->eps))
+        return set_error(FF_EINVAL, "Adam needs 0 <= beta1, beta2 < 1 and a finite eps > 0");
+    for (int k = 0; k < o->n_stages; ++k) {
+        const ff_adam_stage& s = o->stage[k];
+        if (s.steps < 0 || s.steps > 100000) return set_error(FF_EINVAL, "stage steps out of range");
+        if (!(s.lr > 0.0) || !std::isfinite(s.lr)) return set_error(FF_EINVAL, "stage lr must be finite and > 0");
+        if (std::isnan(s.clip_norm) || std::isinf(s.clip_norm)) return set_error(FF_EINVAL, "stage clip_norm must be finite");
+        if (s.free_mask >> n) return set_error(FF_EINVAL, "stage free_mask names a variable the model does not have");
+        for (int j = 0; j < n; ++j) {
+            if (((s.free_mask >> j) & 1u) &&
+                (!std::isfinite(s.window_lo_nm[j]) || !std::isfinite(s.window_hi_nm[j]) ||
+                 !(s.window_lo_nm[j] <= s.window_hi_nm[j])))
+                return set_error(FF_EINVAL, "a free variable needs a finite window with lo <= hi");
+            if (std::isinf(s.z_start[j])) return set_error(FF_EINVAL, "stage z_start must be NaN or finite");
+        }
+    }
+    return FF_OK;
+}
+
 }  // namespace ff
 
 using namespace ff;
@@ -210,4 +242,89 @@ extern "C" ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_
     if (s != FF_OK) return s;
     if (e != hipSuccess) return hip_error(e, "ff_retrieve: stream synchronize");
     return clear_error();
+}
+
+extern "C" ff_status ff_adam_options_default(const ff_prior* prior, ff_adam_options* o)
+{
+    if (!o) return set_error(FF_EINVAL, "ff_adam_options_default: NULL options");
+    ff_status s = check_prior(prior);
+    if (s != FF_OK) return s;
+    *o = ff_adam_options{};
+    o->precision = FF_PRECISION_FP32;
+    o->accumulate = FF_ACCUMULATE_FP32;
+    o->n_quad = 32;
+    o->block_size = 256;
+    o->lanes_per_pixel = 1;
+    o->beta1 = 0.9;
+    o->beta2 = 0.999;
+    o->eps = 1e-8;
+    o->n_stages = 2;
+    const double nan = std::nan("");
+    auto zdef = [&](int j) { return 2.0 * (prior->x0[j] - prior->lo[j]) / (prior->hi[j] - prior->lo[j]) - 1.0; };
+    auto set = [&](ff_adam_stage& st, int j, double lo, double hi) {
+        st.free_mask |= 1u << j;
+        st.window_lo_nm[j] = lo;
+        st.window_hi_nm[j] = hi;
+    };
+    for (int k = 0; k < FF_MAX_ADAM_STAGES; ++k)
+        for (int j = 0; j < FF_MAX_STATE; ++j) o->stage[k].z_start[j] = nan;
+    ff_adam_stage& s1 = o->stage[0];
+    ff_adam_stage& s2 = o->stage[1];
+    s1.steps = 30;
+    s1.lr = 0.03;
+    s1.clip_norm = 1.0;
+    s2.steps = 100;
+    s2.lr = 0.015;
+    s2.clip_norm = 1.0;
+    // stage 1: one temperature (spread at its lower bound), f and the
+    // reflectance over the whole range; stage 2: f and the temperature
+    // distribution over the SWIR windows, reflectance held
+    const double w1lo = 350.0, w1hi = 2500.0;          // Omega_1
+    const double hot_lo = 900.0, hot_hi = 1800.0;      // Omega_2 flaming
+    const double smol_lo = 1500.0, smol_hi = 2500.0;   // Omega_2 smouldering
+    if (prior->model == FF_MODEL_LOGNORMAL_1) {
+        for (int j : {0, 1, 3, 4}) set(s1, j, w1lo, w1hi);
+        s1.z_start[2] = -1.0;
+        for (int j : {0, 1, 2}) set(s2, j, hot_lo, smol_hi);
+        s2.z_start[2] = zdef(2);
+    } else {
+        for (int j : {0, 4, 6, 7}) set(s1, j, w1lo, w1hi);
+        s1.z_start[1] = 1.0;     // all weight on the flaming component
+        s1.z_start[5] = -1.0;
+        set(s2, 0, hot_lo, smol_hi);
+        set(s2, 1, hot_lo, smol_hi);
+        set(s2, 2, smol_lo, smol_hi);
+        set(s2, 3, smol_lo, smol_hi);
+        set(s2, 4, hot_lo, hot_hi);
+        set(s2, 5, hot_lo, hot_hi);
+        s2.z_start[1] = zdef(1);
+        s2.z_start[3] = zdef(3);
+        s2.z_start[5] = zdef(5);
+    }
+    return clear_error();
+}
+
+extern "C" ff_status ff_adam_retrieve_batch(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                            const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                            const float* const* z0_dev, const ff_adam_options* opts,
+                                            const ff_outputs* outs, unsigned long long* evals_dev,
+                                            void* stream)
+{
+    if (n_scenes < 0) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: n_scenes < 0");
+    if (n_scenes == 0) return clear_error();
+    if (!scenes || !radiance_dev || !P || !outs) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: NULL array");
+    ff_status s = check_prior(prior);
+    if (s != FF_OK) return s;
+    s = check_adam_options(opts, n_state(prior->model));
+    if (s != FF_OK) return s;
+    int B = -1;
+    for (int i = 0; i < n_scenes; ++i) {
+        if (!scenes[i]) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: NULL scene");
+        if (P[i] < 0) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: P < 0");
+        if (B < 0) B = scenes[i]->n_bands;
+        if (scenes[i]->n_bands != B) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: scenes differ in band count");
+        if (P[i] > 0 && !radiance_dev[i]) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: NULL radiance");
+    }
+    AdamSpec as{scenes, radiance_dev, P, n_scenes, prior, z0_dev, opts, outs, evals_dev, (hipStream_t)stream};
+    return dispatch_adam(as);
 }

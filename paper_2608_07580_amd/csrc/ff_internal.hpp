@@ -85,6 +85,22 @@ struct BatchSpec {
 
 ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs);
 
+// One staged-Adam launch sequence over a ragged batch of scenes.
+struct AdamSpec {
+    const ff_scene* const* scenes;
+    const float* const* radiance;
+    const int64_t* P;
+    int n_scenes;
+    const ff_prior* prior;
+    const float* const* z0;
+    const ff_adam_options* opts;
+    const ff_outputs* outs;
+    unsigned long long* evals;
+    hipStream_t stream;
+};
+
+ff_status dispatch_adam(const AdamSpec& as);
+
 // Library-owned, grow-only scratch per (device, stream); growth is refused
 // while the stream is being captured into a graph.
 ff_status stream_scratch(hipStream_t stream, size_t bytes, void** out);

@@ -1,0 +1,362 @@
+// Per-pixel pieces shared by the retrieval kernels (Levenberg-Marquardt and
+// staged Adam): launch-descriptor scene slots, group reductions over the
+// lanes of a pixel, the model evaluation with the normal equations in z,
+// FP64 Cholesky, and the output epilogue (Gauss-Newton covariance, moments).
+//
+// Loss and coordinates (Keely et al. Sec. 2.5): r = m (L_obs - L(x(z))),
+// F = r.r (eq. loss), z = 2 (x - lo)/(hi - lo) - 1 (eq. affine).
+#pragma once
+
+#include "physics.hpp"
+
+namespace ff {
+
+constexpr int kMaxScenesPerLaunch = 16;
+
+// One scene of a launch: inputs, per-pixel start, outputs, and the offset of
+// its first pixel in the launch's pixel numbering.
+struct SceneDev {
+    const float* radiance;
+    const void* table;
+    int64_t P;
+    int64_t offset;
+    const float* z0;
+    float* state;
+    float* cov;
+    float* moments;
+    float* rrr;
+    int32_t* iters;
+    uint32_t* status;
+    double* state64;
+};
+
+// Hide a pointer's value from the optimiser: loads through the result are
+// not hoisted across this point (the pointer stays in SGPRs, no code).
+template <typename T>
+__device__ __forceinline__ const T* launder(const T* p)
+{
+#ifdef FF_LAUNDER
+    asm volatile("" : "+s"(p));
+#endif
+    return p;
+}
+
+namespace {
+
+// upper-triangle row-major index of (i, j), i <= j: the output packing
+__device__ __forceinline__ int upper(int n, int i, int j) { return i * n - i * (i - 1) / 2 + (j - i); }
+
+// scene slot of a launch-wide pixel number (slots past n_scenes have offset INT64_MAX)
+template <typename Desc>
+__device__ __forceinline__ int scene_of(const Desc* p, int64_t item)
+{
+    int s = 0;
+    const int ns = p->n_scenes;
+    for (int i = 1; i < ns; ++i)
+        if (item >= p->sc[i].offset) s = i;
+    return s;
+}
+
+// In-place Cholesky M = C C^T of a packed lower-triangular SPD matrix; the
+// diagonal is stored as 1 / C_jj so the triangular solves only multiply.
+// Returns false if a pivot is not strictly positive.
+template <int N>
+__device__ __forceinline__ bool cholesky_packed(double (&m)[N * (N + 1) / 2])
+{
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double dj = m[tri(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dj -= m[tri(j, k)] * m[tri(j, k)];
+        ok = ok && dj > 0.0;
+        const double dd = dj > 0.0 ? dj : 1.0;
+        double inv = __builtin_amdgcn_rsq(dd);
+        inv = inv * (1.5 - 0.5 * dd * inv * inv);   // one Newton step: full FP64 accuracy
+        m[tri(j, j)] = inv;
+#pragma unroll
+        for (int i = j + 1; i < N; ++i) {
+            double v = m[tri(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= m[tri(i, k)] * m[tri(j, k)];
+            m[tri(i, j)] = v * inv;
+        }
+    }
+    return ok;
+}
+
+// Solve C C^T x = rhs with the factor of cholesky_packed.
+template <int N>
+__device__ __forceinline__ void cholesky_solve(const double (&c)[N * (N + 1) / 2], const double (&rhs)[N],
+                                               double (&x)[N])
+{
+    double y[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double v = rhs[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= c[tri(i, k)] * y[k];
+        y[i] = v * c[tri(i, i)];
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        double v = y[i];
+#pragma unroll
+        for (int k = i + 1; k < N; ++k) v -= c[tri(k, i)] * x[k];
+        x[i] = v * c[tri(i, i)];
+    }
+}
+
+// Sum over the L lanes of a pixel's group (aligned, L a power of two) by an
+// xor butterfly: every lane of the group ends with the same bits, since each
+// level adds the same two partial sums (a + b == b + a in IEEE arithmetic).
+__device__ __forceinline__ float group_sum(float v, int L)
+{
+    for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ double group_sum(double v, int L)
+{
+    for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ int group_sum(int v, int L)
+{
+    for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Radiance checks of a new pixel over the group's bands: count of
+// non-finite values, count of unsaturated bands and their squared norm
+// (identical on every lane of the group).
+template <typename R>
+__device__ __forceinline__ void scan_pixel(const float* __restrict__ rad, const R* __restrict__ tab, int B,
+                                           int sub, int L, int& nonfin, int& nvalid, double& lnorm2)
+{
+    nonfin = 0;
+    nvalid = 0;
+    lnorm2 = 0.0;
+    for (int b = sub; b < B; b += L) {
+        const float v = rad[b];
+        nonfin += isfinite(v) ? 0 : 1;
+        if ((R)v < tab[(size_t)b * FF_TABLE_COLS + COL_LSAT]) {
+            ++nvalid;
+            lnorm2 += (double)v * (double)v;
+        }
+    }
+    if (L > 1) {
+        nonfin = group_sum(nonfin, L);
+        nvalid = group_sum(nvalid, L);
+        lnorm2 = group_sum(lnorm2, L);
+    }
+}
+
+// One model evaluation at physical state x: basis Gram matrix G = sum_b u u^T,
+// h = sum_b u r_b and F = sum_b r_b^2 over unmasked bands, then the normal
+// equations in z: A = D M G M^T D, g = J^T r = -D M h (D = diag((hi-lo)/2)).
+// The L lanes of a pixel's group take bands sub, sub + L, ... and their
+// partial sums are combined across the group before the normal equations.
+// Desc provides B and the box lo, hi.
+template <typename R, typename ACC, int MODEL, int Q, typename Desc>
+__device__ __forceinline__ double evaluate(const Desc* descp, const float* __restrict__ rad,
+                                      const R* __restrict__ tab, const double (&x)[ModelDims<MODEL>::N],
+                                      R (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
+                                      R (&g)[ModelDims<MODEL>::N], int sub, int L)
+{
+    using PM = PixelModel<R, MODEL, Q>;
+    constexpr int N = PM::N;
+    constexpr int NT = N * (N + 1) / 2;
+    const int B = launder(descp)->B;
+    PM pm;
+    pm.setup(x, sub, L);
+    ACC G[NT], h[N], F = (ACC)0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) G[i] = (ACC)0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) h[i] = (ACC)0;
+
+    for (int b0 = sub; b0 < B; b0 += 4 * L) {
+        // four radiance values per lane per load group (bands b0 + jL): with
+        // one lane per pixel they share a cache line, with L lanes the group
+        // reads L consecutive values per load
+        float l0 = rad[b0];
+        float l1 = b0 + L < B ? rad[b0 + L] : 0.f;
+        float l2 = b0 + 2 * L < B ? rad[b0 + 2 * L] : 0.f;
+        float l3 = b0 + 3 * L < B ? rad[b0 + 3 * L] : 0.f;
+#pragma unroll 1
+        for (int j = 0; j < 4; ++j) {
+            const int b = b0 + j * L;
+            if (b >= B) break;
+            const float lob = l0;
+            l0 = l1;
+            l1 = l2;
+            l2 = l3;
+            // quadrature weights are re-read (scalar loads) every band
+            const int o = opaque_zero();
+            const BandRow<R> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
+            R ub[N];
+            const R lm = pm.band(row, o, ub);
+            const bool msk = (R)lob < row.lsat;
+            const ACC r = msk ? (ACC)((R)lob - lm) : (ACC)0;
+            ACC ua[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) ua[i] = msk ? (ACC)ub[i] : (ACC)0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                h[i] += ua[i] * r;
+#pragma unroll
+                for (int k = 0; k <= i; ++k) G[tri(i, k)] += ua[i] * ua[k];
+            }
+            F += r * r;
+        }
+    }
+    if (L > 1) {
+#pragma unroll
+        for (int i = 0; i < NT; ++i) G[i] = group_sum(G[i], L);
+#pragma unroll
+        for (int i = 0; i < N; ++i) h[i] = group_sum(h[i], L);
+        F = group_sum(F, L);
+    }
+
+    const Desc* D = launder(descp);
+    double c1[N], c2[N];
+    PM::coefficients(x, c1, c2);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double dzi = 0.5 * (D->hi[i] - D->lo[i]);
+        const int a1 = PM::s1[i], a2 = PM::s2[i];
+        double gi = c1[i] * (double)h[a1];
+        if (a2 >= 0) gi += c2[i] * (double)h[a2];
+        g[i] = (R)(-dzi * gi);
+#pragma unroll
+        for (int k = 0; k <= i; ++k) {
+            const double dzk = 0.5 * (D->hi[k] - D->lo[k]);
+            const int b1 = PM::s1[k], b2 = PM::s2[k];
+            double v = c1[i] * c1[k] * (double)G[tri(a1, b1)];
+            if (b2 >= 0) v += c1[i] * c2[k] * (double)G[tri(a1, b2)];
+            if (a2 >= 0) v += c2[i] * c1[k] * (double)G[tri(a2, b1)];
+            if (a2 >= 0 && b2 >= 0) v += c2[i] * c2[k] * (double)G[tri(a2, b2)];
+            A[tri(i, k)] = (R)(dzi * dzk * v);
+        }
+    }
+    return F;
+}
+
+// Outputs of one pixel (all pointers may be null).
+struct OutPtrs {
+    float* state;
+    float* cov;
+    float* moments;
+    float* rrr;
+    int32_t* iters;
+    uint32_t* status;
+    double* state64;
+};
+
+__device__ __forceinline__ OutPtrs out_ptrs(const SceneDev& d)
+{
+    return OutPtrs{d.state, d.cov, d.moments, d.rrr, d.iters, d.status, d.state64};
+}
+
+template <int N>
+__device__ inline void write_nan(const OutPtrs& o, int64_t pix)
+{
+    constexpr int NT = N * (N + 1) / 2;
+    const float qn = __builtin_nanf("");
+    if (o.state) for (int j = 0; j < N; ++j) o.state[pix * N + j] = qn;
+    if (o.state64) for (int j = 0; j < N; ++j) o.state64[pix * N + j] = __builtin_nan("");
+    if (o.cov) for (int j = 0; j < NT; ++j) o.cov[pix * NT + j] = qn;
+    if (o.moments) { o.moments[2 * pix] = qn; o.moments[2 * pix + 1] = qn; }
+}
+
+// State, covariance and moments of a solved pixel at physical state x with
+// J^T J = A (in z) and loss F over nvalid bands.  The Gauss-Newton
+// covariance sigma^2 A^-1 (sigma^2 = F / (N_valid - n)) is formed in z and
+// scaled to x; variables whose Jacobian column is identically zero are
+// unidentified and get NaN rows/columns.  Returns FF_ST_COV_SINGULAR when
+// some rows are NaN, else 0.
+template <typename R, int MODEL, int Q, typename Desc>
+__device__ __forceinline__ unsigned write_solution(const Desc* D, const OutPtrs& o, int64_t pix,
+                                                   const double (&x)[ModelDims<MODEL>::N],
+                                                   const R (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
+                                                   double F, int nvalid)
+{
+    using PM = PixelModel<R, MODEL, Q>;
+    constexpr int N = PM::N;
+    constexpr int NT = N * (N + 1) / 2;
+    unsigned st = 0;
+    bool keep[N];
+    double cm[NT];
+    bool any_drop = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        keep[i] = (double)A[tri(i, i)] > 0.0;
+        any_drop = any_drop || !keep[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+            cm[tri(i, k)] = (keep[i] && keep[k]) ? (double)A[tri(i, k)] : 0.0;
+        cm[tri(i, i)] = keep[i] ? (double)A[tri(i, i)] : 1.0;
+    }
+    const bool ok = cholesky_packed<N>(cm);
+    if (any_drop || !ok) st |= FF_ST_COV_SINGULAR;
+    const double s2 = F / (double)(nvalid - N);
+    if (o.cov) {
+        for (int c = 0; c < N; ++c) {
+            double e[N], col[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) { e[i] = i == c ? 1.0 : 0.0; col[i] = 0.0; }
+            if (ok) cholesky_solve<N>(cm, e, col);
+            bool keepc = false;
+#pragma unroll
+            for (int i = 0; i < N; ++i) keepc = keepc || (i == c && keep[i]);
+            const double dc = D->hi[c] - D->lo[c];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if (i <= c) {
+                    const double v = (ok && keep[i] && keepc)
+                        ? s2 * col[i] * 0.25 * (D->hi[i] - D->lo[i]) * dc
+                        : __builtin_nan("");
+                    o.cov[pix * NT + upper(N, i, c)] = (float)v;
+                }
+            }
+        }
+    }
+    double et, sd;
+    PM::moments(x, et, sd);
+    if (o.moments) { o.moments[2 * pix] = (float)et; o.moments[2 * pix + 1] = (float)sd; }
+    if (o.state) for (int j = 0; j < N; ++j) o.state[pix * N + j] = (float)x[j];
+    if (o.state64) for (int j = 0; j < N; ++j) o.state64[pix * N + j] = x[j];
+    return st;
+}
+
+template <typename T>
+__global__ void fill_struct(const T v, T* __restrict__ out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = v;
+}
+
+__global__ void zero_u64(unsigned long long* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// one atomic per wave: the wave's sum of v added to *counter (lane 0 adds)
+__device__ __forceinline__ void wave_add(unsigned long long* counter, unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffull), off);
+        const unsigned hi = __shfl_xor((unsigned)(v >> 32), off);
+        v += ((unsigned long long)hi << 32) | lo;
+    }
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(counter, v);
+}
+
+}  // namespace
+}  // namespace ff

@@ -85,3 +85,54 @@ def test_tune_rejects_bad_arguments_on_the_host(L):
     ms = C.c_double(0)
     assert L.ff_tune(None, None, None, 0, C.byref(pr), None, C.byref(o), None, None, 0, C.byref(ms), None) == ff.FF_EINVAL
     assert L.ff_tune(None, None, None, 1, None, None, C.byref(o), None, None, 0, C.byref(ms), None) == ff.FF_EINVAL
+
+
+def test_adam_defaults_are_the_oracles_paper_schedule(L, oracle_mod):
+    """ff_adam_options_default and the oracle's paper_stages are written
+    separately from the same reading of Sec. 2.5."""
+    for model in (1, 2):
+        p = ff.default_prior(model)
+        o = ff.adam_options(p)
+        assert (o.beta1, o.beta2, o.eps) == (oracle_mod.ADAM_BETA1, oracle_mod.ADAM_BETA2, oracle_mod.ADAM_EPS)
+        want = oracle_mod.paper_stages(model, p.lo, p.hi, p.x0)
+        assert o.n_stages == len(want)
+        n = ff.N_STATE[model]
+        for k, w in enumerate(want):
+            s = o.stage[k]
+            assert (s.steps, s.lr, s.clip_norm) == (w.steps, w.lr, w.clip)
+            assert s.free_mask == sum(1 << j for j in w.free)
+            for j in w.free:
+                assert (s.window_lo_nm[j], s.window_hi_nm[j]) == w.window[j]
+            zs = w.zset or {}
+            for j in range(n):
+                if j in zs:
+                    assert s.z_start[j] == pytest.approx(zs[j], abs=1e-15)
+                else:
+                    assert np.isnan(s.z_start[j])
+
+
+def test_adam_rejects_bad_options_on_the_host(L):
+    pr = ff.default_prior(1).to_c()
+    fake = (C.c_void_p * 1)(1)
+    rad = (C.c_void_p * 1)(1)
+    P = (C.c_int64 * 1)(4)
+    outs = (ff.ffOutputs * 1)()
+
+    def call(o):
+        return L.ff_adam_retrieve_batch(fake, rad, P, 1, C.byref(pr), None, C.byref(o), outs, None, None)
+
+    bad = []
+    o = ff.adam_options(); o.stage[0].lr = 0.0; bad.append(o)
+    o = ff.adam_options(); o.eps = 0.0; bad.append(o)
+    o = ff.adam_options(); o.beta2 = 1.0; bad.append(o)
+    o = ff.adam_options(); o.n_stages = 5; bad.append(o)
+    o = ff.adam_options(); o.stage[1].free_mask = 1 << 6; bad.append(o)     # model 1 has 5 variables
+    o = ff.adam_options(); o.stage[0].window_lo_nm[0] = 3000.0; bad.append(o)
+    o = ff.adam_options(); o.stage[0].steps = -1; bad.append(o)
+    o = ff.adam_options(); o.lanes_per_pixel = 3; bad.append(o)
+    o = ff.adam_options(); o.stage[0].z_start[1] = float("inf"); bad.append(o)
+    for o in bad:
+        assert call(o) == ff.FF_EINVAL, ff.lib().ff_last_error()
+    o = ff.adam_options()
+    assert L.ff_adam_retrieve_batch(None, None, None, 0, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_OK
+    assert L.ff_adam_retrieve_batch(None, None, None, -1, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_EINVAL

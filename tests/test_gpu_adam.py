@@ -1,0 +1,276 @@
+"""GPU parity of the paper's staged-Adam solver (Sec. 2.5, eq. adam) through
+the C ABI (ff_adam_retrieve_batch) against the FP64 oracle's staged Adam on
+the same seeded inputs.
+
+The paper's fixed-step schedule does not converge: with a constant learning
+rate the last steps oscillate across a narrow valley, and where the iterate
+stops on that oscillation depends on rounding.  In the oracle itself a
+relative change of 1e-15 in the learning rate moves the final z of 18% of
+the config-0 pixels by more than 1e-7 (up to 0.08) and E[T] of fire pixels
+by up to 70 K, while the first 40 steps stay within 1.2e-10.  So:
+  * the trajectory is compared pixel by pixel over its well-conditioned
+    prefix (stage 1 and the first 10 steps of stage 2): FP64 kernels within
+    1e-7 in z of the oracle.  FP32 rounding (~1e-7 relative) is already
+    amplified there -- the oracle moves by the same kind of amounts when its
+    learning rate changes by 1e-7 -- so FP32 kernels are held to quantiles
+    of the z deviation and to shares of pixels within 0.5 K in E[T], 1e-4
+    in f and 1e-5 in relative residual;
+  * the full 130-step schedule is compared by what it delivers over the
+    pixel set -- median and 90th percentile of the relative residual and of
+    the E[T] and f errors against the true states -- each within 5% of the
+    oracle's (the oracle's own statistics move by up to 1.5% under 1e-15
+    and 2.7% under 1e-7 relative changes of the learning rate).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from _helpers import noisy_spectra, posterior_sd
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2608_07580_amd as ff  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def world(dev):
+    atm = scenegen.make_atmosphere(0, 0)
+    tab = oracle.band_tables(atm)
+    scene = ff.Scene(atm)
+    lo, hi, x0 = scenegen.default_prior(1)
+    return atm, tab, scene, ff.Prior(1, lo, hi, x0)
+
+
+@pytest.fixture(scope="module")
+def cfg0(world):
+    """1,000 px of the seeded 4,096-pixel config-0 set; the paper's schedule
+    and its well-conditioned prefix, with the oracle's results."""
+    atm, tab, scene, prior = world
+    X = scenegen.config0_states(4096)[:1000]
+    lobs = noisy_spectra(tab, X, 1, 0, 0)
+    full = oracle.paper_stages(1, prior.lo, prior.hi, prior.x0)
+    prefix = [full[0], dataclasses.replace(full[1], steps=PREFIX_STEPS)]
+    ref_full = oracle.adam_retrieve(tab, lobs, 1, prior.lo, prior.hi, prior.x0, full)
+    ref_pre = oracle.adam_retrieve(tab, lobs, 1, prior.lo, prior.hi, prior.x0, prefix)
+    return X, lobs, full, prefix, ref_full, ref_pre
+
+
+PREFIX_STEPS = 10
+
+
+def stage_dicts(stages):
+    return [dict(steps=s.steps, lr=s.lr, free=s.free, window=s.window, clip=s.clip, zset=s.zset)
+            for s in stages]
+
+
+def _adam(scene, lobs, prior, dev, stages=None, z0=None, **opt):
+    o = ff.adam_options(prior, **opt)
+    if stages is not None:
+        ff.set_adam_stages(o, stage_dicts(stages))
+    rad = torch.from_numpy(np.ascontiguousarray(lobs)).to(dev)
+    z0t = None if z0 is None else torch.from_numpy(np.ascontiguousarray(z0, np.float32)).to(dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+    out = ff.adam_retrieve(scene, rad, prior, z0=z0t, options=o, evals=evals, state_f64=True)
+    torch.cuda.synchronize()
+    r = out.numpy()
+    r["evals"] = int(evals.item())
+    return r
+
+
+def zdiff(r, ref, prior):
+    return np.abs(oracle.x_to_z(r["state_f64"], prior.lo, prior.hi) - oracle.x_to_z(ref.state, prior.lo, prior.hi))
+
+
+def summary(state, moments, rrr, X):
+    """Median and 90th percentile of the relative residual, of |E[T] - T| on
+    fire pixels (f > 1e-3) and of |f - f_true|."""
+    fire = X[:, 0] > 1e-3
+    eT = np.abs(moments[fire, 0] - X[fire, 1])
+    ef = np.abs(state[:, 0] - X[:, 0])
+    return np.array([np.median(rrr), np.percentile(rrr, 90), np.median(eT), np.percentile(eT, 90),
+                     np.median(ef), np.percentile(ef, 90)])
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("lpp", [1, 4])
+def test_adam_fp64_prefix_parity(world, cfg0, dev, lpp):
+    atm, tab, scene, prior = world
+    X, lobs, full, prefix, ref_full, ref = cfg0
+    r = _adam(scene, lobs, prior, dev, stages=prefix, precision=ff.PRECISION_FP64, lanes_per_pixel=lpp)
+    dz = zdiff(r, ref, prior)
+    drrr = np.abs(r["rrr"] / ref.rrr - 1)
+    dT = np.abs(r["moments"][:, 0] - ref.moments[:, 0])
+    print(f"lpp {lpp}: dz max {dz.max():.3e} p99 {np.percentile(dz, 99):.3e} drrr {drrr.max():.3e} "
+          f"dT {dT.max():.3e}")
+    np.testing.assert_array_equal(r["status"].astype(np.int64), ref.status.astype(np.int64))
+    assert np.all(r["iters"] == 30 + PREFIX_STEPS)
+    assert r["evals"] == (31 + PREFIX_STEPS) * len(lobs)
+    assert dz.max() <= 1e-7
+    assert drrr.max() <= 1e-6      # float32 output
+    assert dT.max() <= 1e-3
+
+
+@pytest.mark.parametrize("acc,lpp", [(ff.ACCUMULATE_FP32, 1), (ff.ACCUMULATE_FP64, 1), (ff.ACCUMULATE_FP32, 4)])
+def test_adam_fp32_prefix_parity(world, cfg0, dev, acc, lpp):
+    """FP32 gradients differ from FP64 by ~1e-7 relative, and the schedule
+    amplifies that even over its first 40 steps: the oracle itself, with its
+    learning rate changed by 1e-7 relative, moves z by p50 2.7e-8, p90
+    1.7e-6, p99 7e-5 (max 4e-3), E[T] of one fire pixel in 400 by more than
+    0.5 K and the relative residual of 6% of the pixels by more than 1e-5.
+    The FP32 kernel is held to deviations of that kind from the FP64 oracle."""
+    atm, tab, scene, prior = world
+    X, lobs, full, prefix, ref_full, ref = cfg0
+    r = _adam(scene, lobs, prior, dev, stages=prefix, accumulate=acc, lanes_per_pixel=lpp)
+    dz = zdiff(r, ref, prior).max(axis=1)
+    fire = X[:, 0] > 1e-3
+    dT = np.abs(r["moments"][fire, 0] - ref.moments[fire, 0])
+    df = np.abs(r["state"][:, 0] - ref.state[:, 0])
+    drrr = np.abs(r["rrr"] - ref.rrr)
+    q = np.percentile(dz, [50, 90, 99])
+    share_T = np.mean(dT <= 0.5)
+    share_f = np.mean(df <= 1e-4)
+    share_r = np.mean(drrr <= 1e-5)
+    print(f"acc {acc} lpp {lpp}: dz p50/p90/p99/max {q[0]:.2e} {q[1]:.2e} {q[2]:.2e} {dz.max():.2e}; "
+          f"fire E[T] within 0.5 K {share_T:.4f} (p99 {np.percentile(dT, 99):.3f} K, max {dT.max():.3f}); "
+          f"f within 1e-4 {share_f:.4f}; rrr within 1e-5 {share_r:.4f} (max {drrr.max():.2e})")
+    keep = oracle.ST_NONFINITE | oracle.ST_NODOF
+    np.testing.assert_array_equal(r["status"].astype(np.int64) & keep, ref.status.astype(np.int64) & keep)
+    assert np.all(r["iters"] == 30 + PREFIX_STEPS)
+    assert fire.sum() >= 300
+    assert q[0] <= 1e-6 and q[1] <= 3e-5 and q[2] <= 3e-4
+    assert share_T >= 0.99 and share_f >= 0.99 and share_r >= 0.90
+
+
+@pytest.mark.parametrize("precision", [ff.PRECISION_FP64, ff.PRECISION_FP32])
+def test_adam_full_schedule_statistics(world, cfg0, dev, precision):
+    atm, tab, scene, prior = world
+    X, lobs, full, prefix, ref, _ = cfg0
+    r = _adam(scene, lobs, prior, dev, precision=precision)
+    assert np.all(r["iters"] == 130)
+    assert r["evals"] == 131 * len(lobs)
+    s_ref = summary(ref.state, ref.moments, ref.rrr, X)
+    s_gpu = summary(r["state_f64"], r["moments"], r["rrr"], X)
+    dz = zdiff(r, ref, prior).max(axis=1)
+    print(f"precision {precision}: oracle {np.round(s_ref, 6)} gpu {np.round(s_gpu, 6)} "
+          f"ratio-1 {np.round(s_gpu / s_ref - 1, 4)}; pixels with dz > 1e-7: {np.mean(dz > 1e-7):.3f}")
+    np.testing.assert_allclose(s_gpu, s_ref, rtol=0.05)
+
+
+def test_adam_block_size_and_batch_invariance(world, cfg0, dev):
+    """A pixel's result does not depend on the workgroup size or on the other
+    scenes of its batch (bitwise)."""
+    atm, tab, scene, prior = world
+    X, lobs = cfg0[:2]
+    a = _adam(scene, lobs, prior, dev, block_size=256)
+    b = _adam(scene, lobs, prior, dev, block_size=64)
+    for k in ("state", "cov", "moments", "rrr", "iters", "status"):
+        np.testing.assert_array_equal(a[k], b[k])
+    atm2 = scenegen.make_atmosphere(0, 5)
+    scene2 = ff.Scene(atm2)
+    lobs2 = noisy_spectra(oracle.band_tables(atm2), scenegen.config0_states(300, scene=5), 1, 0, 5)
+    rads = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (lobs[:257], lobs2)]
+    outs = ff.adam_retrieve_batch([scene, scene2], rads, prior, options=ff.adam_options(prior))
+    torch.cuda.synchronize()
+    single2 = _adam(scene2, lobs2, prior, dev)
+    np.testing.assert_array_equal(outs[0].numpy()["state"], a["state"][:257])
+    np.testing.assert_array_equal(outs[1].numpy()["state"], single2["state"])
+    np.testing.assert_array_equal(outs[1].numpy()["cov"], single2["cov"])
+
+
+def test_adam_two_component_parity(dev):
+    """Eight-parameter mixture with the paper's per-component windows in
+    stage 2: FP64 prefix pixel by pixel (the oracle's own sensitivity there
+    is 1.6e-8 in z under a 1e-15 change of the learning rate), and the full
+    schedule's summary statistics."""
+    atm = scenegen.make_atmosphere(2, 0)
+    tab = oracle.band_tables(atm)
+    X = scenegen.config2_states(256)
+    X[:, 0] = np.exp(np.random.default_rng(4).uniform(np.log(1e-3), np.log(0.05), len(X)))
+    lobs = noisy_spectra(tab, X, 2, 2, 0)
+    lo, hi, x0 = scenegen.default_prior(2)
+    prior = ff.Prior(2, lo, hi, x0)
+    scene = ff.Scene(atm)
+    full = oracle.paper_stages(2, lo, hi, x0)
+    prefix = [full[0], dataclasses.replace(full[1], steps=PREFIX_STEPS)]
+    ref = oracle.adam_retrieve(tab, lobs, 2, lo, hi, x0, prefix)
+    r = _adam(scene, lobs, prior, dev, stages=prefix, precision=ff.PRECISION_FP64)
+    dz = zdiff(r, ref, prior)
+    print(f"n=8 fp64 prefix: dz max {dz.max():.3e} p99 {np.percentile(dz, 99):.3e}")
+    np.testing.assert_array_equal(r["status"].astype(np.int64), ref.status.astype(np.int64))
+    assert dz.max() <= 1e-6
+    np.testing.assert_allclose(r["moments"], ref.moments, rtol=0, atol=1e-3)
+    # full schedule: the oracle's own residual median and 90th percentile on
+    # these 256 pixels move by up to 3.6% under 1e-7 relative changes of the
+    # learning rate (1.5% under 1e-15)
+    ref_full = oracle.adam_retrieve(tab, lobs, 2, lo, hi, x0, full)
+    for prec, tol in ((ff.PRECISION_FP64, 0.05), (ff.PRECISION_FP32, 0.10)):
+        rf = _adam(scene, lobs, prior, dev, precision=prec)
+        assert np.all(rf["iters"] == 130)
+        s_ref = np.array([np.median(ref_full.rrr), np.percentile(ref_full.rrr, 90)])
+        s_gpu = np.array([np.median(rf["rrr"]), np.percentile(rf["rrr"], 90)])
+        print(f"n=8 precision {prec}: rrr p50/p90 oracle {s_ref} gpu {s_gpu}")
+        np.testing.assert_allclose(s_gpu, s_ref, rtol=tol)
+
+
+def test_adam_edge_cases_and_warm_start(world, cfg0, dev):
+    atm, tab, scene, prior = world
+    X, lobs, _, stages = cfg0[:4]
+    # P = 0
+    empty = torch.empty((0, tab.B), dtype=torch.float32, device=dev)
+    ff.adam_retrieve(scene, empty, prior)
+    # non-finite radiance; a pixel saturated in all but 4 bands
+    lob = lobs[:8].copy()
+    lsat = (2.0 * lob.max(axis=0)).astype(np.float32)
+    lob[2, 4:] = 1.5 * lsat[4:]
+    lob[1, 7] = np.nan
+    atm_s = scenegen.make_atmosphere(0, 0, sat_level=lsat)
+    tab_s = oracle.band_tables(atm_s)
+    scene_s = ff.Scene(atm_s)
+    refs = oracle.adam_retrieve(tab_s, lob, 1, prior.lo, prior.hi, prior.x0, stages)
+    r = _adam(scene_s, lob, prior, dev, stages=stages, precision=ff.PRECISION_FP64)
+    assert r["status"][1] & ff.ST_NONFINITE_INPUT and r["iters"][1] == 0 and np.isnan(r["rrr"][1])
+    assert r["status"][2] & ff.ST_NO_DOF and np.all(np.isnan(r["state"][2]))
+    np.testing.assert_array_equal(r["status"].astype(np.int64), refs.status.astype(np.int64))
+    ok = np.isfinite(refs.rrr)
+    assert ok.sum() >= 5
+    assert zdiff(r, refs, prior)[ok].max() <= 1e-7
+    assert r["evals"] == (31 + PREFIX_STEPS) * ok.sum()
+    # per-pixel start, and a schedule with no steps (outputs at the start)
+    z0 = oracle.x_to_z(X[:64], prior.lo, prior.hi) * 0.8
+    refw = oracle.adam_retrieve(tab, lobs[:64], 1, prior.lo, prior.hi, prior.x0, stages,
+                                z0=z0.astype(np.float32).astype(np.float64))
+    rw = _adam(scene, lobs[:64], prior, dev, stages=stages, z0=z0, precision=ff.PRECISION_FP64)
+    assert np.all(rw["status"] & ff.ST_WARM_START)
+    assert zdiff(rw, refw, prior).max() <= 1e-7
+    ref0 = oracle.adam_retrieve(tab, lobs[:64], 1, prior.lo, prior.hi, prior.x0, [],
+                                z0=z0.astype(np.float32).astype(np.float64))
+    r0 = _adam(scene, lobs[:64], prior, dev, stages=[], z0=z0, precision=ff.PRECISION_FP64)
+    assert np.all(r0["iters"] == 0)
+    np.testing.assert_allclose(r0["state_f64"], ref0.state, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(r0["rrr"], ref0.rrr, rtol=1e-6)
+    np.testing.assert_allclose(r0["cov"], ref0.cov, rtol=1e-5)
+
+
+def test_adam_custom_stages_match_the_oracle(world, cfg0, dev):
+    """A three-stage schedule with a held block, clip off, a narrow window
+    and stage start values, FP64."""
+    atm, tab, scene, prior = world
+    X, lobs = cfg0[:2]
+    st = [oracle.AdamStage(5, 0.05, (0, 3, 4), {0: (350.0, 2500.0), 3: (400.0, 1200.0), 4: (350.0, 2500.0)},
+                           0.0, {1: 0.1}),
+          oracle.AdamStage(7, 0.01, (1, 2), {1: (1000.0, 2000.0), 2: (1000.0, 2500.0)}, 0.5),
+          oracle.AdamStage(3, 0.002, (0, 1, 2, 3, 4), {j: (350.0, 2500.0) for j in range(5)}, 2.0)]
+    ref = oracle.adam_retrieve(tab, lobs[:200], 1, prior.lo, prior.hi, prior.x0, st)
+    r = _adam(scene, lobs[:200], prior, dev, stages=st, precision=ff.PRECISION_FP64)
+    assert np.all(r["iters"] == 15)
+    assert zdiff(r, ref, prior).max() <= 1e-7
