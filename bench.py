@@ -43,8 +43,8 @@ HBM_PEAK = 8.0e12
 # kernel sources with the SHA-1 below; any other source reports null.
 TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
                    "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
-TRAFFIC_SHA1 = "5a2887324622c32d821e0ef47ed386133ef339c1"
-TRAFFIC_BYTES = {"plain": 56.13e9, "warm": 35.86e9}
+TRAFFIC_SHA1 = "ffe8152c1333f83d093bb6266cec4e613e1b4665"
+TRAFFIC_BYTES = {"plain": 56.10e9, "warm": 35.53e9}
 
 
 def measured_traffic(leg: str):
@@ -553,6 +553,21 @@ def run_solvers(args):
     conv = (r_lm["status"] & ff.ST_CONVERGED) != 0
     log(f"LM: {ms_lm:.1f} ms, {int(conv.sum())} converged")
 
+    # LM stopped after a few iterations: the budget at which it matches the
+    # accuracy of the paper's schedule
+    lm_budget = []
+    for mi in args.lm_budgets:
+        o2 = ff.default_options(n_quad=args.n_quad, max_iter=mi, lanes_per_pixel=opts.lanes_per_pixel,
+                                block_size=opts.block_size, blocks_per_cu=opts.blocks_per_cu,
+                                schedule=opts.schedule)
+        out2 = ff.allocate_outputs(P, 1, dev)
+        ms2 = timed(lambda: ff.retrieve(scene, rad, prior, options=o2, outputs=out2, stream=stream))
+        r2 = out2.numpy()
+        lm_budget.append({"max_iter": mi, "ms_per_step": ms2,
+                          "accuracy": accuracy(r2["state"], r2["moments"], r2["rrr"], states)})
+        log(f"LM max_iter {mi}: {ms2:.1f} ms")
+        del out2
+
     # the paper's staged Adam
     aopt = ff.adam_options(prior, n_quad=args.n_quad, lanes_per_pixel=args.adam_lpp)
     stages = [dict(steps=aopt.stage[k].steps, lr=aopt.stage[k].lr,
@@ -586,7 +601,8 @@ def run_solvers(args):
                    "pixels": P, "bands": B, "n_quad": args.n_quad},
         "lm": {"ms_per_step": ms_lm, "pixels_per_s": P / (ms_lm * 1e-3), "converged": int(conv.sum()),
                "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
-               "accuracy": accuracy(r_lm["state"], r_lm["moments"], r_lm["rrr"], X)},
+               "accuracy": accuracy(r_lm["state"], r_lm["moments"], r_lm["rrr"], X),
+               "stopped_early": lm_budget},
         "adam": {"ms_per_step": ms_ad, "pixels_per_s": P / (ms_ad * 1e-3), "steps_per_pixel": 130,
                  "lanes_per_pixel": args.adam_lpp,
                  "accuracy": accuracy(r_ad["state"], r_ad["moments"], r_ad["rrr"], X),
@@ -626,6 +642,8 @@ def main():
                          "solvers: the paper's two-stage Adam vs LM on the clustered-fire scene")
     ap.add_argument("--adam-lpp", type=int, default=1, help="lanes per pixel of the Adam kernel")
     ap.add_argument("--solver-sample", type=int, default=4096, help="oracle subsample of the solvers workload")
+    ap.add_argument("--lm-budgets", type=int, nargs="*", default=[1, 2, 3, 5],
+                    help="solvers workload: LM iteration caps timed beside the full LM")
     ap.add_argument("--precision-pixels", type=int, default=262144)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2608_07580_amd", "tuning.json"),
                     help="autotuner table (read, and written on a miss)")

@@ -15,8 +15,9 @@
  * (FF_MODEL_LOGNORMAL_2), integrated by Gauss-Hermite quadrature in log T.
  * The surface reflectance is linear, rho = rho0 + rho1 (lambda - 1440 nm).
  * Each pixel is solved by Levenberg-Marquardt (damped Gauss-Newton on the
- * loss in z, active set for variables held at a bound; the paper's own
- * solver is Adam), and the Gauss-Newton state covariance is reported.
+ * loss in z, active set for variables held at a bound), and the
+ * Gauss-Newton state covariance is reported; the paper's own solver, staged
+ * Adam, is available as ff_adam_retrieve_batch.
  *
  * Conventions for every entry point:
  *  - Return value: ff_status, FF_OK (0) on success, negative on error.  No
