@@ -618,6 +618,80 @@ def run_solvers(args):
     print(json.dumps(line), flush=True)
 
 
+def run_front_end(args):
+    """The paper's candidate selection in front of the retrieval: the HFDI
+    pre-filter (Sec. 2.1, threshold -0.1) builds the candidate list on the
+    device and LM solves only the listed pixels (the count never leaves the
+    device).  Timed per step: HFDI + listed LM; reported beside the plain LM
+    over every pixel of the same scene."""
+    import torch
+    import paper_2608_07580_amd as ff
+    dev = torch.device("cuda:0")
+    ff.lib()
+    atm, scene, states, fire, noise, rad = make_workload(args, dev)
+    P, B = rad.shape
+    prior = ff.default_prior(1)
+    stream = torch.cuda.Stream(device=dev)
+    # launch shape for the candidate set: tuned on the gathered candidate rows
+    with torch.cuda.stream(stream):
+        idx, cnt, _ = ff.hfdi_candidates(scene, rad, args.hfdi_threshold, with_index_values=False, stream=stream)
+    torch.cuda.synchronize()
+    n = int(cnt.item())
+    opts = ff.default_options(n_quad=args.n_quad)
+    if not args.no_tune and n > 0:
+        sub = rad[idx[:n]].contiguous()
+        with torch.cuda.stream(stream):
+            opts, _ = ff.tune([scene], [sub], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+        torch.cuda.synchronize()
+        del sub
+    out = ff.allocate_outputs(P, 1, dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+    ev = []
+
+    def step(timed):
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record(stream)
+        ix, ct, _ = ff.hfdi_candidates(scene, rad, args.hfdi_threshold, with_index_values=False, stream=stream)
+        b.record(stream)
+        ff.retrieve_listed(scene, rad, ix, ct, prior, options=opts, outputs=out, evals=evals, stream=stream)
+        c.record(stream)
+        if timed:
+            ev.append((a, b, c))
+        return ix, ct
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        evals.zero_()
+        for _ in range(args.steps):
+            ix, ct = step(True)
+    torch.cuda.synchronize()
+    hfdi_ms = sum(a.elapsed_time(b) for a, b, c in ev) / len(ev)
+    lm_ms = sum(b.elapsed_time(c) for a, b, c in ev) / len(ev)
+    ms = hfdi_ms + lm_ms
+    n = int(ct.item())
+    cands = ix[:n].cpu().numpy()
+    r = out.numpy()
+    conv = int(((r["status"][cands].astype(np.int64) & ff.ST_CONVERGED) != 0).sum())
+    fire_idx = np.nonzero(fire)[0]
+    line = {
+        "metric": "HFDI front end + LM on the candidates: scene pixels/s and converged candidates/s",
+        "config": {"workload": f"clustered-fire scene {args.cross} x {args.lines} px x {B} bands, 3% fire, "
+                               f"SNR {args.snr:g}; HFDI >= {args.hfdi_threshold:g} (Sec. 2.1), plain LM on the "
+                               f"candidates", "pixels": P, "bands": B},
+        "candidates": n, "fire_pixels": int(fire.sum()),
+        "fire_recall": float(np.isin(fire_idx, cands).mean()),
+        "background_candidates": int((~fire[cands]).sum()),
+        "ms_per_step": ms, "hfdi_ms": hfdi_ms, "lm_ms": lm_ms,
+        "scene_pixels_per_s": P / (ms * 1e-3), "converged_candidates": conv,
+        "converged_per_s": conv / (ms * 1e-3), "evals_per_candidate": int(evals.item()) / args.steps / max(n, 1),
+        "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size,
+                   "blocks_per_cu": opts.blocks_per_cu, "schedule": opts.schedule},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -635,12 +709,14 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the tuner's")
-    ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers"),
+    ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers", "front-end"),
                     default="clustered-fire",
                     help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
                          "precision: FP32/FP64 variants on the two-component stress set; "
-                         "solvers: the paper's two-stage Adam vs LM on the clustered-fire scene")
+                         "solvers: the paper's two-stage Adam vs LM on the clustered-fire scene; "
+                         "front-end: HFDI candidate selection + LM on the candidates")
     ap.add_argument("--adam-lpp", type=int, default=1, help="lanes per pixel of the Adam kernel")
+    ap.add_argument("--hfdi-threshold", type=float, default=-0.1, help="front-end workload: HFDI threshold")
     ap.add_argument("--solver-sample", type=int, default=4096, help="oracle subsample of the solvers workload")
     ap.add_argument("--lm-budgets", type=int, nargs="*", default=[1, 2, 3, 5],
                     help="solvers workload: LM iteration caps timed beside the full LM")
@@ -660,6 +736,9 @@ def main():
         return
     if args.workload == "solvers":
         run_solvers(args)
+        return
+    if args.workload == "front-end":
+        run_front_end(args)
         return
     if args.workload == "precision":
         if args.cpu_sample == 65536:

@@ -263,6 +263,39 @@ ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,
                       const ff_options* opts, const ff_outputs* out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Fire-candidate pre-filter (Keely et al. Sec. 2.1).  Per pixel
+ *   HFDI = (L(2430 nm) - L(2061 nm)) / (L(2430 nm) + L(2061 nm)),
+ * L(lambda) the radiance of the band whose centre is nearest lambda (the
+ * lower band index on a tie), in IEEE float32 arithmetic.  A pixel is a
+ * candidate when (double)HFDI >= threshold (the paper uses -0.1) or either
+ * of the two bands is saturated (L >= the scene's saturation level: the
+ * paper keeps such pixels, saturation there being itself a sign of hot
+ * emission).  A NaN index (zero sum of zeros, non-finite radiance) is not a
+ * candidate unless a band is saturated.
+ *   radiance_dev: [P][n_bands] float32; hfdi_dev: [P] float32 index values
+ *   or NULL; index_dev: [P] int64, receives the candidates' pixel numbers
+ *   in increasing order in its first *count_dev entries; count_dev: one
+ *   int64 in device memory, receives the number of candidates.
+ * Asynchronous on stream; the count stays on the device (pass it to
+ * ff_retrieve_listed without reading it back).  Per-tile counters live in
+ * the stream's scratch buffer (see ff_retrieve_scene).  FF_EINVAL for NULL
+ * arguments, P < 0 or a NaN threshold. */
+ff_status ff_hfdi_candidates(const ff_scene* scene, const float* radiance_dev, int64_t P, double threshold,
+                             float* hfdi_dev, int64_t* index_dev, int64_t* count_dev, void* stream);
+
+/* Retrieve the listed pixels of one scene: items 0 .. min(*count_dev, P) - 1
+ * of index_dev name radiance rows (entries outside [0, P) are skipped); each
+ * listed row is solved as by ff_retrieve_scene and its outputs (and its z0
+ * row, if z0_dev is given) use the row's own position in the [P]-sized
+ * arrays; rows not listed are left untouched.  index_dev and count_dev are
+ * device memory, for example from ff_hfdi_candidates; the count is read by
+ * the kernel, so nothing waits on the host.  Asynchronous on stream. */
+ff_status ff_retrieve_listed(const ff_scene* scene, const float* radiance_dev, int64_t P,
+                             const int64_t* index_dev, const int64_t* count_dev, const ff_prior* prior,
+                             const float* z0_dev, const ff_options* opts, const ff_outputs* out,
+                             unsigned long long* evals_dev, void* stream);
+
+/* ------------------------------------------------------------------------
  * The paper's own solver: staged Adam (Keely et al. Sec. 2.5, eq. adam;
  * Kingma & Ba 2015) on the windowed loss of eq. (loss) in the z coordinate of
  * eq. (affine).  Each stage runs a fresh optimiser (t = 1, m = v = 0) for a

@@ -19,6 +19,9 @@ Parts (Keely et al., real-time physics inversion of VSWIR fire spectra):
     eq. (fm)/(solar)/(thermal) with the analytic Jacobian, the masked loss of
     eq. (loss) minimised in the z coordinate of eq. (affine) by
     Levenberg-Marquardt, Gauss-Newton covariance and mixture moments.
+  * ``adam_retrieve`` / ``paper_stages``: the paper's staged Adam (Sec. 2.5,
+    eq. adam) in the C oracle.
+  * ``hfdi`` / ``hfdi_candidates``: the fire-candidate index of Sec. 2.1.
 """
 from __future__ import annotations
 
@@ -384,6 +387,42 @@ def adam_retrieve(tab: Tables, lobs, model: int, lo, hi, x0, stages, z0=None, q:
     if rc != 0:
         raise ValueError("orc_adam_retrieve: bad arguments")
     return out
+
+
+# ----------------------------------------------------------------------------
+# Fire-candidate pre-filter (Sec. 2.1)
+# ----------------------------------------------------------------------------
+HFDI_LAMBDA_NM = (2430.0, 2061.0)
+HFDI_THRESHOLD = -0.1
+
+
+def nearest_band(lam, target_nm: float) -> int:
+    """Index of the band centre nearest target_nm (the lower index on a tie)."""
+    return int(np.argmin(np.abs(np.asarray(lam, np.float64) - target_nm)))
+
+
+def hfdi(tab: Tables, lobs):
+    """Sec. 2.1: HFDI = (L(2430) - L(2061)) / (L(2430) + L(2061)) per pixel,
+    L(lambda) the radiance of the nearest band, in float32 arithmetic (the
+    precision of the radiance), with IEEE results for a zero sum."""
+    lobs = np.asarray(lobs, np.float32)
+    a = lobs[:, nearest_band(tab.lam, HFDI_LAMBDA_NM[0])]
+    b = lobs[:, nearest_band(tab.lam, HFDI_LAMBDA_NM[1])]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return (a - b) / (a + b)
+
+
+def hfdi_candidates(tab: Tables, lobs, threshold: float = HFDI_THRESHOLD):
+    """Candidate pixels in increasing order: HFDI >= threshold (compared in
+    double), or either HFDI band saturated (Sec. 2.1 keeps saturated
+    candidates: saturation there itself indicates hot emission)."""
+    lobs = np.asarray(lobs, np.float32)
+    h = hfdi(tab, lobs)
+    keep = h.astype(np.float64) >= threshold
+    if tab.lsat is not None:
+        ia, ib = nearest_band(tab.lam, HFDI_LAMBDA_NM[0]), nearest_band(tab.lam, HFDI_LAMBDA_NM[1])
+        keep |= (lobs[:, ia] >= tab.lsat[ia]) | (lobs[:, ib] >= tab.lsat[ib])
+    return np.nonzero(keep)[0].astype(np.int64), h
 
 
 def max_threads() -> int:

@@ -43,7 +43,8 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_set_params", "ff_mlp_set_normalization", "ff_mlp_get_normalization",
            "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
-           "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch")
+           "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
+           "ff_hfdi_candidates", "ff_retrieve_listed")
 
 
 class FirefitError(RuntimeError):
@@ -172,7 +173,12 @@ def lib():
                                              C.POINTER(C.c_int64), C.c_int32, C.POINTER(ffPrior),
                                              C.POINTER(C.c_void_p), C.POINTER(ffAdamOptions),
                                              C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
-        for name in ("ff_adam_options_default", "ff_adam_retrieve_batch",
+        L.ff_hfdi_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ff_retrieve_listed.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
+                                         C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
+        for name in ("ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
                      "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
@@ -376,6 +382,52 @@ def retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None, opti
     _check(lib().ff_retrieve_batch(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
                                    _stream_handle(stream)), "ff_retrieve_batch")
     return outs
+
+
+HFDI_THRESHOLD = -0.1
+
+
+def hfdi_candidates(scene: Scene, radiance, threshold: float = HFDI_THRESHOLD, with_index_values: bool = True,
+                    stream=None):
+    """Fire-candidate pre-filter (ff_hfdi_candidates) on radiance [P, B]
+    float32 (device).  Returns (index [P] int64 whose first count entries are
+    the candidates in increasing order, count [1] int64, hfdi [P] float32 or
+    None), all on the device; the count is not read back."""
+    torch = _torch()
+    assert radiance.is_cuda and radiance.dtype == torch.float32 and radiance.is_contiguous()
+    assert radiance.dim() == 2 and radiance.shape[1] == scene.n_bands
+    P = radiance.shape[0]
+    index = torch.empty(P, dtype=torch.int64, device=radiance.device)
+    count = torch.empty(1, dtype=torch.int64, device=radiance.device)
+    h = torch.empty(P, dtype=torch.float32, device=radiance.device) if with_index_values else None
+    _check(lib().ff_hfdi_candidates(scene.handle, _ptr(radiance), P, float(threshold), _ptr(h), _ptr(index),
+                                    _ptr(count), _stream_handle(stream)), "ff_hfdi_candidates")
+    return index, count, h
+
+
+def retrieve_listed(scene: Scene, radiance, index, count, prior: Prior | None = None, z0=None,
+                    options: ffOptions | None = None, outputs: Outputs | None = None, evals=None,
+                    stream=None, state_f64: bool = False) -> Outputs:
+    """Retrieve only the rows listed by (index, count) (ff_retrieve_listed);
+    outputs are [P]-sized and unlisted rows are left as they were."""
+    torch = _torch()
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    options = options or default_options()
+    assert radiance.is_cuda and radiance.dtype == torch.float32 and radiance.is_contiguous()
+    assert radiance.dim() == 2 and radiance.shape[1] == scene.n_bands
+    P = radiance.shape[0]
+    assert index.is_cuda and index.dtype == torch.int64 and index.numel() >= 1 and index.is_contiguous()
+    assert count.is_cuda and count.dtype == torch.int64 and count.numel() == 1
+    if z0 is not None:
+        assert z0.is_cuda and z0.dtype == torch.float32 and z0.is_contiguous()
+        assert tuple(z0.shape) == (P, N_STATE[prior.model])
+    out = outputs or allocate_outputs(P, prior.model, radiance.device, state_f64)
+    pc = prior.to_c()
+    oc = out.to_c()
+    _check(lib().ff_retrieve_listed(scene.handle, _ptr(radiance), P, _ptr(index), _ptr(count), C.byref(pc),
+                                    _ptr(z0), C.byref(options), C.byref(oc), _ptr(evals),
+                                    _stream_handle(stream)), "ff_retrieve_listed")
+    return out
 
 
 def adam_options(prior: Prior | None = None, **kw) -> ffAdamOptions:

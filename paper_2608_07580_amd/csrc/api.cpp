@@ -216,6 +216,30 @@ extern "C" ff_status ff_retrieve_batch(const ff_scene* const* scenes, const floa
     return dispatch_lm(opts->precision, prior->model, opts->n_quad, bs);
 }
 
+extern "C" ff_status ff_retrieve_listed(const ff_scene* scene, const float* radiance_dev, int64_t P,
+                                        const int64_t* index_dev, const int64_t* count_dev, const ff_prior* prior,
+                                        const float* z0_dev, const ff_options* opts, const ff_outputs* out,
+                                        unsigned long long* evals_dev, void* stream)
+{
+    if (!scene || !out) return set_error(FF_EINVAL, "ff_retrieve_listed: NULL scene or outputs");
+    if (P < 0) return set_error(FF_EINVAL, "ff_retrieve_listed: P < 0");
+    if (P == 0) return clear_error();
+    if (!radiance_dev || !index_dev || !count_dev)
+        return set_error(FF_EINVAL, "ff_retrieve_listed: NULL radiance, index or count");
+    ff_status s = check_prior(prior);
+    if (s != FF_OK) return s;
+    s = check_options(opts);
+    if (s != FF_OK) return s;
+    const float* const rads[1] = {radiance_dev};
+    const float* const z0s[1] = {z0_dev};
+    const ff_scene* const scs[1] = {scene};
+    const int64_t Ps[1] = {P};
+    BatchSpec bs{scs, rads, Ps, 1, prior, z0_dev ? z0s : nullptr, opts, out, evals_dev, (hipStream_t)stream};
+    bs.index = index_dev;
+    bs.count_dev = count_dev;
+    return dispatch_lm(opts->precision, prior->model, opts->n_quad, bs);
+}
+
 extern "C" ff_status ff_retrieve_scene(const ff_scene* scene, const float* radiance_dev, int64_t P,
                                        const ff_prior* prior, const float* z0_dev, const ff_options* opts,
                                        const ff_outputs* out, unsigned long long* evals_dev, void* stream)

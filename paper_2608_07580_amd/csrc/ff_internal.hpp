@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "firefit.h"
 
@@ -42,12 +43,15 @@ static_assert(FF_TABLE_COLS == 12, "table layout");
 
 }  // namespace ff
 
-// Scene handle: per-band tables in device memory, FP32 and FP64 copies.
+// Scene handle: per-band tables in device memory, FP32 and FP64 copies, and
+// the band centres on the host.
 struct ff_scene {
     int32_t n_bands = 0;
     int device = 0;
     float* table_f32 = nullptr;   // [B][12]
     double* table_f64 = nullptr;  // [B][12]
+    std::vector<double> lambda;   // [B] band centres, nm
+    std::vector<float> lsat;      // [B] saturation levels (+inf: none)
 };
 
 namespace ff {
@@ -81,6 +85,8 @@ struct BatchSpec {
     const ff_outputs* outs;
     unsigned long long* evals;
     hipStream_t stream;
+    const int64_t* index = nullptr;     // one scene only: pixel rows to solve, or null for all
+    const int64_t* count_dev = nullptr; // with index: number of listed pixels, read on the device
 };
 
 ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs);

@@ -40,6 +40,7 @@ struct LmDesc {
     int n_scenes;
     int B;
     int64_t total;
+    const int64_t* total_dev;      // if set: min(total, *total_dev) items (a device-side count)
     unsigned long long* queue;     // queue head
     int lpp;                       // lanes per pixel (power of two, <= 64)
     unsigned long long* evals;     // += model evaluations (may be null)
@@ -102,7 +103,8 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
 #pragma unroll
     for (int j = 0; j < NT; ++j) A[j] = (R)0;
 
-    const int64_t total = launder(descp)->total;
+    int64_t total = launder(descp)->total;
+    if (const int64_t* td = launder(descp)->total_dev) total = min(total, *td);
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 
     for (;;) {
@@ -146,6 +148,10 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     sidx = scene_of(D, item);
                     const SceneDev& sd = D->sc[sidx];
                     pix = item - sd.offset;
+                    if (sd.index) pix = sd.index[pix];
+                }
+                if (need && my >= 0 && my < total && pix >= 0 && pix < D->sc[sidx].P) {
+                    const SceneDev& sd = D->sc[sidx];
                     const int B = D->B;
                     rad = sd.radiance + pix * B;
                     tab = reinterpret_cast<const R*>(sd.table);
@@ -471,6 +477,7 @@ static ff_status launch_lm(const BatchSpec& bs)
             d.table = sizeof(R) == 4 ? (const void*)bs.scenes[s]->table_f32 : (const void*)bs.scenes[s]->table_f64;
             d.P = bs.P[s];
             d.offset = off;
+            d.index = bs.index;
             d.z0 = bs.z0 ? bs.z0[s] : nullptr;
             d.state = out.state;
             d.cov = out.cov_packed;
@@ -486,6 +493,7 @@ static ff_status launch_lm(const BatchSpec& bs)
         prm.n_scenes = ns;
         prm.B = bs.scenes[0]->n_bands;
         prm.total = off;
+        prm.total_dev = bs.count_dev;
         prm.evals = bs.evals;
         prm.max_iter = o.max_iter;
         prm.warm_max_iter = o.warm_max_iter;

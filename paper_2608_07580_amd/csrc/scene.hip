@@ -99,6 +99,9 @@ extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm
 
     ff_scene* sc = new ff_scene();
     sc->n_bands = B;
+    sc->lambda.assign(srf->wavelength_nm, srf->wavelength_nm + B);
+    if (atm->sat_level) sc->lsat.assign(atm->sat_level, atm->sat_level + B);
+    else sc->lsat.assign(B, INFINITY);
     hipError_t e = hipGetDevice(&sc->device);
     // staging: [lam_b, fwhm_b, hr_lam, E, tdn, tup, ratm, S] doubles + sat floats + bad flag
     const size_t nd = 2 * (size_t)B + 6 * (size_t)H;

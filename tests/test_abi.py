@@ -136,3 +136,13 @@ def test_adam_rejects_bad_options_on_the_host(L):
     o = ff.adam_options()
     assert L.ff_adam_retrieve_batch(None, None, None, 0, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_OK
     assert L.ff_adam_retrieve_batch(None, None, None, -1, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_EINVAL
+
+
+def test_front_end_rejects_bad_arguments_on_the_host(L):
+    pr = ff.default_prior(1).to_c()
+    o = ff.default_options()
+    outs = ff.ffOutputs()
+    one = C.c_void_p(8)
+    assert L.ff_hfdi_candidates(None, one, 4, -0.1, None, one, one, None) == ff.FF_EINVAL
+    assert L.ff_retrieve_listed(None, one, 4, one, one, C.byref(pr), None, C.byref(o), C.byref(outs), None,
+                                None) == ff.FF_EINVAL
