@@ -92,6 +92,7 @@ typedef int32_t ff_status;
 #define FF_ST_USED_FALLBACK 256u   /* the solve from z0 failed; the result is from the default start x0 */
 #define FF_ST_WARM_START 512u      /* a per-pixel start z0 was used (see FF_ST_USED_FALLBACK) */
 #define FF_ST_NO_DOF 1024u         /* fewer unmasked bands than n + 1: no solve */
+#define FF_ST_BAD_ATMOSPHERE 2048u /* per-pixel atmosphere index out of range: no solve */
 #define FF_ST_CONVERGED (FF_ST_CONVERGED_GTOL | FF_ST_CONVERGED_XTOL | FF_ST_CONVERGED_FTOL)
 
 /* Columns of the per-band table of a scene (FP64 copy via
@@ -261,6 +262,21 @@ ff_status ff_tune(const ff_scene* const* scenes, const float* const* radiance_de
 ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,
                       const ff_atmosphere* atm, const ff_prior* prior, const float* z0_dev,
                       const ff_options* opts, const ff_outputs* out, void* stream);
+
+/* Per-pixel atmosphere (Keely et al. Sec. 2.3: the atmosphere is cached for
+ * the scene on a grid of quantised column water vapour and each pixel takes
+ * the entry of its pre-solved water vapour).  atmospheres: n_atm scenes
+ * (1 <= n_atm <= FF_MAX_ATMOSPHERES, the same band count), one per quantised
+ * atmosphere; atm_index_dev: [P] int32, pixel p is solved with
+ * atmospheres[atm_index_dev[p]]; a pixel whose index is outside [0, n_atm)
+ * is not solved (NaN outputs, FF_ST_BAD_ATMOSPHERE).  Otherwise as
+ * ff_retrieve_scene (radiance [P][n_bands], optional z0, outputs [P]).
+ * Asynchronous on stream. */
+#define FF_MAX_ATMOSPHERES 16
+ff_status ff_retrieve_atm_indexed(const ff_scene* const* atmospheres, int32_t n_atm, const int32_t* atm_index_dev,
+                                  const float* radiance_dev, int64_t P, const ff_prior* prior, const float* z0_dev,
+                                  const ff_options* opts, const ff_outputs* out, unsigned long long* evals_dev,
+                                  void* stream);
 
 /* ------------------------------------------------------------------------
  * Fire-candidate pre-filter (Keely et al. Sec. 2.1).  Per pixel

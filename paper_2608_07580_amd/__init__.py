@@ -30,6 +30,8 @@ TABLE_COLS = 12
 ST_CONVERGED_GTOL, ST_CONVERGED_XTOL, ST_CONVERGED_FTOL = 1, 2, 4
 ST_MAX_ITER, ST_NONFINITE_INPUT, ST_DAMPING_OVERFLOW = 8, 16, 32
 ST_COV_SINGULAR, ST_AT_BOUND, ST_USED_FALLBACK, ST_WARM_START, ST_NO_DOF = 64, 128, 256, 512, 1024
+ST_BAD_ATMOSPHERE = 2048
+MAX_ATMOSPHERES = 16
 ST_CONVERGED = ST_CONVERGED_GTOL | ST_CONVERGED_XTOL | ST_CONVERGED_FTOL
 
 N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8}
@@ -44,7 +46,7 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
            "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
-           "ff_hfdi_candidates", "ff_retrieve_listed")
+           "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed")
 
 
 class FirefitError(RuntimeError):
@@ -178,7 +180,10 @@ def lib():
         L.ff_retrieve_listed.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                          C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
                                          C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
-        for name in ("ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
+        L.ff_retrieve_atm_indexed.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                              C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
+                                              C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
+        for name in ("ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
                      "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
@@ -427,6 +432,30 @@ def retrieve_listed(scene: Scene, radiance, index, count, prior: Prior | None = 
     _check(lib().ff_retrieve_listed(scene.handle, _ptr(radiance), P, _ptr(index), _ptr(count), C.byref(pc),
                                     _ptr(z0), C.byref(options), C.byref(oc), _ptr(evals),
                                     _stream_handle(stream)), "ff_retrieve_listed")
+    return out
+
+
+def retrieve_atm_indexed(atmospheres, atm_index, radiance, prior: Prior | None = None, z0=None,
+                         options: ffOptions | None = None, outputs: Outputs | None = None, evals=None,
+                         stream=None, state_f64: bool = False) -> Outputs:
+    """Retrieval with a per-pixel atmosphere (ff_retrieve_atm_indexed): pixel p
+    uses atmospheres[atm_index[p]] (atm_index: [P] int32 device tensor)."""
+    torch = _torch()
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    options = options or default_options()
+    assert radiance.is_cuda and radiance.dtype == torch.float32 and radiance.is_contiguous()
+    P = radiance.shape[0]
+    assert atm_index.is_cuda and atm_index.dtype == torch.int32 and atm_index.numel() == P
+    if z0 is not None:
+        assert z0.is_cuda and z0.dtype == torch.float32 and z0.is_contiguous()
+    out = outputs or allocate_outputs(P, prior.model, radiance.device, state_f64)
+    na = len(atmospheres)
+    sc = (C.c_void_p * na)(*[s.handle.value for s in atmospheres])
+    pc = prior.to_c()
+    oc = out.to_c()
+    _check(lib().ff_retrieve_atm_indexed(sc, na, _ptr(atm_index), _ptr(radiance), P, C.byref(pc), _ptr(z0),
+                                         C.byref(options), C.byref(oc), _ptr(evals), _stream_handle(stream)),
+           "ff_retrieve_atm_indexed")
     return out
 
 

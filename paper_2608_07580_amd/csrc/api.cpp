@@ -240,6 +240,37 @@ extern "C" ff_status ff_retrieve_listed(const ff_scene* scene, const float* radi
     return dispatch_lm(opts->precision, prior->model, opts->n_quad, bs);
 }
 
+extern "C" ff_status ff_retrieve_atm_indexed(const ff_scene* const* atmospheres, int32_t n_atm,
+                                             const int32_t* atm_index_dev, const float* radiance_dev, int64_t P,
+                                             const ff_prior* prior, const float* z0_dev, const ff_options* opts,
+                                             const ff_outputs* out, unsigned long long* evals_dev, void* stream)
+{
+    if (!atmospheres || !out) return set_error(FF_EINVAL, "ff_retrieve_atm_indexed: NULL atmospheres or outputs");
+    if (n_atm < 1 || n_atm > FF_MAX_ATMOSPHERES)
+        return set_error(FF_EINVAL, "ff_retrieve_atm_indexed: n_atm must be in [1, FF_MAX_ATMOSPHERES]");
+    for (int a = 0; a < n_atm; ++a) {
+        if (!atmospheres[a]) return set_error(FF_EINVAL, "ff_retrieve_atm_indexed: NULL atmosphere");
+        if (atmospheres[a]->n_bands != atmospheres[0]->n_bands)
+            return set_error(FF_EINVAL, "ff_retrieve_atm_indexed: atmospheres differ in band count");
+    }
+    if (P < 0) return set_error(FF_EINVAL, "ff_retrieve_atm_indexed: P < 0");
+    if (P == 0) return clear_error();
+    if (!radiance_dev || !atm_index_dev) return set_error(FF_EINVAL, "ff_retrieve_atm_indexed: NULL radiance or index");
+    ff_status s = check_prior(prior);
+    if (s != FF_OK) return s;
+    s = check_options(opts);
+    if (s != FF_OK) return s;
+    const float* const rads[1] = {radiance_dev};
+    const float* const z0s[1] = {z0_dev};
+    const ff_scene* const scs[1] = {atmospheres[0]};
+    const int64_t Ps[1] = {P};
+    BatchSpec bs{scs, rads, Ps, 1, prior, z0_dev ? z0s : nullptr, opts, out, evals_dev, (hipStream_t)stream};
+    bs.atms = atmospheres;
+    bs.n_atm = n_atm;
+    bs.atm_index = atm_index_dev;
+    return dispatch_lm(opts->precision, prior->model, opts->n_quad, bs);
+}
+
 extern "C" ff_status ff_retrieve_scene(const ff_scene* scene, const float* radiance_dev, int64_t P,
                                        const ff_prior* prior, const float* z0_dev, const ff_options* opts,
                                        const ff_outputs* out, unsigned long long* evals_dev, void* stream)

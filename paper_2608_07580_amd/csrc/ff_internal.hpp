@@ -87,6 +87,9 @@ struct BatchSpec {
     hipStream_t stream;
     const int64_t* index = nullptr;     // one scene only: pixel rows to solve, or null for all
     const int64_t* count_dev = nullptr; // with index: number of listed pixels, read on the device
+    const ff_scene* const* atms = nullptr;  // one scene only: per-pixel atmospheres ...
+    int n_atm = 0;
+    const int32_t* atm_index = nullptr;     // ... chosen by this [P] index
 };
 
 ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs);

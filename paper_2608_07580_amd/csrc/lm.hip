@@ -50,6 +50,8 @@ struct LmDesc {
     int fallback;
     double xtol, ftol, gtol, kappa, tau;
     double lo[FF_MAX_STATE], hi[FF_MAX_STATE], zdef[FF_MAX_STATE];
+    int n_atm;                     // per-pixel atmospheres (with SceneDev::atm)
+    const void* atm_tables[FF_MAX_ATMOSPHERES];
 };
 
 namespace {
@@ -155,21 +157,31 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     const int B = D->B;
                     rad = sd.radiance + pix * B;
                     tab = reinterpret_cast<const R*>(sd.table);
+                    bool atm_ok = true;
+                    if (sd.atm) {
+                        const int a = sd.atm[pix];
+                        atm_ok = a >= 0 && a < D->n_atm;
+                        tab = atm_ok ? reinterpret_cast<const R*>(D->atm_tables[a]) : nullptr;
+                    }
                     int nonfin = 0;
-                    scan_pixel<R>(rad, tab, B, sub, L, nonfin, nvalid, lnorm2);
+                    nvalid = 0;
+                    lnorm2 = 0.0;
+                    if (atm_ok) scan_pixel<R>(rad, tab, B, sub, L, nonfin, nvalid, lnorm2);
                     const bool fin = nonfin == 0;
                     it = 0;
                     phase = 0;
                     st = 0;
                     warm = false;
                     fbmode = false;
-                    if (!fin || nvalid <= N) {
+                    if (!atm_ok || !fin || nvalid <= N) {
                         if (head) {
                             const OutPtrs o = out_ptrs(sd);
                             write_nan<N>(o, pix);
                             if (o.rrr) o.rrr[pix] = __builtin_nanf("");
                             if (o.iters) o.iters[pix] = 0;
-                            if (o.status) o.status[pix] = !fin ? FF_ST_NONFINITE_INPUT : FF_ST_NO_DOF;
+                            if (o.status)
+                                o.status[pix] = !atm_ok ? FF_ST_BAD_ATMOSPHERE
+                                                        : (!fin ? FF_ST_NONFINITE_INPUT : FF_ST_NO_DOF);
                         }
                     } else {
                         const float* z0 = sd.z0;
@@ -478,6 +490,7 @@ static ff_status launch_lm(const BatchSpec& bs)
             d.P = bs.P[s];
             d.offset = off;
             d.index = bs.index;
+            d.atm = bs.atm_index;
             d.z0 = bs.z0 ? bs.z0[s] : nullptr;
             d.state = out.state;
             d.cov = out.cov_packed;
@@ -494,6 +507,9 @@ static ff_status launch_lm(const BatchSpec& bs)
         prm.B = bs.scenes[0]->n_bands;
         prm.total = off;
         prm.total_dev = bs.count_dev;
+        prm.n_atm = bs.atm_index ? bs.n_atm : 0;
+        for (int a = 0; a < prm.n_atm; ++a)
+            prm.atm_tables[a] = sizeof(R) == 4 ? (const void*)bs.atms[a]->table_f32 : (const void*)bs.atms[a]->table_f64;
         prm.evals = bs.evals;
         prm.max_iter = o.max_iter;
         prm.warm_max_iter = o.warm_max_iter;

@@ -16,13 +16,15 @@ constexpr int kMaxScenesPerLaunch = 16;
 // One scene of a launch: inputs, per-pixel start, outputs, and the offset of
 // its first pixel in the launch's pixel numbering.  With a row list, item i
 // of the scene solves radiance row index[i] (rows outside [0, P) are
-// skipped) and writes that row's outputs.
+// skipped) and writes that row's outputs.  With a per-pixel atmosphere
+// index, row p uses the launch's atmosphere table atm[p].
 struct SceneDev {
     const float* radiance;
     const void* table;
     int64_t P;
     int64_t offset;
     const int64_t* index;
+    const int32_t* atm;
     const float* z0;
     float* state;
     float* cov;

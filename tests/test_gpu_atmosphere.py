@@ -1,0 +1,88 @@
+"""GPU tests of the atmosphere terms of eq. (solar) and of the per-pixel
+atmosphere choice (Sec. 2.3: atmospheres cached per quantised water vapour,
+one per pixel) through the C ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from _helpers import CONVERGED, assert_parity, noisy_spectra
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2608_07580_amd as ff  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def _np(out):
+    return out.numpy()
+
+
+def test_retrieval_with_path_reflectance_and_spherical_albedo(dev):
+    """rho_atm = 0.02, S = 0.15, cos(sza) = 0.7: the 1/(1 - S rho) term and its
+    Jacobian in the retrieval, FP64 and FP32 against the oracle."""
+    atm = scenegen.make_atmosphere(0, 3, rho_atm=0.02, s_sph=0.15, cos_sza=0.7)
+    tab = oracle.band_tables(atm)
+    X = scenegen.config0_states(800, scene=3)
+    lobs = noisy_spectra(tab, X, 1, 0, 3)
+    lo, hi, x0 = scenegen.default_prior(1)
+    prior = ff.Prior(1, lo, hi, x0)
+    ref = oracle.retrieve(tab, lobs, 1, lo, hi, x0)
+    scene = ff.Scene(atm)
+    rad = torch.from_numpy(lobs).to(dev)
+    r64 = _np(ff.retrieve(scene, rad, prior, options=ff.default_options(precision=ff.PRECISION_FP64),
+                          state_f64=True))
+    torch.cuda.synchronize()
+    both = ((r64["status"].astype(np.int64) & CONVERGED) != 0) & ref.converged
+    assert both.mean() >= 0.97
+    assert np.abs(r64["state_f64"][both, 0] - ref.state[both, 0]).max() <= 1e-7
+    assert np.abs(r64["moments"][both, 0] - ref.moments[both, 0]).max() <= 1e-2
+    r32 = _np(ff.retrieve(scene, rad, prior))
+    torch.cuda.synchronize()
+    assert_parity(r32, ref, min_t=400, label="rho_atm, S")
+
+
+def test_per_pixel_atmosphere_index(dev):
+    """Four atmospheres (different water-vapour dips, one with path
+    reflectance and spherical albedo); each pixel made and solved with its
+    own.  The indexed retrieval equals the per-atmosphere retrievals bitwise
+    and matches the oracle; indices outside [0, 4) are not solved."""
+    atms = [scenegen.make_atmosphere(0, s) for s in range(3)]
+    atms.append(scenegen.make_atmosphere(0, 3, rho_atm=0.02, s_sph=0.15, cos_sza=0.8))
+    tabs = [oracle.band_tables(a) for a in atms]
+    P = 2400
+    X = scenegen.config0_states(P, scene=11)
+    aid = np.random.default_rng(5).integers(0, 4, P).astype(np.int32)
+    aid[[3, 77, 500]] = [-1, 4, 9]
+    noise = scenegen.noise_normals(0, 11, P, tabs[0].B)
+    lobs = np.zeros((P, tabs[0].B), np.float32)
+    for a in range(4):
+        m = aid == a
+        L = oracle.forward(tabs[a], X[m], 1)
+        lobs[m] = (L * (1.0 + noise[m] / 300.0)).astype(np.float32)
+    bad = (aid < 0) | (aid > 3)
+    lobs[bad] = lobs[~bad][:bad.sum()]
+    scenes = [ff.Scene(a) for a in atms]
+    prior = ff.default_prior(1)
+    rad = torch.from_numpy(lobs).to(dev)
+    ids = torch.from_numpy(aid).to(dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+    r = _np(ff.retrieve_atm_indexed(scenes, ids, rad, prior, evals=evals))
+    torch.cuda.synchronize()
+    assert np.all(r["status"][bad] == ff.ST_BAD_ATMOSPHERE) and np.all(np.isnan(r["state"][bad]))
+    for a in range(4):
+        m = aid == a
+        single = _np(ff.retrieve(scenes[a], torch.from_numpy(lobs[m]).to(dev), prior))
+        torch.cuda.synchronize()
+        for k in ("state", "cov", "moments", "rrr", "iters", "status"):
+            np.testing.assert_array_equal(r[k][m], single[k])
+        ref = oracle.retrieve(tabs[a], lobs[m], 1, prior.lo, prior.hi, prior.x0)
+        sub = {k: v[m] for k, v in r.items() if v is not None}
+        assert_parity(sub, ref, min_same=0.97, min_t=50, label=f"atmosphere {a}")
+    assert int(evals.item()) == int((r["iters"][~bad] + 1).sum())
