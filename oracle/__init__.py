@@ -196,7 +196,13 @@ def planck(lam_nm, T, with_derivative: bool = False):
 
 
 def n_state(model: int) -> int:
-    return {1: 5, 2: 8}[model]
+    return {1: 5, 2: 8, 3: 8}[model]
+
+
+def grid_nodes(G: int):
+    """Temperature grid of the Gaussian-mixture model (model 3): G uniform
+    nodes over [350, 2200] K (Sec. 2.2)."""
+    return 350.0 + (2200.0 - 350.0) * np.arange(G) / (G - 1)
 
 
 def x_to_z(x, lo, hi):

@@ -16,7 +16,9 @@
  *     with p(T) a lognormal of mean m and s.d. s (one component) or the
  *     eta-weighted mixture of a smouldering and a flaming lognormal (Sec. 2.2,
  *     two-component mixture), integrated by Gauss-Hermite quadrature in log T,
- *     and a linear reflectance rho = rho0 + rho1 (lambda - 1440 nm).
+ *     or the paper's own form: the eta-weighted mixture of two Gaussians
+ *     summed over a temperature grid spanning [350, 2200] K (model 3), and a
+ *     linear reflectance rho = rho0 + rho1 (lambda - 1440 nm).
  *   - analytic Jacobian of L with respect to the physical state
  *   - the masked least-squares loss (Sec. 2.5, eq. loss) minimised in the
  *     normalised coordinate z of eq. (affine) with z clipped to [-1, 1]
@@ -122,6 +124,55 @@ static void component_integrals(double lam, double mu, double sig, int Q,
     *I = si; *Imu = sm; *Isig = ss;
 }
 
+/* Gaussian component on the temperature grid of Sec. 2.2 (the thermal
+ * integral is a discrete sum over a grid spanning [350, 2200] K): G uniform
+ * nodes T_i = 350 + i (2200 - 350)/(G - 1), weights
+ *   p_i = w_i / sum_j w_j,  w_i = exp(-(T_i - mu)^2 / (2 sig^2))
+ * (the normalisation truncates the Gaussian to the grid).  Also the
+ * weighted moments m1 = sum p_i d_i and m2 = sum p_i d_i^2, d_i = T_i - mu. */
+static const double GRID_T_LO = 350.0, GRID_T_HI = 2200.0;
+
+static double grid_node(int G, int i) { return GRID_T_LO + (GRID_T_HI - GRID_T_LO) * i / (G - 1); }
+
+static void grid_weights(int G, double mu, double sig, double* pw, double* m1, double* m2)
+{
+    double emax = -INFINITY;
+    for (int i = 0; i < G; ++i) {
+        const double d = grid_node(G, i) - mu;
+        pw[i] = -d * d / (2.0 * sig * sig);
+        if (pw[i] > emax) emax = pw[i];
+    }
+    double W = 0.0;
+    for (int i = 0; i < G; ++i) { pw[i] = exp(pw[i] - emax); W += pw[i]; }
+    *m1 = *m2 = 0.0;
+    for (int i = 0; i < G; ++i) {
+        pw[i] /= W;
+        const double d = grid_node(G, i) - mu;
+        *m1 += pw[i] * d;
+        *m2 += pw[i] * d * d;
+    }
+}
+
+/* Grid sums of one component at one band: I = sum p_i B(lam, T_i) and its
+ * derivatives dI/dmu = (M1 - m1 I)/sig^2, dI/dsig = (M2 - m2 I)/sig^3, with
+ * M_k = sum p_i d_i^k B(lam, T_i) (from dp_i/dmu = p_i (d_i - m1)/sig^2 and
+ * dp_i/dsig = p_i (d_i^2 - m2)/sig^3). */
+static void grid_integrals(double lam, int G, double mu, double sig, double* I, double* Imu, double* Isig)
+{
+    double pw[QMAX], m1, m2, M0 = 0.0, M1 = 0.0, M2 = 0.0;
+    grid_weights(G, mu, sig, pw, &m1, &m2);
+    for (int i = 0; i < G; ++i) {
+        const double T = grid_node(G, i), d = T - mu;
+        const double b = orc_planck(lam, T, 0) * pw[i];
+        M0 += b;
+        M1 += b * d;
+        M2 += b * d * d;
+    }
+    *I = M0;
+    *Imu = (M1 - m1 * M0) / (sig * sig);
+    *Isig = (M2 - m2 * M0) / (sig * sig * sig);
+}
+
 typedef struct {
     int B;
     const double *lam, *K, *tau2, *tup, *ratm, *S;
@@ -129,7 +180,7 @@ typedef struct {
     const double *gx, *gw;
 } scene_t;
 
-static int n_of_model(int model) { return model == 1 ? 5 : (model == 2 ? 8 : -1); }
+static int n_of_model(int model) { return model == 1 ? 5 : ((model == 2 || model == 3) ? 8 : -1); }
 
 /* Forward model at one band for physical state x; fills dL/dx if dl != 0. */
 static double model_band(const scene_t* sc, int b, int model, const double* x, double* dl)
@@ -152,6 +203,22 @@ static double model_band(const scene_t* sc, int b, int model, const double* x, d
             dl[0] = tup * I;
             dl[1] = f * tup * (Imu * dmu[0] + Isig * dsig[0]);
             dl[2] = f * tup * (Imu * dmu[1] + Isig * dsig[1]);
+        }
+    } else if (model == 3) {
+        /* the paper's mixture: eta-weighted flaming and smouldering Gaussians
+         * on the temperature grid (Q = grid nodes) */
+        const double eta = x[1];
+        double Is, Ism, Iss, Ih, Ihm, Ihs;
+        grid_integrals(lam, sc->Q, x[2], x[3], &Is, &Ism, &Iss);
+        grid_integrals(lam, sc->Q, x[4], x[5], &Ih, &Ihm, &Ihs);
+        thermal_I = eta * Ih + (1.0 - eta) * Is;
+        if (dl) {
+            dl[0] = tup * thermal_I;
+            dl[1] = f * tup * (Ih - Is);
+            dl[2] = f * tup * (1.0 - eta) * Ism;
+            dl[3] = f * tup * (1.0 - eta) * Iss;
+            dl[4] = f * tup * eta * Ihm;
+            dl[5] = f * tup * eta * Ihs;
         }
     } else {
         const double eta = x[1];
@@ -186,7 +253,7 @@ int orc_forward(int B, const double* lam, const double* K, const double* tau2,
                 int nthreads)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || B <= 0) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || B <= 0) return -1;
     scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -516,7 +583,7 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
                  int* iters, unsigned* status)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || B <= 0 || P < 0) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || B <= 0 || P < 0) return -1;
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
     scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
     lmopt_t o = {max_iter, xtol, ftol, gtol, kappa, tau};
@@ -648,7 +715,7 @@ int orc_adam_retrieve(int B, const double* lam, const double* K, const double* t
                       int* iters, unsigned* status)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || B <= 0 || P < 0 || n_stages < 0 || n_stages > 16) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || B <= 0 || P < 0 || n_stages < 0 || n_stages > 16) return -1;
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
     adam_stage_t st[16];
     for (int k = 0; k < n_stages; ++k) {

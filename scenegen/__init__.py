@@ -34,12 +34,14 @@ STREAM_SUBSAMPLE = 4
 
 MODEL_LOGNORMAL_1 = 1  # state (f, m, s, rho0, rho1)
 MODEL_LOGNORMAL_2 = 2  # state (f, eta, m_s, s_s, m_h, s_h, rho0, rho1)
+MODEL_GAUSS_GRID_2 = 3  # state (f, eta, mu_s, sig_s, mu_h, sig_h, rho0, rho1)
 
-N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8}
+N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8}
 
 STATE_NAMES = {
     MODEL_LOGNORMAL_1: ("f", "m", "s", "rho0", "rho1"),
     MODEL_LOGNORMAL_2: ("f", "eta", "m_s", "s_s", "m_h", "s_h", "rho0", "rho1"),
+    MODEL_GAUSS_GRID_2: ("f", "eta", "mu_s", "sig_s", "mu_h", "sig_h", "rho0", "rho1"),
 }
 
 # Exact SI constants (2019 redefinition) used to define the synthetic sun.
@@ -157,6 +159,10 @@ def default_prior(model: int):
         lo = np.array([0.0, 0.0, 350.0, 1.0, 900.0, 1.0, -0.2, -5e-4])
         hi = np.array([0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 5e-4])
         x0 = np.array([0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.0])
+    elif model == MODEL_GAUSS_GRID_2:
+        lo = np.array([0.0, 0.0, 350.0, 10.0, 900.0, 10.0, -0.2, -5e-4])
+        hi = np.array([0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 5e-4])
+        x0 = np.array([0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.0])
     else:
         raise ValueError(f"unknown model {model}")
     return lo, hi, x0
@@ -189,6 +195,27 @@ def draw_states_lognormal2(rng: np.random.Generator, n: int) -> np.ndarray:
     r0 = rng.uniform(0.05, 0.4, n)
     r1 = rng.uniform(-1e-4, 1e-4, n)
     return np.stack([f, eta, ms, ss, mh, sh, r0, r1], axis=1)
+
+
+def draw_states_gauss_grid2(rng: np.random.Generator, n: int) -> np.ndarray:
+    """States of the Gaussian-mixture model: f ~ logU[1e-4, 0.1], eta ~
+    U[0.05, 0.95], smouldering mean U[450, 850] K, flaming mean U[950, 1700]
+    K, spreads U[30, 250] K, reflectance as in the one-component draw.
+    Shape [n, 8]."""
+    f = np.exp(rng.uniform(math.log(1e-4), math.log(0.1), n))
+    eta = rng.uniform(0.05, 0.95, n)
+    ms = rng.uniform(450.0, 850.0, n)
+    ss = rng.uniform(30.0, 250.0, n)
+    mh = rng.uniform(950.0, 1700.0, n)
+    sh = rng.uniform(30.0, 250.0, n)
+    r0 = rng.uniform(0.05, 0.4, n)
+    r1 = rng.uniform(-1e-4, 1e-4, n)
+    return np.stack([f, eta, ms, ss, mh, sh, r0, r1], axis=1)
+
+
+def config5_states(n_pixels: int = 262144, scene: int = 0) -> np.ndarray:
+    """The paper's two-Gaussian mixture on the temperature grid."""
+    return draw_states_gauss_grid2(rng_for(5, scene, STREAM_PARAMS), n_pixels)
 
 
 def config0_states(n_pixels: int = 4096, scene: int = 0) -> np.ndarray:
