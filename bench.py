@@ -618,6 +618,110 @@ def run_solvers(args):
     print(json.dumps(line), flush=True)
 
 
+def grid_slots_per_eval(n_bands: int, n_nodes: int) -> int:
+    """Algorithmic VALU slots of one evaluation of the Gaussian-mixture model
+    on the temperature grid: per (band, node) one Planck ratio shared by the
+    two components (x = a2/T: 1, exp2: 2, minus 1: 1, rcp: 2) and 7 per
+    component for its weight product and the three centred sums; per band 70
+    for the scaling, solar term, basis, residual and the J^T J, J^T r, r.r
+    accumulations (n = 8)."""
+    return n_bands * (n_nodes * (6 + 2 * 7) + 70)
+
+
+def run_paper_model(args):
+    """The paper's thermal form (two Gaussians on a [350, 2200] K grid, Sec.
+    2.2) on a 262,144-pixel two-component set: LM (tuned launch) and the
+    paper's staged Adam, timed, with E[T] accuracy against the truth and the
+    FP64 oracle's LM on a seeded subsample."""
+    import torch
+    import oracle
+    import paper_2608_07580_amd as ff
+    import scenegen
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _helpers import parity_report
+    dev = torch.device("cuda:0")
+    ff.lib()
+    P = args.precision_pixels
+    model = ff.MODEL_GAUSS_GRID_2
+    X = scenegen.config5_states(P)
+    atm = scenegen.make_atmosphere(5, 0)
+    sc = ff.Scene(atm)
+    B = sc.n_bands
+    L = torch.empty((P, B), dtype=torch.float64, device=dev)
+    for s0 in range(0, P, 1 << 16):
+        L[s0:s0 + (1 << 16)] = ff.forward(sc, torch.tensor(X[s0:s0 + (1 << 16)], dtype=torch.float64, device=dev),
+                                          model)
+    noise = torch.from_numpy(scenegen.noise_normals(5, 0, P, B)).to(dev)
+    rad = (L * (1.0 + noise.double() / args.snr)).float().contiguous()
+    del L, noise
+    torch.cuda.synchronize()
+    prior = ff.default_prior(model)
+    stream = torch.cuda.Stream(device=dev)
+    opts = ff.default_options(n_quad=args.n_quad, max_iter=args.grid_max_iter)
+    if not args.no_tune:
+        with torch.cuda.stream(stream):
+            opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+        torch.cuda.synchronize()
+
+    def timed(launch):
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                launch()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                launch()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    et_true, _ = oracle.mixture_moments(X[:, 1], X[:, 4], X[:, 5], X[:, 2], X[:, 3])
+    strong = X[:, 0] >= 1e-2
+
+    def acc(r):
+        d = np.abs(r["moments"][:, 0] - et_true)
+        return {"dT_median_K": float(np.median(d)), "dT_median_strong_K": float(np.median(d[strong])),
+                "rrr_median": float(np.nanmedian(r["rrr"]))}
+
+    out = ff.allocate_outputs(P, model, dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms_lm = timed(lambda: ff.retrieve(sc, rad, prior, options=opts, outputs=out, evals=evals, stream=stream))
+    r_lm = out.numpy()
+    ev = int(evals.item()) / (args.steps + args.warmup)
+    conv = int(((r_lm["status"].astype(np.int64) & ff.ST_CONVERGED) != 0).sum())
+    spe = grid_slots_per_eval(B, args.n_quad)
+    achieved = ev * spe / (ms_lm * 1e-3)
+    aopt = ff.adam_options(prior, n_quad=args.n_quad)
+    out_a = ff.allocate_outputs(P, model, dev)
+    ms_ad = timed(lambda: ff.adam_retrieve(sc, rad, prior, options=aopt, outputs=out_a, stream=stream))
+    r_ad = out_a.numpy()
+    idx = scenegen.subsample(5, 0, P, args.solver_sample)
+    tab = oracle.band_tables(atm)
+    lo, hi, x0 = scenegen.default_prior(model)
+    t0 = time.time()
+    ref = oracle.retrieve(tab, rad[torch.from_numpy(idx).to(dev)].cpu().numpy(), model, lo, hi, x0,
+                          opts=oracle.LMOptions(max_iter=args.grid_max_iter), nthreads=len(os.sched_getaffinity(0)))
+    t_or = time.time() - t0
+    rep = parity_report({k: v[idx] for k, v in r_lm.items() if v is not None}, ref, model=2)
+    line = {
+        "metric": "the paper's Gaussian-mixture thermal model: LM and staged Adam retrievals per second",
+        "config": {"workload": f"two-Gaussian mixture on a {args.n_quad}-node [350, 2200] K grid, {P} px x {B} bands, "
+                               f"1e-4 <= f <= 0.1, SNR {args.snr:g}", "pixels": P, "nodes": args.n_quad,
+                   "max_iter": args.grid_max_iter},
+        "lm": {"ms_per_step": ms_lm, "converged": conv, "converged_per_s": conv / (ms_lm * 1e-3),
+               "evals_per_pixel": ev / P, "accuracy": acc(r_lm),
+               "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
+               "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tops/s",
+                            "frac": achieved / PEAK_SLOTS, "kernel": "lm_kernel", "ops_per_eval": spe}},
+        "adam": {"ms_per_step": ms_ad, "pixels_per_s": P / (ms_ad * 1e-3), "accuracy": acc(r_ad)},
+        "oracle_sample": {"pixels": len(idx), "s": t_or, "converged": int(ref.converged.sum()),
+                          "gpu_lm_vs_oracle": {k: v for k, v in rep.items() if not k.endswith("_mask")}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_front_end(args):
     """The paper's candidate selection in front of the retrieval: the HFDI
     pre-filter (Sec. 2.1, threshold -0.1) builds the candidate list on the
@@ -709,12 +813,15 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the tuner's")
-    ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers", "front-end"),
+    ap.add_argument("--grid-max-iter", type=int, default=200, help="paper-model workload: LM iteration cap")
+    ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers", "front-end",
+                                           "paper-model"),
                     default="clustered-fire",
                     help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
                          "precision: FP32/FP64 variants on the two-component stress set; "
                          "solvers: the paper's two-stage Adam vs LM on the clustered-fire scene; "
-                         "front-end: HFDI candidate selection + LM on the candidates")
+                         "front-end: HFDI candidate selection + LM on the candidates; "
+                         "paper-model: the paper's two-Gaussian grid thermal model, LM and staged Adam")
     ap.add_argument("--adam-lpp", type=int, default=1, help="lanes per pixel of the Adam kernel")
     ap.add_argument("--hfdi-threshold", type=float, default=-0.1, help="front-end workload: HFDI threshold")
     ap.add_argument("--solver-sample", type=int, default=4096, help="oracle subsample of the solvers workload")
@@ -739,6 +846,9 @@ def main():
         return
     if args.workload == "front-end":
         run_front_end(args)
+        return
+    if args.workload == "paper-model":
+        run_paper_model(args)
         return
     if args.workload == "precision":
         if args.cpu_sample == 65536:

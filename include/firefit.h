@@ -59,11 +59,19 @@ typedef int32_t ff_status;
 /* Temperature-distribution models and their state vectors (physical units):
  *   FF_MODEL_LOGNORMAL_1: n = 5, x = (f, m, s, rho0, rho1)
  *   FF_MODEL_LOGNORMAL_2: n = 8, x = (f, eta, m_s, s_s, m_h, s_h, rho0, rho1)
+ *   FF_MODEL_GAUSS_GRID_2: n = 8, x = (f, eta, mu_s, sig_s, mu_h, sig_h, rho0, rho1)
  * f: emitting fraction scaling the thermal term (the paper's alpha),
  * m/s: lognormal mean and s.d. in K, eta: weight of the flaming component,
- * rho0: reflectance at 1440 nm, rho1: reflectance slope per nm. */
+ * rho0: reflectance at 1440 nm, rho1: reflectance slope per nm.  The
+ * lognormal models integrate the Planck radiance by n_quad-node
+ * Gauss-Hermite quadrature in log T.  FF_MODEL_GAUSS_GRID_2 is the paper's
+ * own form (Sec. 2.2): the eta-weighted mixture of a smouldering and a
+ * flaming Gaussian of means mu and s.d. sig, each normalised over a grid of
+ * n_quad uniform temperatures spanning [350, 2200] K, and the thermal term
+ * the grid sum of the Planck radiance. */
 #define FF_MODEL_LOGNORMAL_1 1
 #define FF_MODEL_LOGNORMAL_2 2
+#define FF_MODEL_GAUSS_GRID_2 3
 #define FF_MAX_STATE 8
 
 /* Arithmetic of the forward model, Jacobian and reductions.  The damped
@@ -186,7 +194,9 @@ void ff_options_default(ff_options* opts);
  * [0, 1], smouldering mean in [350, 900] K and flaming mean in
  * [900, 2200] K (the 900 K regime split of Sec. 3.4), rho0 in [-0.2, 1],
  * rho1 in [-5e-4, 5e-4] /nm; start f = 0.01, m = 1000, s = 150, eta = 0.5,
- * m_s = 650, m_h = 1200, rho0 = 0.2, rho1 = 0.  FF_EINVAL for an unknown model. */
+ * m_s = 650, m_h = 1200, rho0 = 0.2, rho1 = 0.  FF_MODEL_GAUSS_GRID_2 takes
+ * the two-component box and start with the spreads in [10, 500] K.
+ * FF_EINVAL for an unknown model. */
 ff_status ff_prior_default(int32_t model, ff_prior* prior);
 
 /* Gauss-Hermite rule for weight e^{-x^2}: q nodes and weights (host arrays

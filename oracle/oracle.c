@@ -154,23 +154,25 @@ static void grid_weights(int G, double mu, double sig, double* pw, double* m1, d
 }
 
 /* Grid sums of one component at one band: I = sum p_i B(lam, T_i) and its
- * derivatives dI/dmu = (M1 - m1 I)/sig^2, dI/dsig = (M2 - m2 I)/sig^3, with
- * M_k = sum p_i d_i^k B(lam, T_i) (from dp_i/dmu = p_i (d_i - m1)/sig^2 and
- * dp_i/dsig = p_i (d_i^2 - m2)/sig^3). */
+ * derivatives from dp_i/dmu = p_i (d_i - m1)/sig^2 and
+ * dp_i/dsig = p_i (d_i^2 - m2)/sig^3:
+ *   dI/dmu = sum p_i (d_i - m1) B_i / sig^2,  dI/dsig = sum p_i (d_i^2 - m2) B_i / sig^3
+ * (summed in this centred form, which keeps full precision when one node
+ * carries nearly all the weight). */
 static void grid_integrals(double lam, int G, double mu, double sig, double* I, double* Imu, double* Isig)
 {
-    double pw[QMAX], m1, m2, M0 = 0.0, M1 = 0.0, M2 = 0.0;
+    double pw[QMAX], m1, m2, M0 = 0.0, S1 = 0.0, S2 = 0.0;
     grid_weights(G, mu, sig, pw, &m1, &m2);
     for (int i = 0; i < G; ++i) {
         const double T = grid_node(G, i), d = T - mu;
         const double b = orc_planck(lam, T, 0) * pw[i];
         M0 += b;
-        M1 += b * d;
-        M2 += b * d * d;
+        S1 += b * (d - m1);
+        S2 += b * (d * d - m2);
     }
     *I = M0;
-    *Imu = (M1 - m1 * M0) / (sig * sig);
-    *Isig = (M2 - m2 * M0) / (sig * sig * sig);
+    *Imu = S1 / (sig * sig);
+    *Isig = S2 / (sig * sig * sig);
 }
 
 typedef struct {

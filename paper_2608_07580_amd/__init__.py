@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfirefit.so")
 
 FF_OK, FF_EINVAL, FF_EDEVICE, FF_ENOMEM, FF_EUNSUPPORTED = 0, -1, -2, -3, -4
-MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2 = 1, 2
+MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2, MODEL_GAUSS_GRID_2 = 1, 2, 3
 PRECISION_FP32, PRECISION_FP64 = 0, 1
 SCHEDULE_PERSISTENT, SCHEDULE_STATIC = 0, 1
 ACCUMULATE_FP32, ACCUMULATE_FP64 = 0, 1
@@ -34,7 +34,7 @@ ST_BAD_ATMOSPHERE = 2048
 MAX_ATMOSPHERES = 16
 ST_CONVERGED = ST_CONVERGED_GTOL | ST_CONVERGED_XTOL | ST_CONVERGED_FTOL
 
-N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8}
+N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8}
 
 # exported symbols of include/firefit.h
 EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_default",

@@ -286,7 +286,7 @@ static ff_status launch_adam(const AdamSpec& as)
     const int lpp = o.lanes_per_pixel > 0 ? o.lanes_per_pixel : 1;
     int dev = 0;
     FF_HIP_TRY(hipGetDevice(&dev));
-    if (!ensure_quad<R, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
+    if (!ensure_tables<R, MODEL, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
     int64_t total = 0;
     for (int s = 0; s < as.n_scenes; ++s) total += as.P[s];
     if (total == 0) return clear_error();
@@ -401,11 +401,16 @@ ff_status dispatch_adam(const AdamSpec& as)
             if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_LOGNORMAL_1) }
             FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_LOGNORMAL_1)
         }
+        if (model == FF_MODEL_GAUSS_GRID_2) {
+            if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_GAUSS_GRID_2) }
+            FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_GAUSS_GRID_2)
+        }
         if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_LOGNORMAL_2) }
         FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_LOGNORMAL_2)
     }
     if (o.n_quad != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_adam<double, double, FF_MODEL_LOGNORMAL_1, 32>(as);
+    if (model == FF_MODEL_GAUSS_GRID_2) return launch_adam<double, double, FF_MODEL_GAUSS_GRID_2, 32>(as);
     return launch_adam<double, double, FF_MODEL_LOGNORMAL_2, 32>(as);
 }
 

@@ -31,7 +31,12 @@ ff_status hip_error(hipError_t e, const char* what)
 
 int n_state(int model)
 {
-    return model == FF_MODEL_LOGNORMAL_1 ? 5 : (model == FF_MODEL_LOGNORMAL_2 ? 8 : -1);
+    switch (model) {
+    case FF_MODEL_LOGNORMAL_1: return 5;
+    case FF_MODEL_LOGNORMAL_2: return 8;
+    case FF_MODEL_GAUSS_GRID_2: return 8;
+    default: return -1;
+    }
 }
 
 static ff_status check_prior(const ff_prior* prior)
@@ -44,8 +49,8 @@ static ff_status check_prior(const ff_prior* prior)
             return set_error(FF_EINVAL, "prior box needs finite lo < hi for every state variable");
         if (!std::isfinite(prior->x0[j])) return set_error(FF_EINVAL, "prior x0 is not finite");
     }
-    // the lognormal mean and s.d. must stay positive over the whole box
-    const int pos[2][4] = {{1, 2, -1, -1}, {2, 3, 4, 5}};
+    // the temperature means and spreads must stay positive over the whole box
+    const int pos[3][4] = {{1, 2, -1, -1}, {2, 3, 4, 5}, {2, 3, 4, 5}};
     for (int k = 0; k < 4; ++k) {
         const int j = pos[prior->model - 1][k];
         if (j >= 0 && !(prior->lo[j] > 0.0))
@@ -159,6 +164,11 @@ extern "C" ff_status ff_prior_default(int32_t model, ff_prior* p)
         for (int j = 0; j < 5; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
     } else if (model == FF_MODEL_LOGNORMAL_2) {
         const double lo[8] = {0.0, 0.0, 350.0, 1.0, 900.0, 1.0, -0.2, -5e-4};
+        const double hi[8] = {0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 5e-4};
+        const double x0[8] = {0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.0};
+        for (int j = 0; j < 8; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
+    } else if (model == FF_MODEL_GAUSS_GRID_2) {
+        const double lo[8] = {0.0, 0.0, 350.0, 10.0, 900.0, 10.0, -0.2, -5e-4};
         const double hi[8] = {0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 5e-4};
         const double x0[8] = {0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.0};
         for (int j = 0; j < 8; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }

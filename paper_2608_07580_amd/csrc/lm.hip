@@ -444,7 +444,7 @@ static ff_status launch_lm(const BatchSpec& bs)
     const int lpp = o.lanes_per_pixel > 0 ? o.lanes_per_pixel : 1;
     int dev = 0;
     FF_HIP_TRY(hipGetDevice(&dev));
-    if (!ensure_quad<R, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
+    if (!ensure_tables<R, MODEL, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
     int n_cu = 0;
     FF_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     int occ = 0;
@@ -554,7 +554,7 @@ static ff_status launch_forward(const ff_scene* sc, const void* state, int64_t P
     if (P == 0) return clear_error();
     int dev = 0;
     FF_HIP_TRY(hipGetDevice(&dev));
-    if (!ensure_quad<R, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
+    if (!ensure_tables<R, MODEL, Q>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
     const int block = 256;
     const int64_t grid = (P + block - 1) / block;
     if (grid > 0x7fffffff) return set_error(FF_EINVAL, "ff_forward: P too large");
@@ -582,11 +582,16 @@ ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs)
             if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_LOGNORMAL_1) }
             FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_LOGNORMAL_1)
         }
+        if (model == FF_MODEL_GAUSS_GRID_2) {
+            if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_GAUSS_GRID_2) }
+            FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_GAUSS_GRID_2)
+        }
         if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_LOGNORMAL_2) }
         FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_LOGNORMAL_2)
     }
     if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_lm<double, double, FF_MODEL_LOGNORMAL_1, 32>(bs);
+    if (model == FF_MODEL_GAUSS_GRID_2) return launch_lm<double, double, FF_MODEL_GAUSS_GRID_2, 32>(bs);
     return launch_lm<double, double, FF_MODEL_LOGNORMAL_2, 32>(bs);
 }
 
@@ -603,10 +608,12 @@ ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, 
 {
     if (precision == FF_PRECISION_FP32) {
         if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_1) }
+        if (model == FF_MODEL_GAUSS_GRID_2) { FF_DISPATCH_FWD(q, float, FF_MODEL_GAUSS_GRID_2) }
         FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_2)
     }
     if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_forward<double, FF_MODEL_LOGNORMAL_1, 32>(sc, state, P, L, J, stream);
+    if (model == FF_MODEL_GAUSS_GRID_2) return launch_forward<double, FF_MODEL_GAUSS_GRID_2, 32>(sc, state, P, L, J, stream);
     return launch_forward<double, FF_MODEL_LOGNORMAL_2, 32>(sc, state, P, L, J, stream);
 }
 

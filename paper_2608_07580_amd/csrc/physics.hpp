@@ -28,6 +28,7 @@ namespace ff {
 template <int MODEL> struct ModelDims;
 template <> struct ModelDims<FF_MODEL_LOGNORMAL_1> { static constexpr int N = 5; static constexpr int C = 1; };
 template <> struct ModelDims<FF_MODEL_LOGNORMAL_2> { static constexpr int N = 8; static constexpr int C = 2; };
+template <> struct ModelDims<FF_MODEL_GAUSS_GRID_2> { static constexpr int N = 8; static constexpr int C = 2; };
 
 // Quadrature rule of order Q in constant memory (filled once per device by
 // the host before the first launch).  Kernels index it with a laundered zero
@@ -354,6 +355,201 @@ struct PixelModel<R, FF_MODEL_LOGNORMAL_2, Q> {
     }
 };
 
+// ------------------------------------------------------------------------
+// The paper's thermal form (Sec. 2.2): two Gaussian components summed over a
+// temperature grid of Q uniform nodes T_i = 350 + i (2200 - 350)/(Q - 1) K.
+// Node weights of a component: p_i = w_i / sum_j w_j, w_i = exp(-(T_i -
+// mu)^2 / (2 sig^2)) (the normalisation truncates to the grid); d_i = T_i -
+// mu, m1 = sum p_i d_i, m2 = sum p_i d_i^2.  With B_i = B(lambda, T_i):
+//   I = sum p_i B_i,  dI/dmu = S1 / sig^2,  dI/dsig = S2 / sig^3,
+//   S1 = sum p_i (d_i - m1) B_i,  S2 = sum p_i (d_i^2 - m2) B_i
+// (dp_i/dmu = p_i (d_i - m1)/sig^2, dp_i/dsig = p_i (d_i^2 - m2)/sig^3); the
+// centred forms avoid subtracting two large sums in FP32.
+template <int Q>
+__host__ __device__ constexpr double grid_node(int i) { return 350.0 + (2200.0 - 350.0) * i / (Q - 1); }
+
+// Node temperatures and their inverses in constant memory (pairs, so one
+// scalar load fetches both); read with a laundered zero offset at the point
+// of use so they do not occupy registers across the band loop.
+template <typename R, int Q>
+struct GridNodes {
+    R ti[2 * Q];   // T_0, 1/T_0, T_1, 1/T_1, ...
+};
+namespace {
+template <typename R, int Q>
+__constant__ GridNodes<R, Q> c_grid;
+}
+
+struct GridComponent {
+    double mu1;   // mu + m1: d_i - m1 = T_i - mu1
+    double m2;
+};
+
+// Normalised node weights (FP64, rounded once to R) and the centring
+// constants of one component.
+template <typename R, int Q>
+__device__ inline GridComponent grid_component(double mu, double sig, R (&p)[Q])
+{
+    const double inv2s2 = 0.5 / (sig * sig);
+    // the largest exponent is at the node nearest mu (clamped to the grid)
+    const double h = (2200.0 - 350.0) / (Q - 1);
+    double kn = rint((mu - 350.0) / h);
+    kn = fmin((double)(Q - 1), fmax(0.0, kn));
+    const double dn = 350.0 + h * kn - mu;
+    const double emax = -dn * dn * inv2s2;
+    // one node at a time (each exponent depends, through an empty asm, on the
+    // previous result), the unnormalised weight parked in p
+    double W = 0.0, m = mu;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double d = grid_node<Q>(i) - m;
+        const double w = exp(-d * d * inv2s2 - emax);
+        W += w;
+        p[i] = (R)w;
+        asm volatile("" : "+v"(m) : "v"(p[i]));
+    }
+    const double iW = 1.0 / W;
+    double m1 = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double pi = (double)p[i] * iW;
+        const double d = grid_node<Q>(i) - mu;
+        m1 += pi * d;
+        m2 += pi * d * d;
+        p[i] = (R)pi;
+    }
+    return GridComponent{mu + m1, m2};
+}
+
+// Grid sums of both components at one band: per node one Planck ratio
+// q = e/(1 - e) (e = 2^(-a2/T_i), as in thermal_sums) shared by the two
+// components, then I, S1, S2 of each: 6 FMA-class + 2 subtractions per
+// component per node.
+template <int Q>
+__device__ __forceinline__ void grid_sums(float a2, const float (&ps)[Q], const float (&ph)[Q], float mus, float mus1,
+                                          float m2s, float muh, float muh1, float m2h, int o, float (&out)[6])
+{
+    float i0 = 0.f, s1 = 0.f, s2 = 0.f, j0 = 0.f, t1 = 0.f, t2 = 0.f;
+    float a = a2;
+    const GridNodes<float, Q>& gn = c_grid<float, Q>;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const float T = gn.ti[2 * k + o];
+        const float x = a * gn.ti[2 * k + 1 + o];
+        const float q = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x) - 1.0f);
+        const float ys = ps[k] * q;
+        i0 += ys;
+        s1 = __builtin_fmaf(ys, T - mus1, s1);
+        const float ds = T - mus;
+        s2 = __builtin_fmaf(ys, __builtin_fmaf(ds, ds, -m2s), s2);
+        const float yh = ph[k] * q;
+        j0 += yh;
+        t1 = __builtin_fmaf(yh, T - muh1, t1);
+        const float dh = T - muh;
+        t2 = __builtin_fmaf(yh, __builtin_fmaf(dh, dh, -m2h), t2);
+        if ((k + 1) % FF_NODE_GROUP == 0) asm volatile("" : "+v"(a) : "v"(i0), "v"(j0), "v"(s2), "v"(t2));
+    }
+    out[0] = i0; out[1] = s1; out[2] = s2; out[3] = j0; out[4] = t1; out[5] = t2;
+}
+
+template <int Q>
+__device__ __forceinline__ void grid_sums(double a2, const double (&ps)[Q], const double (&ph)[Q], double mus,
+                                          double mus1, double m2s, double muh, double muh1, double m2h, int o,
+                                          double (&out)[6])
+{
+    double i0 = 0.0, s1 = 0.0, s2 = 0.0, j0 = 0.0, t1 = 0.0, t2 = 0.0;
+    const GridNodes<double, Q>& gn = c_grid<double, Q>;
+#pragma unroll 4
+    for (int k = 0; k < Q; ++k) {
+        const double T = gn.ti[2 * k + o];
+        const double e = exp2(-a2 * gn.ti[2 * k + 1 + o]);
+        const double q = e / (1.0 - e);
+        const double ys = ps[k] * q;
+        i0 += ys;
+        s1 = fma(ys, T - mus1, s1);
+        const double ds = T - mus;
+        s2 = fma(ys, fma(ds, ds, -m2s), s2);
+        const double yh = ph[k] * q;
+        j0 += yh;
+        t1 = fma(yh, T - muh1, t1);
+        const double dh = T - muh;
+        t2 = fma(yh, fma(dh, dh, -m2h), t2);
+    }
+    out[0] = i0; out[1] = s1; out[2] = s2; out[3] = j0; out[4] = t1; out[5] = t2;
+}
+
+template <typename R, int Q>
+struct PixelModel<R, FF_MODEL_GAUSS_GRID_2, Q> {
+    static constexpr int N = 8;
+    static_assert(Q >= 2, "the temperature grid needs two nodes");
+    R f, eta, r0, r1;
+    R mus, mus1, m2s, muh, muh1, m2h;
+    R ps[Q], ph[Q];
+    // (node weights are computed by every lane of a group)
+    __device__ void setup(const double (&x)[N], int lane = 0, int L = 1)
+    {
+        (void)lane;
+        (void)L;
+        f = (R)x[0];
+        eta = (R)x[1];
+        r0 = (R)x[6];
+        r1 = (R)x[7];
+        const GridComponent gs = grid_component<R, Q>(x[2], x[3], ps);
+        const GridComponent gh = grid_component<R, Q>(x[4], x[5], ph);
+        mus = (R)x[2];
+        mus1 = (R)gs.mu1;
+        m2s = (R)gs.m2;
+        muh = (R)x[4];
+        muh1 = (R)gh.mu1;
+        m2h = (R)gh.m2;
+    }
+    __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N]) const
+    {
+        R g[6];
+        grid_sums<Q>(t.a2, ps, ph, mus, mus1, m2s, muh, muh1, m2h, o, g);
+        const R rho = r0 + r1 * t.dl;
+        const R rden = fast_rcp<R>((R)1 - t.S * rho);
+        const R ls = t.K * (t.ratm + t.tau2 * rho * rden);
+        const R tb = t.tup * t.cb;
+        const R is_ = tb * g[0], ih = tb * g[3];
+        ub[0] = is_ + eta * (ih - is_);   // tau_up (eta I_h + (1 - eta) I_s)
+        ub[1] = ih - is_;
+        ub[2] = tb * g[1];
+        ub[3] = tb * g[2];
+        ub[4] = tb * g[4];
+        ub[5] = tb * g[5];
+        ub[6] = t.K * t.tau2 * rden * rden;
+        ub[7] = ub[6] * t.dl;
+        return ls + f * ub[0];
+    }
+    static constexpr int s1[N] = {0, 1, 2, 3, 4, 5, 6, 7};
+    static constexpr int s2[N] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    __device__ static void coefficients(const double (&x)[N], double (&c1)[N], double (&c2)[N])
+    {
+        const double f = x[0], eta = x[1], ss = x[3], sh = x[5];
+        const double fs = f * (1.0 - eta), fh = f * eta;
+        c1[0] = 1.0;
+        c1[1] = f;
+        c1[2] = fs / (ss * ss);
+        c1[3] = fs / (ss * ss * ss);
+        c1[4] = fh / (sh * sh);
+        c1[5] = fh / (sh * sh * sh);
+        c1[6] = 1.0;
+        c1[7] = 1.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) c2[i] = 0.0;
+    }
+    // Sec. 2.2 moment matching (as for the lognormal mixture, on the
+    // components' nominal means and spreads)
+    __device__ static void moments(const double (&x)[N], double& et, double& sd)
+    {
+        const double eta = x[1], ms = x[2], ss = x[3], mh = x[4], sh = x[5];
+        et = eta * mh + (1.0 - eta) * ms;
+        const double dm = mh - ms;
+        sd = sqrt(eta * sh * sh + (1.0 - eta) * ss * ss + eta * (1.0 - eta) * dm * dm);
+    }
+};
+
 // ---------------------------------------------------------------- host side
 // The quadrature rule (computed once per process) and its copy into this
 // translation unit's constant memory on each device.  Internal linkage: with
@@ -389,6 +585,38 @@ bool ensure_quad(int dev)
             return false;
         done[dev] = true;
     }
+    return true;
+}
+
+// The temperature grid of the Gaussian-mixture model in this translation
+// unit's constant memory on each device.
+template <typename R, int Q>
+bool ensure_grid(int dev)
+{
+    static std::mutex mtx;
+    static bool done[64] = {};
+    if (dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lock(mtx);
+    if (!done[dev]) {
+        GridNodes<R, Q> g;
+        for (int i = 0; i < Q; ++i) {
+            g.ti[2 * i] = (R)grid_node<Q>(i);
+            g.ti[2 * i + 1] = (R)(1.0 / grid_node<Q>(i));
+        }
+        const void* sym = reinterpret_cast<const void*>(&c_grid<R, Q>);
+        if (hipMemcpyToSymbol(sym, &g, sizeof(g), 0, hipMemcpyHostToDevice) != hipSuccess) return false;
+        done[dev] = true;
+    }
+    return true;
+}
+
+// Constant tables a model's kernels read: the quadrature rule, and for the
+// Gaussian-mixture model the temperature grid.
+template <typename R, int MODEL, int Q>
+bool ensure_tables(int dev)
+{
+    if (!ensure_quad<R, Q>(dev)) return false;
+    if constexpr (MODEL == FF_MODEL_GAUSS_GRID_2) return ensure_grid<R, Q>(dev);
     return true;
 }
 
