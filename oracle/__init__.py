@@ -22,6 +22,8 @@ Parts (Keely et al., real-time physics inversion of VSWIR fire spectra):
   * ``adam_retrieve`` / ``paper_stages``: the paper's staged Adam (Sec. 2.5,
     eq. adam) in the C oracle.
   * ``hfdi`` / ``hfdi_candidates``: the fire-candidate index of Sec. 2.1.
+  * ``coarsen``: block-mean aggregation and the Quantile Error Curve of the
+    resolution-rescaling analysis.
 """
 from __future__ import annotations
 
