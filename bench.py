@@ -722,6 +722,84 @@ def run_paper_model(args):
     print(json.dumps(line), flush=True)
 
 
+def run_coarsening(args):
+    """The paper's resolution-rescaling analysis on the clustered-fire scene:
+    12 x 12 block means of the fine radiance, LM at both resolutions, and the
+    Quantile Error Curve of every coarse fire pixel against the fine
+    retrievals in its footprint (empirical and Gaussian-mixture).  Times each
+    stage; reports the mean curves."""
+    import torch
+    import paper_2608_07580_amd as ff
+    dev = torch.device("cuda:0")
+    ff.lib()
+    atm, scene, states, fire, noise, rad = make_workload(args, dev)
+    P, B = rad.shape
+    rows, cols, b = args.lines, args.cross, args.block
+    prior = ff.default_prior(1)
+    stream = torch.cuda.Stream(device=dev)
+    opts = ff.default_options(n_quad=args.n_quad)
+    if not args.no_tune:
+        with torch.cuda.stream(stream):
+            opts, _ = ff.tune([scene], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+        torch.cuda.synchronize()
+    K = (rows // b) * (cols // b)
+    fine = ff.allocate_outputs(P, 1, dev)
+    coarse = ff.allocate_outputs(K, 1, dev)
+    ev = []
+
+    def step():
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record(stream)
+        crad = ff.block_mean(rad, rows, cols, b, stream=stream)
+        e[1].record(stream)
+        ff.retrieve(scene, rad, prior, options=opts, outputs=fine, stream=stream)
+        e[2].record(stream)
+        ff.retrieve(scene, crad, prior, options=opts, outputs=coarse, stream=stream)
+        e[3].record(stream)
+        out = ff.qec(fine, coarse, rows, cols, b, stream=stream)
+        e[4].record(stream)
+        ev.append(e)
+        return out
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup + args.steps):
+            emp, mix, n_used = step()
+    torch.cuda.synchronize()
+    ev = ev[args.warmup:]
+    stage = [sum(e[i].elapsed_time(e[i + 1]) for e in ev) / len(ev) for i in range(4)]
+    emp, mix, n_used = emp.cpu().numpy(), mix.cpu().numpy(), n_used.cpu().numpy()
+    ok = np.isfinite(emp[:, 0])
+    f, c = fine.numpy(), coarse.numpy()
+    # mean fine E[T] of the footprint against the coarse E[T]
+    R, C = rows // b, cols // b
+    d = []
+    for k in np.nonzero(ok)[0]:
+        r0, c0 = divmod(int(k), C)
+        idx = ((r0 * b + np.arange(b))[:, None] * cols + (c0 * b + np.arange(b))[None, :]).ravel()
+        sel = idx[((f["status"][idx].astype(np.int64) & ff.ST_CONVERGED) != 0) & (f["state"][idx, 0] >= 1e-4)
+                  & np.isfinite(f["moments"][idx, 1]) & (f["moments"][idx, 1] > 0)]
+        d.append(c["moments"][k, 0] - f["moments"][sel, 0].mean())
+    d = np.array(d)
+    line = {
+        "metric": "resolution rescaling: QEC of coarse (12 x 12 block-mean) posteriors against fine retrievals",
+        "config": {"workload": f"clustered-fire scene {cols} x {rows} px x {B} bands, 3% fire, SNR {args.snr:g}; "
+                               f"{b} x {b} block means -> {C} x {R} coarse px", "fine_pixels": P,
+                   "coarse_pixels": K, "block": b, "levels": list(ff.QEC_LEVELS), "f_min": 1e-4, "min_fine": 5},
+        "ms": {"block_mean": stage[0], "fine_lm": stage[1], "coarse_lm": stage[2], "qec": stage[3],
+               "total": sum(stage)},
+        "coarse_evaluated": int(ok.sum()),
+        "fine_used_mean": float(n_used[ok].mean()) if ok.any() else None,
+        "qec_empirical_mean_K": [float(v) for v in emp[ok].mean(0)],
+        "qec_mixture_mean_K": [float(v) for v in mix[ok].mean(0)],
+        "qec_empirical_mean_abs_K": float(np.abs(emp[ok].mean(0)).mean()),
+        "qec_mixture_mean_abs_K": float(np.abs(mix[ok].mean(0)).mean()),
+        "coarse_minus_fine_mean_ET": {"mae_K": float(np.abs(d).mean()), "bias_K": float(d.mean())},
+        "block_mean_hbm": {"bytes": P * B * 4 + K * B * 4, "GB_per_s": (P * B * 4 + K * B * 4) / (stage[0] * 1e-3) / 1e9,
+                           "frac_of_8TBs": (P * B * 4 + K * B * 4) / (stage[0] * 1e-3) / HBM_PEAK},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_front_end(args):
     """The paper's candidate selection in front of the retrieval: the HFDI
     pre-filter (Sec. 2.1, threshold -0.1) builds the candidate list on the
@@ -814,14 +892,16 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the tuner's")
     ap.add_argument("--grid-max-iter", type=int, default=200, help="paper-model workload: LM iteration cap")
+    ap.add_argument("--block", type=int, default=12, help="coarsening workload: block side")
     ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers", "front-end",
-                                           "paper-model"),
+                                           "paper-model", "coarsening"),
                     default="clustered-fire",
                     help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
                          "precision: FP32/FP64 variants on the two-component stress set; "
                          "solvers: the paper's two-stage Adam vs LM on the clustered-fire scene; "
                          "front-end: HFDI candidate selection + LM on the candidates; "
-                         "paper-model: the paper's two-Gaussian grid thermal model, LM and staged Adam")
+                         "paper-model: the paper's two-Gaussian grid thermal model, LM and staged Adam; "
+                         "coarsening: 12 x 12 block means, LM at both resolutions, Quantile Error Curves")
     ap.add_argument("--adam-lpp", type=int, default=1, help="lanes per pixel of the Adam kernel")
     ap.add_argument("--hfdi-threshold", type=float, default=-0.1, help="front-end workload: HFDI threshold")
     ap.add_argument("--solver-sample", type=int, default=4096, help="oracle subsample of the solvers workload")
@@ -849,6 +929,9 @@ def main():
         return
     if args.workload == "paper-model":
         run_paper_model(args)
+        return
+    if args.workload == "coarsening":
+        run_coarsening(args)
         return
     if args.workload == "precision":
         if args.cpu_sample == 65536:

@@ -322,6 +322,41 @@ ff_status ff_retrieve_listed(const ff_scene* scene, const float* radiance_dev, i
                              unsigned long long* evals_dev, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Resolution rescaling (Keely et al.: fine radiance aggregated to a coarse
+ * grid in radiance space, both retrieved, and the coarse pixels' Gaussian
+ * posteriors compared with the fine retrievals in their footprints by a
+ * Quantile Error Curve).  Pixels are row-major images of rows x cols.
+ *
+ * ff_block_mean: out[(r C + c)][b] = mean of radiance over the block x block
+ * fine pixels of coarse pixel (r, c), R = rows / block, C = cols / block
+ * (partial blocks at the right and bottom edges are dropped); summed in
+ * FP64, rounded once to float32.  block in [1, 32].  Asynchronous. */
+ff_status ff_block_mean(const float* radiance_dev, int32_t rows, int32_t cols, int32_t n_bands, int32_t block,
+                        float* out_dev, void* stream);
+
+/* ff_qec: per coarse pixel k, QEC_j = Q_coarse(q_j) - Q_fine(q_j) with
+ * Q_coarse the quantile of N(E[T]_k, sigma[T]_k) and Q_fine of the fine
+ * pixels in k's footprint that take part: qec_emp uses their empirical
+ * distribution of E[T] (linear interpolation between order statistics,
+ * h = (n - 1) q), qec_mix the equal-weight mixture of their N(E[T], sigma[T])
+ * (quantile by bisection to ~1e-9 relative).  A pixel takes part when its
+ * status has a convergence bit, its f = state[0] >= f_min and its sigma[T]
+ * is finite and positive; a coarse pixel is evaluated when it takes part
+ * itself and at least min_fine of its fine pixels do, else its QEC entries
+ * are NaN.  fine_mask_dev [rows cols] / coarse_mask_dev [R C] (uint8, may
+ * be NULL) restrict the pixels that take part to those with a nonzero entry
+ * (for example the fire candidates).  Inputs are the outputs of a retrieval
+ * (moments [.][2], state [.][n_state], status); levels_host: n_levels values
+ * in (0, 1), n_levels <= 16; outputs [R C][n_levels] float32 and n_used
+ * [R C] (fine pixels taking part).  Asynchronous. */
+ff_status ff_qec(const float* fine_moments_dev, const float* fine_state_dev, const uint32_t* fine_status_dev,
+                 const uint8_t* fine_mask_dev, const float* coarse_moments_dev, const float* coarse_state_dev,
+                 const uint32_t* coarse_status_dev, const uint8_t* coarse_mask_dev,
+                 int32_t n_state, int32_t rows, int32_t cols, int32_t block, double f_min, int32_t min_fine,
+                 int32_t n_levels, const double* levels_host, float* qec_emp_dev, float* qec_mix_dev,
+                 int32_t* n_used_dev, void* stream);
+
+/* ------------------------------------------------------------------------
  * The paper's own solver: staged Adam (Keely et al. Sec. 2.5, eq. adam;
  * Kingma & Ba 2015) on the windowed loss of eq. (loss) in the z coordinate of
  * eq. (affine).  Each stage runs a fresh optimiser (t = 1, m = v = 0) for a

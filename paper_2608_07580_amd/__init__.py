@@ -46,7 +46,7 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
            "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
-           "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed")
+           "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec")
 
 
 class FirefitError(RuntimeError):
@@ -183,7 +183,10 @@ def lib():
         L.ff_retrieve_atm_indexed.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                               C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
                                               C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
-        for name in ("ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
+        L.ff_block_mean.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+        L.ff_qec.argtypes = [C.c_void_p] * 8 + [C.c_int32] * 4 + [C.c_double, C.c_int32, C.c_int32, _dp] + \
+            [C.c_void_p] * 4
+        for name in ("ff_block_mean", "ff_qec", "ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
                      "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
@@ -457,6 +460,47 @@ def retrieve_atm_indexed(atmospheres, atm_index, radiance, prior: Prior | None =
                                          C.byref(options), C.byref(oc), _ptr(evals), _stream_handle(stream)),
            "ff_retrieve_atm_indexed")
     return out
+
+
+QEC_LEVELS = (0.05, 0.10, 0.25, 0.50, 0.75, 0.90, 0.95)
+
+
+def block_mean(radiance, rows: int, cols: int, block: int = 12, stream=None):
+    """Coarse radiance [(rows // block) * (cols // block), B] float32 from fine
+    radiance [rows * cols, B] (ff_block_mean)."""
+    torch = _torch()
+    assert radiance.is_cuda and radiance.dtype == torch.float32 and radiance.is_contiguous()
+    assert radiance.shape[0] == rows * cols
+    B = radiance.shape[1]
+    out = torch.empty(((rows // block) * (cols // block), B), dtype=torch.float32, device=radiance.device)
+    _check(lib().ff_block_mean(_ptr(radiance), rows, cols, B, block, _ptr(out), _stream_handle(stream)),
+           "ff_block_mean")
+    return out
+
+
+def qec(fine: Outputs, coarse: Outputs, rows: int, cols: int, block: int = 12, f_min: float = 1e-4,
+        min_fine: int = 5, levels=QEC_LEVELS, fine_mask=None, coarse_mask=None, stream=None):
+    """Quantile Error Curves of every coarse pixel (ff_qec): (empirical [K, L],
+    mixture [K, L], n_used [K]) device tensors, NaN where not evaluated.
+    fine_mask / coarse_mask: optional uint8 device tensors restricting the
+    pixels that take part."""
+    torch = _torch()
+    K = (rows // block) * (cols // block)
+    n = fine.state.shape[1]
+    lv = np.ascontiguousarray(levels, np.float64)
+    dev = fine.state.device
+    emp = torch.empty((K, len(lv)), dtype=torch.float32, device=dev)
+    mix = torch.empty_like(emp)
+    n_used = torch.empty(K, dtype=torch.int32, device=dev)
+    for m, size in ((fine_mask, fine.state.shape[0]), (coarse_mask, K)):
+        if m is not None:
+            assert m.is_cuda and m.dtype == torch.uint8 and m.numel() == size and m.is_contiguous()
+    _check(lib().ff_qec(_ptr(fine.moments), _ptr(fine.state), _ptr(fine.status), _ptr(fine_mask),
+                        _ptr(coarse.moments), _ptr(coarse.state), _ptr(coarse.status), _ptr(coarse_mask), n,
+                        rows, cols, block, float(f_min), min_fine,
+                        len(lv), lv.ctypes.data_as(_dp), _ptr(emp), _ptr(mix), _ptr(n_used),
+                        _stream_handle(stream)), "ff_qec")
+    return emp, mix, n_used
 
 
 def adam_options(prior: Prior | None = None, **kw) -> ffAdamOptions:
