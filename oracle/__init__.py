@@ -72,21 +72,23 @@ def lib():
         L.orc_planck_many.restype = None
         L.orc_planck_many.argtypes = [C.c_long, dp, dp, dp, dp]
         L.orc_forward.restype = C.c_int
-        L.orc_forward.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, C.c_int, dp, dp,
+        L.orc_forward.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, C.c_int, dp, dp,
                                   C.c_int, C.c_long, dp, dp, dp, C.c_int]
         L.orc_retrieve.restype = C.c_int
-        L.orc_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
+        L.orc_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
                                    C.c_int, dp, dp, dp, dp, C.c_long, fp,
                                    C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_int,
                                    dp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_uint)]
         L.orc_adam_retrieve.restype = C.c_int
-        L.orc_adam_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
+        L.orc_adam_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
                                         C.c_int, dp, dp, dp, dp, C.c_long, fp,
                                         C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_uint), dp, dp,
                                         dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                         dp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_uint)]
         L.orc_max_threads.restype = C.c_int
+        L.orc_project_simplex.restype = None
+        L.orc_project_simplex.argtypes = [C.c_int, dp]
         _lib = L
     return _lib
 
@@ -148,6 +150,7 @@ class Tables:
     ratm: np.ndarray   # rho_atm [B]
     S: np.ndarray      # spherical albedo [B]
     lsat: np.ndarray | None  # [B] float32 saturation level, or None
+    endm: np.ndarray | None = None  # [5, B] endmember reflectance (model 4), or None
 
     @property
     def B(self):
@@ -167,10 +170,17 @@ def srf_matrix(lam_b, fwhm_b, hr_lam):
     return w / s[:, None]
 
 
-def band_tables(atm) -> Tables:
+def band_tables(atm, endmembers=None) -> Tables:
     """Per-band factors of eq. (solar): each atmospheric quantity is resampled
-    to band resolution separately; tau2 = resampled tau_down * resampled tau_up."""
+    to band resolution separately; tau2 = resampled tau_down * resampled tau_up.
+    ``endmembers`` [5, H] on the high-resolution grid are resampled with the
+    same responses (Sec. 2.4)."""
     W = srf_matrix(atm.wavelength_nm, atm.fwhm_nm, atm.hr_lambda_nm)
+    endm = None
+    if endmembers is not None:
+        e = np.asarray(endmembers, np.float64)
+        assert e.shape == (N_ENDMEMBERS, W.shape[1])
+        endm = np.ascontiguousarray(e @ W.T)
     E = W @ atm.e_solar
     tdn = W @ atm.tau_down
     tup = W @ atm.tau_up
@@ -178,7 +188,8 @@ def band_tables(atm) -> Tables:
     S = W @ atm.s_sph
     return Tables(lam=np.ascontiguousarray(atm.wavelength_nm, np.float64),
                   K=E * atm.cos_sza / np.pi, tau2=tdn * tup, tup=tup, ratm=ratm, S=S,
-                  lsat=None if atm.sat_level is None else np.asarray(atm.sat_level, np.float32))
+                  lsat=None if atm.sat_level is None else np.asarray(atm.sat_level, np.float32),
+                  endm=endm)
 
 
 # ----------------------------------------------------------------------------
@@ -197,8 +208,28 @@ def planck(lam_nm, T, with_derivative: bool = False):
     return out.reshape(lam_nm.shape)
 
 
+N_ENDMEMBERS = 5          # Sec. 2.4: the library's five spectra
+SIMPLEX_FIRST = 3         # model 4: state (f, m, s, x_surf,1 .. x_surf,5)
+
+
 def n_state(model: int) -> int:
-    return {1: 5, 2: 8, 3: 8}[model]
+    return {1: 5, 2: 8, 3: 8, 4: 8}[model]
+
+
+def project_simplex(v):
+    """Euclidean projection of v onto the unit simplex {x >= 0, sum x = 1},
+    the step applied to the surface fractions (Sec. 2.5)."""
+    x = np.ascontiguousarray(v, np.float64).copy()
+    lib().orc_project_simplex(x.size, _dp(x))
+    return x
+
+
+def _endm(tab: Tables, model: int):
+    if model != 4:
+        return None
+    if tab.endm is None:
+        raise ValueError("model 4 needs the band tables' endmember spectra")
+    return np.ascontiguousarray(tab.endm, np.float64)
 
 
 def grid_nodes(G: int):
@@ -236,8 +267,9 @@ def forward(tab: Tables, state, model: int, q: int = 32, jacobian: bool = False,
     gx, gw = gauss_hermite(q)
     L = np.empty((P, tab.B))
     J = np.empty((P, tab.B, n)) if jacobian else None
+    endm = _endm(tab, model)
     rc = lib().orc_forward(tab.B, _dp(tab.lam), _dp(tab.K), _dp(tab.tau2), _dp(tab.tup),
-                           _dp(tab.ratm), _dp(tab.S), q, _dp(gx), _dp(gw), model, P,
+                           _dp(tab.ratm), _dp(tab.S), _dp(endm), q, _dp(gx), _dp(gw), model, P,
                            _dp(st), _dp(L), _dp(J), nthreads)
     if rc != 0:
         raise ValueError("orc_forward: bad arguments")
@@ -285,8 +317,9 @@ def retrieve(tab: Tables, lobs, model: int, lo, hi, x0, z0=None, q: int = 32,
                  moments=np.empty((P, 2)), rrr=np.empty(P),
                  iters=np.empty(P, np.int32), status=np.empty(P, np.uint32))
     lsat = None if tab.lsat is None else np.ascontiguousarray(tab.lsat, np.float32)
+    endm = _endm(tab, model)
     rc = lib().orc_retrieve(tab.B, _dp(tab.lam), _dp(tab.K), _dp(tab.tau2), _dp(tab.tup),
-                            _dp(tab.ratm), _dp(tab.S), _fp(lsat), q, _dp(gx), _dp(gw),
+                            _dp(tab.ratm), _dp(tab.S), _dp(endm), _fp(lsat), q, _dp(gx), _dp(gw),
                             model, _dp(lo), _dp(hi), _dp(x0), _dp(z0c), P, _fp(lobs),
                             opts.max_iter, opts.xtol, opts.ftol, opts.gtol, opts.kappa,
                             opts.tau, nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),
@@ -337,12 +370,18 @@ def paper_stages(model: int, lo, hi, x0, clip: float = ADAM_CLIP):
     fits f and the temperature distribution, whose spreads (and eta) restart
     from the prior start x0; the one-component model's f, m, s use OMEGA_2,
     the two-component model's flaming (m_h, s_h) and smouldering (m_s, s_s)
-    variables their own windows."""
+    variables their own windows.  With the endmember surface (model 4) the
+    surface fractions take the reflectance's place in stage 1, as the paper's
+    stage-1 state {x_surf, alpha_1, T_1} has them."""
     z0 = x_to_z(np.asarray(x0, np.float64), np.asarray(lo, np.float64), np.asarray(hi, np.float64))
     if model == 1:
         s1 = AdamStage(30, 0.03, (0, 1, 3, 4), {j: OMEGA_1 for j in (0, 1, 3, 4)}, clip, {2: -1.0})
         s2 = AdamStage(100, 0.015, (0, 1, 2), {j: OMEGA_2 for j in (0, 1, 2)}, clip, {2: float(z0[2])})
-    elif model == 2:
+    elif model == 4:
+        surf = (0, 1, 3, 4, 5, 6, 7)
+        s1 = AdamStage(30, 0.03, surf, {j: OMEGA_1 for j in surf}, clip, {2: -1.0})
+        s2 = AdamStage(100, 0.015, (0, 1, 2), {j: OMEGA_2 for j in (0, 1, 2)}, clip, {2: float(z0[2])})
+    elif model in (2, 3):
         s1 = AdamStage(30, 0.03, (0, 4, 6, 7), {j: OMEGA_1 for j in (0, 4, 6, 7)}, clip,
                        {1: 1.0, 5: -1.0})
         win = {0: OMEGA_2, 1: OMEGA_2, 2: OMEGA_SMOL, 3: OMEGA_SMOL, 4: OMEGA_HOT, 5: OMEGA_HOT}
@@ -384,9 +423,10 @@ def adam_retrieve(tab: Tables, lobs, model: int, lo, hi, x0, stages, z0=None, q:
                  moments=np.empty((P, 2)), rrr=np.empty(P),
                  iters=np.empty(P, np.int32), status=np.empty(P, np.uint32))
     lsat = None if tab.lsat is None else np.ascontiguousarray(tab.lsat, np.float32)
+    endm = _endm(tab, model)
     rc = lib().orc_adam_retrieve(
         tab.B, _dp(tab.lam), _dp(tab.K), _dp(tab.tau2), _dp(tab.tup), _dp(tab.ratm), _dp(tab.S),
-        _fp(lsat), q, _dp(gx), _dp(gw), model, _dp(lo), _dp(hi), _dp(x0), _dp(z0c), P,
+        _dp(endm), _fp(lsat), q, _dp(gx), _dp(gw), model, _dp(lo), _dp(hi), _dp(x0), _dp(z0c), P,
         _fp(lobs), k, steps.ctypes.data_as(C.POINTER(C.c_int)),
         free.ctypes.data_as(C.POINTER(C.c_uint)), _dp(lr), _dp(clip), _dp(wlo), _dp(whi),
         _dp(zset), beta1, beta2, eps, nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),

@@ -175,28 +175,78 @@ static void grid_integrals(double lam, int G, double mu, double sig, double* I, 
     *Isig = S2 / (sig * sig * sig);
 }
 
+#define N_ENDMEMBERS 5
+
 typedef struct {
     int B;
     const double *lam, *K, *tau2, *tup, *ratm, *S;
     int Q;
     const double *gx, *gw;
+    const double* endm;   /* [N_ENDMEMBERS][B] endmember reflectance (model 4) */
 } scene_t;
 
-static int n_of_model(int model) { return model == 1 ? 5 : ((model == 2 || model == 3) ? 8 : -1); }
+static int n_of_model(int model) { return model == 1 ? 5 : ((model >= 2 && model <= 4) ? 8 : -1); }
+
+/* model 4 keeps its surface fractions (state 3..7) on the unit simplex */
+static int simplex_first(int model) { return model == 4 ? 3 : -1; }
+
+/* Euclidean projection of v[0..k) onto the unit simplex {x >= 0, sum x = 1}
+ * (sort-based, Duchi, Shalev-Shwartz, Singer & Chandra 2008). */
+static void project_simplex(int k, double* v)
+{
+    double u[NMAX];
+    for (int i = 0; i < k; ++i) u[i] = v[i];
+    for (int i = 1; i < k; ++i) {           /* insertion sort, descending */
+        const double t = u[i];
+        int j = i - 1;
+        while (j >= 0 && u[j] < t) { u[j + 1] = u[j]; --j; }
+        u[j + 1] = t;
+    }
+    double cum = 0.0, theta = 0.0;
+    for (int j = 0; j < k; ++j) {
+        cum += u[j];
+        const double t = (cum - 1.0) / (j + 1);
+        if (u[j] - t > 0.0) theta = t;
+    }
+    for (int i = 0; i < k; ++i) v[i] = v[i] - theta > 0.0 ? v[i] - theta : 0.0;
+}
+
+/* The simplex step works in x = (z + 1)/2, so a simplex block needs the
+ * box [0, 1] on each of its fractions. */
+static int simplex_box_ok(int model, const double* lo, const double* hi)
+{
+    const int sf = simplex_first(model);
+    if (sf < 0) return 1;
+    for (int k = sf; k < sf + N_ENDMEMBERS; ++k)
+        if (lo[k] != 0.0 || hi[k] != 1.0) return 0;
+    return 1;
+}
+
+/* exported for the projection's own tests */
+void orc_project_simplex(int k, double* v)
+{
+    if (k >= 1 && k <= NMAX) project_simplex(k, v);
+}
 
 /* Forward model at one band for physical state x; fills dL/dx if dl != 0. */
 static double model_band(const scene_t* sc, int b, int model, const double* x, double* dl)
 {
     const double lam = sc->lam[b];
     const int n = n_of_model(model);
-    const double r0 = x[n - 2], r1 = x[n - 1];
-    const double rho = r0 + r1 * (lam - LAMBDA_REF_NM);
+    double rho;
+    if (model == 4) {
+        /* Sec. 2.2: surface reflectance as a mixture of the endmember library */
+        rho = 0.0;
+        for (int k = 0; k < N_ENDMEMBERS; ++k) rho += x[3 + k] * sc->endm[k * sc->B + b];
+    } else {
+        rho = x[n - 2] + x[n - 1] * (lam - LAMBDA_REF_NM);
+    }
     const double den = 1.0 - sc->S[b] * rho;
     const double ls = sc->K[b] * (sc->ratm[b] + sc->tau2[b] * rho / den);
     const double f = x[0];
     const double tup = sc->tup[b];
     double thermal_I;
-    if (model == 1) {
+    if (model == 1 || model == 4) {
         double mu, sig, dmu[2], dsig[2], I, Imu, Isig;
         lognormal_params(x[1], x[2], &mu, &sig, dmu, dsig);
         component_integrals(lam, mu, sig, sc->Q, sc->gx, sc->gw, &I, &Imu, &Isig);
@@ -241,22 +291,27 @@ static double model_band(const scene_t* sc, int b, int model, const double* x, d
         }
     }
     if (dl) {
-        dl[n - 2] = sc->K[b] * sc->tau2[b] / (den * den);
-        dl[n - 1] = dl[n - 2] * (lam - LAMBDA_REF_NM);
+        const double drho = sc->K[b] * sc->tau2[b] / (den * den);
+        if (model == 4) {
+            for (int k = 0; k < N_ENDMEMBERS; ++k) dl[3 + k] = drho * sc->endm[k * sc->B + b];
+        } else {
+            dl[n - 2] = drho;
+            dl[n - 1] = drho * (lam - LAMBDA_REF_NM);
+        }
     }
     return ls + f * tup * thermal_I;
 }
 
 /* Forward model (and optionally dL/dx, layout [P][B][n]) for P states. */
 int orc_forward(int B, const double* lam, const double* K, const double* tau2,
-                const double* tup, const double* ratm, const double* S,
+                const double* tup, const double* ratm, const double* S, const double* endm,
                 int Q, const double* gx, const double* gw,
                 int model, long P, const double* state, double* L, double* dLdx,
                 int nthreads)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || B <= 0) return -1;
-    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
+    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || (model == 4 && !endm) || B <= 0) return -1;
+    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw, endm};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -349,25 +404,83 @@ static double evaluate(const problem_t* pb, const double* z, double* A, double* 
     return F;
 }
 
-/* variables held at a bound by a gradient pointing out of the box */
-static void active_set(int n, const double* z, const double* g, int* act)
+/* Variables held at a bound by a gradient pointing out of the box.  For a
+ * simplex block (fractions sf .. sf+4 of model 4, x = (z + 1)/2 summing to
+ * one) a fraction at zero is held when its gradient exceeds the mean
+ * gradient of the fractions above zero (moving weight onto it would raise
+ * the loss). */
+static void active_set(int n, int sf, const double* z, const double* g, int* act)
 {
     for (int j = 0; j < n; ++j)
         act[j] = (z[j] <= -1.0 && g[j] > 0.0) || (z[j] >= 1.0 && g[j] < 0.0);
+    if (sf < 0) return;
+    double gs = 0.0;
+    int m = 0;
+    for (int k = sf; k < sf + N_ENDMEMBERS; ++k)
+        if (z[k] > -1.0) { gs += g[k]; ++m; }
+    const double gbar = m > 0 ? gs / m : 0.0;
+    for (int k = sf; k < sf + N_ENDMEMBERS; ++k) act[k] = z[k] <= -1.0 && g[k] - gbar > 0.0;
 }
 
-/* projected-gradient test: max_j |g_j| / sqrt(A_jj F) over free j */
-static int gradient_small(int n, const double* z, const double* A, const double* g,
+/* projected-gradient test: max_j |g_j| / sqrt(A_jj F) over free j; in a
+ * simplex block the gradient less its mean over the free fractions */
+static int gradient_small(int n, int sf, const double* z, const double* A, const double* g,
                           double F, double gtol)
 {
     if (!(F > 0.0)) return 1;
     int act[NMAX];
-    active_set(n, z, g, act);
+    active_set(n, sf, z, g, act);
+    double gr[NMAX];
+    for (int j = 0; j < n; ++j) gr[j] = g[j];
+    if (sf >= 0) {
+        double gs = 0.0;
+        int m = 0;
+        for (int k = sf; k < sf + N_ENDMEMBERS; ++k)
+            if (!act[k]) { gs += g[k]; ++m; }
+        for (int k = sf; k < sf + N_ENDMEMBERS; ++k) gr[k] = g[k] - (m > 0 ? gs / m : 0.0);
+    }
     for (int j = 0; j < n; ++j) {
         if (act[j] || !(A[j * n + j] > 0.0)) continue;
-        if (fabs(g[j]) > gtol * sqrt(A[j * n + j] * F)) return 0;
+        if (fabs(gr[j]) > gtol * sqrt(A[j * n + j] * F)) return 0;
     }
     return 1;
+}
+
+/* The simplex block of z (fractions x = (z + 1)/2) projected onto the unit
+ * simplex: the step the paper applies to the surface mixture after each
+ * optimiser update (Sec. 2.5). */
+static void project_block(int sf, double* z)
+{
+    if (sf < 0) return;
+    double x[NMAX];
+    for (int k = 0; k < N_ENDMEMBERS; ++k) x[k] = 0.5 * (z[sf + k] + 1.0);
+    project_simplex(N_ENDMEMBERS, x);
+    for (int k = 0; k < N_ENDMEMBERS; ++k) z[sf + k] = 2.0 * x[k] - 1.0;
+}
+
+/* Levenberg-Marquardt trial point z + a delta: the box variables clipped to
+ * [-1, 1]; with a simplex block the step is first shortened (a <= 1, the
+ * ratio test of active-set methods) so that no fraction goes below zero,
+ * the fraction that stops it is set to exactly zero, and the block is
+ * projected onto the simplex to remove rounding from its sum.  The step
+ * keeps its direction, so a descent step of the damped model stays one.
+ * Returns 1 when the step was shortened. */
+static int trial_point(int n, int sf, const double* z, const double* delta, double* zt)
+{
+    double a = 1.0;
+    int stop = -1;
+    if (sf >= 0)
+        for (int k = sf; k < sf + N_ENDMEMBERS; ++k) {
+            const double x = 0.5 * (z[k] + 1.0), dx = 0.5 * delta[k];
+            if (dx < 0.0 && x + dx < 0.0 && x / -dx < a) { a = x / -dx; stop = k; }
+        }
+    for (int j = 0; j < n; ++j) {
+        const double zz = z[j] + a * delta[j];
+        zt[j] = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
+    }
+    if (stop >= 0) zt[stop] = -1.0;
+    project_block(sf, zt);
+    return stop >= 0;
 }
 
 typedef struct {
@@ -381,6 +494,7 @@ static unsigned lm_solve(const problem_t* pb, const lmopt_t* o, double* z,
                          double* A, double* g, double* Fout, int* iters)
 {
     const int n = pb->n;
+    const int sf = simplex_first(pb->model);
     double At[NMAX * NMAX], gt[NMAX], M[NMAX * NMAX], C[NMAX * NMAX];
     double d[NMAX], zt[NMAX], h[NMAX], delta[NMAX], rhs[NMAX];
     int act[NMAX];
@@ -388,7 +502,7 @@ static unsigned lm_solve(const problem_t* pb, const lmopt_t* o, double* z,
     *iters = 0;
     double F = evaluate(pb, z, A, g);
     if (!isfinite(F)) { *Fout = F; return ST_NONFINITE; }
-    if (gradient_small(n, z, A, g, F, o->gtol)) { *Fout = F; return ST_GTOL; }
+    if (gradient_small(n, sf, z, A, g, F, o->gtol)) { *Fout = F; return ST_GTOL; }
     double amax = 0.0;
     for (int j = 0; j < n; ++j) amax = fmax(amax, A[j * n + j]);
     if (!(amax > 0.0)) amax = 1.0;
@@ -400,27 +514,50 @@ static unsigned lm_solve(const problem_t* pb, const lmopt_t* o, double* z,
         /* damped step on the free variables, retried with more damping
          * until it is a descent step of the quadratic model */
         double pred = 0.0;
-        int have_step = 0, tries = 0;
+        int have_step = 0, tries = 0, cut = 0;
         while (!have_step) {
             if (++tries > 64 || mu > 1e30 * amax) { st = ST_DAMPING; break; }
-            active_set(n, z, g, act);
-            for (int i = 0; i < n; ++i) {
-                for (int j = 0; j < n; ++j)
-                    M[i * n + j] = (act[i] || act[j]) ? 0.0 : A[i * n + j];
-                M[i * n + i] = act[i] ? 1.0 : A[i * n + i] + mu * d[i];
-                rhs[i] = act[i] ? 0.0 : -g[i];
+            active_set(n, sf, z, g, act);
+            int factored = 1;
+            for (;;) {
+                for (int i = 0; i < n; ++i) {
+                    for (int j = 0; j < n; ++j)
+                        M[i * n + j] = (act[i] || act[j]) ? 0.0 : A[i * n + j];
+                    M[i * n + i] = act[i] ? 1.0 : A[i * n + i] + mu * d[i];
+                    rhs[i] = act[i] ? 0.0 : -g[i];
+                }
+                if (!cholesky(n, M, C)) { factored = 0; break; }
+                chol_solve(n, C, rhs, delta);
+                if (sf < 0) break;
+                /* keep the free fractions' sum: delta -= nu' M^-1 c with c the
+                 * indicator of the free fractions and nu' = c.delta / c.M^-1 c
+                 * (the equality-constrained minimiser of the damped model) */
+                double c[NMAX], y[NMAX], cd = 0.0, cy = 0.0;
+                for (int j = 0; j < n; ++j) c[j] = (j >= sf && j < sf + N_ENDMEMBERS && !act[j]) ? 1.0 : 0.0;
+                chol_solve(n, C, c, y);
+                for (int j = 0; j < n; ++j) { cd += c[j] * delta[j]; cy += c[j] * y[j]; }
+                if (cy > 0.0)
+                    for (int j = 0; j < n; ++j) delta[j] -= cd / cy * y[j];
+                /* a fraction at zero that the step would push below zero is
+                 * held too, and the step is solved again (at most once per
+                 * fraction), so the projection only ever stops fractions that
+                 * start above zero */
+                int more = 0;
+                for (int k = sf; k < sf + N_ENDMEMBERS; ++k)
+                    if (!act[k] && z[k] <= -1.0 && delta[k] < 0.0) { act[k] = 1; more = 1; }
+                if (!more) break;
             }
-            if (!cholesky(n, M, C)) { mu *= nu; nu *= 2.0; continue; }
-            chol_solve(n, C, rhs, delta);
+            if (!factored) { mu *= nu; nu *= 2.0; continue; }
+            /* a step cut short by the simplex is no sign of convergence: the
+             * fraction it stops at zero is held from the next step on, so
+             * neither the step-size nor the decrease test is taken on it */
+            cut = trial_point(n, sf, z, delta, zt);
             double hmax = 0.0;
             for (int j = 0; j < n; ++j) {
-                double zz = z[j] + delta[j];
-                zz = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
-                zt[j] = zz;
-                h[j] = zz - z[j];
+                h[j] = zt[j] - z[j];
                 hmax = fmax(hmax, fabs(h[j]));
             }
-            if (hmax <= o->xtol) { st = ST_XTOL; break; }
+            if (hmax <= o->xtol && !cut) { st = ST_XTOL; break; }
             double hg = 0.0, hah = 0.0;
             for (int i = 0; i < n; ++i) {
                 hg += h[i] * g[i];
@@ -446,8 +583,8 @@ static unsigned lm_solve(const problem_t* pb, const lmopt_t* o, double* z,
             mu *= fmax(1.0 / 3.0, 1.0 - t * t * t);
             nu = 2.0;
             for (int j = 0; j < n; ++j) d[j] = fmax(d[j], A[j * n + j]);
-            if (pred <= o->ftol * Fold) { st = ST_FTOL; break; }
-            if (gradient_small(n, z, A, g, F, o->gtol)) { st = ST_GTOL; break; }
+            if (pred <= o->ftol * Fold && !cut) { st = ST_FTOL; break; }
+            if (gradient_small(n, sf, z, A, g, F, o->gtol)) { st = ST_GTOL; break; }
         } else {
             mu *= nu;
             nu *= 2.0;
@@ -505,7 +642,7 @@ static unsigned covariance(int n, const double* A, double F, int nvalid,
 /* moment-matched mean and s.d. of the temperature distribution */
 static void moments_of(int model, const double* x, double* et, double* sdt)
 {
-    if (model == 1) { *et = x[1]; *sdt = x[2]; return; }
+    if (model == 1 || model == 4) { *et = x[1]; *sdt = x[2]; return; }
     const double eta = x[1], ms = x[2], ss = x[3], mh = x[4], sh = x[5];
     *et = eta * mh + (1.0 - eta) * ms;
     const double dm = mh - ms;
@@ -532,13 +669,14 @@ static int pixel_bands(int B, const float* lp, const float* lsat, unsigned char*
 
 /* Starting z of one pixel: z0 if given, else x0 mapped by eq. (affine);
  * clipped to [-1, 1]. */
-static void start_z(int n, const double* lo, const double* hi, const double* x0,
+static void start_z(int n, int sf, const double* lo, const double* hi, const double* x0,
                     const double* z0p, double* z)
 {
     for (int j = 0; j < n; ++j) {
         const double zz = z0p ? z0p[j] : 2.0 * (x0[j] - lo[j]) / (hi[j] - lo[j]) - 1.0;
         z[j] = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
     }
+    project_block(sf, z);
 }
 
 /* Outputs of pixel p from its final z, J^T J (A) and loss F over all used
@@ -575,7 +713,7 @@ static void write_pixel(int model, int n, long p, unsigned st, const double* z, 
  * state [P][n] physical, cov [P][n(n+1)/2], moments [P][2], rrr [P],
  * iters [P], status [P]. */
 int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
-                 const double* tup, const double* ratm, const double* S,
+                 const double* tup, const double* ratm, const double* S, const double* endm,
                  const float* lsat, int Q, const double* gx, const double* gw,
                  int model, const double* lo, const double* hi, const double* x0,
                  const double* z0, long P, const float* lobs,
@@ -585,9 +723,10 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
                  int* iters, unsigned* status)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || B <= 0 || P < 0) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || (model == 4 && !endm) || B <= 0 || P < 0) return -1;
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
-    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
+    if (!simplex_box_ok(model, lo, hi)) return -1;
+    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw, endm};
     lmopt_t o = {max_iter, xtol, ftol, gtol, kappa, tau};
     if (!(tau > 0.0)) return -1;
 #ifdef _OPENMP
@@ -606,7 +745,7 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
         if (!finite_in) st = ST_NONFINITE;
         else if (nvalid <= n) st = ST_NODOF;
         if (!st) {
-            start_z(n, lo, hi, x0, z0 ? z0 + p * n : 0, z);
+            start_z(n, simplex_first(model), lo, hi, x0, z0 ? z0 + p * n : 0, z);
             problem_t pb = {&sc, model, n, lo, hi, lp, mask};
             st = lm_solve(&pb, &o, z, A, g, &F, &it);
         }
@@ -678,6 +817,7 @@ static int adam_solve(const problem_t* pb, int nst, const adam_stage_t* stages, 
             m[j] = v[j] = 0.0;
             if (!isnan(s->zset[j])) z[j] = clamp1(s->zset[j]);
         }
+        project_block(simplex_first(pb->model), z);
         for (int t = 1; t <= s->steps; ++t) {
             if (!windowed_gradient(pb, s, z, G)) return -1;
             double norm2 = 0.0;
@@ -693,6 +833,8 @@ static int adam_solve(const problem_t* pb, int nst, const adam_stage_t* stages, 
                 const double mhat = m[j] / bc1, vhat = v[j] / bc2;
                 z[j] = clamp1(z[j] - s->lr * mhat / (sqrt(vhat) + eps));
             }
+            /* the surface mixture back onto the unit simplex (Sec. 2.5) */
+            project_block(simplex_first(pb->model), z);
             ++steps;
         }
     }
@@ -705,7 +847,7 @@ static int adam_solve(const problem_t* pb, int nst, const adam_stage_t* stages, 
  * over).  iters = Adam steps taken.  The covariance, moments and relative
  * residual are those of the final z over all used bands. */
 int orc_adam_retrieve(int B, const double* lam, const double* K, const double* tau2,
-                      const double* tup, const double* ratm, const double* S,
+                      const double* tup, const double* ratm, const double* S, const double* endm,
                       const float* lsat, int Q, const double* gx, const double* gw,
                       int model, const double* lo, const double* hi, const double* x0,
                       const double* z0, long P, const float* lobs,
@@ -717,8 +859,9 @@ int orc_adam_retrieve(int B, const double* lam, const double* K, const double* t
                       int* iters, unsigned* status)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || B <= 0 || P < 0 || n_stages < 0 || n_stages > 16) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || (model == 4 && !endm) || B <= 0 || P < 0 || n_stages < 0 || n_stages > 16) return -1;
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
+    if (!simplex_box_ok(model, lo, hi)) return -1;
     adam_stage_t st[16];
     for (int k = 0; k < n_stages; ++k) {
         if (steps[k] < 0 || !(lr[k] > 0.0)) return -1;
@@ -730,7 +873,7 @@ int orc_adam_retrieve(int B, const double* lam, const double* K, const double* t
         st[k].whi = whi + k * n;
         st[k].zset = zset + k * n;
     }
-    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw};
+    scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw, endm};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -747,7 +890,7 @@ int orc_adam_retrieve(int B, const double* lam, const double* K, const double* t
         if (!finite_in) s = ST_NONFINITE;
         else if (nvalid <= n) s = ST_NODOF;
         if (!s) {
-            start_z(n, lo, hi, x0, z0 ? z0 + p * n : 0, z);
+            start_z(n, simplex_first(model), lo, hi, x0, z0 ? z0 + p * n : 0, z);
             problem_t pb = {&sc, model, n, lo, hi, lp, mask};
             it = adam_solve(&pb, n_stages, st, beta1, beta2, eps, z);
             if (it < 0) {

@@ -35,13 +35,15 @@ STREAM_SUBSAMPLE = 4
 MODEL_LOGNORMAL_1 = 1  # state (f, m, s, rho0, rho1)
 MODEL_LOGNORMAL_2 = 2  # state (f, eta, m_s, s_s, m_h, s_h, rho0, rho1)
 MODEL_GAUSS_GRID_2 = 3  # state (f, eta, mu_s, sig_s, mu_h, sig_h, rho0, rho1)
+MODEL_ENDMEMBER_1 = 4  # state (f, m, s, x_gv, x_npv, x_soil1, x_soil2, x_char)
 
-N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8}
+N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8, MODEL_ENDMEMBER_1: 8}
 
 STATE_NAMES = {
     MODEL_LOGNORMAL_1: ("f", "m", "s", "rho0", "rho1"),
     MODEL_LOGNORMAL_2: ("f", "eta", "m_s", "s_s", "m_h", "s_h", "rho0", "rho1"),
     MODEL_GAUSS_GRID_2: ("f", "eta", "mu_s", "sig_s", "mu_h", "sig_h", "rho0", "rho1"),
+    MODEL_ENDMEMBER_1: ("f", "m", "s", "x_gv", "x_npv", "x_soil1", "x_soil2", "x_char"),
 }
 
 # Exact SI constants (2019 redefinition) used to define the synthetic sun.
@@ -163,6 +165,11 @@ def default_prior(model: int):
         lo = np.array([0.0, 0.0, 350.0, 10.0, 900.0, 10.0, -0.2, -5e-4])
         hi = np.array([0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 5e-4])
         x0 = np.array([0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.0])
+    elif model == MODEL_ENDMEMBER_1:
+        # the surface fractions live on [0, 1] and start at the simplex centre
+        lo = np.array([0.0, 350.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+        hi = np.array([0.5, 2200.0, 500.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+        x0 = np.array([0.01, 1000.0, 150.0, 0.2, 0.2, 0.2, 0.2, 0.2])
     else:
         raise ValueError(f"unknown model {model}")
     return lo, hi, x0
@@ -211,6 +218,48 @@ def draw_states_gauss_grid2(rng: np.random.Generator, n: int) -> np.ndarray:
     r0 = rng.uniform(0.05, 0.4, n)
     r1 = rng.uniform(-1e-4, 1e-4, n)
     return np.stack([f, eta, ms, ss, mh, sh, r0, r1], axis=1)
+
+
+def draw_states_endmember1(rng: np.random.Generator, n: int) -> np.ndarray:
+    """One lognormal fire component over the endmember surface: f, m, s as in
+    the one-component draw, surface fractions ~ Dirichlet(0.7, ..., 0.7) (a
+    sparse mix: many pixels have fractions near zero).  Shape [n, 8]."""
+    f = np.exp(rng.uniform(math.log(1e-4), math.log(0.3), n))
+    m = rng.uniform(600.0, 1400.0, n)
+    s = rng.uniform(50.0, 300.0, n)
+    x = rng.dirichlet(np.full(5, 0.7), n)
+    return np.concatenate([np.stack([f, m, s], axis=1), x], axis=1)
+
+
+def endmember_library(hr_lambda_nm: np.ndarray) -> np.ndarray:
+    """Five synthetic surface reflectance spectra [5, H] on the
+    high-resolution grid, standing in for the paper's fire-relevant library
+    (Sec. 2.4: green vegetation, non-photosynthetic vegetation, two soils,
+    char/ash), built from smooth logistic edges and Gaussian absorption
+    features of the usual shapes:
+      0 green vegetation: low visible with a green peak, red edge near 715
+        nm to a 0.45 NIR plateau, liquid-water bands at 1450 and 1940 nm;
+      1 non-photosynthetic vegetation: a rise from 0.10 to 0.40 with a
+        cellulose-lignin feature at 2100 nm;
+      2 bright soil: 0.15 rising to 0.45 with a clay feature at 2200 nm;
+      3 dark iron-rich soil: 0.06 rising to 0.30 with a ferric feature at
+        900 nm;
+      4 char/ash: flat and dark, 0.04 rising to 0.08."""
+    lam = np.asarray(hr_lambda_nm, np.float64)
+
+    def edge(c, w):
+        return 1.0 / (1.0 + np.exp(-(lam - c) / w))
+
+    def dip(c, w, d):
+        return 1.0 - d * np.exp(-0.5 * ((lam - c) / w) ** 2)
+
+    gv = (0.04 + 0.05 * np.exp(-0.5 * ((lam - 550.0) / 30.0) ** 2) + 0.41 * edge(715.0, 12.0)
+          - 0.20 * edge(1300.0, 60.0)) * dip(1450.0, 60.0, 0.5) * dip(1940.0, 70.0, 0.6)
+    npv = (0.10 + 0.30 * edge(900.0, 250.0)) * dip(2100.0, 50.0, 0.25) * dip(1940.0, 60.0, 0.15)
+    soil1 = (0.15 + 0.30 * edge(800.0, 300.0)) * dip(2200.0, 25.0, 0.15)
+    soil2 = (0.06 + 0.24 * edge(1100.0, 350.0)) * dip(900.0, 80.0, 0.2)
+    char = 0.04 + 0.04 * (lam - lam.min()) / (lam.max() - lam.min())
+    return np.stack([gv, npv, soil1, soil2, char])
 
 
 def config5_states(n_pixels: int = 262144, scene: int = 0) -> np.ndarray:
