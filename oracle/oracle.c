@@ -461,10 +461,11 @@ static void project_block(int sf, double* z)
 /* Levenberg-Marquardt trial point z + a delta: the box variables clipped to
  * [-1, 1]; with a simplex block the step is first shortened (a <= 1, the
  * ratio test of active-set methods) so that no fraction goes below zero,
- * the fraction that stops it is set to exactly zero, and the block is
- * projected onto the simplex to remove rounding from its sum.  The step
- * keeps its direction, so a descent step of the damped model stays one.
- * Returns 1 when the step was shortened. */
+ * and the fraction that stops it is set to exactly zero, where the next
+ * step can hold it.  The step keeps its direction, so a descent step of the
+ * damped model stays one, and keeps the fractions' sum up to rounding (no
+ * projection here: shifting every fraction by the rounding of the sum would
+ * lift the zeros off zero).  Returns 1 when the step was shortened. */
 static int trial_point(int n, int sf, const double* z, const double* delta, double* zt)
 {
     double a = 1.0;
@@ -479,7 +480,6 @@ static int trial_point(int n, int sf, const double* z, const double* delta, doub
         zt[j] = zz < -1.0 ? -1.0 : (zz > 1.0 ? 1.0 : zz);
     }
     if (stop >= 0) zt[stop] = -1.0;
-    project_block(sf, zt);
     return stop >= 0;
 }
 
