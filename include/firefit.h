@@ -60,6 +60,7 @@ typedef int32_t ff_status;
  *   FF_MODEL_LOGNORMAL_1: n = 5, x = (f, m, s, rho0, rho1)
  *   FF_MODEL_LOGNORMAL_2: n = 8, x = (f, eta, m_s, s_s, m_h, s_h, rho0, rho1)
  *   FF_MODEL_GAUSS_GRID_2: n = 8, x = (f, eta, mu_s, sig_s, mu_h, sig_h, rho0, rho1)
+ *   FF_MODEL_ENDMEMBER_1: n = 8, x = (f, m, s, x_1, x_2, x_3, x_4, x_5)
  * f: emitting fraction scaling the thermal term (the paper's alpha),
  * m/s: lognormal mean and s.d. in K, eta: weight of the flaming component,
  * rho0: reflectance at 1440 nm, rho1: reflectance slope per nm.  The
@@ -68,11 +69,18 @@ typedef int32_t ff_status;
  * own form (Sec. 2.2): the eta-weighted mixture of a smouldering and a
  * flaming Gaussian of means mu and s.d. sig, each normalised over a grid of
  * n_quad uniform temperatures spanning [350, 2200] K, and the thermal term
- * the grid sum of the Planck radiance. */
+ * the grid sum of the Planck radiance.  FF_MODEL_ENDMEMBER_1 replaces the
+ * linear reflectance by the paper's surface mixture (Sec. 2.2, library
+ * Sec. 2.4): rho(lambda) = sum_k x_k E_k(lambda) over the scene's
+ * FF_N_ENDMEMBERS library spectra (ff_scene_set_endmembers), with the
+ * fractions on the unit simplex (x_k >= 0, sum x_k = 1); the thermal term
+ * is the one-component lognormal.  Its fractions must have the box [0, 1]. */
 #define FF_MODEL_LOGNORMAL_1 1
 #define FF_MODEL_LOGNORMAL_2 2
 #define FF_MODEL_GAUSS_GRID_2 3
+#define FF_MODEL_ENDMEMBER_1 4
 #define FF_MAX_STATE 8
+#define FF_N_ENDMEMBERS 5
 
 /* Arithmetic of the forward model, Jacobian and reductions.  The damped
  * Cholesky solve and the covariance inversion are FP64 in both. */
@@ -196,7 +204,8 @@ void ff_options_default(ff_options* opts);
  * rho1 in [-5e-4, 5e-4] /nm; start f = 0.01, m = 1000, s = 150, eta = 0.5,
  * m_s = 650, m_h = 1200, rho0 = 0.2, rho1 = 0.  FF_MODEL_GAUSS_GRID_2 takes
  * the two-component box and start with the spreads in [10, 500] K.
- * FF_EINVAL for an unknown model. */
+ * FF_MODEL_ENDMEMBER_1 takes the one-component f, m, s and fractions in
+ * [0, 1] starting at 1/5 each.  FF_EINVAL for an unknown model. */
 ff_status ff_prior_default(int32_t model, ff_prior* prior);
 
 /* Gauss-Hermite rule for weight e^{-x^2}: q nodes and weights (host arrays
@@ -216,6 +225,22 @@ int32_t ff_scene_n_bands(const ff_scene* scene);
 /* Copy the scene's FP64 band table to host memory [n_bands][FF_TABLE_COLS].
  * Synchronous. */
 ff_status ff_scene_band_tables(const ff_scene* scene, double* out_host);
+
+/* Surface endmember library of the scene (Keely et al. Sec. 2.4): the
+ * FF_N_ENDMEMBERS reflectance spectra reflectance_host [FF_N_ENDMEMBERS][n_hr]
+ * on the high-resolution grid lambda_nm [n_hr] are resampled to the bands
+ * with the scene's Gaussian spectral responses (the same weights as the
+ * atmosphere) and kept on the device for FF_MODEL_ENDMEMBER_1.  Host
+ * arrays, read during the call; synchronous.  A second call replaces the
+ * library.  FF_EINVAL for NULL arrays, n_hr < 1, non-finite values or a
+ * band whose response window holds no sample. */
+ff_status ff_scene_set_endmembers(ff_scene* scene, int32_t n_hr, const double* lambda_nm,
+                                  const double* reflectance_host);
+
+/* Copy the scene's band-resampled library to host memory
+ * [FF_N_ENDMEMBERS][n_bands] (FP64).  FF_EINVAL if none was set.
+ * Synchronous. */
+ff_status ff_scene_endmembers(const ff_scene* scene, double* out_host);
 
 /* Forward model of eq. (fm) at P states.  state_dev: [P][n] physical units,
  * float (FF_PRECISION_FP32) or double (FF_PRECISION_FP64).  radiance_dev:

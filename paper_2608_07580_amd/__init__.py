@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfirefit.so")
 
 FF_OK, FF_EINVAL, FF_EDEVICE, FF_ENOMEM, FF_EUNSUPPORTED = 0, -1, -2, -3, -4
-MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2, MODEL_GAUSS_GRID_2 = 1, 2, 3
+MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2, MODEL_GAUSS_GRID_2, MODEL_ENDMEMBER_1 = 1, 2, 3, 4
+N_ENDMEMBERS = 5
 PRECISION_FP32, PRECISION_FP64 = 0, 1
 SCHEDULE_PERSISTENT, SCHEDULE_STATIC = 0, 1
 ACCUMULATE_FP32, ACCUMULATE_FP64 = 0, 1
@@ -34,7 +35,7 @@ ST_BAD_ATMOSPHERE = 2048
 MAX_ATMOSPHERES = 16
 ST_CONVERGED = ST_CONVERGED_GTOL | ST_CONVERGED_XTOL | ST_CONVERGED_FTOL
 
-N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8}
+N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8, MODEL_ENDMEMBER_1: 8}
 
 # exported symbols of include/firefit.h
 EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_default",
@@ -46,7 +47,8 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
            "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
-           "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec")
+           "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec",
+           "ff_scene_set_endmembers", "ff_scene_endmembers")
 
 
 class FirefitError(RuntimeError):
@@ -129,6 +131,8 @@ def lib():
         L.ff_scene_destroy.restype = None
         L.ff_scene_n_bands.argtypes = [C.c_void_p]
         L.ff_scene_band_tables.argtypes = [C.c_void_p, _dp]
+        L.ff_scene_set_endmembers.argtypes = [C.c_void_p, C.c_int32, _dp, _dp]
+        L.ff_scene_endmembers.argtypes = [C.c_void_p, _dp]
         L.ff_forward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ff_retrieve_scene.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(ffPrior),
@@ -186,7 +190,7 @@ def lib():
         L.ff_block_mean.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         L.ff_qec.argtypes = [C.c_void_p] * 8 + [C.c_int32] * 4 + [C.c_double, C.c_int32, C.c_int32, _dp] + \
             [C.c_void_p] * 4
-        for name in ("ff_block_mean", "ff_qec", "ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
+        for name in ("ff_scene_set_endmembers", "ff_scene_endmembers", "ff_block_mean", "ff_qec", "ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
                      "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
@@ -289,6 +293,23 @@ class Scene:
     def band_tables(self) -> np.ndarray:
         out = np.empty((self.n_bands, TABLE_COLS))
         _check(lib().ff_scene_band_tables(self.handle, out.ctypes.data_as(_dp)), "ff_scene_band_tables")
+        return out
+
+    def set_endmembers(self, hr_lambda_nm, reflectance):
+        """ff_scene_set_endmembers: the library [N_ENDMEMBERS, n_hr] on the
+        high-resolution grid, resampled to the bands on the device."""
+        lam = np.ascontiguousarray(hr_lambda_nm, np.float64)
+        refl = np.ascontiguousarray(reflectance, np.float64)
+        if refl.shape != (N_ENDMEMBERS, lam.size):
+            raise ValueError("reflectance must be [N_ENDMEMBERS, n_hr]")
+        _check(lib().ff_scene_set_endmembers(self.handle, lam.size, lam.ctypes.data_as(_dp),
+                                             refl.ctypes.data_as(_dp)), "ff_scene_set_endmembers")
+        return self
+
+    def endmembers(self) -> np.ndarray:
+        """ff_scene_endmembers: the band-resampled library [N_ENDMEMBERS, n_bands]."""
+        out = np.empty((N_ENDMEMBERS, self.n_bands))
+        _check(lib().ff_scene_endmembers(self.handle, out.ctypes.data_as(_dp)), "ff_scene_endmembers")
         return out
 
     def close(self):

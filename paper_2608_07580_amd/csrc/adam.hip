@@ -109,7 +109,7 @@ __device__ __forceinline__ void windowed_gradient(const Desc* descp, const float
             const int o = opaque_zero();
             const BandRow<R> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
             R ub[N];
-            const R lm = pm.band(row, o, ub);
+            const R lm = band_of<MODEL>(pm, tab, B, b, o, row, ub);
             const bool msk = (R)lob < row.lsat;
             const ACC r = msk ? (ACC)((R)lob - lm) : (ACC)0;
 #pragma unroll
@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(256) adam_kernel(const AdamDesc<R, Q>* __restr
                 zz = isfinite(zz) ? zz : D->zdef[j];
                 z[j] = fmin(1.0, fmax(-1.0, zz));
             }
+            project_block<MODEL>(z);
             int steps = 0;
             bool bad = false;
             const int K = D->n_stages;
@@ -192,6 +193,7 @@ __global__ void __launch_bounds__(256) adam_kernel(const AdamDesc<R, Q>* __restr
                     const double zs = Dk->zset[k][j];
                     if (!__builtin_isnan(zs)) z[j] = fmin(1.0, fmax(-1.0, zs));
                 }
+                project_block<MODEL>(z);
                 const uint8_t* bits = Dk->bits + ((size_t)sidx * K + k) * B;
                 const int T = Dk->steps[k];
                 double p1 = 1.0, p2 = 1.0;    // beta1^t, beta2^t
@@ -237,6 +239,7 @@ __global__ void __launch_bounds__(256) adam_kernel(const AdamDesc<R, Q>* __restr
                             z[j] = fmin(1.0, fmax(-1.0, z[j] - lr * mhat / (sqrt(vhat) + eps)));
                         }
                     }
+                    project_block<MODEL>(z);   // surface mixture back onto the simplex (Sec. 2.5)
                     ++steps;
                 }
             }
@@ -405,12 +408,17 @@ ff_status dispatch_adam(const AdamSpec& as)
             if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_GAUSS_GRID_2) }
             FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_GAUSS_GRID_2)
         }
+        if (model == FF_MODEL_ENDMEMBER_1) {
+            if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_ENDMEMBER_1) }
+            FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_ENDMEMBER_1)
+        }
         if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_LOGNORMAL_2) }
         FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_LOGNORMAL_2)
     }
     if (o.n_quad != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_adam<double, double, FF_MODEL_LOGNORMAL_1, 32>(as);
     if (model == FF_MODEL_GAUSS_GRID_2) return launch_adam<double, double, FF_MODEL_GAUSS_GRID_2, 32>(as);
+    if (model == FF_MODEL_ENDMEMBER_1) return launch_adam<double, double, FF_MODEL_ENDMEMBER_1, 32>(as);
     return launch_adam<double, double, FF_MODEL_LOGNORMAL_2, 32>(as);
 }
 

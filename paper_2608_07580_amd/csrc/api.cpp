@@ -35,6 +35,7 @@ int n_state(int model)
     case FF_MODEL_LOGNORMAL_1: return 5;
     case FF_MODEL_LOGNORMAL_2: return 8;
     case FF_MODEL_GAUSS_GRID_2: return 8;
+    case FF_MODEL_ENDMEMBER_1: return 8;
     default: return -1;
     }
 }
@@ -50,12 +51,25 @@ static ff_status check_prior(const ff_prior* prior)
         if (!std::isfinite(prior->x0[j])) return set_error(FF_EINVAL, "prior x0 is not finite");
     }
     // the temperature means and spreads must stay positive over the whole box
-    const int pos[3][4] = {{1, 2, -1, -1}, {2, 3, 4, 5}, {2, 3, 4, 5}};
+    const int pos[4][4] = {{1, 2, -1, -1}, {2, 3, 4, 5}, {2, 3, 4, 5}, {1, 2, -1, -1}};
     for (int k = 0; k < 4; ++k) {
         const int j = pos[prior->model - 1][k];
         if (j >= 0 && !(prior->lo[j] > 0.0))
             return set_error(FF_EINVAL, "temperature mean and spread bounds must be positive");
     }
+    // the simplex step works on x = (z + 1)/2: surface fractions need the box [0, 1]
+    if (prior->model == FF_MODEL_ENDMEMBER_1)
+        for (int j = 3; j < 3 + FF_N_ENDMEMBERS; ++j)
+            if (prior->lo[j] != 0.0 || prior->hi[j] != 1.0)
+                return set_error(FF_EINVAL, "surface fractions need the box [0, 1]");
+    return FF_OK;
+}
+
+// The endmember model reads the scene's library.
+static ff_status check_library(int model, const ff_scene* sc, const char* who)
+{
+    if (model == FF_MODEL_ENDMEMBER_1 && sc && !sc->has_endmembers)
+        return set_error(FF_EINVAL, (std::string(who) + ": the endmember model needs ff_scene_set_endmembers").c_str());
     return FF_OK;
 }
 
@@ -172,6 +186,11 @@ extern "C" ff_status ff_prior_default(int32_t model, ff_prior* p)
         const double hi[8] = {0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 5e-4};
         const double x0[8] = {0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.0};
         for (int j = 0; j < 8; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
+    } else if (model == FF_MODEL_ENDMEMBER_1) {
+        const double lo[8] = {0.0, 350.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const double hi[8] = {0.5, 2200.0, 500.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+        const double x0[8] = {0.01, 1000.0, 150.0, 0.2, 0.2, 0.2, 0.2, 0.2};
+        for (int j = 0; j < 8; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
     } else {
         return set_error(FF_EINVAL, "ff_prior_default: unknown model");
     }
@@ -197,6 +216,7 @@ extern "C" ff_status ff_forward(const ff_scene* scene, int32_t model, int32_t pr
     if (P < 0) return set_error(FF_EINVAL, "ff_forward: P < 0");
     if (P == 0) return clear_error();
     if (!state_dev || !radiance_dev) return set_error(FF_EINVAL, "ff_forward: NULL state or radiance");
+    if (check_library(model, scene, "ff_forward") != FF_OK) return FF_EINVAL;
     return dispatch_forward(precision, model, n_quad, scene, state_dev, P, radiance_dev, jac_dev,
                             (hipStream_t)stream);
 }
@@ -221,6 +241,7 @@ extern "C" ff_status ff_retrieve_batch(const ff_scene* const* scenes, const floa
         if (B < 0) B = scenes[i]->n_bands;
         if (scenes[i]->n_bands != B) return set_error(FF_EINVAL, "ff_retrieve_batch: scenes differ in band count");
         if (P[i] > 0 && !radiance_dev[i]) return set_error(FF_EINVAL, "ff_retrieve_batch: NULL radiance");
+        if (check_library(prior->model, scenes[i], "ff_retrieve_batch") != FF_OK) return FF_EINVAL;
     }
     BatchSpec bs{scenes, radiance_dev, P, n_scenes, prior, z0_dev, opts, outs, evals_dev, (hipStream_t)stream};
     return dispatch_lm(opts->precision, prior->model, opts->n_quad, bs);
@@ -240,6 +261,7 @@ extern "C" ff_status ff_retrieve_listed(const ff_scene* scene, const float* radi
     if (s != FF_OK) return s;
     s = check_options(opts);
     if (s != FF_OK) return s;
+    if (check_library(prior->model, scene, "ff_retrieve_listed") != FF_OK) return FF_EINVAL;
     const float* const rads[1] = {radiance_dev};
     const float* const z0s[1] = {z0_dev};
     const ff_scene* const scs[1] = {scene};
@@ -270,6 +292,8 @@ extern "C" ff_status ff_retrieve_atm_indexed(const ff_scene* const* atmospheres,
     if (s != FF_OK) return s;
     s = check_options(opts);
     if (s != FF_OK) return s;
+    for (int a = 0; a < n_atm; ++a)
+        if (check_library(prior->model, atmospheres[a], "ff_retrieve_atm_indexed") != FF_OK) return FF_EINVAL;
     const float* const rads[1] = {radiance_dev};
     const float* const z0s[1] = {z0_dev};
     const ff_scene* const scs[1] = {atmospheres[0]};
@@ -347,8 +371,14 @@ extern "C" ff_status ff_adam_options_default(const ff_prior* prior, ff_adam_opti
     const double w1lo = 350.0, w1hi = 2500.0;          // Omega_1
     const double hot_lo = 900.0, hot_hi = 1800.0;      // Omega_2 flaming
     const double smol_lo = 1500.0, smol_hi = 2500.0;   // Omega_2 smouldering
-    if (prior->model == FF_MODEL_LOGNORMAL_1) {
-        for (int j : {0, 1, 3, 4}) set(s1, j, w1lo, w1hi);
+    if (prior->model == FF_MODEL_LOGNORMAL_1 || prior->model == FF_MODEL_ENDMEMBER_1) {
+        // the endmember surface: its fractions take the reflectance's place
+        // in stage 1 (the paper's x_1 = {x_surf, alpha_1, T_1})
+        if (prior->model == FF_MODEL_LOGNORMAL_1) {
+            for (int j : {0, 1, 3, 4}) set(s1, j, w1lo, w1hi);
+        } else {
+            for (int j : {0, 1, 3, 4, 5, 6, 7}) set(s1, j, w1lo, w1hi);
+        }
         s1.z_start[2] = -1.0;
         for (int j : {0, 1, 2}) set(s2, j, hot_lo, smol_hi);
         s2.z_start[2] = zdef(2);
@@ -389,6 +419,7 @@ extern "C" ff_status ff_adam_retrieve_batch(const ff_scene* const* scenes, const
         if (B < 0) B = scenes[i]->n_bands;
         if (scenes[i]->n_bands != B) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: scenes differ in band count");
         if (P[i] > 0 && !radiance_dev[i]) return set_error(FF_EINVAL, "ff_adam_retrieve_batch: NULL radiance");
+        if (check_library(prior->model, scenes[i], "ff_adam_retrieve_batch") != FF_OK) return FF_EINVAL;
     }
     AdamSpec as{scenes, radiance_dev, P, n_scenes, prior, z0_dev, opts, outs, evals_dev, (hipStream_t)stream};
     return dispatch_adam(as);

@@ -41,6 +41,12 @@ enum TableCol : int {
 };
 static_assert(FF_TABLE_COLS == 12, "table layout");
 
+// The endmember library follows the band rows in the same allocation: row b
+// of that section (kEndmCols values, FF_N_ENDMEMBERS used, the rest zero)
+// starts at table + B * FF_TABLE_COLS + b * kEndmCols.
+constexpr int kEndmCols = 8;
+static_assert(FF_N_ENDMEMBERS <= kEndmCols, "endmember row");
+
 }  // namespace ff
 
 // Scene handle: per-band tables in device memory, FP32 and FP64 copies, and
@@ -48,10 +54,12 @@ static_assert(FF_TABLE_COLS == 12, "table layout");
 struct ff_scene {
     int32_t n_bands = 0;
     int device = 0;
-    float* table_f32 = nullptr;   // [B][12]
-    double* table_f64 = nullptr;  // [B][12]
+    float* table_f32 = nullptr;   // [B][12] band rows, then [B][8] endmember rows
+    double* table_f64 = nullptr;  // the same in FP64
     std::vector<double> lambda;   // [B] band centres, nm
+    std::vector<double> fwhm;     // [B] band FWHM, nm
     std::vector<float> lsat;      // [B] saturation levels (+inf: none)
+    bool has_endmembers = false;  // the endmember section holds a library
 };
 
 namespace ff {

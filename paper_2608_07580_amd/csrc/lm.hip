@@ -72,6 +72,60 @@ __device__ __forceinline__ bool gradient_small(const R (&z)[N], const R (&A)[N *
     return small;
 }
 
+// Fractions of a simplex block held at zero (Karush-Kuhn-Tucker sign):
+// fraction k at zero is held when its gradient exceeds the mean gradient of
+// the fractions above zero, so moving weight onto it would raise the loss.
+template <typename R, int N, int SF>
+__device__ __forceinline__ void simplex_hold(const R (&z)[N], const R (&g)[N], bool (&act)[N])
+{
+    double gs = 0.0;
+    int m = 0;
+#pragma unroll
+    for (int k = SF; k < SF + FF_N_ENDMEMBERS; ++k)
+        if ((double)z[k] > -1.0) { gs += (double)g[k]; ++m; }
+    const double gbar = m > 0 ? gs / m : 0.0;
+#pragma unroll
+    for (int k = SF; k < SF + FF_N_ENDMEMBERS; ++k) act[k] = (double)z[k] <= -1.0 && (double)g[k] - gbar > 0.0;
+}
+
+// The projected-gradient test with a simplex block: the free fractions'
+// gradient less its mean over them.
+template <typename R, int N, int SF>
+__device__ __forceinline__ bool gradient_small_simplex(const R (&z)[N], const R (&A)[N * (N + 1) / 2],
+                                                       const R (&g)[N], double F, double gtol)
+{
+    if (!(F > 0.0)) return true;
+    bool act[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double gj = (double)g[j], zj = (double)z[j];
+        act[j] = (zj <= -1.0 && gj > 0.0) || (zj >= 1.0 && gj < 0.0);
+    }
+    simplex_hold<R, N, SF>(z, g, act);
+    double gs = 0.0;
+    int m = 0;
+#pragma unroll
+    for (int k = SF; k < SF + FF_N_ENDMEMBERS; ++k)
+        if (!act[k]) { gs += (double)g[k]; ++m; }
+    const double gm = m > 0 ? gs / m : 0.0;
+    bool small = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double gr = (j >= SF && j < SF + FF_N_ENDMEMBERS) ? (double)g[j] - gm : (double)g[j];
+        const double ajj = (double)A[tri(j, j)];
+        if (!act[j] && ajj > 0.0 && fabs(gr) > gtol * sqrt(ajj * F)) small = false;
+    }
+    return small;
+}
+
+template <int MODEL, typename R, int N>
+__device__ __forceinline__ bool converged_gradient(const R (&z)[N], const R (&A)[N * (N + 1) / 2], const R (&g)[N],
+                                                   double F, double gtol)
+{
+    if constexpr (simplex_first_v<MODEL> >= 0) return gradient_small_simplex<R, N, simplex_first_v<MODEL>>(z, A, g, F, gtol);
+    else return gradient_small<R, N>(z, A, g, F, gtol);
+}
+
 template <typename R, typename ACC, int MODEL, int Q>
 __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
 {
@@ -94,7 +148,9 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
     const R* tab = nullptr;
     double lnorm2 = 0.0, amax = 1.0;
     int nvalid = 0;
+    constexpr int SF = simplex_first_v<MODEL>;
     R z[N], zt[N], A[NT], g[N], d[N];
+    bool cut = false;           // the last step was shortened by the simplex (no convergence test on it)
     double F = 0.0;
     double mu = 0.0, nu = 2.0, pred = 0.0;
     int it = 0, phase = 0;
@@ -192,6 +248,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                             zz = isfinite(zz) ? zz : D->zdef[j];
                             z[j] = (R)fmin(1.0, fmax(-1.0, zz));
                         }
+                        project_block<MODEL>(z);
                         if (warm) st |= FF_ST_WARM_START;
                         has = true;
                     }
@@ -225,7 +282,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                 if (!isfinite(Fe)) {
                     st |= FF_ST_NONFINITE_INPUT;
                     done = true;
-                } else if (gradient_small<R, N>(z, A, g, F, D->gtol)) {
+                } else if (converged_gradient<MODEL>(z, A, g, F, D->gtol)) {
                     st |= FF_ST_CONVERGED_GTOL;
                     done = true;
                 } else {
@@ -256,10 +313,10 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     nu = 2.0;
 #pragma unroll
                     for (int j = 0; j < N; ++j) d[j] = (R)fmax((double)d[j], (double)A[tri(j, j)]);
-                    if (pred <= D->ftol * fold) {
+                    if (pred <= D->ftol * fold && (SF < 0 || !cut)) {
                         st |= FF_ST_CONVERGED_FTOL;
                         done = true;
-                    } else if (gradient_small<R, N>(z, A, g, F, D->gtol)) {
+                    } else if (converged_gradient<MODEL>(z, A, g, F, D->gtol)) {
                         st |= FF_ST_CONVERGED_GTOL;
                         done = true;
                     }
@@ -293,6 +350,8 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                         }
                         bool act[N];
                         double m[NT], rhs[N], delta[N];
+                        double hstep[N], hmax = 0.0;
+                        if constexpr (SF < 0) {
 #pragma unroll
                         for (int j = 0; j < N; ++j) {
                             const double gj = (double)g[j], zj = (double)z[j];
@@ -312,7 +371,6 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                             continue;
                         }
                         cholesky_solve<N>(m, rhs, delta);
-                        double hstep[N], hmax = 0.0;
 #pragma unroll
                         for (int j = 0; j < N; ++j) {
                             const R zz = (R)fmin(1.0, fmax(-1.0, (double)z[j] + delta[j]));
@@ -324,6 +382,93 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                             st |= FF_ST_CONVERGED_XTOL;
                             done = true;
                             break;
+                        }
+                        } else {
+                        // Simplex block: the damped step on the free variables
+                        // keeps the free fractions' sum (delta -= nu' M^-1 c, c
+                        // the free fractions' indicator, nu' = c.delta / c.M^-1
+                        // c); a fraction at zero the step would push below
+                        // zero is held and the step solved again; the step is
+                        // then shortened (ratio test) so no fraction goes
+                        // negative, the stopping fraction set to exactly zero
+                        // (no projection: shifting every fraction by the
+                        // rounding of the sum would lift zeros off zero).
+#pragma unroll
+                        for (int j = 0; j < N; ++j) {
+                            const double gj = (double)g[j], zj = (double)z[j];
+                            act[j] = (zj <= -1.0 && gj > 0.0) || (zj >= 1.0 && gj < 0.0);
+                        }
+                        simplex_hold<R, N, SF>(z, g, act);
+                        bool factored = true;
+#pragma unroll 1
+                        for (int pass = 0; pass <= FF_N_ENDMEMBERS; ++pass) {
+#pragma unroll
+                            for (int j = 0; j < N; ++j) rhs[j] = act[j] ? 0.0 : -(double)g[j];
+#pragma unroll
+                            for (int i = 0; i < N; ++i) {
+#pragma unroll
+                                for (int k = 0; k < i; ++k)
+                                    m[tri(i, k)] = (act[i] || act[k]) ? 0.0 : (double)A[tri(i, k)];
+                                m[tri(i, i)] = act[i] ? 1.0 : (double)A[tri(i, i)] + mu * (double)d[i];
+                            }
+                            if (!cholesky_packed<N>(m)) {
+                                factored = false;
+                                break;
+                            }
+                            cholesky_solve<N>(m, rhs, delta);
+                            double c[N], y[N], cd = 0.0, cy = 0.0;
+#pragma unroll
+                            for (int j = 0; j < N; ++j) c[j] = (j >= SF && j < SF + FF_N_ENDMEMBERS && !act[j]) ? 1.0 : 0.0;
+                            cholesky_solve<N>(m, c, y);
+#pragma unroll
+                            for (int j = 0; j < N; ++j) {
+                                cd += c[j] * delta[j];
+                                cy += c[j] * y[j];
+                            }
+                            if (cy > 0.0) {
+#pragma unroll
+                                for (int j = 0; j < N; ++j) delta[j] -= cd / cy * y[j];
+                            }
+                            bool more = false;
+#pragma unroll
+                            for (int k = SF; k < SF + FF_N_ENDMEMBERS; ++k)
+                                if (!act[k] && (double)z[k] <= -1.0 && delta[k] < 0.0) {
+                                    act[k] = true;
+                                    more = true;
+                                }
+                            if (!more) break;
+                        }
+                        if (!factored) {
+                            mu *= nu;
+                            nu *= 2.0;
+                            continue;
+                        }
+                        double a = 1.0;
+                        int stop = -1;
+#pragma unroll
+                        for (int k = SF; k < SF + FF_N_ENDMEMBERS; ++k) {
+                            const double x = 0.5 * ((double)z[k] + 1.0), dx = 0.5 * delta[k];
+                            if (dx < 0.0 && x + dx < 0.0 && x / -dx < a) {
+                                a = x / -dx;
+                                stop = k;
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < N; ++j) zt[j] = (R)fmin(1.0, fmax(-1.0, (double)z[j] + a * delta[j]));
+#pragma unroll
+                        for (int k = SF; k < SF + FF_N_ENDMEMBERS; ++k)
+                            if (k == stop) zt[k] = (R)-1.0;
+                        cut = stop >= 0;
+#pragma unroll
+                        for (int j = 0; j < N; ++j) {
+                            hstep[j] = (double)zt[j] - (double)z[j];
+                            hmax = fmax(hmax, fabs(hstep[j]));
+                        }
+                        if (hmax <= xtol && !cut) {
+                            st |= FF_ST_CONVERGED_XTOL;
+                            done = true;
+                            break;
+                        }
                         }
                         double hg = 0.0, hah = 0.0;
 #pragma unroll
@@ -390,6 +535,7 @@ __global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict_
                     st = 0;
 #pragma unroll
                     for (int j = 0; j < N; ++j) z[j] = (R)fmin(1.0, fmax(-1.0, D->zdef[j]));
+                    project_block<MODEL>(z);
                 }
             }
         }
@@ -420,7 +566,7 @@ forward_kernel(const R* __restrict__ tab, int B, const R* __restrict__ state, in
     for (int b = 0; b < B; ++b) {
         const BandRow<R> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
         R ub[N];
-        const R lm = pm.band(row, opaque_zero(), ub);
+        const R lm = band_of<MODEL>(pm, tab, B, b, opaque_zero(), row, ub);
         L[p * B + b] = lm;
         if (J) {
 #pragma unroll
@@ -586,12 +732,17 @@ ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs)
             if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_GAUSS_GRID_2) }
             FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_GAUSS_GRID_2)
         }
+        if (model == FF_MODEL_ENDMEMBER_1) {
+            if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_ENDMEMBER_1) }
+            FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_ENDMEMBER_1)
+        }
         if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_LOGNORMAL_2) }
         FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_LOGNORMAL_2)
     }
     if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_lm<double, double, FF_MODEL_LOGNORMAL_1, 32>(bs);
     if (model == FF_MODEL_GAUSS_GRID_2) return launch_lm<double, double, FF_MODEL_GAUSS_GRID_2, 32>(bs);
+    if (model == FF_MODEL_ENDMEMBER_1) return launch_lm<double, double, FF_MODEL_ENDMEMBER_1, 32>(bs);
     return launch_lm<double, double, FF_MODEL_LOGNORMAL_2, 32>(bs);
 }
 
@@ -609,11 +760,13 @@ ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, 
     if (precision == FF_PRECISION_FP32) {
         if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_1) }
         if (model == FF_MODEL_GAUSS_GRID_2) { FF_DISPATCH_FWD(q, float, FF_MODEL_GAUSS_GRID_2) }
+        if (model == FF_MODEL_ENDMEMBER_1) { FF_DISPATCH_FWD(q, float, FF_MODEL_ENDMEMBER_1) }
         FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_2)
     }
     if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_forward<double, FF_MODEL_LOGNORMAL_1, 32>(sc, state, P, L, J, stream);
     if (model == FF_MODEL_GAUSS_GRID_2) return launch_forward<double, FF_MODEL_GAUSS_GRID_2, 32>(sc, state, P, L, J, stream);
+    if (model == FF_MODEL_ENDMEMBER_1) return launch_forward<double, FF_MODEL_ENDMEMBER_1, 32>(sc, state, P, L, J, stream);
     return launch_forward<double, FF_MODEL_LOGNORMAL_2, 32>(sc, state, P, L, J, stream);
 }
 

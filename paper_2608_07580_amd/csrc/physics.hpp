@@ -29,6 +29,12 @@ template <int MODEL> struct ModelDims;
 template <> struct ModelDims<FF_MODEL_LOGNORMAL_1> { static constexpr int N = 5; static constexpr int C = 1; };
 template <> struct ModelDims<FF_MODEL_LOGNORMAL_2> { static constexpr int N = 8; static constexpr int C = 2; };
 template <> struct ModelDims<FF_MODEL_GAUSS_GRID_2> { static constexpr int N = 8; static constexpr int C = 2; };
+template <> struct ModelDims<FF_MODEL_ENDMEMBER_1> { static constexpr int N = 8; static constexpr int C = 1; };
+
+// First state index of a block of surface fractions on the unit simplex
+// (x = (z + 1)/2 per fraction, box [0, 1]), or -1 when the model has none.
+template <int MODEL>
+constexpr int simplex_first_v = MODEL == FF_MODEL_ENDMEMBER_1 ? 3 : -1;
 
 // Quadrature rule of order Q in constant memory (filled once per device by
 // the host before the first launch).  Kernels index it with a laundered zero
@@ -185,6 +191,31 @@ __device__ __forceinline__ BandRow<double> load_row(const double* __restrict__ t
     return r;
 }
 
+// Endmember row b of a scene table (the library section after the band rows).
+template <typename R>
+struct EndmRow {
+    R e[FF_N_ENDMEMBERS];
+};
+
+__device__ __forceinline__ EndmRow<float> load_endm(const float* __restrict__ t)
+{
+    const float4 p0 = *reinterpret_cast<const float4*>(t);
+    EndmRow<float> r;
+    r.e[0] = p0.x; r.e[1] = p0.y; r.e[2] = p0.z; r.e[3] = p0.w;
+    r.e[4] = t[4];
+    return r;
+}
+
+__device__ __forceinline__ EndmRow<double> load_endm(const double* __restrict__ t)
+{
+    const double2 p0 = *reinterpret_cast<const double2*>(t);
+    const double2 p1 = *reinterpret_cast<const double2*>(t + 2);
+    EndmRow<double> r;
+    r.e[0] = p0.x; r.e[1] = p0.y; r.e[2] = p1.x; r.e[3] = p1.y;
+    r.e[4] = t[4];
+    return r;
+}
+
 // Per-pixel constants of one model evaluation.
 // Broadcast the value of lane M of each aligned group of G lanes (G = 2 or 4,
 // so a group lies inside a quad) to the whole group: one DPP quad_perm move
@@ -292,6 +323,69 @@ struct PixelModel<R, FF_MODEL_LOGNORMAL_1, Q> {
         sd = x[2];
     }
 };
+
+// One lognormal fire component over the endmember surface (Sec. 2.2,
+// library Sec. 2.4): rho = sum_k x_k E_k, dL/dx_k = K tau2 E_k / (1 - S rho)^2.
+template <typename R, int Q>
+struct PixelModel<R, FF_MODEL_ENDMEMBER_1, Q> {
+    static constexpr int N = 8;
+    static constexpr int NE = FF_N_ENDMEMBERS;
+    R f, xs[NE];
+    R u[Q];
+    __device__ void setup(const double (&x)[N], int lane = 0, int L = 1)
+    {
+        f = (R)x[0];
+#pragma unroll
+        for (int k = 0; k < NE; ++k) xs[k] = (R)x[3 + k];
+        node_inverse_temperatures_lanes<R, Q>(lognormal(x[1], x[2]), u, lane, L);
+    }
+    __device__ __forceinline__ R band(const BandRow<R>& t, const EndmRow<R>& em, int o, R (&ub)[N]) const
+    {
+        R sI, sM, sS;
+        thermal_sums<Q>(t.a2, u, o, sI, sM, sS);
+        R rho = xs[0] * em.e[0];
+#pragma unroll
+        for (int k = 1; k < NE; ++k) rho += xs[k] * em.e[k];
+        const R rden = fast_rcp<R>((R)1 - t.S * rho);
+        const R ls = t.K * (t.ratm + t.tau2 * rho * rden);
+        ub[0] = t.tup * t.cb * sI;
+        ub[1] = t.tup * t.cj * sM;
+        ub[2] = t.tup * t.cj * sS;
+        const R ds = t.K * t.tau2 * rden * rden;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) ub[3 + k] = ds * em.e[k];
+        return ls + f * ub[0];
+    }
+    static constexpr int s1[N] = {0, 1, 1, 3, 4, 5, 6, 7};
+    static constexpr int s2[N] = {-1, 2, 2, -1, -1, -1, -1, -1};
+    __device__ static void coefficients(const double (&x)[N], double (&c1)[N], double (&c2)[N])
+    {
+        const LogNormal l = lognormal(x[1], x[2]);
+        const double f = x[0];
+        c1[0] = 1.0; c2[0] = 0.0;
+        c1[1] = f * l.dmu_dm; c2[1] = f * l.dsig_dm;
+        c1[2] = f * l.dmu_ds; c2[2] = f * l.dsig_ds;
+#pragma unroll
+        for (int k = 3; k < N; ++k) { c1[k] = 1.0; c2[k] = 0.0; }
+    }
+    __device__ static void moments(const double (&x)[N], double& et, double& sd)
+    {
+        et = x[1];
+        sd = x[2];
+    }
+};
+
+// Model radiance and basis at band b of a scene table (tab: band rows, then
+// for the endmember model the library rows); row receives the band row.
+template <int MODEL, typename PM, typename R>
+__device__ __forceinline__ R band_of(const PM& pm, const R* __restrict__ tab, int B, int b, int o,
+                                     const BandRow<R>& row, R (&ub)[PM::N])
+{
+    if constexpr (MODEL == FF_MODEL_ENDMEMBER_1)
+        return pm.band(row, load_endm(tab + (size_t)B * FF_TABLE_COLS + (size_t)b * kEndmCols), o, ub);
+    else
+        return pm.band(row, o, ub);
+}
 
 template <typename R, int Q>
 struct PixelModel<R, FF_MODEL_LOGNORMAL_2, Q> {

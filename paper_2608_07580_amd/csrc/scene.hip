@@ -74,6 +74,46 @@ srf_band_tables(int B, int H, const double* __restrict__ lam_b, const double* __
     }
 }
 
+// Band resampling of the endmember library with the same Gaussian
+// responses as srf_band_tables: one workgroup per band, FP64 sums, rows
+// written to the endmember section of both tables.
+__global__ void __launch_bounds__(kSetupThreads)
+srf_endmembers(int B, int H, const double* __restrict__ lam_b, const double* __restrict__ fwhm_b,
+               const double* __restrict__ hr_lam, const double* __restrict__ refl,
+               double* __restrict__ endm64, float* __restrict__ endm32, int* __restrict__ bad)
+{
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const double lc = lam_b[b];
+    const double sig = fwhm_b[b] / (2.0 * sqrt(2.0 * log(2.0)));
+    constexpr int NE = FF_N_ENDMEMBERS;
+    double acc[NE + 1] = {};
+    for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        const double d = hr_lam[j] - lc;
+        if (fabs(d) > 4.0 * sig) continue;
+        const double w = exp(-0.5 * (d / sig) * (d / sig));
+        acc[0] += w;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) acc[k + 1] += w * refl[(size_t)k * H + j];
+    }
+    __shared__ double red[NE + 1][kSetupThreads];
+    for (int c = 0; c <= NE; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int stride = kSetupThreads / 2; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+            for (int c = 0; c <= NE; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + stride];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double sw = red[0][0];
+    if (!(sw > 0.0)) { bad[0] = 1; return; }
+    for (int c = 0; c < kEndmCols; ++c) {
+        const double v = c < NE ? red[c + 1][0] / sw : 0.0;
+        endm64[(size_t)b * kEndmCols + c] = v;
+        endm32[(size_t)b * kEndmCols + c] = (float)v;
+    }
+}
+
 }  // namespace
 }  // namespace ff
 
@@ -100,6 +140,7 @@ extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm
     ff_scene* sc = new ff_scene();
     sc->n_bands = B;
     sc->lambda.assign(srf->wavelength_nm, srf->wavelength_nm + B);
+    sc->fwhm.assign(srf->fwhm_nm, srf->fwhm_nm + B);
     if (atm->sat_level) sc->lsat.assign(atm->sat_level, atm->sat_level + B);
     else sc->lsat.assign(B, INFINITY);
     hipError_t e = hipGetDevice(&sc->device);
@@ -111,8 +152,11 @@ extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm
     if (e == hipSuccess) e = hipMalloc(&stage, nd * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&sat_d, (size_t)B * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&bad_d, sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&sc->table_f64, (size_t)B * FF_TABLE_COLS * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&sc->table_f32, (size_t)B * FF_TABLE_COLS * sizeof(float));
+    const size_t n_tab = (size_t)B * (FF_TABLE_COLS + kEndmCols);
+    if (e == hipSuccess) e = hipMalloc(&sc->table_f64, n_tab * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&sc->table_f32, n_tab * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(sc->table_f64, 0, n_tab * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(sc->table_f32, 0, n_tab * sizeof(float));
     if (e == hipSuccess) {
         std::vector<double> host(nd);
         std::memcpy(&host[0], srf->wavelength_nm, B * sizeof(double));
@@ -166,5 +210,68 @@ extern "C" ff_status ff_scene_band_tables(const ff_scene* sc, double* out_host)
     if (!sc || !out_host) return set_error(FF_EINVAL, "ff_scene_band_tables: NULL argument");
     FF_HIP_TRY(hipMemcpy(out_host, sc->table_f64, (size_t)sc->n_bands * FF_TABLE_COLS * sizeof(double),
                          hipMemcpyDeviceToHost));
+    return clear_error();
+}
+
+extern "C" ff_status ff_scene_set_endmembers(ff_scene* sc, int32_t n_hr, const double* lambda_nm,
+                                             const double* reflectance_host)
+{
+    if (!sc || !lambda_nm || !reflectance_host) return set_error(FF_EINVAL, "ff_scene_set_endmembers: NULL argument");
+    if (n_hr < 1) return set_error(FF_EINVAL, "ff_scene_set_endmembers: n_hr < 1");
+    const int B = sc->n_bands, H = n_hr;
+    if ((int)sc->fwhm.size() != B || (int)sc->lambda.size() != B)
+        return set_error(FF_EINVAL, "ff_scene_set_endmembers: scene without band responses");
+    for (int j = 0; j < H; ++j)
+        if (!std::isfinite(lambda_nm[j])) return set_error(FF_EINVAL, "ff_scene_set_endmembers: non-finite wavelength");
+    for (size_t i = 0; i < (size_t)FF_N_ENDMEMBERS * H; ++i)
+        if (!std::isfinite(reflectance_host[i]))
+            return set_error(FF_EINVAL, "ff_scene_set_endmembers: non-finite reflectance");
+    int cur = 0;
+    FF_HIP_TRY(hipGetDevice(&cur));
+    if (cur != sc->device) FF_HIP_TRY(hipSetDevice(sc->device));
+    const size_t nd = 2 * (size_t)B + (size_t)H * (1 + FF_N_ENDMEMBERS);
+    double* stage = nullptr;
+    int* bad_d = nullptr;
+    hipError_t e = hipMalloc(&stage, nd * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&bad_d, sizeof(int));
+    if (e == hipSuccess) {
+        std::vector<double> host(nd);
+        std::memcpy(&host[0], sc->lambda.data(), B * sizeof(double));
+        std::memcpy(&host[B], sc->fwhm.data(), B * sizeof(double));
+        std::memcpy(&host[2 * (size_t)B], lambda_nm, H * sizeof(double));
+        std::memcpy(&host[2 * (size_t)B + H], reflectance_host, (size_t)FF_N_ENDMEMBERS * H * sizeof(double));
+        e = hipMemcpy(stage, host.data(), nd * sizeof(double), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemset(bad_d, 0, sizeof(int));
+    if (e == hipSuccess) {
+        const size_t off = (size_t)B * FF_TABLE_COLS;
+        hipLaunchKernelGGL(srf_endmembers, dim3(B), dim3(kSetupThreads), 0, 0, B, H, stage, stage + B,
+                           stage + 2 * B, stage + 2 * (size_t)B + H, sc->table_f64 + off, sc->table_f32 + off, bad_d);
+        e = hipGetLastError();
+    }
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpy(&bad, bad_d, sizeof(int), hipMemcpyDeviceToHost);
+    hipFree(stage);
+    hipFree(bad_d);
+    if (cur != sc->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_error(e, "ff_scene_set_endmembers");
+    if (bad) {
+        sc->has_endmembers = false;
+        return set_error(FF_EINVAL, "ff_scene_set_endmembers: a band's response window holds no sample");
+    }
+    sc->has_endmembers = true;
+    return clear_error();
+}
+
+extern "C" ff_status ff_scene_endmembers(const ff_scene* sc, double* out_host)
+{
+    if (!sc || !out_host) return set_error(FF_EINVAL, "ff_scene_endmembers: NULL argument");
+    if (!sc->has_endmembers) return set_error(FF_EINVAL, "ff_scene_endmembers: no library set");
+    const int B = sc->n_bands;
+    std::vector<double> rows((size_t)B * kEndmCols);
+    FF_HIP_TRY(hipMemcpy(rows.data(), sc->table_f64 + (size_t)B * FF_TABLE_COLS, rows.size() * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    for (int k = 0; k < FF_N_ENDMEMBERS; ++k)
+        for (int b = 0; b < B; ++b) out_host[(size_t)k * B + b] = rows[(size_t)b * kEndmCols + k];
     return clear_error();
 }

@@ -112,6 +112,49 @@ __device__ __forceinline__ void cholesky_solve(const double (&c)[N * (N + 1) / 2
     }
 }
 
+// Euclidean projection of v onto the unit simplex {x >= 0, sum x = 1}
+// (sort-based, Duchi, Shalev-Shwartz, Singer & Chandra 2008): sort
+// descending (a 9-comparator network, all indices fixed so v stays in
+// registers), theta = (sum of the largest j values - 1)/j for the largest j
+// with u_j > theta, x = max(v - theta, 0).
+__device__ __forceinline__ void project_simplex5(double (&v)[5])
+{
+    double u[5] = {v[0], v[1], v[2], v[3], v[4]};
+    auto cx = [&](int a, int b) {
+        const double hi = fmax(u[a], u[b]), lo = fmin(u[a], u[b]);
+        u[a] = hi;
+        u[b] = lo;
+    };
+    cx(0, 1); cx(3, 4); cx(2, 4); cx(2, 3); cx(0, 3); cx(0, 2); cx(1, 4); cx(1, 3); cx(1, 2);
+    double cum = 0.0, theta = 0.0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        cum += u[j];
+        const double t = (cum - 1.0) / (double)(j + 1);
+        if (u[j] - t > 0.0) theta = t;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) v[i] = v[i] - theta > 0.0 ? v[i] - theta : 0.0;
+}
+
+// The model's simplex block of z (fractions x = (z + 1)/2) projected onto
+// the unit simplex (Sec. 2.5: the surface mixture after each step); no-op
+// for models without one.
+template <int MODEL, typename T, int N>
+__device__ __forceinline__ void project_block(T (&z)[N])
+{
+    constexpr int SF = simplex_first_v<MODEL>;
+    if constexpr (SF >= 0) {
+        static_assert(FF_N_ENDMEMBERS == 5, "simplex block of five fractions");
+        double x[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[k] = 0.5 * ((double)z[SF + k] + 1.0);
+        project_simplex5(x);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) z[SF + k] = (T)(2.0 * x[k] - 1.0);
+    }
+}
+
 // Sum over the L lanes of a pixel's group (aligned, L a power of two) by an
 // xor butterfly: every lane of the group ends with the same bits, since each
 // level adds the same two partial sums (a + b == b + a in IEEE arithmetic).
@@ -202,7 +245,7 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
             const int o = opaque_zero();
             const BandRow<R> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
             R ub[N];
-            const R lm = pm.band(row, o, ub);
+            const R lm = band_of<MODEL>(pm, tab, B, b, o, row, ub);
             const bool msk = (R)lob < row.lsat;
             const ACC r = msk ? (ACC)((R)lob - lm) : (ACC)0;
             ACC ua[N];

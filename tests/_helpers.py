@@ -53,7 +53,7 @@ def posterior_sd(ref, model):
     n = oracle.n_state(model)
     C = oracle.unpack_cov(ref.cov, n)
     sd_f = np.sqrt(np.abs(C[:, 0, 0]))
-    if model == 1:
+    if model in (1, 4):                  # one lognormal component: E[T] = m
         sd_t = np.sqrt(np.abs(C[:, 1, 1]))
     else:
         x = ref.state
