@@ -43,8 +43,8 @@ HBM_PEAK = 8.0e12
 # kernel sources with the SHA-1 below; any other source reports null.
 TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
                    "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
-TRAFFIC_SHA1 = "4ee34affd79ab90b195c4752e0e783d1ee9f99b2"
-TRAFFIC_BYTES = {"plain": 56.11e9, "warm": 35.50e9}
+TRAFFIC_SHA1 = "d8a3e0b7b98138453b187d2d6bbed8a20c0a5f95"
+TRAFFIC_BYTES = {"plain": 56.11e9, "warm": 35.51e9}
 
 
 def measured_traffic(leg: str):
@@ -63,6 +63,11 @@ def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> int:
     slots each) = 11; per band and component 5 slots of scaling plus 19
     (n=5) / 49 (n=8) for the solar term, basis, residual and the J^T J, J^T r,
     r.r accumulations."""
+    if model == 4:
+        # one component; the endmember surface: 5 FMAs for rho and 5 basis
+        # products where the linear surface has 2 and 2 (25), and the n = 8
+        # accumulations (45)
+        return n_bands * (11 * n_quad + 5 + 25 + 45)
     comps = 1 if model == 1 else 2
     per_band = comps * (11 * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45)
     return n_bands * per_band
@@ -722,6 +727,105 @@ def run_paper_model(args):
     print(json.dumps(line), flush=True)
 
 
+def run_endmember(args):
+    """The endmember surface (Sec. 2.2 with the library of Sec. 2.4: five
+    spectra, fractions on the unit simplex) under one lognormal fire
+    component, on a 262,144-pixel set with path reflectance and spherical
+    albedo: the simplex-constrained LM (tuned launch) and the paper's
+    staged Adam with its projection, timed, with E[T] and fraction accuracy
+    against the truth and the FP64 oracle's LM on a seeded subsample."""
+    import torch
+    import oracle
+    import paper_2608_07580_amd as ff
+    import scenegen
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _helpers import parity_report
+    dev = torch.device("cuda:0")
+    ff.lib()
+    P = args.precision_pixels
+    model = ff.MODEL_ENDMEMBER_1
+    X = scenegen.draw_states_endmember1(scenegen.rng_for(6, 0, scenegen.STREAM_PARAMS), P)
+    atm = scenegen.make_atmosphere(6, 0, rho_atm=0.02, s_sph=0.1)
+    lib = scenegen.endmember_library(atm.hr_lambda_nm)
+    sc = ff.Scene(atm).set_endmembers(atm.hr_lambda_nm, lib)
+    B = sc.n_bands
+    L = torch.empty((P, B), dtype=torch.float64, device=dev)
+    for s0 in range(0, P, 1 << 16):
+        L[s0:s0 + (1 << 16)] = ff.forward(sc, torch.tensor(X[s0:s0 + (1 << 16)], dtype=torch.float64, device=dev),
+                                          model)
+    noise = torch.from_numpy(scenegen.noise_normals(6, 0, P, B)).to(dev)
+    rad = (L * (1.0 + noise.double() / args.snr)).float().contiguous()
+    del L, noise
+    torch.cuda.synchronize()
+    prior = ff.default_prior(model)
+    stream = torch.cuda.Stream(device=dev)
+    opts = ff.default_options(n_quad=args.n_quad, max_iter=args.grid_max_iter)
+    if not args.no_tune:
+        with torch.cuda.stream(stream):
+            opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+        torch.cuda.synchronize()
+
+    def timed(launch):
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                launch()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                launch()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    strong = X[:, 0] >= 1e-2
+
+    def acc(r):
+        d = np.abs(r["moments"][:, 0] - X[:, 1])
+        fr = r["state"][:, 3:]
+        return {"dT_median_K": float(np.nanmedian(d)), "dT_median_strong_K": float(np.nanmedian(d[strong])),
+                "fraction_mae": float(np.nanmean(np.abs(fr - X[:, 3:]))),
+                "max_simplex_sum_error": float(np.nanmax(np.abs(fr.sum(axis=1) - 1.0))),
+                "min_fraction": float(np.nanmin(fr)), "rrr_median": float(np.nanmedian(r["rrr"]))}
+
+    out = ff.allocate_outputs(P, model, dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms_lm = timed(lambda: ff.retrieve(sc, rad, prior, options=opts, outputs=out, evals=evals, stream=stream))
+    r_lm = out.numpy()
+    ev = int(evals.item()) / (args.steps + args.warmup)
+    conv = int(((r_lm["status"].astype(np.int64) & ff.ST_CONVERGED) != 0).sum())
+    spe = slots_per_eval(B, args.n_quad, model)
+    achieved = ev * spe / (ms_lm * 1e-3)
+    aopt = ff.adam_options(prior, n_quad=args.n_quad)
+    out_a = ff.allocate_outputs(P, model, dev)
+    ms_ad = timed(lambda: ff.adam_retrieve(sc, rad, prior, options=aopt, outputs=out_a, stream=stream))
+    r_ad = out_a.numpy()
+    idx = scenegen.subsample(6, 0, P, args.solver_sample)
+    tab = oracle.band_tables(atm, lib)
+    lo, hi, x0 = scenegen.default_prior(model)
+    t0 = time.time()
+    ref = oracle.retrieve(tab, rad[torch.from_numpy(idx).to(dev)].cpu().numpy(), model, lo, hi, x0,
+                          opts=oracle.LMOptions(max_iter=args.grid_max_iter), nthreads=len(os.sched_getaffinity(0)))
+    t_or = time.time() - t0
+    rep = parity_report({k: v[idx] for k, v in r_lm.items() if v is not None}, ref, model=model)
+    line = {
+        "metric": "endmember surface on the unit simplex: LM and staged Adam retrievals per second",
+        "config": {"workload": f"one lognormal fire component over a 5-endmember simplex surface, {P} px x {B} "
+                               f"bands, rho_atm 0.02, S 0.1, 1e-4 <= f <= 0.3, Dirichlet(0.7) fractions, "
+                               f"SNR {args.snr:g}", "pixels": P, "max_iter": args.grid_max_iter},
+        "lm": {"ms_per_step": ms_lm, "converged": conv, "converged_per_s": conv / (ms_lm * 1e-3),
+               "evals_per_pixel": ev / P, "accuracy": acc(r_lm),
+               "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
+               "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tops/s",
+                            "frac": achieved / PEAK_SLOTS, "kernel": "lm_kernel", "ops_per_eval": spe}},
+        "adam": {"ms_per_step": ms_ad, "pixels_per_s": P / (ms_ad * 1e-3), "accuracy": acc(r_ad)},
+        "oracle_sample": {"pixels": len(idx), "s": t_or, "converged": int(ref.converged.sum()),
+                          "gpu_lm_vs_oracle": {k: v for k, v in rep.items() if not k.endswith("_mask")}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_coarsening(args):
     """The paper's resolution-rescaling analysis on the clustered-fire scene:
     12 x 12 block means of the fine radiance, LM at both resolutions, and the
@@ -894,13 +998,14 @@ def main():
     ap.add_argument("--grid-max-iter", type=int, default=200, help="paper-model workload: LM iteration cap")
     ap.add_argument("--block", type=int, default=12, help="coarsening workload: block side")
     ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers", "front-end",
-                                           "paper-model", "coarsening"),
+                                           "paper-model", "endmember-surface", "coarsening"),
                     default="clustered-fire",
                     help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
                          "precision: FP32/FP64 variants on the two-component stress set; "
                          "solvers: the paper's two-stage Adam vs LM on the clustered-fire scene; "
                          "front-end: HFDI candidate selection + LM on the candidates; "
                          "paper-model: the paper's two-Gaussian grid thermal model, LM and staged Adam; "
+                         "endmember-surface: the 5-endmember simplex surface, LM and staged Adam; "
                          "coarsening: 12 x 12 block means, LM at both resolutions, Quantile Error Curves")
     ap.add_argument("--adam-lpp", type=int, default=1, help="lanes per pixel of the Adam kernel")
     ap.add_argument("--hfdi-threshold", type=float, default=-0.1, help="front-end workload: HFDI threshold")
@@ -932,6 +1037,9 @@ def main():
         return
     if args.workload == "coarsening":
         run_coarsening(args)
+        return
+    if args.workload == "endmember-surface":
+        run_endmember(args)
         return
     if args.workload == "precision":
         if args.cpu_sample == 65536:
