@@ -212,8 +212,14 @@ N_ENDMEMBERS = 5          # Sec. 2.4: the library's five spectra
 SIMPLEX_FIRST = 3         # model 4: state (f, m, s, x_surf,1 .. x_surf,5)
 
 
+def simplex_first(model: int) -> int:
+    """First surface fraction of the model's state (model 4: after f, m, s;
+    model 5: after f, eta, mu_s, sig_s, mu_h, sig_h), or -1."""
+    return {4: 3, 5: 6}.get(model, -1)
+
+
 def n_state(model: int) -> int:
-    return {1: 5, 2: 8, 3: 8, 4: 8}[model]
+    return {1: 5, 2: 8, 3: 8, 4: 8, 5: 11}[model]
 
 
 def project_simplex(v):
@@ -225,10 +231,10 @@ def project_simplex(v):
 
 
 def _endm(tab: Tables, model: int):
-    if model != 4:
+    if simplex_first(model) < 0:
         return None
     if tab.endm is None:
-        raise ValueError("model 4 needs the band tables' endmember spectra")
+        raise ValueError("the endmember models need the band tables' endmember spectra")
     return np.ascontiguousarray(tab.endm, np.float64)
 
 
@@ -370,9 +376,11 @@ def paper_stages(model: int, lo, hi, x0, clip: float = ADAM_CLIP):
     fits f and the temperature distribution, whose spreads (and eta) restart
     from the prior start x0; the one-component model's f, m, s use OMEGA_2,
     the two-component model's flaming (m_h, s_h) and smouldering (m_s, s_s)
-    variables their own windows.  With the endmember surface (model 4) the
-    surface fractions take the reflectance's place in stage 1, as the paper's
-    stage-1 state {x_surf, alpha_1, T_1} has them."""
+    variables their own windows.  With the endmember surface (models 4 and
+    5) the surface fractions take the reflectance's place in stage 1, as the
+    paper's stage-1 state {x_surf, alpha_1, T_1} has them; for model 5 (the
+    paper's full forward model) the two stages free exactly the paper's
+    state vectors x_1 and x_2."""
     z0 = x_to_z(np.asarray(x0, np.float64), np.asarray(lo, np.float64), np.asarray(hi, np.float64))
     if model == 1:
         s1 = AdamStage(30, 0.03, (0, 1, 3, 4), {j: OMEGA_1 for j in (0, 1, 3, 4)}, clip, {2: -1.0})
@@ -381,6 +389,14 @@ def paper_stages(model: int, lo, hi, x0, clip: float = ADAM_CLIP):
         surf = (0, 1, 3, 4, 5, 6, 7)
         s1 = AdamStage(30, 0.03, surf, {j: OMEGA_1 for j in surf}, clip, {2: -1.0})
         s2 = AdamStage(100, 0.015, (0, 1, 2), {j: OMEGA_2 for j in (0, 1, 2)}, clip, {2: float(z0[2])})
+    elif model == 5:
+        # the paper's own state vectors: x_1 = {x_surf, alpha_1, T_1} and
+        # x_2 = {mu_hot, sig_hot, mu_smol, sig_smol, eta, alpha}
+        surf = (0, 4, 6, 7, 8, 9, 10)
+        s1 = AdamStage(30, 0.03, surf, {j: OMEGA_1 for j in surf}, clip, {1: 1.0, 5: -1.0})
+        win = {0: OMEGA_2, 1: OMEGA_2, 2: OMEGA_SMOL, 3: OMEGA_SMOL, 4: OMEGA_HOT, 5: OMEGA_HOT}
+        s2 = AdamStage(100, 0.015, (0, 1, 2, 3, 4, 5), win, clip,
+                       {1: float(z0[1]), 3: float(z0[3]), 5: float(z0[5])})
     elif model in (2, 3):
         s1 = AdamStage(30, 0.03, (0, 4, 6, 7), {j: OMEGA_1 for j in (0, 4, 6, 7)}, clip,
                        {1: 1.0, 5: -1.0})

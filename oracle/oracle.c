@@ -43,7 +43,7 @@
 #include <omp.h>
 #endif
 
-#define NMAX 8
+#define NMAX 12
 #define QMAX 128
 
 /* ---- physical constants: exact SI values ---------------------------------- */
@@ -185,10 +185,22 @@ typedef struct {
     const double* endm;   /* [N_ENDMEMBERS][B] endmember reflectance (model 4) */
 } scene_t;
 
-static int n_of_model(int model) { return model == 1 ? 5 : ((model >= 2 && model <= 4) ? 8 : -1); }
+static int n_of_model(int model)
+{
+    switch (model) {
+    case 1: return 5;
+    case 2: case 3: case 4: return 8;
+    case 5: return 11;
+    default: return -1;
+    }
+}
 
-/* model 4 keeps its surface fractions (state 3..7) on the unit simplex */
-static int simplex_first(int model) { return model == 4 ? 3 : -1; }
+/* the temperature-grid thermal term (models 3 and 5) needs two nodes */
+static int grid_model(int model) { return model == 3 || model == 5; }
+
+/* models 4 and 5 keep their surface fractions (state 3..7, 6..10) on the
+ * unit simplex */
+static int simplex_first(int model) { return model == 4 ? 3 : (model == 5 ? 6 : -1); }
 
 /* Euclidean projection of v[0..k) onto the unit simplex {x >= 0, sum x = 1}
  * (sort-based, Duchi, Shalev-Shwartz, Singer & Chandra 2008). */
@@ -234,10 +246,11 @@ static double model_band(const scene_t* sc, int b, int model, const double* x, d
     const double lam = sc->lam[b];
     const int n = n_of_model(model);
     double rho;
-    if (model == 4) {
+    const int sf = simplex_first(model);
+    if (sf >= 0) {
         /* Sec. 2.2: surface reflectance as a mixture of the endmember library */
         rho = 0.0;
-        for (int k = 0; k < N_ENDMEMBERS; ++k) rho += x[3 + k] * sc->endm[k * sc->B + b];
+        for (int k = 0; k < N_ENDMEMBERS; ++k) rho += x[sf + k] * sc->endm[k * sc->B + b];
     } else {
         rho = x[n - 2] + x[n - 1] * (lam - LAMBDA_REF_NM);
     }
@@ -256,7 +269,7 @@ static double model_band(const scene_t* sc, int b, int model, const double* x, d
             dl[1] = f * tup * (Imu * dmu[0] + Isig * dsig[0]);
             dl[2] = f * tup * (Imu * dmu[1] + Isig * dsig[1]);
         }
-    } else if (model == 3) {
+    } else if (grid_model(model)) {
         /* the paper's mixture: eta-weighted flaming and smouldering Gaussians
          * on the temperature grid (Q = grid nodes) */
         const double eta = x[1];
@@ -292,8 +305,8 @@ static double model_band(const scene_t* sc, int b, int model, const double* x, d
     }
     if (dl) {
         const double drho = sc->K[b] * sc->tau2[b] / (den * den);
-        if (model == 4) {
-            for (int k = 0; k < N_ENDMEMBERS; ++k) dl[3 + k] = drho * sc->endm[k * sc->B + b];
+        if (sf >= 0) {
+            for (int k = 0; k < N_ENDMEMBERS; ++k) dl[sf + k] = drho * sc->endm[k * sc->B + b];
         } else {
             dl[n - 2] = drho;
             dl[n - 1] = drho * (lam - LAMBDA_REF_NM);
@@ -310,7 +323,7 @@ int orc_forward(int B, const double* lam, const double* K, const double* tau2,
                 int nthreads)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || (model == 4 && !endm) || B <= 0) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (grid_model(model) && Q < 2) || (simplex_first(model) >= 0 && !endm) || B <= 0) return -1;
     scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw, endm};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -723,7 +736,7 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
                  int* iters, unsigned* status)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || (model == 4 && !endm) || B <= 0 || P < 0) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (grid_model(model) && Q < 2) || (simplex_first(model) >= 0 && !endm) || B <= 0 || P < 0) return -1;
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
     if (!simplex_box_ok(model, lo, hi)) return -1;
     scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw, endm};
@@ -859,7 +872,7 @@ int orc_adam_retrieve(int B, const double* lam, const double* K, const double* t
                       int* iters, unsigned* status)
 {
     const int n = n_of_model(model);
-    if (n < 0 || Q <= 0 || Q > QMAX || (model == 3 && Q < 2) || (model == 4 && !endm) || B <= 0 || P < 0 || n_stages < 0 || n_stages > 16) return -1;
+    if (n < 0 || Q <= 0 || Q > QMAX || (grid_model(model) && Q < 2) || (simplex_first(model) >= 0 && !endm) || B <= 0 || P < 0 || n_stages < 0 || n_stages > 16) return -1;
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
     if (!simplex_box_ok(model, lo, hi)) return -1;
     adam_stage_t st[16];

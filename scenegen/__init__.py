@@ -36,14 +36,17 @@ MODEL_LOGNORMAL_1 = 1  # state (f, m, s, rho0, rho1)
 MODEL_LOGNORMAL_2 = 2  # state (f, eta, m_s, s_s, m_h, s_h, rho0, rho1)
 MODEL_GAUSS_GRID_2 = 3  # state (f, eta, mu_s, sig_s, mu_h, sig_h, rho0, rho1)
 MODEL_ENDMEMBER_1 = 4  # state (f, m, s, x_gv, x_npv, x_soil1, x_soil2, x_char)
+MODEL_FULL = 5  # state (f, eta, mu_s, sig_s, mu_h, sig_h, x_gv, x_npv, x_soil1, x_soil2, x_char)
 
-N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8, MODEL_ENDMEMBER_1: 8}
+N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8, MODEL_ENDMEMBER_1: 8,
+           MODEL_FULL: 11}
 
 STATE_NAMES = {
     MODEL_LOGNORMAL_1: ("f", "m", "s", "rho0", "rho1"),
     MODEL_LOGNORMAL_2: ("f", "eta", "m_s", "s_s", "m_h", "s_h", "rho0", "rho1"),
     MODEL_GAUSS_GRID_2: ("f", "eta", "mu_s", "sig_s", "mu_h", "sig_h", "rho0", "rho1"),
     MODEL_ENDMEMBER_1: ("f", "m", "s", "x_gv", "x_npv", "x_soil1", "x_soil2", "x_char"),
+    MODEL_FULL: ("f", "eta", "mu_s", "sig_s", "mu_h", "sig_h", "x_gv", "x_npv", "x_soil1", "x_soil2", "x_char"),
 }
 
 # Exact SI constants (2019 redefinition) used to define the synthetic sun.
@@ -170,6 +173,11 @@ def default_prior(model: int):
         lo = np.array([0.0, 350.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
         hi = np.array([0.5, 2200.0, 500.0, 1.0, 1.0, 1.0, 1.0, 1.0])
         x0 = np.array([0.01, 1000.0, 150.0, 0.2, 0.2, 0.2, 0.2, 0.2])
+    elif model == MODEL_FULL:
+        # the Gaussian-mixture box and start, fractions as for model 4
+        lo = np.array([0.0, 0.0, 350.0, 10.0, 900.0, 10.0] + [0.0] * 5)
+        hi = np.array([0.5, 1.0, 900.0, 500.0, 2200.0, 500.0] + [1.0] * 5)
+        x0 = np.array([0.01, 0.5, 650.0, 150.0, 1200.0, 150.0] + [0.2] * 5)
     else:
         raise ValueError(f"unknown model {model}")
     return lo, hi, x0
@@ -229,6 +237,15 @@ def draw_states_endmember1(rng: np.random.Generator, n: int) -> np.ndarray:
     s = rng.uniform(50.0, 300.0, n)
     x = rng.dirichlet(np.full(5, 0.7), n)
     return np.concatenate([np.stack([f, m, s], axis=1), x], axis=1)
+
+
+def draw_states_full(rng: np.random.Generator, n: int) -> np.ndarray:
+    """The paper's full state: the Gaussian-mixture draw for f, eta and the
+    two components, surface fractions ~ Dirichlet(0.7, ..., 0.7).
+    Shape [n, 11]."""
+    th = draw_states_gauss_grid2(rng, n)[:, :6]
+    x = rng.dirichlet(np.full(5, 0.7), n)
+    return np.concatenate([th, x], axis=1)
 
 
 def endmember_library(hr_lambda_nm: np.ndarray) -> np.ndarray:
