@@ -61,6 +61,7 @@ typedef int32_t ff_status;
  *   FF_MODEL_LOGNORMAL_2: n = 8, x = (f, eta, m_s, s_s, m_h, s_h, rho0, rho1)
  *   FF_MODEL_GAUSS_GRID_2: n = 8, x = (f, eta, mu_s, sig_s, mu_h, sig_h, rho0, rho1)
  *   FF_MODEL_ENDMEMBER_1: n = 8, x = (f, m, s, x_1, x_2, x_3, x_4, x_5)
+ *   FF_MODEL_FULL: n = 11, x = (f, eta, mu_s, sig_s, mu_h, sig_h, x_1 .. x_5)
  * f: emitting fraction scaling the thermal term (the paper's alpha),
  * m/s: lognormal mean and s.d. in K, eta: weight of the flaming component,
  * rho0: reflectance at 1440 nm, rho1: reflectance slope per nm.  The
@@ -74,12 +75,15 @@ typedef int32_t ff_status;
  * Sec. 2.4): rho(lambda) = sum_k x_k E_k(lambda) over the scene's
  * FF_N_ENDMEMBERS library spectra (ff_scene_set_endmembers), with the
  * fractions on the unit simplex (x_k >= 0, sum x_k = 1); the thermal term
- * is the one-component lognormal.  Its fractions must have the box [0, 1]. */
+ * is the one-component lognormal.  FF_MODEL_FULL is the paper's full
+ * forward model: the FF_MODEL_GAUSS_GRID_2 thermal term over the endmember
+ * surface.  Surface fractions must have the box [0, 1]. */
 #define FF_MODEL_LOGNORMAL_1 1
 #define FF_MODEL_LOGNORMAL_2 2
 #define FF_MODEL_GAUSS_GRID_2 3
 #define FF_MODEL_ENDMEMBER_1 4
-#define FF_MAX_STATE 8
+#define FF_MODEL_FULL 5
+#define FF_MAX_STATE 11
 #define FF_N_ENDMEMBERS 5
 
 /* Arithmetic of the forward model, Jacobian and reductions.  The damped
@@ -205,7 +209,9 @@ void ff_options_default(ff_options* opts);
  * m_s = 650, m_h = 1200, rho0 = 0.2, rho1 = 0.  FF_MODEL_GAUSS_GRID_2 takes
  * the two-component box and start with the spreads in [10, 500] K.
  * FF_MODEL_ENDMEMBER_1 takes the one-component f, m, s and fractions in
- * [0, 1] starting at 1/5 each.  FF_EINVAL for an unknown model. */
+ * [0, 1] starting at 1/5 each; FF_MODEL_FULL the FF_MODEL_GAUSS_GRID_2
+ * thermal box and start with those fractions.  FF_EINVAL for an unknown
+ * model. */
 ff_status ff_prior_default(int32_t model, ff_prior* prior);
 
 /* Gauss-Hermite rule for weight e^{-x^2}: q nodes and weights (host arrays

@@ -20,12 +20,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfirefit.so")
 
 FF_OK, FF_EINVAL, FF_EDEVICE, FF_ENOMEM, FF_EUNSUPPORTED = 0, -1, -2, -3, -4
-MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2, MODEL_GAUSS_GRID_2, MODEL_ENDMEMBER_1 = 1, 2, 3, 4
+MODEL_LOGNORMAL_1, MODEL_LOGNORMAL_2, MODEL_GAUSS_GRID_2, MODEL_ENDMEMBER_1, MODEL_FULL = 1, 2, 3, 4, 5
 N_ENDMEMBERS = 5
 PRECISION_FP32, PRECISION_FP64 = 0, 1
 SCHEDULE_PERSISTENT, SCHEDULE_STATIC = 0, 1
 ACCUMULATE_FP32, ACCUMULATE_FP64 = 0, 1
-MAX_STATE = 8
+MAX_STATE = 11
 TABLE_COLS = 12
 
 ST_CONVERGED_GTOL, ST_CONVERGED_XTOL, ST_CONVERGED_FTOL = 1, 2, 4
@@ -35,7 +35,8 @@ ST_BAD_ATMOSPHERE = 2048
 MAX_ATMOSPHERES = 16
 ST_CONVERGED = ST_CONVERGED_GTOL | ST_CONVERGED_XTOL | ST_CONVERGED_FTOL
 
-N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8, MODEL_ENDMEMBER_1: 8}
+N_STATE = {MODEL_LOGNORMAL_1: 5, MODEL_LOGNORMAL_2: 8, MODEL_GAUSS_GRID_2: 8, MODEL_ENDMEMBER_1: 8,
+           MODEL_FULL: 11}
 
 # exported symbols of include/firefit.h
 EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_default",

@@ -24,7 +24,7 @@ template <typename R, int Q>
 struct AdamDesc {
     SceneDev sc[kMaxScenesPerLaunch];
     const double* tab64[kMaxScenesPerLaunch];  // FP64 table of each scene (band centres)
-    uint8_t* bits;                 // [scene][stage][B] window bits (bit j: variable j)
+    uint16_t* bits;                // [scene][stage][B] window bits (bit j: variable j)
     int n_scenes;
     int B;
     int64_t total;
@@ -60,7 +60,7 @@ __global__ void window_bits(const Desc* __restrict__ D)
     unsigned bits = 0;
     for (int j = 0; j < D->n; ++j)
         if (((D->free_mask[k] >> j) & 1u) && lam >= D->wlo[k][j] && lam <= D->whi[k][j]) bits |= 1u << j;
-    D->bits[i] = (uint8_t)bits;
+    D->bits[i] = (uint16_t)bits;
 }
 
 // Windowed loss gradient in z at physical state x:
@@ -70,7 +70,7 @@ __global__ void window_bits(const Desc* __restrict__ D)
 // bands sub, sub + L, ... and combine their sums across the group.
 template <typename R, typename ACC, int MODEL, int Q, typename Desc>
 __device__ __forceinline__ void windowed_gradient(const Desc* descp, const float* __restrict__ rad,
-                                                  const R* __restrict__ tab, const uint8_t* __restrict__ bits,
+                                                  const R* __restrict__ tab, const uint16_t* __restrict__ bits,
                                                   const double (&x)[ModelDims<MODEL>::N],
                                                   double (&G)[ModelDims<MODEL>::N], int sub, int L)
 {
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) adam_kernel(const AdamDesc<R, Q>* __restr
                     if (!__builtin_isnan(zs)) z[j] = fmin(1.0, fmax(-1.0, zs));
                 }
                 project_block<MODEL>(z);
-                const uint8_t* bits = Dk->bits + ((size_t)sidx * K + k) * B;
+                const uint16_t* bits = Dk->bits + ((size_t)sidx * K + k) * B;
                 const int T = Dk->steps[k];
                 double p1 = 1.0, p2 = 1.0;    // beta1^t, beta2^t
                 for (int t = 1; t <= T; ++t) {
@@ -300,7 +300,7 @@ static ff_status launch_adam(const AdamSpec& as)
     const int K = std::max(o.n_stages, 1);
     const int B = as.scenes[0]->n_bands;
     const size_t desc_bytes = (sizeof(Desc) + 255) / 256 * 256;
-    const size_t bits_bytes = ((size_t)kMaxScenesPerLaunch * K * B + 255) / 256 * 256;
+    const size_t bits_bytes = ((size_t)kMaxScenesPerLaunch * K * B * sizeof(uint16_t) + 255) / 256 * 256;
     const size_t chunk_bytes = desc_bytes + bits_bytes;
     char* scratch = nullptr;
     {
@@ -335,7 +335,7 @@ static ff_status launch_adam(const AdamSpec& as)
         if (off == 0) continue;
         char* base = scratch + (size_t)c * chunk_bytes;
         Desc* dptr = reinterpret_cast<Desc*>(base);
-        prm.bits = reinterpret_cast<uint8_t*>(base + desc_bytes);
+        prm.bits = reinterpret_cast<uint16_t*>(base + desc_bytes);
         prm.n_scenes = ns;
         prm.B = B;
         prm.total = off;
@@ -412,6 +412,10 @@ ff_status dispatch_adam(const AdamSpec& as)
             if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_ENDMEMBER_1) }
             FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_ENDMEMBER_1)
         }
+        if (model == FF_MODEL_FULL) {
+            if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_FULL) }
+            FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_FULL)
+        }
         if (acc64) { FF_DISPATCH_ADAM_Q(o.n_quad, float, double, FF_MODEL_LOGNORMAL_2) }
         FF_DISPATCH_ADAM_Q(o.n_quad, float, float, FF_MODEL_LOGNORMAL_2)
     }
@@ -419,6 +423,7 @@ ff_status dispatch_adam(const AdamSpec& as)
     if (model == FF_MODEL_LOGNORMAL_1) return launch_adam<double, double, FF_MODEL_LOGNORMAL_1, 32>(as);
     if (model == FF_MODEL_GAUSS_GRID_2) return launch_adam<double, double, FF_MODEL_GAUSS_GRID_2, 32>(as);
     if (model == FF_MODEL_ENDMEMBER_1) return launch_adam<double, double, FF_MODEL_ENDMEMBER_1, 32>(as);
+    if (model == FF_MODEL_FULL) return launch_adam<double, double, FF_MODEL_FULL, 32>(as);
     return launch_adam<double, double, FF_MODEL_LOGNORMAL_2, 32>(as);
 }
 

@@ -36,6 +36,7 @@ int n_state(int model)
     case FF_MODEL_LOGNORMAL_2: return 8;
     case FF_MODEL_GAUSS_GRID_2: return 8;
     case FF_MODEL_ENDMEMBER_1: return 8;
+    case FF_MODEL_FULL: return 11;
     default: return -1;
     }
 }
@@ -51,15 +52,16 @@ static ff_status check_prior(const ff_prior* prior)
         if (!std::isfinite(prior->x0[j])) return set_error(FF_EINVAL, "prior x0 is not finite");
     }
     // the temperature means and spreads must stay positive over the whole box
-    const int pos[4][4] = {{1, 2, -1, -1}, {2, 3, 4, 5}, {2, 3, 4, 5}, {1, 2, -1, -1}};
+    const int pos[5][4] = {{1, 2, -1, -1}, {2, 3, 4, 5}, {2, 3, 4, 5}, {1, 2, -1, -1}, {2, 3, 4, 5}};
     for (int k = 0; k < 4; ++k) {
         const int j = pos[prior->model - 1][k];
         if (j >= 0 && !(prior->lo[j] > 0.0))
             return set_error(FF_EINVAL, "temperature mean and spread bounds must be positive");
     }
     // the simplex step works on x = (z + 1)/2: surface fractions need the box [0, 1]
-    if (prior->model == FF_MODEL_ENDMEMBER_1)
-        for (int j = 3; j < 3 + FF_N_ENDMEMBERS; ++j)
+    const int sf = prior->model == FF_MODEL_ENDMEMBER_1 ? 3 : (prior->model == FF_MODEL_FULL ? 6 : -1);
+    if (sf >= 0)
+        for (int j = sf; j < sf + FF_N_ENDMEMBERS; ++j)
             if (prior->lo[j] != 0.0 || prior->hi[j] != 1.0)
                 return set_error(FF_EINVAL, "surface fractions need the box [0, 1]");
     return FF_OK;
@@ -68,7 +70,7 @@ static ff_status check_prior(const ff_prior* prior)
 // The endmember model reads the scene's library.
 static ff_status check_library(int model, const ff_scene* sc, const char* who)
 {
-    if (model == FF_MODEL_ENDMEMBER_1 && sc && !sc->has_endmembers)
+    if ((model == FF_MODEL_ENDMEMBER_1 || model == FF_MODEL_FULL) && sc && !sc->has_endmembers)
         return set_error(FF_EINVAL, (std::string(who) + ": the endmember model needs ff_scene_set_endmembers").c_str());
     return FF_OK;
 }
@@ -191,6 +193,11 @@ extern "C" ff_status ff_prior_default(int32_t model, ff_prior* p)
         const double hi[8] = {0.5, 2200.0, 500.0, 1.0, 1.0, 1.0, 1.0, 1.0};
         const double x0[8] = {0.01, 1000.0, 150.0, 0.2, 0.2, 0.2, 0.2, 0.2};
         for (int j = 0; j < 8; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
+    } else if (model == FF_MODEL_FULL) {
+        const double lo[11] = {0.0, 0.0, 350.0, 10.0, 900.0, 10.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const double hi[11] = {0.5, 1.0, 900.0, 500.0, 2200.0, 500.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+        const double x0[11] = {0.01, 0.5, 650.0, 150.0, 1200.0, 150.0, 0.2, 0.2, 0.2, 0.2, 0.2};
+        for (int j = 0; j < 11; ++j) { p->lo[j] = lo[j]; p->hi[j] = hi[j]; p->x0[j] = x0[j]; }
     } else {
         return set_error(FF_EINVAL, "ff_prior_default: unknown model");
     }
@@ -383,7 +390,13 @@ extern "C" ff_status ff_adam_options_default(const ff_prior* prior, ff_adam_opti
         for (int j : {0, 1, 2}) set(s2, j, hot_lo, smol_hi);
         s2.z_start[2] = zdef(2);
     } else {
-        for (int j : {0, 4, 6, 7}) set(s1, j, w1lo, w1hi);
+        // two components; with the endmember surface (the paper's full
+        // model) stage 1 frees exactly x_1 = {x_surf, alpha_1, T_1}
+        if (prior->model == FF_MODEL_FULL) {
+            for (int j : {0, 4, 6, 7, 8, 9, 10}) set(s1, j, w1lo, w1hi);
+        } else {
+            for (int j : {0, 4, 6, 7}) set(s1, j, w1lo, w1hi);
+        }
         s1.z_start[1] = 1.0;     // all weight on the flaming component
         s1.z_start[5] = -1.0;
         set(s2, 0, hot_lo, smol_hi);

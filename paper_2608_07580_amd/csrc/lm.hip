@@ -736,6 +736,10 @@ ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs)
             if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_ENDMEMBER_1) }
             FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_ENDMEMBER_1)
         }
+        if (model == FF_MODEL_FULL) {
+            if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_FULL) }
+            FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_FULL)
+        }
         if (acc64) { FF_DISPATCH_Q(launch_lm, q, float, double, FF_MODEL_LOGNORMAL_2) }
         FF_DISPATCH_Q(launch_lm, q, float, float, FF_MODEL_LOGNORMAL_2)
     }
@@ -743,6 +747,7 @@ ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs)
     if (model == FF_MODEL_LOGNORMAL_1) return launch_lm<double, double, FF_MODEL_LOGNORMAL_1, 32>(bs);
     if (model == FF_MODEL_GAUSS_GRID_2) return launch_lm<double, double, FF_MODEL_GAUSS_GRID_2, 32>(bs);
     if (model == FF_MODEL_ENDMEMBER_1) return launch_lm<double, double, FF_MODEL_ENDMEMBER_1, 32>(bs);
+    if (model == FF_MODEL_FULL) return launch_lm<double, double, FF_MODEL_FULL, 32>(bs);
     return launch_lm<double, double, FF_MODEL_LOGNORMAL_2, 32>(bs);
 }
 
@@ -761,12 +766,14 @@ ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, 
         if (model == FF_MODEL_LOGNORMAL_1) { FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_1) }
         if (model == FF_MODEL_GAUSS_GRID_2) { FF_DISPATCH_FWD(q, float, FF_MODEL_GAUSS_GRID_2) }
         if (model == FF_MODEL_ENDMEMBER_1) { FF_DISPATCH_FWD(q, float, FF_MODEL_ENDMEMBER_1) }
+        if (model == FF_MODEL_FULL) { FF_DISPATCH_FWD(q, float, FF_MODEL_FULL) }
         FF_DISPATCH_FWD(q, float, FF_MODEL_LOGNORMAL_2)
     }
     if (q != 32) return set_error(FF_EUNSUPPORTED, "FP64 supports quadrature order 32 only");
     if (model == FF_MODEL_LOGNORMAL_1) return launch_forward<double, FF_MODEL_LOGNORMAL_1, 32>(sc, state, P, L, J, stream);
     if (model == FF_MODEL_GAUSS_GRID_2) return launch_forward<double, FF_MODEL_GAUSS_GRID_2, 32>(sc, state, P, L, J, stream);
     if (model == FF_MODEL_ENDMEMBER_1) return launch_forward<double, FF_MODEL_ENDMEMBER_1, 32>(sc, state, P, L, J, stream);
+    if (model == FF_MODEL_FULL) return launch_forward<double, FF_MODEL_FULL, 32>(sc, state, P, L, J, stream);
     return launch_forward<double, FF_MODEL_LOGNORMAL_2, 32>(sc, state, P, L, J, stream);
 }
 

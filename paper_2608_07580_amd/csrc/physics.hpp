@@ -30,11 +30,16 @@ template <> struct ModelDims<FF_MODEL_LOGNORMAL_1> { static constexpr int N = 5;
 template <> struct ModelDims<FF_MODEL_LOGNORMAL_2> { static constexpr int N = 8; static constexpr int C = 2; };
 template <> struct ModelDims<FF_MODEL_GAUSS_GRID_2> { static constexpr int N = 8; static constexpr int C = 2; };
 template <> struct ModelDims<FF_MODEL_ENDMEMBER_1> { static constexpr int N = 8; static constexpr int C = 1; };
+template <> struct ModelDims<FF_MODEL_FULL> { static constexpr int N = 11; static constexpr int C = 2; };
 
 // First state index of a block of surface fractions on the unit simplex
 // (x = (z + 1)/2 per fraction, box [0, 1]), or -1 when the model has none.
 template <int MODEL>
-constexpr int simplex_first_v = MODEL == FF_MODEL_ENDMEMBER_1 ? 3 : -1;
+constexpr int simplex_first_v = MODEL == FF_MODEL_ENDMEMBER_1 ? 3 : (MODEL == FF_MODEL_FULL ? 6 : -1);
+
+// Models whose thermal term is the Gaussian mixture on the temperature grid.
+template <int MODEL>
+constexpr bool grid_thermal_v = MODEL == FF_MODEL_GAUSS_GRID_2 || MODEL == FF_MODEL_FULL;
 
 // Quadrature rule of order Q in constant memory (filled once per device by
 // the host before the first launch).  Kernels index it with a laundered zero
@@ -381,7 +386,7 @@ template <int MODEL, typename PM, typename R>
 __device__ __forceinline__ R band_of(const PM& pm, const R* __restrict__ tab, int B, int b, int o,
                                      const BandRow<R>& row, R (&ub)[PM::N])
 {
-    if constexpr (MODEL == FF_MODEL_ENDMEMBER_1)
+    if constexpr (simplex_first_v<MODEL> >= 0)
         return pm.band(row, load_endm(tab + (size_t)B * FF_TABLE_COLS + (size_t)b * kEndmCols), o, ub);
     else
         return pm.band(row, o, ub);
@@ -644,6 +649,82 @@ struct PixelModel<R, FF_MODEL_GAUSS_GRID_2, Q> {
     }
 };
 
+// The paper's full forward model (Sec. 2.2, library Sec. 2.4): the Gaussian
+// mixture on the temperature grid over the endmember surface; state (f, eta,
+// mu_s, sig_s, mu_h, sig_h, x_1 .. x_5).
+template <typename R, int Q>
+struct PixelModel<R, FF_MODEL_FULL, Q> {
+    static constexpr int N = 11;
+    static constexpr int NE = FF_N_ENDMEMBERS;
+    static_assert(Q >= 2, "the temperature grid needs two nodes");
+    R f, eta, xs[NE];
+    R mus, mus1, m2s, muh, muh1, m2h;
+    R ps[Q], ph[Q];
+    __device__ void setup(const double (&x)[N], int lane = 0, int L = 1)
+    {
+        (void)lane;
+        (void)L;
+        f = (R)x[0];
+        eta = (R)x[1];
+#pragma unroll
+        for (int k = 0; k < NE; ++k) xs[k] = (R)x[6 + k];
+        const GridComponent gs = grid_component<R, Q>(x[2], x[3], ps);
+        const GridComponent gh = grid_component<R, Q>(x[4], x[5], ph);
+        mus = (R)x[2];
+        mus1 = (R)gs.mu1;
+        m2s = (R)gs.m2;
+        muh = (R)x[4];
+        muh1 = (R)gh.mu1;
+        m2h = (R)gh.m2;
+    }
+    __device__ __forceinline__ R band(const BandRow<R>& t, const EndmRow<R>& em, int o, R (&ub)[N]) const
+    {
+        R g[6];
+        grid_sums<Q>(t.a2, ps, ph, mus, mus1, m2s, muh, muh1, m2h, o, g);
+        R rho = xs[0] * em.e[0];
+#pragma unroll
+        for (int k = 1; k < NE; ++k) rho += xs[k] * em.e[k];
+        const R rden = fast_rcp<R>((R)1 - t.S * rho);
+        const R ls = t.K * (t.ratm + t.tau2 * rho * rden);
+        const R tb = t.tup * t.cb;
+        const R is_ = tb * g[0], ih = tb * g[3];
+        ub[0] = is_ + eta * (ih - is_);
+        ub[1] = ih - is_;
+        ub[2] = tb * g[1];
+        ub[3] = tb * g[2];
+        ub[4] = tb * g[4];
+        ub[5] = tb * g[5];
+        const R ds = t.K * t.tau2 * rden * rden;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) ub[6 + k] = ds * em.e[k];
+        return ls + f * ub[0];
+    }
+    static constexpr int s1[N] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
+    static constexpr int s2[N] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+    __device__ static void coefficients(const double (&x)[N], double (&c1)[N], double (&c2)[N])
+    {
+        const double f = x[0], eta = x[1], ss = x[3], sh = x[5];
+        const double fs = f * (1.0 - eta), fh = f * eta;
+        c1[0] = 1.0;
+        c1[1] = f;
+        c1[2] = fs / (ss * ss);
+        c1[3] = fs / (ss * ss * ss);
+        c1[4] = fh / (sh * sh);
+        c1[5] = fh / (sh * sh * sh);
+#pragma unroll
+        for (int k = 6; k < N; ++k) c1[k] = 1.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) c2[i] = 0.0;
+    }
+    __device__ static void moments(const double (&x)[N], double& et, double& sd)
+    {
+        const double eta = x[1], ms = x[2], ss = x[3], mh = x[4], sh = x[5];
+        et = eta * mh + (1.0 - eta) * ms;
+        const double dm = mh - ms;
+        sd = sqrt(eta * sh * sh + (1.0 - eta) * ss * ss + eta * (1.0 - eta) * dm * dm);
+    }
+};
+
 // ---------------------------------------------------------------- host side
 // The quadrature rule (computed once per process) and its copy into this
 // translation unit's constant memory on each device.  Internal linkage: with
@@ -710,7 +791,7 @@ template <typename R, int MODEL, int Q>
 bool ensure_tables(int dev)
 {
     if (!ensure_quad<R, Q>(dev)) return false;
-    if constexpr (MODEL == FF_MODEL_GAUSS_GRID_2) return ensure_grid<R, Q>(dev);
+    if constexpr (grid_thermal_v<MODEL>) return ensure_grid<R, Q>(dev);
     return true;
 }
 
