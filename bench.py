@@ -43,7 +43,7 @@ HBM_PEAK = 8.0e12
 # kernel sources with the SHA-1 below; any other source reports null.
 TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
                    "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
-TRAFFIC_SHA1 = "d8a3e0b7b98138453b187d2d6bbed8a20c0a5f95"
+TRAFFIC_SHA1 = "00eeaf014a18bdebafabf6b8464a96b1193cd7e8"
 TRAFFIC_BYTES = {"plain": 56.11e9, "warm": 35.51e9}
 
 
@@ -623,21 +623,26 @@ def run_solvers(args):
     print(json.dumps(line), flush=True)
 
 
-def grid_slots_per_eval(n_bands: int, n_nodes: int) -> int:
+def grid_slots_per_eval(n_bands: int, n_nodes: int, model: int = 3) -> int:
     """Algorithmic VALU slots of one evaluation of the Gaussian-mixture model
     on the temperature grid: per (band, node) one Planck ratio shared by the
     two components (x = a2/T: 1, exp2: 2, minus 1: 1, rcp: 2) and 7 per
-    component for its weight product and the three centred sums; per band 70
-    for the scaling, solar term, basis, residual and the J^T J, J^T r, r.r
-    accumulations (n = 8)."""
-    return n_bands * (n_nodes * (6 + 2 * 7) + 70)
+    component for its weight product and the three centred sums; per band 25
+    for the scaling, solar term, basis and residual and 45 for the J^T J,
+    J^T r, r.r accumulations (n = 8).  The full model (endmember surface,
+    n = 11) adds 6 for the five-term reflectance and basis and accumulates
+    78."""
+    per_band = 25 + 45 if model == 3 else 25 + 6 + 78
+    return n_bands * (n_nodes * (6 + 2 * 7) + per_band)
 
 
-def run_paper_model(args):
+def run_paper_model(args, model: int = 3):
     """The paper's thermal form (two Gaussians on a [350, 2200] K grid, Sec.
     2.2) on a 262,144-pixel two-component set: LM (tuned launch) and the
     paper's staged Adam, timed, with E[T] accuracy against the truth and the
-    FP64 oracle's LM on a seeded subsample."""
+    FP64 oracle's LM on a seeded subsample.  model 5: the paper's full
+    forward model, the same thermal term over the five-endmember simplex
+    surface (Sec. 2.4), with path reflectance and spherical albedo."""
     import torch
     import oracle
     import paper_2608_07580_amd as ff
@@ -647,10 +652,16 @@ def run_paper_model(args):
     dev = torch.device("cuda:0")
     ff.lib()
     P = args.precision_pixels
-    model = ff.MODEL_GAUSS_GRID_2
-    X = scenegen.config5_states(P)
-    atm = scenegen.make_atmosphere(5, 0)
-    sc = ff.Scene(atm)
+    lib = None
+    if model == ff.MODEL_FULL:
+        X = scenegen.draw_states_full(scenegen.rng_for(5, 0, scenegen.STREAM_PARAMS), P)
+        atm = scenegen.make_atmosphere(5, 0, rho_atm=0.01, s_sph=0.1)
+        lib = scenegen.endmember_library(atm.hr_lambda_nm)
+        sc = ff.Scene(atm).set_endmembers(atm.hr_lambda_nm, lib)
+    else:
+        X = scenegen.config5_states(P)
+        atm = scenegen.make_atmosphere(5, 0)
+        sc = ff.Scene(atm)
     B = sc.n_bands
     L = torch.empty((P, B), dtype=torch.float64, device=dev)
     for s0 in range(0, P, 1 << 16):
@@ -687,8 +698,14 @@ def run_paper_model(args):
 
     def acc(r):
         d = np.abs(r["moments"][:, 0] - et_true)
-        return {"dT_median_K": float(np.median(d)), "dT_median_strong_K": float(np.median(d[strong])),
-                "rrr_median": float(np.nanmedian(r["rrr"]))}
+        a = {"dT_median_K": float(np.median(d)), "dT_median_strong_K": float(np.median(d[strong])),
+             "rrr_median": float(np.nanmedian(r["rrr"]))}
+        if lib is not None:
+            fr = r["state"][:, 6:]
+            a.update({"fraction_mae": float(np.nanmean(np.abs(fr - X[:, 6:]))),
+                      "max_simplex_sum_error": float(np.nanmax(np.abs(fr.sum(axis=1) - 1.0))),
+                      "min_fraction": float(np.nanmin(fr))})
+        return a
 
     out = ff.allocate_outputs(P, model, dev)
     evals = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -696,25 +713,28 @@ def run_paper_model(args):
     r_lm = out.numpy()
     ev = int(evals.item()) / (args.steps + args.warmup)
     conv = int(((r_lm["status"].astype(np.int64) & ff.ST_CONVERGED) != 0).sum())
-    spe = grid_slots_per_eval(B, args.n_quad)
+    spe = grid_slots_per_eval(B, args.n_quad, model)
     achieved = ev * spe / (ms_lm * 1e-3)
     aopt = ff.adam_options(prior, n_quad=args.n_quad)
     out_a = ff.allocate_outputs(P, model, dev)
     ms_ad = timed(lambda: ff.adam_retrieve(sc, rad, prior, options=aopt, outputs=out_a, stream=stream))
     r_ad = out_a.numpy()
     idx = scenegen.subsample(5, 0, P, args.solver_sample)
-    tab = oracle.band_tables(atm)
+    tab = oracle.band_tables(atm, lib)
     lo, hi, x0 = scenegen.default_prior(model)
     t0 = time.time()
     ref = oracle.retrieve(tab, rad[torch.from_numpy(idx).to(dev)].cpu().numpy(), model, lo, hi, x0,
                           opts=oracle.LMOptions(max_iter=args.grid_max_iter), nthreads=len(os.sched_getaffinity(0)))
     t_or = time.time() - t0
-    rep = parity_report({k: v[idx] for k, v in r_lm.items() if v is not None}, ref, model=2)
+    rep = parity_report({k: v[idx] for k, v in r_lm.items() if v is not None}, ref, model=model)
+    what = ("the paper's full forward model (Gaussian mixture on the grid over the 5-endmember simplex surface)"
+            if lib is not None else "the paper's Gaussian-mixture thermal model")
+    surface = ", 5-endmember simplex surface, rho_atm 0.01, S 0.1" if lib is not None else ""
     line = {
-        "metric": "the paper's Gaussian-mixture thermal model: LM and staged Adam retrievals per second",
-        "config": {"workload": f"two-Gaussian mixture on a {args.n_quad}-node [350, 2200] K grid, {P} px x {B} bands, "
-                               f"1e-4 <= f <= 0.1, SNR {args.snr:g}", "pixels": P, "nodes": args.n_quad,
-                   "max_iter": args.grid_max_iter},
+        "metric": f"{what}: LM and staged Adam retrievals per second",
+        "config": {"workload": f"two-Gaussian mixture on a {args.n_quad}-node [350, 2200] K grid{surface}, "
+                               f"{P} px x {B} bands, 1e-4 <= f <= 0.1, SNR {args.snr:g}", "pixels": P,
+                   "nodes": args.n_quad, "max_iter": args.grid_max_iter},
         "lm": {"ms_per_step": ms_lm, "converged": conv, "converged_per_s": conv / (ms_lm * 1e-3),
                "evals_per_pixel": ev / P, "accuracy": acc(r_lm),
                "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
@@ -998,7 +1018,7 @@ def main():
     ap.add_argument("--grid-max-iter", type=int, default=200, help="paper-model workload: LM iteration cap")
     ap.add_argument("--block", type=int, default=12, help="coarsening workload: block side")
     ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers", "front-end",
-                                           "paper-model", "endmember-surface", "coarsening"),
+                                           "paper-model", "full-model", "endmember-surface", "coarsening"),
                     default="clustered-fire",
                     help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
                          "precision: FP32/FP64 variants on the two-component stress set; "
@@ -1006,6 +1026,7 @@ def main():
                          "front-end: HFDI candidate selection + LM on the candidates; "
                          "paper-model: the paper's two-Gaussian grid thermal model, LM and staged Adam; "
                          "endmember-surface: the 5-endmember simplex surface, LM and staged Adam; "
+                         "full-model: the paper's full forward model (grid mixture over the endmember surface); "
                          "coarsening: 12 x 12 block means, LM at both resolutions, Quantile Error Curves")
     ap.add_argument("--adam-lpp", type=int, default=1, help="lanes per pixel of the Adam kernel")
     ap.add_argument("--hfdi-threshold", type=float, default=-0.1, help="front-end workload: HFDI threshold")
@@ -1040,6 +1061,9 @@ def main():
         return
     if args.workload == "endmember-surface":
         run_endmember(args)
+        return
+    if args.workload == "full-model":
+        run_paper_model(args, model=5)
         return
     if args.workload == "precision":
         if args.cpu_sample == 65536:
