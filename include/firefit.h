@@ -397,7 +397,9 @@ ff_status ff_qec(const float* fine_moments_dev, const float* fine_state_dev, con
  *         (g_j = -2 sum_b r_b dL_b/dz_j, r = L_obs - L);
  *   g  *= clip_norm / ||g||  when ||g|| > clip_norm > 0 (norm over free j);
  *   m   = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2;
- *   z_j = clip(z_j - lr (m_j / (1 - beta1^t)) / (sqrt(v_j / (1 - beta2^t)) + eps), -1, 1).
+ *   z_j = clip(z_j - lr (m_j / (1 - beta1^t)) / (sqrt(v_j / (1 - beta2^t)) + eps), -1, 1);
+ * for the endmember models the surface fractions are then projected onto the
+ * unit simplex (Sec. 2.5), also after the stage's start values are set.
  * Every pixel takes the same number of steps (no convergence test). */
 #define FF_MAX_ADAM_STAGES 4
 
