@@ -12,12 +12,16 @@
  *   summary         E[T], sigma[T] of the moment-matched temperature mixture        (Sec. 2.2)
  * p(T) is a lognormal of mean m and s.d. s (FF_MODEL_LOGNORMAL_1) or the
  * eta-weighted mixture of a smouldering and a flaming lognormal
- * (FF_MODEL_LOGNORMAL_2), integrated by Gauss-Hermite quadrature in log T.
- * The surface reflectance is linear, rho = rho0 + rho1 (lambda - 1440 nm).
+ * (FF_MODEL_LOGNORMAL_2), integrated by Gauss-Hermite quadrature in log T,
+ * or the paper's Gaussians on a temperature grid (FF_MODEL_GAUSS_GRID_2).
+ * The surface reflectance is linear, rho = rho0 + rho1 (lambda - 1440 nm),
+ * or the endmember mixture of Sec. 2.2 (FF_MODEL_ENDMEMBER_1, FF_MODEL_FULL).
  * Each pixel is solved by Levenberg-Marquardt (damped Gauss-Newton on the
- * loss in z, active set for variables held at a bound), and the
- * Gauss-Newton state covariance is reported; the paper's own solver, staged
- * Adam, is available as ff_adam_retrieve_batch.
+ * loss in z, active set for variables held at a bound; with the endmember
+ * surface the step keeps the fractions' sum, holds fractions at zero by the
+ * sign of their reduced gradient and is shortened so none goes negative),
+ * and the Gauss-Newton state covariance is reported; the paper's own
+ * solver, staged Adam, is available as ff_adam_retrieve_batch.
  *
  * Conventions for every entry point:
  *  - Return value: ff_status, FF_OK (0) on success, negative on error.  No
