@@ -126,8 +126,13 @@ __device__ __forceinline__ bool converged_gradient(const R (&z)[N], const R (&A)
     else return gradient_small<R, N>(z, A, g, F, gtol);
 }
 
+// Occupancy target (second launch bound, waves per SIMD): the one-component
+// FP32 kernel runs three waves per SIMD (at most 168 VGPRs); the band loop
+// stays free of spills and ~124 B per lane of per-pixel state outside it goes
+// to scratch.  Other models keep the compiler's choice.
 template <typename R, typename ACC, int MODEL, int Q>
-__global__ void __launch_bounds__(256) lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
+__global__ void __launch_bounds__(256, (MODEL == FF_MODEL_LOGNORMAL_1 && sizeof(R) == 4) ? 3 : 1)
+lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
 {
     using PM = PixelModel<R, MODEL, Q>;
     constexpr int N = PM::N;
