@@ -138,12 +138,12 @@ __device__ __forceinline__ void windowed_gradient(const Desc* descp, const float
     }
 }
 
-// Second launch bound (waves per SIMD): the one-component FP32 kernel runs
-// three waves per SIMD in at most 168 VGPRs (a few dozen bytes per lane of
-// state outside the band loop go to scratch); other models keep the
-// compiler's choice.
+// Second launch bound (waves per SIMD), FP32 kernels: the one-component
+// model runs three waves per SIMD in at most 168 VGPRs, the others two in
+// 256 (some per-pixel state outside the band loop goes to scratch); FP64
+// keeps the compiler's choice.
 template <typename R, typename ACC, int MODEL, int Q>
-__global__ void __launch_bounds__(256, (MODEL == FF_MODEL_LOGNORMAL_1 && sizeof(R) == 4) ? 3 : 1)
+__global__ void __launch_bounds__(256, sizeof(R) != 4 ? 1 : (MODEL == FF_MODEL_LOGNORMAL_1 ? 3 : 2))
 adam_kernel(const AdamDesc<R, Q>* __restrict__ descp)
 {
     using PM = PixelModel<R, MODEL, Q>;
