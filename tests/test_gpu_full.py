@@ -200,3 +200,54 @@ def test_adam_full_schedule_statistics(world, spectra, dev):
     print(f"adam model 5 full schedule: median rrr gpu {a:.4e} oracle {b:.4e}; fraction error {ea:.4f} {eb:.4f}")
     assert abs(a / b - 1) <= 0.1
     assert abs(ea / eb - 1) <= 0.1
+
+
+def test_per_pixel_atmospheres_and_listed_rows(world, dev):
+    """The full model through the per-pixel atmosphere index (Sec. 2.3's
+    quantised water-vapour tables) and the front end's row list: three
+    atmospheres, each with the library resampled to its bands; the indexed
+    retrieval equals the per-atmosphere retrievals bitwise, an atmosphere
+    without a library is refused, and a listed retrieval equals the full
+    one on the listed rows and leaves the others untouched."""
+    atm0, tab0, scene0, prior = world
+    atms = [scenegen.make_atmosphere(7, s, rho_atm=0.01 * s, s_sph=0.05 * s) for s in range(3)]
+    libs = [scenegen.endmember_library(a.hr_lambda_nm) for a in atms]
+    tabs = [oracle.band_tables(a, lib) for a, lib in zip(atms, libs)]
+    P = 600
+    X = states(P, 31)
+    aid = np.random.default_rng(31).integers(0, 3, P).astype(np.int32)
+    noise = scenegen.noise_normals(7, 31, P, tabs[0].B)
+    lobs = np.zeros((P, tabs[0].B), np.float32)
+    for a in range(3):
+        m = aid == a
+        lobs[m] = (oracle.forward(tabs[a], X[m], MODEL) * (1.0 + noise[m] / 300.0)).astype(np.float32)
+    scenes = [ff.Scene(a).set_endmembers(a.hr_lambda_nm, lib) for a, lib in zip(atms, libs)]
+    opts = ff.default_options(max_iter=200)
+    rad = torch.from_numpy(lobs).to(dev)
+    r = ff.retrieve_atm_indexed(scenes, torch.from_numpy(aid).to(dev), rad, prior, options=opts).numpy()
+    torch.cuda.synchronize()
+    for a in range(3):
+        m = aid == a
+        single = ff.retrieve(scenes[a], torch.from_numpy(lobs[m]).to(dev), prior, options=opts).numpy()
+        torch.cuda.synchronize()
+        for k in ("state", "cov", "moments", "rrr", "iters", "status"):
+            np.testing.assert_array_equal(r[k][m], single[k])
+    on_simplex(r["state"], 3e-6)
+    with pytest.raises(ff.FirefitError):
+        ff.retrieve_atm_indexed(scenes[:2] + [ff.Scene(atms[2])], torch.from_numpy(aid).to(dev), rad, prior)
+    # front end row list on the first atmosphere
+    m0 = aid == 0
+    rad0 = torch.from_numpy(np.ascontiguousarray(lobs[m0])).to(dev)
+    full = ff.retrieve(scenes[0], rad0, prior, options=opts).numpy()
+    P0 = int(m0.sum())
+    rows = np.sort(np.random.default_rng(3).choice(P0, P0 // 3, replace=False)).astype(np.int64)
+    out = ff.allocate_outputs(P0, MODEL, dev)
+    out.state.fill_(-7.0)
+    ff.retrieve_listed(scenes[0], rad0, torch.from_numpy(rows).to(dev),
+                       torch.tensor([len(rows)], dtype=torch.int64, device=dev), prior, options=opts, outputs=out)
+    torch.cuda.synchronize()
+    lst = out.numpy()
+    for k in ("state", "cov", "moments", "rrr", "iters", "status"):
+        np.testing.assert_array_equal(lst[k][rows], full[k][rows])
+    others = np.setdiff1d(np.arange(P0), rows)
+    assert np.all(lst["state"][others] == -7.0)
