@@ -19,6 +19,10 @@
 // replaces the paper's Adam: (A + mu diag(d)) delta = -g on the free
 // variables (a variable at a bound whose gradient points out of the box is
 // held), z_t = clip(z + delta), gain-ratio acceptance and damping update.
+// With an endmember surface the fractions' sum is kept by the step, a
+// fraction at zero is held by the sign of its reduced gradient (or when the
+// step would push it negative), and the step is shortened so that no
+// fraction goes below zero.
 #include <algorithm>
 #include <cmath>
 #include <mutex>

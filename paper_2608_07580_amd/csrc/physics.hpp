@@ -1,8 +1,9 @@
 // Device-side forward model of the fire-temperature inversion (Keely et al.,
-// Sec. 2.2): solar term (eq. solar), thermal term (eq. thermal) with a
-// lognormal (or two-lognormal mixture) sub-pixel temperature density
-// integrated by Gauss-Hermite quadrature in log T, and the per-band basis
-// from which the Jacobian follows.
+// Sec. 2.2): solar term (eq. solar) over a linear or endmember-mixture
+// surface, thermal term (eq. thermal) with a lognormal (or two-lognormal
+// mixture) sub-pixel temperature density integrated by Gauss-Hermite
+// quadrature in log T, or the paper's two Gaussians summed over a uniform
+// temperature grid, and the per-band basis from which the Jacobian follows.
 //
 // Range-safe Planck: with x2 = a2 / T (a2 = c2 / lambda * log2 e) and
 // e = 2^(-x2) in (0, 1],

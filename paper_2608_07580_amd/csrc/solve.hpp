@@ -1,7 +1,8 @@
 // Per-pixel pieces shared by the retrieval kernels (Levenberg-Marquardt and
 // staged Adam): launch-descriptor scene slots, group reductions over the
 // lanes of a pixel, the model evaluation with the normal equations in z,
-// FP64 Cholesky, and the output epilogue (Gauss-Newton covariance, moments).
+// FP64 Cholesky, the projection of surface fractions onto the unit simplex,
+// and the output epilogue (Gauss-Newton covariance, moments).
 //
 // Loss and coordinates (Keely et al. Sec. 2.5): r = m (L_obs - L(x(z))),
 // F = r.r (eq. loss), z = 2 (x - lo)/(hi - lo) - 1 (eq. affine).
