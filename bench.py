@@ -1037,6 +1037,9 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2608_07580_amd", "tuning.json"),
                     help="autotuner table (read, and written on a miss)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-quadrature", action="store_true",
+                    help="also run the tuner's quadrature-order choice on the scene and report it "
+                         "(the headline keeps --n-quad)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -1123,6 +1126,16 @@ def main():
         "plain_lm": plain,
         "warm_start": warm,
     }
+    if args.tune_quadrature:
+        # the tuner's quadrature dimension on this scene (plain start), reported
+        # beside the headline, which keeps the configuration's 32 nodes
+        with torch.cuda.stream(stream):
+            _, rep = ff.tune_quadrature([scene], [rad], ff.default_prior(1),
+                                        options=ff.default_options(n_quad=args.n_quad),
+                                        cache_path=args.tune_cache, stream=stream)
+        torch.cuda.synchronize()
+        line["quadrature_choice"] = rep
+        log(f"quadrature choice: {rep}")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, atm, states, noise, {"plain": res_plain, "warm": res_warm})
     print(json.dumps(line), flush=True)

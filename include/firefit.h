@@ -302,6 +302,30 @@ ff_status ff_tune(const ff_scene* const* scenes, const float* const* radiance_de
                   const ff_outputs* outs, const char* cache_path, int32_t flags, double* best_ms,
                   void* stream);
 
+/* Quadrature-order choice, the tuner's third dimension (FP32 path of the
+ * lognormal models FF_MODEL_LOGNORMAL_1/2 and FF_MODEL_ENDMEMBER_1, whose
+ * thermal integral the order only approximates; the grid models' order is
+ * their temperature grid and is never changed).  The batch is retrieved at
+ * the requested order opts->n_quad into outs_ref and at each lower order of
+ * {16, 24} into outs_trial, each at its own launch shape from ff_tune (with
+ * cache_path and flags as there).  A lower order is accepted when, on the
+ * pixels both runs converge on, at least 99 % agree with the requested
+ * order: relative radiance residuals within 1e-5, f within 1e-4, and E[T]
+ * within max(0.5 K, 2 % of its posterior s.d. from the requested order's
+ * covariance) where both fits have f >= 1e-4; and the converged counts
+ * differ by at most 0.5 %.  The fastest accepted order (the requested one if
+ * none) and its launch shape are written to opts; report_host[8], if not
+ * NULL, receives {chosen order, its time ms, requested order's time ms, the
+ * agreeing share of the chosen order (1 for the requested), then share and
+ * time ms at order 24 and at order 16 (NaN where not tested; a share of -1
+ * means the converged counts differed by more than 0.5 %)}.  Synchronous
+ * (copies the per-pixel outputs to the host for the comparison).
+ * FF_EUNSUPPORTED for FP64 or a grid model (opts unchanged). */
+ff_status ff_tune_quadrature(const ff_scene* const* scenes, const float* const* radiance_dev, const int64_t* P,
+                             int32_t n_scenes, const ff_prior* prior, const float* const* z0_dev,
+                             ff_options* opts, const ff_outputs* outs_ref, const ff_outputs* outs_trial,
+                             const char* cache_path, int32_t flags, double* report_host, void* stream);
+
 /* One-shot form: builds a scene from srf/atm, retrieves, destroys the scene.
  * Synchronous (waits for stream). */
 ff_status ff_retrieve(const float* radiance_dev, int64_t P, const ff_srf* srf,

@@ -49,7 +49,7 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
            "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
            "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec",
-           "ff_scene_set_endmembers", "ff_scene_endmembers")
+           "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_tune_quadrature")
 
 
 class FirefitError(RuntimeError):
@@ -133,6 +133,10 @@ def lib():
         L.ff_scene_n_bands.argtypes = [C.c_void_p]
         L.ff_scene_band_tables.argtypes = [C.c_void_p, _dp]
         L.ff_scene_set_endmembers.argtypes = [C.c_void_p, C.c_int32, _dp, _dp]
+        L.ff_tune_quadrature.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                         C.c_int32, C.POINTER(ffPrior), C.POINTER(C.c_void_p),
+                                         C.POINTER(ffOptions), C.POINTER(ffOutputs), C.POINTER(ffOutputs),
+                                         C.c_char_p, C.c_int32, _dp, C.c_void_p]
         L.ff_scene_endmembers.argtypes = [C.c_void_p, _dp]
         L.ff_forward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -191,7 +195,7 @@ def lib():
         L.ff_block_mean.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         L.ff_qec.argtypes = [C.c_void_p] * 8 + [C.c_int32] * 4 + [C.c_double, C.c_int32, C.c_int32, _dp] + \
             [C.c_void_p] * 4
-        for name in ("ff_scene_set_endmembers", "ff_scene_endmembers", "ff_block_mean", "ff_qec", "ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
+        for name in ("ff_tune_quadrature", "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_block_mean", "ff_qec", "ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
                      "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
@@ -630,6 +634,37 @@ def tune(scenes, radiances, prior: Prior | None = None, z0s=None, options: ffOpt
                          None if cache_path is None else os.fsencode(cache_path),
                          TUNE_IGNORE_CACHE if retune else 0, C.byref(ms), _stream_handle(stream)), "ff_tune")
     return opts, ms.value
+
+
+def tune_quadrature(scenes, radiances, prior: Prior | None = None, z0s=None, options: ffOptions | None = None,
+                    cache_path: str | None = None, retune: bool = False, stream=None):
+    """Quadrature-order choice (ff_tune_quadrature): returns (options, report)
+    with report = {chosen order, its ms, requested order's ms, agreeing
+    share, and per tested order (24, 16) its share and ms}."""
+    prior = prior or default_prior(MODEL_LOGNORMAL_1)
+    opts = ffOptions()
+    C.memmove(C.byref(opts), C.byref(options or default_options()), C.sizeof(ffOptions))
+    ns = len(scenes)
+    ref = [allocate_outputs(r.shape[0], prior.model, r.device) for r in radiances]
+    tri = [allocate_outputs(r.shape[0], prior.model, r.device) for r in radiances]
+    sc = (C.c_void_p * ns)(*[s.handle.value for s in scenes])
+    rd = (C.c_void_p * ns)(*[r.data_ptr() for r in radiances])
+    Ps = (C.c_int64 * ns)(*[r.shape[0] for r in radiances])
+    z0p = None
+    if z0s is not None:
+        z0p = (C.c_void_p * ns)(*[0 if z is None else z.data_ptr() for z in z0s])
+    oref = (ffOutputs * ns)(*[o.to_c() for o in ref])
+    otri = (ffOutputs * ns)(*[o.to_c() for o in tri])
+    pc = prior.to_c()
+    rep = np.zeros(8)
+    _check(lib().ff_tune_quadrature(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(opts), oref, otri,
+                                    None if cache_path is None else os.fsencode(cache_path),
+                                    TUNE_IGNORE_CACHE if retune else 0, rep.ctypes.data_as(_dp),
+                                    _stream_handle(stream)), "ff_tune_quadrature")
+    report = {"n_quad": int(rep[0]), "ms": float(rep[1]), "ms_requested": float(rep[2]), "share": float(rep[3]),
+              "tested": {24: {"share": float(rep[4]), "ms": float(rep[5])},
+                         16: {"share": float(rep[6]), "ms": float(rep[7])}}}
+    return opts, report
 
 
 # ----------------------------------------------------------------------------

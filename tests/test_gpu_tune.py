@@ -52,3 +52,67 @@ def test_tune_choice_cache_and_parity(tmp_path):
     out = ff.retrieve(scene, rad, prior, options=opts)
     torch.cuda.synchronize()
     assert_parity(out.numpy(), ref, min_t=500, label="tuned")
+
+
+def _agreement(ref, t):
+    """The tuner's acceptance rule for a lower quadrature order, in numpy."""
+    cr = (ref["status"].astype(np.int64) & ff.ST_CONVERGED) != 0
+    ct = (t["status"].astype(np.int64) & ff.ST_CONVERGED) != 0
+    if abs(int(cr.sum()) - int(ct.sum())) > 0.005 * max(int(cr.sum()), 1):
+        return -1.0
+    both = cr & ct
+    C = oracle.unpack_cov(ref["cov"].astype(np.float64), 5)
+    sd = np.nan_to_num(np.sqrt(np.abs(C[:, 1, 1])), nan=np.inf)
+    ok = (np.abs(ref["rrr"].astype(np.float64) - t["rrr"]) <= 1e-5) & \
+         (np.abs(ref["state"][:, 0].astype(np.float64) - t["state"][:, 0]) <= 1e-4)
+    fire = (ref["state"][:, 0] >= 1e-4) & (t["state"][:, 0] >= 1e-4)
+    et_ok = np.abs(ref["moments"][:, 0].astype(np.float64) - t["moments"][:, 0]) <= np.maximum(0.5, 0.02 * sd)
+    ok &= ~fire | et_ok
+    return float(ok[both].mean())
+
+
+def test_quadrature_order_choice(tmp_path):
+    """The tuner's quadrature dimension (ff_tune_quadrature): it keeps the
+    requested 32 nodes unless a lower order reproduces the 32-node results on
+    the batch (the rule recomputed here from the two runs' outputs), it
+    reports what it tested, and it refuses the grid model (whose order is its
+    temperature grid) and FP64."""
+    dev = torch.device("cuda:0")
+    atm = scenegen.make_atmosphere(0, 0)
+    tab = oracle.band_tables(atm)
+    scene = ff.Scene(atm)
+    lo, hi, x0 = scenegen.default_prior(1)
+    prior = ff.Prior(1, lo, hi, x0)
+    X = scenegen.config0_states(4096)
+    lobs = noisy_spectra(tab, X, 1, 0, 0)
+    rad = torch.from_numpy(lobs).to(dev)
+    path = str(tmp_path / "tuning.json")
+    opts, rep = ff.tune_quadrature([scene], [rad], prior, cache_path=path)
+    print(f"\n  quadrature choice: {rep}")
+    assert rep["n_quad"] in (16, 24, 32) and opts.n_quad == rep["n_quad"]
+    assert rep["ms_requested"] > 0 and rep["ms"] > 0 and rep["ms"] <= rep["ms_requested"]
+    for q in (24, 16):
+        assert np.isfinite(rep["tested"][q]["ms"])
+    # recompute the rule for every tested order from fresh runs at its launch shape
+    o32 = ff.default_options()
+    o32, _ = ff.tune([scene], [rad], prior, options=o32, cache_path=path)
+    ref = ff.retrieve(scene, rad, prior, options=o32).numpy()
+    for q in (24, 16):
+        oq = ff.default_options(n_quad=q)
+        oq, _ = ff.tune([scene], [rad], prior, options=oq, cache_path=path)
+        t = ff.retrieve(scene, rad, prior, options=oq).numpy()
+        torch.cuda.synchronize()
+        share = _agreement(ref, t)
+        print(f"  order {q}: agreeing share {share:.4f} (tuner {rep['tested'][q]['share']:.4f})")
+        assert share == pytest.approx(rep["tested"][q]["share"], abs=1e-12)
+        if rep["n_quad"] == q:
+            assert share >= 0.99
+    # 24 nodes reproduce the 32-node radiance to ~3e-7 relative on this set:
+    # that order must be accepted here
+    assert rep["tested"][24]["share"] >= 0.99
+    # the grid model and FP64 are refused
+    lo3, hi3, x03 = scenegen.default_prior(3)
+    with pytest.raises(ff.FirefitError):
+        ff.tune_quadrature([scene], [rad], ff.Prior(3, lo3, hi3, x03))
+    with pytest.raises(ff.FirefitError):
+        ff.tune_quadrature([scene], [rad], prior, options=ff.default_options(precision=ff.PRECISION_FP64))
