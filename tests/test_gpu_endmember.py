@@ -239,3 +239,48 @@ def test_adam_fp32_prefix_and_schedule(world, spectra, dev):
     a, b = np.median(rf["rrr"]), np.median(ref_f.rrr)
     print(f"adam model 4 full schedule: median rrr gpu {a:.4e} oracle {b:.4e}")
     assert abs(a / b - 1) <= 0.05
+
+
+def test_warm_start_projection_and_fallback(world, spectra, dev):
+    """Per-pixel starts z0 whose fractions are off the simplex are projected
+    onto it before the first evaluation (an infeasible start is never
+    evaluated), and with a one-iteration cap on the warm solve the fallback
+    re-solve from the prior start (also projected) reproduces the plain
+    retrieval bitwise wherever it is kept."""
+    atm, tab, scene, prior = world
+    X, lobs, _ = spectra
+    n = 300
+    rad = torch.from_numpy(lobs[:n]).to(dev)
+    rng = np.random.default_rng(41)
+    z0 = oracle.x_to_z(X[:n], prior.lo, prior.hi)
+    z0[:, SF:] = rng.uniform(-1.0, 1.0, (n, 5))           # fractions summing to anything in [0, 5]
+    z0t = torch.tensor(z0, dtype=torch.float32, device=dev)
+    opts = ff.default_options(precision=ff.PRECISION_FP64, max_iter=200)
+    warm = ff.retrieve(scene, rad, prior, z0=z0t, options=opts, state_f64=True).numpy()
+    torch.cuda.synchronize()
+    st = warm["status"].astype(np.int64)
+    assert np.all(st & ff.ST_WARM_START)
+    on_simplex(warm["state_f64"], 1e-13)
+    conv = (st & CONVERGED) != 0
+    assert conv.mean() >= 0.95
+    # the oracle from the same float32 starts (its start is projected too):
+    # where neither side fell back, the same FP64 iteration
+    ref = oracle.retrieve(tab, lobs[:n], MODEL, prior.lo, prior.hi, prior.x0,
+                          z0=z0.astype(np.float32).astype(np.float64), opts=oracle.LMOptions(max_iter=200))
+    same = conv & ref.converged & ((st & ff.ST_USED_FALLBACK) == 0)
+    sd_t, _ = posterior_sd(ref, MODEL)
+    dT = np.abs(warm["moments"][:, 0] - ref.moments[:, 0])
+    print(f"warm starts: {same.sum()} compared, dT max {dT[same].max():.2e} K")
+    assert same.sum() >= 0.9 * n
+    assert np.all(dT[same] <= np.maximum(1e-2, 0.005 * sd_t[same]))
+    plain = ff.retrieve(scene, rad, prior, options=opts, state_f64=True).numpy()
+    torch.cuda.synchronize()
+    opts1 = ff.default_options(precision=ff.PRECISION_FP64, max_iter=200, warm_max_iter=1)
+    fb = ff.retrieve(scene, rad, prior, z0=z0t, options=opts1, state_f64=True).numpy()
+    torch.cuda.synchronize()
+    used = (fb["status"].astype(np.int64) & ff.ST_USED_FALLBACK) != 0
+    print(f"fallback kept on {used.sum()} of {n}")
+    assert used.sum() >= n // 2
+    np.testing.assert_array_equal(fb["state_f64"][used], plain["state_f64"][used])
+    np.testing.assert_array_equal(fb["moments"][used], plain["moments"][used])
+    on_simplex(fb["state_f64"], 1e-13)
