@@ -928,8 +928,10 @@ def run_front_end(args):
     """The paper's candidate selection in front of the retrieval: the HFDI
     pre-filter (Sec. 2.1, threshold -0.1) builds the candidate list on the
     device and LM solves only the listed pixels (the count never leaves the
-    device).  Timed per step: HFDI + listed LM; reported beside the plain LM
-    over every pixel of the same scene."""
+    device).  Timed per step: HFDI + listed LM.  The warm leg adds the
+    learned start on the candidates only: HFDI, the count read back, the
+    network on the listed rows (ff_mlp_infer_listed), LM on the listed rows
+    from those starts with fallback."""
     import torch
     import paper_2608_07580_amd as ff
     dev = torch.device("cuda:0")
@@ -980,7 +982,68 @@ def run_front_end(args):
     cands = ix[:n].cpu().numpy()
     r = out.numpy()
     conv = int(((r["status"][cands].astype(np.int64) & ff.ST_CONVERGED) != 0).sum())
+    plain_evals = int(evals.item()) / args.steps / max(n, 1)
     fire_idx = np.nonzero(fire)[0]
+
+    # warm leg: the network on the candidates only, LM from its starts
+    net, info = train_network(args, atm, dev)
+    z0 = torch.empty((P, ff.N_STATE[1]), dtype=torch.float32, device=dev)
+    wout = ff.allocate_outputs(P, 1, dev)
+    wopts = ff.default_options(n_quad=args.n_quad)
+    if not args.no_tune and n > 0:
+        sub = rad[idx[:n]].contiguous()
+        with torch.cuda.stream(stream):
+            zs = net.infer(sub, stream=stream)
+            wopts, _ = ff.tune([scene], [sub], prior, z0s=[zs], options=wopts, cache_path=args.tune_cache,
+                               stream=stream)
+        torch.cuda.synchronize()
+        del sub, zs
+    wev = []
+
+    def warm_step(timed):
+        t0 = time.perf_counter()
+        a, b, c, d = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        a.record(stream)
+        ix, ct, _ = ff.hfdi_candidates(scene, rad, args.hfdi_threshold, with_index_values=False, stream=stream)
+        b.record(stream)
+        m = int(ct.item())                      # the one host round trip: the inference grid needs the count
+        net.infer_listed(rad, ix, m, z0=z0, stream=stream)
+        c.record(stream)
+        ff.retrieve_listed(scene, rad, ix, ct, prior, z0=z0, options=wopts, outputs=wout, evals=evals,
+                           stream=stream)
+        d.record(stream)
+        stream.synchronize()
+        if timed:
+            wev.append((a, b, c, d, time.perf_counter() - t0))
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            warm_step(False)
+        torch.cuda.synchronize()
+        evals.zero_()
+        for _ in range(args.steps):
+            warm_step(True)
+    torch.cuda.synchronize()
+    w_hfdi = sum(a.elapsed_time(b) for a, b, c, d, t in wev) / len(wev)
+    w_net = sum(b.elapsed_time(c) for a, b, c, d, t in wev) / len(wev)
+    w_lm = sum(c.elapsed_time(d) for a, b, c, d, t in wev) / len(wev)
+    w_wall = sum(t for a, b, c, d, t in wev) / len(wev) * 1e3
+    wr = wout.numpy()
+    wst = wr["status"][cands].astype(np.int64)
+    wconv = int(((wst & ff.ST_CONVERGED) != 0).sum())
+    isf = fire[cands]
+    warm = {"ms_per_step": w_hfdi + w_net + w_lm, "wall_ms_per_step": w_wall, "hfdi_ms": w_hfdi,
+            "network_ms": w_net, "lm_ms": w_lm, "converged_candidates": wconv,
+            "converged_per_s": wconv / ((w_hfdi + w_net + w_lm) * 1e-3),
+            "mean_iters": float(wr["iters"][cands].mean()), "mean_iters_fire": float(wr["iters"][cands][isf].mean()),
+            "evals_per_candidate": int(evals.item()) / args.steps / max(n, 1),
+            "fallback_rate": float(((wst & ff.ST_USED_FALLBACK) != 0).mean()),
+            "launch": {"lanes_per_pixel": wopts.lanes_per_pixel, "block_size": wopts.block_size,
+                       "blocks_per_cu": wopts.blocks_per_cu, "schedule": wopts.schedule},
+            "train_s": info["train_s"]}
+    log(f"front end, warm: HFDI {w_hfdi:.3f} + network {w_net:.3f} + LM {w_lm:.3f} ms "
+        f"(wall {w_wall:.3f} ms), {wconv} of {n} converge, iterations {warm['mean_iters']:.2f} "
+        f"against {float(r['iters'][cands].mean()):.2f}")
     line = {
         "metric": "HFDI front end + LM on the candidates: scene pixels/s and converged candidates/s",
         "config": {"workload": f"clustered-fire scene {args.cross} x {args.lines} px x {B} bands, 3% fire, "
@@ -991,9 +1054,11 @@ def run_front_end(args):
         "background_candidates": int((~fire[cands]).sum()),
         "ms_per_step": ms, "hfdi_ms": hfdi_ms, "lm_ms": lm_ms,
         "scene_pixels_per_s": P / (ms * 1e-3), "converged_candidates": conv,
-        "converged_per_s": conv / (ms * 1e-3), "evals_per_candidate": int(evals.item()) / args.steps / max(n, 1),
+        "converged_per_s": conv / (ms * 1e-3), "evals_per_candidate": plain_evals,
+        "mean_iters": float(r["iters"][cands].mean()), "mean_iters_fire": float(r["iters"][cands][isf].mean()),
         "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size,
                    "blocks_per_cu": opts.blocks_per_cu, "schedule": opts.schedule},
+        "warm_start": warm,
     }
     print(json.dumps(line), flush=True)
 

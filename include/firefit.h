@@ -529,6 +529,18 @@ ff_status ff_mlp_fit_normalization(ff_mlp* mlp, const float* radiance_dev, int64
 ff_status ff_mlp_infer(const ff_mlp* mlp, const float* radiance_dev, int64_t P, float* z0_dev,
                        void* stream);
 
+/* Warm start for listed rows (the front end's candidates, Sec. 2.1, in
+ * front of the network of Sec. 2.5): for items i < n_listed of index_dev,
+ * z0_dev row index_dev[i] = network(radiance_dev row index_dev[i]), the
+ * same values ff_mlp_infer gives that row.  radiance_dev [P][n_in];
+ * index_dev: n_listed int64 pixel numbers in device memory (for example the
+ * first count entries from ff_hfdi_candidates; the caller reads that count
+ * back); entries outside [0, P) are skipped; z0_dev [P][n_out], rows not
+ * listed are left untouched.  Asynchronous on stream.  FF_EINVAL for NULL
+ * buffers or negative sizes. */
+ff_status ff_mlp_infer_listed(const ff_mlp* mlp, const float* radiance_dev, int64_t P, const int64_t* index_dev,
+                              int64_t n_listed, float* z0_dev, void* stream);
+
 /* Loss and gradient of one batch: loss_dev[0] = mean over the batch and
  * outputs of (z - target)^2, grads_dev [ff_mlp_n_params] (either may be
  * NULL).  target_dev [P][n_out].  P <= 65536.  Asynchronous on stream. */

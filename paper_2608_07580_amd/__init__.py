@@ -45,7 +45,8 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_retrieve_batch", "ff_retrieve", "ff_tune",
            "ff_mlp_create", "ff_mlp_destroy", "ff_mlp_n_params", "ff_mlp_get_params",
            "ff_mlp_set_params", "ff_mlp_set_normalization", "ff_mlp_get_normalization",
-           "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_gradients", "ff_mlp_train_step",
+           "ff_mlp_fit_normalization", "ff_mlp_infer", "ff_mlp_infer_listed", "ff_mlp_gradients",
+           "ff_mlp_train_step",
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
            "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
            "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec",
@@ -165,6 +166,7 @@ def lib():
         L.ff_mlp_get_normalization.argtypes = [vp, _fp, _fp, _fp]
         L.ff_mlp_fit_normalization.argtypes = [vp, vp, C.c_int64, C.c_float, vp]
         L.ff_mlp_infer.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.ff_mlp_infer_listed.argtypes = [vp, vp, C.c_int64, vp, C.c_int64, vp, vp]
         L.ff_mlp_gradients.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
         L.ff_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, vp, vp]
         L.ff_mlp_generate.argtypes = [vp, C.POINTER(ffPrior), C.c_uint64, C.c_uint64, C.c_int64, C.c_double,
@@ -201,7 +203,7 @@ def lib():
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
                      "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
                      "ff_mlp_get_normalization", "ff_mlp_fit_normalization", "ff_mlp_infer",
-                     "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train"):
+                     "ff_mlp_infer_listed", "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -739,6 +741,22 @@ class WarmStart:
         z0 = torch.empty((radiance.shape[0], self.sizes[4]), dtype=torch.float32, device=radiance.device)
         _check(lib().ff_mlp_infer(self.handle, _ptr(radiance), radiance.shape[0], _ptr(z0), _stream_handle(stream)),
                "ff_mlp_infer")
+        return z0
+
+    def infer_listed(self, radiance, index, n_listed: int, z0=None, stream=None):
+        """z0 rows of the first n_listed pixels named by index (ff_mlp_infer_listed);
+        z0 [P, n_out] is allocated (unlisted rows then undefined) or updated in place."""
+        torch = _torch()
+        assert radiance.is_cuda and radiance.dtype == torch.float32 and radiance.is_contiguous()
+        assert index.is_cuda and index.dtype == torch.int64 and index.is_contiguous()
+        assert 0 <= n_listed <= index.numel()
+        P = radiance.shape[0]
+        if z0 is None:
+            z0 = torch.empty((P, self.sizes[4]), dtype=torch.float32, device=radiance.device)
+        assert z0.is_cuda and z0.dtype == torch.float32 and z0.is_contiguous()
+        assert tuple(z0.shape) == (P, self.sizes[4])
+        _check(lib().ff_mlp_infer_listed(self.handle, _ptr(radiance), P, _ptr(index), int(n_listed), _ptr(z0),
+                                         _stream_handle(stream)), "ff_mlp_infer_listed")
         return z0
 
     def gradients(self, radiance, target, stream=None):

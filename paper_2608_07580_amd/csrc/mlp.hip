@@ -454,6 +454,25 @@ __global__ void features_kernel(const float* __restrict__ L, int P, int n_in, in
     X[i] = (__bf16)u;
 }
 
+// features_kernel for listed rows: row r of X is radiance row index[r];
+// entries outside [0, P) give a row of zeros (its output is not stored)
+__global__ void features_listed_kernel(const float* __restrict__ L, const int64_t* __restrict__ index, int64_t P,
+                                       int R, int n_in, int kin, const float* __restrict__ mean,
+                                       const float* __restrict__ inv_std, float floor_v, __bf16* __restrict__ X)
+{
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (unsigned)R * (unsigned)kin) return;
+    const unsigned r = i / (unsigned)kin;
+    const int b = (int)(i - r * (unsigned)kin);
+    const int64_t p = index[r];
+    float u = 0.f;
+    if (b < n_in && p >= 0 && p < P) {
+        const float v = L[p * n_in + b];
+        u = (__builtin_amdgcn_logf(fmaxf(v, floor_v)) * 0.6931471805599453f - mean[b]) * inv_std[b];
+    }
+    X[i] = (__bf16)u;
+}
+
 // z = tanh(y); loss += (z - t)^2; dY = d loss_mean / dy = scale (z - t)(1 - z^2)
 // as bf16 (16 columns, zero beyond n_out)
 __global__ void loss_kernel(const float* __restrict__ Y, const float* __restrict__ target, int64_t P,
@@ -492,6 +511,19 @@ __global__ void output_kernel(const float* __restrict__ Y, int64_t P, int n_out,
     const int64_t p = i / n_out;
     const int j = (int)(i - p * n_out);
     z[i] = tanhf(Y[p * 16 + j]);
+}
+
+// output_kernel for listed rows: row r goes to z row index[r] (skipped
+// outside [0, P))
+__global__ void output_listed_kernel(const float* __restrict__ Y, const int64_t* __restrict__ index, int64_t P,
+                                     int64_t R, int n_out, float* __restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R * n_out) return;
+    const int64_t r = i / n_out;
+    const int j = (int)(i - r * n_out);
+    const int64_t p = index[r];
+    if (p >= 0 && p < P) z[p * n_out + j] = tanhf(Y[r * 16 + j]);
 }
 
 // out[n] = sum_m D[m][n] for n < N (bias gradients)
@@ -990,6 +1022,30 @@ extern "C" ff_status ff_mlp_infer(const ff_mlp* mc, const float* rad, int64_t P,
         forward_rows(m, R, false, s);
         hipLaunchKernelGGL(output_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y, R, m->n_out,
                            z0 + p0 * m->n_out);
+    }
+    FF_HIP_TRY(hipGetLastError());
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_infer_listed(const ff_mlp* mc, const float* rad, int64_t P, const int64_t* index,
+                                        int64_t n_listed, float* z0, void* stream)
+{
+    if (check_mlp(mc, "ff_mlp_infer_listed")) return FF_EINVAL;
+    if (P < 0 || n_listed < 0) return set_error(FF_EINVAL, "ff_mlp_infer_listed: P < 0 or n_listed < 0");
+    if (n_listed == 0 || P == 0) return clear_error();
+    if (!rad || !index || !z0) return set_error(FF_EINVAL, "ff_mlp_infer_listed: NULL buffer");
+    ff_mlp* m = const_cast<ff_mlp*>(mc);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t chunk = std::min<int64_t>(n_listed, 1 << 18);
+    ff_status st = ensure_ws(m, chunk, s);
+    if (st != FF_OK) return st;
+    for (int64_t i0 = 0; i0 < n_listed; i0 += chunk) {
+        const int64_t R = std::min(chunk, n_listed - i0);
+        hipLaunchKernelGGL(features_listed_kernel, dim3((unsigned)cdiv(R * m->kin, 256)), dim3(256), 0, s, rad,
+                           index + i0, P, (int)R, m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
+        forward_rows(m, R, false, s);
+        hipLaunchKernelGGL(output_listed_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y,
+                           index + i0, P, R, m->n_out, z0);
     }
     FF_HIP_TRY(hipGetLastError());
     return clear_error();

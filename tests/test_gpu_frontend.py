@@ -131,3 +131,82 @@ def test_listed_retrieval_matches_the_oracle(clustered, dev):
     rec = np.isin(np.nonzero(fire)[0], cands).mean()
     print(f"{len(cands)} candidates, fire recall {rec:.3f}, background candidates {(~fire[cands]).sum()}")
     assert_parity(r, ref, min_same=0.97, label="listed")
+
+
+@pytest.fixture(scope="module")
+def frontend_net(clustered, dev):
+    """A network trained on the scene's own generated spectra, with a share
+    of background samples (as for the clustered-fire benchmark)."""
+    atm = clustered[0]
+    scene = ff.Scene(atm)
+    prior = ff.default_prior(1)
+    net = ff.WarmStart(seed=1)
+    net.fit_normalization(ff.generate(scene, prior, 999, 0, 16384, bg_fraction=0.3)[0])
+    net.train(scene, prior, steps=1500, batch=2048, seed=2, bg_fraction=0.3, lr=1e-3, lr_final=1e-5)
+    torch.cuda.synchronize()
+    return net
+
+
+def test_listed_inference_equals_the_full_inference(clustered, dev, frontend_net):
+    """ff_mlp_infer_listed writes exactly the full inference's rows at the
+    listed pixels, leaves the other rows untouched and skips entries outside
+    [0, P)."""
+    atm, tab, states, fire, lobs = clustered
+    scene = ff.Scene(atm)
+    net = frontend_net
+    rad, idx, cnt, cands, _ = _cands(scene, lobs, dev)
+    n = len(cands)
+    full = net.infer(rad).cpu().numpy()
+    z0 = torch.full((len(lobs), 5), -7.0, dtype=torch.float32, device=dev)
+    net.infer_listed(rad, idx, n, z0=z0)
+    torch.cuda.synchronize()
+    got = z0.cpu().numpy()
+    np.testing.assert_array_equal(got[cands], full[cands])
+    rest = np.setdiff1d(np.arange(len(lobs)), cands)
+    assert np.all(got[rest] == -7.0)
+    # nothing listed: nothing written; entries outside [0, P) skipped
+    z1 = torch.full((len(lobs), 5), -7.0, dtype=torch.float32, device=dev)
+    net.infer_listed(rad, idx, 0, z0=z1)
+    bad = torch.tensor([-1, len(lobs), len(lobs) + 5, int(cands[0])], dtype=torch.int64, device=dev)
+    net.infer_listed(rad, bad, 4, z0=z1)
+    torch.cuda.synchronize()
+    g1 = z1.cpu().numpy()
+    np.testing.assert_array_equal(g1[cands[0]], full[cands[0]])
+    assert np.sum(np.any(g1 != -7.0, axis=1)) == 1
+
+
+def test_warm_started_candidates(clustered, dev, frontend_net):
+    """The paper's pipeline with the learned start: HFDI candidates, the
+    network on the listed rows only, LM on the listed rows from those starts
+    (fallback on).  The listed warm retrieval equals the full warm retrieval
+    on the listed rows; against the plain listed retrieval it takes fewer
+    iterations and converges as often; its fits reach the FP64 oracle's
+    (default-start) minimum."""
+    atm, tab, states, fire, lobs = clustered
+    scene = ff.Scene(atm)
+    prior = ff.default_prior(1)
+    net = frontend_net
+    rad, idx, cnt, cands, _ = _cands(scene, lobs, dev)
+    z0 = net.infer(rad)
+    net.infer_listed(rad, idx, len(cands), z0=z0)
+    full = ff.retrieve(scene, rad, prior, z0=z0).numpy()
+    warm = ff.retrieve_listed(scene, rad, idx, cnt, prior, z0=z0)
+    plain = ff.retrieve_listed(scene, rad, idx, cnt, prior)
+    torch.cuda.synchronize()
+    w = {k: v[cands] for k, v in warm.numpy().items() if v is not None}
+    p = {k: v[cands] for k, v in plain.numpy().items() if v is not None}
+    for k in ("state", "cov", "moments", "rrr", "iters", "status"):
+        np.testing.assert_array_equal(w[k], full[k][cands])
+    assert np.all((w["status"] & ff.ST_WARM_START) != 0)
+    cw = (w["status"] & ff.ST_CONVERGED) != 0
+    cp = (p["status"] & ff.ST_CONVERGED) != 0
+    fb = (w["status"] & ff.ST_USED_FALLBACK) != 0
+    isf = fire[cands]
+    print(f"\n  {len(cands)} candidates ({isf.sum()} fire): plain conv {cp.mean():.4f} iters {p['iters'].mean():.2f} "
+          f"(fire {p['iters'][isf].mean():.2f}); warm conv {cw.mean():.4f} iters {w['iters'].mean():.2f} "
+          f"(fire {w['iters'][isf].mean():.2f}) fallback {fb.mean():.4f}")
+    assert cw.mean() >= cp.mean() - 0.002
+    assert w["iters"].mean() < 0.7 * p["iters"].mean()
+    assert w["iters"][isf].mean() < 0.6 * p["iters"][isf].mean()
+    ref = oracle.retrieve(tab, lobs[cands], 1, prior.lo, prior.hi, prior.x0)
+    assert_parity(w, ref, min_same=0.97, label="warm-started candidates")
