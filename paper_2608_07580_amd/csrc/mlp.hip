@@ -16,6 +16,7 @@
 #include "physics.hpp"
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
@@ -352,7 +353,12 @@ gemm_nt_lds(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, 
     };
     // 32x32x16 operand layout: lane l holds row (A) / column (B) l % 32 and
     // k = 8 (l / 32) + 0..7 of a 16-wide k half; result element e of lane l
-    // is D[8 (e / 4) + 4 (l / 32) + e % 4][l % 32]
+    // is D[8 (e / 4) + 4 (l / 32) + e % 4][l % 32].  The inference epilogue
+    // (BF16 output only) swaps the operands, so a lane holds one output row
+    // and runs of four consecutive columns, which it packs into 8-byte LDS
+    // writes; the tile then leaves through LDS as 16-byte row-contiguous
+    // stores.
+    constexpr bool kRowsInLanes = EPI == EPI_FWD_GELU_NOH;
     f32x16_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -399,9 +405,14 @@ gemm_nt_lds(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, 
 #pragma unroll
             for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                for (int tj = 0; tj < 2; ++tj)
-                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ti * 2 + kh], b[tj * 2 + kh],
-                                                                           acc[ti][tj], 0, 0, 0);
+                for (int tj = 0; tj < 2; ++tj) {
+                    if constexpr (kRowsInLanes)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[tj * 2 + kh], a[ti * 2 + kh],
+                                                                               acc[ti][tj], 0, 0, 0);
+                    else
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ti * 2 + kh], b[tj * 2 + kh],
+                                                                               acc[ti][tj], 0, 0, 0);
+                }
     };
     // slice kt lives in stage kt % 3; at step kt: wait for slice kt, barrier
     // (everyone is done with slice kt - 1, whose stage slice kt + 2 reuses),
@@ -421,6 +432,46 @@ gemm_nt_lds(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, 
         if (kt + 1 < KT) step(kt + 1, KT, A1, B1, A0, B0);
         if (kt + 2 < KT) step(kt + 2, KT, A2, B2, A1, B1);
     }
+    if constexpr (kRowsInLanes) {
+        // Every wave is past its last operand read (and every load has
+        // landed) after this barrier; wave w then owns stage buffer w
+        // (8 KB = its 64 x 64 BF16 sub-tile).  Rows of 128 B, 16-byte chunk
+        // c of row r at chunk c ^ ((r >> 1) & 7) against bank conflicts.
+        __builtin_amdgcn_s_barrier();
+        __bf16* stage = w == 0 ? A0 : w == 1 ? A1 : w == 2 ? A2 : B0;
+        const int r = lane & 31;
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int nl = tj * 32 + 8 * q + 4 * (lane >> 5);   // first of this lane's 4 columns
+                const float* bias = ep.bias + n0 + wn * 64 + nl;
+                const float b0 = bias[0], b1 = bias[1], b2 = bias[2], b3 = bias[3];
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti) {
+                    const int rr = ti * 32 + r;
+                    bf16x4_t v;
+                    v[0] = (__bf16)gelu_only(acc[ti][tj][4 * q + 0] + b0);
+                    v[1] = (__bf16)gelu_only(acc[ti][tj][4 * q + 1] + b1);
+                    v[2] = (__bf16)gelu_only(acc[ti][tj][4 * q + 2] + b2);
+                    v[3] = (__bf16)gelu_only(acc[ti][tj][4 * q + 3] + b3);
+                    const int chunk = (nl >> 3) ^ ((rr >> 1) & 7);
+                    *reinterpret_cast<bf16x4_t*>(stage + rr * 64 + chunk * 8 + (nl & 4)) = v;
+                }
+            }
+        }
+        __builtin_amdgcn_s_barrier();
+        // 8 rows x 8 chunks per pass, 8 passes
+#pragma unroll
+        for (int pass = 0; pass < 8; ++pass) {
+            const int rr = pass * 8 + (lane >> 3), c = lane & 7;
+            const bf16x8_t v = *reinterpret_cast<const bf16x8_t*>(stage + rr * 64 + ((c ^ ((rr >> 1) & 7)) * 8));
+            const int m = m0 + wm * 64 + rr;
+            if (m < M)
+                *reinterpret_cast<bf16x8_t*>(ep.outb + (size_t)m * ep.ldob + n0 + wn * 64 + 8 * c) = v;
+        }
+        return;
+    }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti) {
 #pragma unroll
@@ -436,22 +487,57 @@ gemm_nt_lds(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, 
 }
 
 // u_b = (ln max(L_b, floor) - mean_b) * inv_std_b, zero-padded to kin columns
-// (one element per thread; P * kin < 2^31).  ln from the hardware log2
+// (kin a multiple of 8).  One thread per 8 consecutive features of a row: two
+// 16-byte radiance loads when the row's length is a multiple of 4 (rows
+// 16-byte aligned), one 16-byte BF16 store.  ln from the hardware log2
 // (v_log_f32, ~1 ulp): the feature is rounded to BF16 (8 significant bits).
+__device__ __forceinline__ void features_chunk(const float* __restrict__ row, int n_in, int b0,
+                                               const float* __restrict__ mean, const float* __restrict__ inv_std,
+                                               float floor_v, __bf16* __restrict__ out)
+{
+    float v[8], mu[8], is[8];
+    if ((n_in & 3) == 0) {
+        // whole 16-byte quarters (row, mean and 1/s.d. alike), a quarter past
+        // the row's end re-read from its last quarter and masked below: no
+        // divergent element-wise tail (n_in >= 4 here)
+        const int o0 = min(b0, n_in - 4), o1 = min(b0 + 4, n_in - 4);
+        const float4 x0 = *reinterpret_cast<const float4*>(row + o0);
+        const float4 x1 = *reinterpret_cast<const float4*>(row + o1);
+        const float4 m0 = *reinterpret_cast<const float4*>(mean + o0);
+        const float4 m1 = *reinterpret_cast<const float4*>(mean + o1);
+        const float4 s0 = *reinterpret_cast<const float4*>(inv_std + o0);
+        const float4 s1 = *reinterpret_cast<const float4*>(inv_std + o1);
+        v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w; v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+        mu[0] = m0.x; mu[1] = m0.y; mu[2] = m0.z; mu[3] = m0.w; mu[4] = m1.x; mu[5] = m1.y; mu[6] = m1.z; mu[7] = m1.w;
+        is[0] = s0.x; is[1] = s0.y; is[2] = s0.z; is[3] = s0.w; is[4] = s1.x; is[5] = s1.y; is[6] = s1.z; is[7] = s1.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool in = b0 + j < n_in;
+            v[j] = in ? row[b0 + j] : 0.f;
+            mu[j] = in ? mean[b0 + j] : 0.f;
+            is[j] = in ? inv_std[b0 + j] : 0.f;
+        }
+    }
+    bf16x8_t u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        u[j] = (__bf16)(b0 + j < n_in
+                            ? (__builtin_amdgcn_logf(fmaxf(v[j], floor_v)) * 0.6931471805599453f - mu[j]) * is[j]
+                            : 0.f);
+    *reinterpret_cast<bf16x8_t*>(out) = u;
+}
+
 __global__ void features_kernel(const float* __restrict__ L, int P, int n_in, int kin,
                                 const float* __restrict__ mean, const float* __restrict__ inv_std,
                                 float floor_v, __bf16* __restrict__ X)
 {
     const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (unsigned)P * (unsigned)kin) return;
-    const unsigned p = i / (unsigned)kin;
-    const int b = (int)(i - p * (unsigned)kin);
-    float u = 0.f;
-    if (b < n_in) {
-        const float v = L[(size_t)p * n_in + b];
-        u = (__builtin_amdgcn_logf(fmaxf(v, floor_v)) * 0.6931471805599453f - mean[b]) * inv_std[b];
-    }
-    X[i] = (__bf16)u;
+    const unsigned cpr = (unsigned)kin / 8u;   // chunks per row
+    if (i >= (unsigned)P * cpr) return;
+    const unsigned p = i / cpr;
+    const int b0 = 8 * (int)(i - p * cpr);
+    features_chunk(L + (size_t)p * n_in, n_in, b0, mean, inv_std, floor_v, X + (size_t)p * kin + b0);
 }
 
 // features_kernel for listed rows: row r of X is radiance row index[r];
@@ -461,16 +547,16 @@ __global__ void features_listed_kernel(const float* __restrict__ L, const int64_
                                        const float* __restrict__ inv_std, float floor_v, __bf16* __restrict__ X)
 {
     const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (unsigned)R * (unsigned)kin) return;
-    const unsigned r = i / (unsigned)kin;
-    const int b = (int)(i - r * (unsigned)kin);
+    const unsigned cpr = (unsigned)kin / 8u;
+    if (i >= (unsigned)R * cpr) return;
+    const unsigned r = i / cpr;
+    const int b0 = 8 * (int)(i - r * cpr);
     const int64_t p = index[r];
-    float u = 0.f;
-    if (b < n_in && p >= 0 && p < P) {
-        const float v = L[p * n_in + b];
-        u = (__builtin_amdgcn_logf(fmaxf(v, floor_v)) * 0.6931471805599453f - mean[b]) * inv_std[b];
-    }
-    X[i] = (__bf16)u;
+    __bf16* out = X + (size_t)r * kin + b0;
+    if (p >= 0 && p < P)
+        features_chunk(L + p * n_in, n_in, b0, mean, inv_std, floor_v, out);
+    else
+        *reinterpret_cast<bf16x8_t*>(out) = bf16x8_t{};
 }
 
 // z = tanh(y); loss += (z - t)^2; dY = d loss_mean / dy = scale (z - t)(1 - z^2)
@@ -1017,7 +1103,7 @@ extern "C" ff_status ff_mlp_infer(const ff_mlp* mc, const float* rad, int64_t P,
     if (st != FF_OK) return st;
     for (int64_t p0 = 0; p0 < P; p0 += chunk) {
         const int64_t R = std::min(chunk, P - p0);
-        hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(R * m->kin, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(R * m->kin / 8, 256)), dim3(256), 0, s,
                            rad + p0 * m->n_in, (int)R, m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
         forward_rows(m, R, false, s);
         hipLaunchKernelGGL(output_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y, R, m->n_out,
@@ -1041,7 +1127,7 @@ extern "C" ff_status ff_mlp_infer_listed(const ff_mlp* mc, const float* rad, int
     if (st != FF_OK) return st;
     for (int64_t i0 = 0; i0 < n_listed; i0 += chunk) {
         const int64_t R = std::min(chunk, n_listed - i0);
-        hipLaunchKernelGGL(features_listed_kernel, dim3((unsigned)cdiv(R * m->kin, 256)), dim3(256), 0, s, rad,
+        hipLaunchKernelGGL(features_listed_kernel, dim3((unsigned)cdiv(R * m->kin / 8, 256)), dim3(256), 0, s, rad,
                            index + i0, P, (int)R, m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
         forward_rows(m, R, false, s);
         hipLaunchKernelGGL(output_listed_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y,
@@ -1056,7 +1142,7 @@ static ff_status grads_impl(ff_mlp* m, const float* rad, const float* target, in
 {
     ff_status st = ensure_ws(m, P, s);
     if (st != FF_OK) return st;
-    hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(P * m->kin, 256)), dim3(256), 0, s, rad, (int)P,
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(P * m->kin / 8, 256)), dim3(256), 0, s, rad, (int)P,
                        m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
     forward_rows(m, P, true, s);
     if (loss) hipLaunchKernelGGL(zero_f64, dim3(1), dim3(64), 0, s, loss);
