@@ -146,3 +146,6 @@ def test_front_end_rejects_bad_arguments_on_the_host(L):
     assert L.ff_hfdi_candidates(None, one, 4, -0.1, None, one, one, None) == ff.FF_EINVAL
     assert L.ff_retrieve_listed(None, one, 4, one, one, C.byref(pr), None, C.byref(o), C.byref(outs), None,
                                 None) == ff.FF_EINVAL
+    # the network on listed rows: a NULL network is refused before any launch
+    assert L.ff_mlp_infer_listed(None, one, 4, one, 2, one, None) == ff.FF_EINVAL
+    assert "NULL network" in L.ff_last_error().decode()
