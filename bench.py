@@ -1162,6 +1162,29 @@ def main():
     dT = np.abs(res_warm["moments"][:, 0] - res_plain["moments"][:, 0])[fok]
     warm["dT_vs_plain_K"] = {"pixels": int(fok.sum()), "median": float(np.median(dT)),
                              "p99": float(np.percentile(dT, 99)), "max": float(dT.max())}
+    # the radiance hand-over from host memory, timed apart from the step (the
+    # boundary takes device buffers): pinned host copy of the scene -> device
+    head_ms = (warm if args.start == "warm" else plain)["ms_per_step"]
+    # (skipped in counter runs, whose calibration copy must be the only copy)
+    h2d_info = None
+    if not args.copy_calibration:
+        host = torch.empty(rad.shape, dtype=rad.dtype, pin_memory=True)
+        host.copy_(rad)
+        torch.cuda.synchronize()
+        h2d = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                e0.record(stream)
+                rad.copy_(host, non_blocking=True)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            h2d.append(e0.elapsed_time(e1))
+        del host
+        h2d_ms = min(h2d)
+        h2d_info = {"ms": h2d_ms, "GB_per_s": rad.numel() * 4 / (h2d_ms * 1e-3) / 1e9, "host_memory": "pinned",
+                    "step_ms_with_h2d": head_ms + h2d_ms}
+        log(f"radiance host -> device: {h2d_ms:.1f} ms ({h2d_info['GB_per_s']:.1f} GB/s, pinned)")
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -1190,6 +1213,7 @@ def main():
                      "ops_per_eval": spe, "evals_per_launch": ev_head},
         "plain_lm": plain,
         "warm_start": warm,
+        "h2d": h2d_info,
     }
     if args.tune_quadrature:
         # the tuner's quadrature dimension on this scene (plain start), reported
