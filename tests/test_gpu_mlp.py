@@ -129,6 +129,45 @@ def test_inference_empty_and_ragged(world, dev, probe):
         np.testing.assert_allclose(zp, zf, rtol=0, atol=1e-6)
 
 
+@pytest.mark.parametrize("n_in", [283, 281, 7])
+def test_inference_input_widths_not_a_multiple_of_four(dev, n_in):
+    """Widths that are not a multiple of 4 take the features kernel's
+    element-wise path (rows not 16-byte aligned), with a padded tail up to
+    the next multiple of 32; a hidden width of 64 takes the 64-wide GEMM."""
+    sizes = (n_in, 128, 128, 64, 5)
+    rng = np.random.default_rng(n_in)
+    rad = rng.lognormal(-3.0, 1.0, (700, n_in)).astype(np.float32)
+    feats = omlp.features(rad, 0.0, 1.0, 1e-6)
+    mean = feats.mean(0).astype(np.float32)
+    inv = (1.0 / feats.std(0)).astype(np.float32)
+    p = omlp.init_params(sizes, 5).astype(np.float32)
+    net = ff.WarmStart(n_in=n_in, hidden=sizes[1:4], n_out=5, seed=1)
+    net.set_params(p)
+    net.set_normalization(mean, inv, 1e-6)
+    z = net.infer(torch.from_numpy(rad).to(dev)).cpu().double().numpy()
+    X = omlp.features(rad, mean.astype(np.float64), inv.astype(np.float64), np.float64(np.float32(1e-6)))
+    zq, _ = omlp.forward(p.astype(np.float64), sizes, X, bf16_storage=True)
+    assert np.abs(z - zq).max() < 2e-3, np.abs(z - zq).max()
+
+
+def test_listed_inference_across_chunks(world, dev, probe):
+    """More listed rows than one 262,144-row chunk, in a random order: every
+    listed row equals the full inference's, the others stay untouched."""
+    net = _net(probe)
+    big = torch.from_numpy(np.tile(probe[0], (60, 1))).to(dev)         # 300,000 rows
+    P = big.shape[0]
+    perm = np.random.default_rng(3).permutation(P)[:(1 << 18) + 1234]
+    idx = torch.from_numpy(perm.astype(np.int64)).to(dev)
+    full = net.infer(big).cpu().numpy()
+    z0 = torch.full((P, 5), -7.0, dtype=torch.float32, device=dev)
+    net.infer_listed(big, idx, len(perm), z0=z0)
+    torch.cuda.synchronize()
+    got = z0.cpu().numpy()
+    np.testing.assert_array_equal(got[perm], full[perm])
+    rest = np.setdiff1d(np.arange(P), perm)
+    assert np.all(got[rest] == -7.0)
+
+
 def test_gradients_match_oracle(world, dev, probe):
     rad, tgt, mean, inv, p = probe
     net = _net(probe)
