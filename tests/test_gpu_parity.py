@@ -252,6 +252,33 @@ def test_batch_equals_single_scene_runs(dev):
             np.testing.assert_array_equal(o[k], s1[k])
 
 
+def test_batch_beyond_one_launch_equals_single_scene_runs(dev):
+    """More scenes than one launch takes (16): the batch is split into
+    launches of at most 16 scenes, each scene's outputs bitwise those of its
+    own run; scenes of one and zero pixels included."""
+    lo, hi, x0 = scenegen.default_prior(1)
+    prior = ff.Prior(1, lo, hi, x0)
+    sizes = [37, 1, 0, 90, 5, 64, 65, 3, 120, 17, 2, 33, 8, 71, 1, 44, 29, 12, 6, 50]
+    scenes, rads, singles = [], [], []
+    for s, P in enumerate(sizes):
+        atm = scenegen.make_atmosphere(7, s % 5)
+        tab = oracle.band_tables(atm)
+        X = scenegen.config0_states(max(P, 1), scene=40 + s)[:P]
+        lobs = noisy_spectra(tab, X, 1, 7, s) if P else np.zeros((0, tab.B), np.float32)
+        sc = ff.Scene(atm)
+        scenes.append(sc)
+        rads.append(torch.from_numpy(np.ascontiguousarray(lobs)).to(dev))
+        singles.append(_run(sc, lobs, prior, dev))
+    outs = ff.retrieve_batch(scenes, rads, prior)
+    torch.cuda.synchronize()
+    assert len(outs) == len(sizes)
+    for o, s1, P in zip(outs, singles, sizes):
+        o = o.numpy()
+        assert o["state"].shape[0] == P
+        for k in ("state", "cov", "rrr", "iters", "status"):
+            np.testing.assert_array_equal(o[k], s1[k])
+
+
 @pytest.mark.parametrize("lpp", [1, 4])
 def test_warm_start_and_fallback(world, dev, cfg0, lpp):
     """A per-pixel start z0: pixels that converge from it keep that result;
