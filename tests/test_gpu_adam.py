@@ -187,6 +187,33 @@ def test_adam_block_size_and_batch_invariance(world, cfg0, dev):
     np.testing.assert_array_equal(outs[1].numpy()["cov"], single2["cov"])
 
 
+def test_adam_batch_beyond_one_launch(dev):
+    """More scenes than one launch takes (16), with an empty and a one-pixel
+    scene: each scene's outputs are bitwise those of its own run (the window
+    bits are made per scene of each launch)."""
+    lo, hi, x0 = scenegen.default_prior(1)
+    prior = ff.Prior(1, lo, hi, x0)
+    sizes = [20, 1, 0, 33, 5, 64, 7, 3, 41, 17, 2, 9, 8, 12, 1, 30, 11, 6]
+    scenes, rads, singles = [], [], []
+    for s, P in enumerate(sizes):
+        atm = scenegen.make_atmosphere(8, s % 6)
+        tab = oracle.band_tables(atm)
+        lobs = noisy_spectra(tab, scenegen.config0_states(max(P, 1), scene=60 + s)[:P], 1, 8, s) if P else \
+            np.zeros((0, tab.B), np.float32)
+        sc = ff.Scene(atm)
+        scenes.append(sc)
+        rads.append(torch.from_numpy(np.ascontiguousarray(lobs)).to(dev))
+        singles.append(_adam(sc, lobs, prior, dev) if P else None)
+    outs = ff.adam_retrieve_batch(scenes, rads, prior, options=ff.adam_options(prior))
+    torch.cuda.synchronize()
+    for o, s1, P in zip(outs, singles, sizes):
+        o = o.numpy()
+        assert o["state"].shape[0] == P
+        if P:
+            for k in ("state", "cov", "moments", "rrr", "iters", "status"):
+                np.testing.assert_array_equal(o[k], s1[k])
+
+
 def test_adam_two_component_parity(dev):
     """Eight-parameter mixture with the paper's per-component windows in
     stage 2: FP64 prefix pixel by pixel (the oracle's own sensitivity there
