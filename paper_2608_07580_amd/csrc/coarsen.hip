@@ -3,10 +3,13 @@
 // radiance space, and the Quantile Error Curve between each coarse pixel's
 // moment-matched Gaussian and the fine retrievals inside its footprint.
 //
-// block_mean_kernel (HBM-bound): one workgroup per coarse pixel, lanes over
-// bands, so every load of the b x b loop reads consecutive bands of one fine
-// row; sums in FP64 (exact for up to 1,024 float32 values of similar size),
-// one rounding to float32.
+// block_mean_kernel (HBM-bound): one workgroup per coarse pixel.  With a
+// band count divisible by 4 each thread owns a quad of bands (16-byte loads)
+// and the workgroup's threads form G = 256 / (B / 4) groups that take every
+// G-th fine pixel of the footprint, so G fine rows stream at once; the group
+// sums meet in LDS.  Sums in FP64 (exact for up to 1,024 float32 values of
+// similar size, so the order of the additions does not change them), one
+// rounding to float32.  Other band counts: lanes over bands, one float each.
 //
 // qec_kernel: one wave per coarse pixel.  The wave gathers the selected fine
 // pixels of the footprint into LDS (ballot compaction), ranks them by
@@ -33,6 +36,43 @@ __global__ void __launch_bounds__(256) block_mean_kernel(const float* __restrict
     const int k = blockIdx.x;       // coarse pixel
     const int r = k / C, c = k % C;
     const double inv = 1.0 / (double)(block * block);
+    const int nq = B / 4;
+    if ((B & 3) == 0 && nq <= 256) {
+        __shared__ double part[256 * 4];
+        const int G = 256 / nq;
+        const int t = threadIdx.x, q = t % nq, g = t / nq;
+        const int n = block * block;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (g < G) {
+#pragma unroll 4
+            for (int idx = g; idx < n; idx += G) {
+                const int i = idx / block, j = idx - i * block;
+                const int64_t px = (int64_t)(r * block + i) * cols + (int64_t)c * block + j;
+                const float4 v = *reinterpret_cast<const float4*>(rad + px * B + 4 * q);
+                s0 += (double)v.x;
+                s1 += (double)v.y;
+                s2 += (double)v.z;
+                s3 += (double)v.w;
+            }
+            part[4 * t + 0] = s0;
+            part[4 * t + 1] = s1;
+            part[4 * t + 2] = s2;
+            part[4 * t + 3] = s3;
+        }
+        __syncthreads();
+        if (t < nq) {
+            for (int h = 1; h < G; ++h) {
+                const double* p = part + 4 * (h * nq + t);
+                s0 += p[0];
+                s1 += p[1];
+                s2 += p[2];
+                s3 += p[3];
+            }
+            const float4 m = {(float)(s0 * inv), (float)(s1 * inv), (float)(s2 * inv), (float)(s3 * inv)};
+            *reinterpret_cast<float4*>(out + (int64_t)k * B + 4 * t) = m;
+        }
+        return;
+    }
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
         double s = 0.0;
         for (int i = 0; i < block; ++i) {
