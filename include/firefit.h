@@ -284,6 +284,25 @@ ff_status ff_retrieve_batch(const ff_scene* const* scenes, const float* const* r
                             const float* const* z0_dev, const ff_options* opts,
                             const ff_outputs* outs, unsigned long long* evals_dev, void* stream);
 
+/* Allocation-free form of ff_retrieve_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels,
+ * launch shape and results as ff_retrieve_batch; the queue counters and
+ * launch descriptors live in a fixed 16 KiB device array of the library
+ * (one copy per device, held until the process ends) instead of the
+ * stream's scratch buffer, and the call allocates nothing (the first call
+ * on a device for a precision / model / quadrature order copies that
+ * quadrature rule into constant memory, synchronously, without
+ * allocating).  At most FF_NOALLOC_MAX_SCENES scenes per call (FF_EINVAL
+ * beyond).  Every call on one device shares that array and clears its
+ * counters first: calls that overlap on one device, on any streams, race
+ * and must be ordered by the caller. */
+#define FF_NOALLOC_MAX_SCENES 64
+ff_status ff_retrieve_batch_noalloc(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                    const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                    const float* const* z0_dev, const ff_options* opts,
+                                    const ff_outputs* outs, unsigned long long* evals_dev, void* stream);
+
 /* Launch-shape autotuner.  Times ff_retrieve_batch on the given batch
  * (writing its results to outs) for candidate lanes_per_pixel (1..64),
  * block_size (64, 128, 256), blocks_per_cu (occupancy limit or 1) and

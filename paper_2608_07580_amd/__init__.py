@@ -50,7 +50,8 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_mlp_generate", "ff_mlp_train", "ff_pipeline_create", "ff_pipeline_launch", "ff_pipeline_z0",
            "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
            "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec",
-           "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_tune_quadrature")
+           "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_tune_quadrature",
+           "ff_retrieve_batch_noalloc")
 
 
 class FirefitError(RuntimeError):
@@ -148,6 +149,7 @@ def lib():
                                         C.POINTER(C.c_int64), C.c_int32, C.POINTER(ffPrior),
                                         C.POINTER(C.c_void_p), C.POINTER(ffOptions),
                                         C.POINTER(ffOutputs), C.c_void_p, C.c_void_p]
+        L.ff_retrieve_batch_noalloc.argtypes = L.ff_retrieve_batch.argtypes
         L.ff_retrieve.argtypes = [C.c_void_p, C.c_int64, C.POINTER(ffSrf), C.POINTER(ffAtmosphere),
                                   C.POINTER(ffPrior), C.c_void_p, C.POINTER(ffOptions),
                                   C.POINTER(ffOutputs), C.c_void_p]
@@ -200,7 +202,8 @@ def lib():
         for name in ("ff_tune_quadrature", "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_block_mean", "ff_qec", "ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
                      "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
-                     "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve", "ff_prior_default", "ff_tune",
+                     "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve_batch_noalloc", "ff_retrieve",
+                     "ff_prior_default", "ff_tune",
                      "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
                      "ff_mlp_get_normalization", "ff_mlp_fit_normalization", "ff_mlp_infer",
                      "ff_mlp_infer_listed", "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train"):
@@ -400,9 +403,24 @@ def retrieve(scene: Scene, radiance, prior: Prior | None = None, z0=None, option
     return out
 
 
+NOALLOC_MAX_SCENES = 64
+
+
 def retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None, options: ffOptions | None = None,
                    outputs=None, evals=None, stream=None) -> list:
     """One launch sequence over a ragged batch of scenes (same band count)."""
+    return _retrieve_batch("ff_retrieve_batch", scenes, radiances, prior, z0s, options, outputs, evals, stream)
+
+
+def retrieve_batch_noalloc(scenes, radiances, outputs, prior: Prior | None = None, z0s=None,
+                           options: ffOptions | None = None, evals=None, stream=None) -> list:
+    """ff_retrieve_batch_noalloc: the same retrieval with the library's fixed
+    device array as scratch (the caller passes the outputs)."""
+    return _retrieve_batch("ff_retrieve_batch_noalloc", scenes, radiances, prior, z0s, options, outputs, evals,
+                           stream)
+
+
+def _retrieve_batch(fn, scenes, radiances, prior, z0s, options, outputs, evals, stream) -> list:
     prior = prior or default_prior(MODEL_LOGNORMAL_1)
     options = options or default_options()
     ns = len(scenes)
@@ -415,8 +433,8 @@ def retrieve_batch(scenes, radiances, prior: Prior | None = None, z0s=None, opti
         z0p = (C.c_void_p * ns)(*[0 if z is None else z.data_ptr() for z in z0s])
     oc = (ffOutputs * ns)(*[o.to_c() for o in outs])
     pc = prior.to_c()
-    _check(lib().ff_retrieve_batch(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
-                                   _stream_handle(stream)), "ff_retrieve_batch")
+    _check(getattr(lib(), fn)(sc, rd, Ps, ns, C.byref(pc), z0p, C.byref(options), oc, _ptr(evals),
+                              _stream_handle(stream)), fn)
     return outs
 
 

@@ -228,30 +228,57 @@ extern "C" ff_status ff_forward(const ff_scene* scene, int32_t model, int32_t pr
                             (hipStream_t)stream);
 }
 
-extern "C" ff_status ff_retrieve_batch(const ff_scene* const* scenes, const float* const* radiance_dev,
-                                       const int64_t* P, int32_t n_scenes, const ff_prior* prior,
-                                       const float* const* z0_dev, const ff_options* opts,
-                                       const ff_outputs* outs, unsigned long long* evals_dev,
-                                       void* stream)
+static ff_status retrieve_batch(const char* who, const ff_scene* const* scenes, const float* const* radiance_dev,
+                                const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                const float* const* z0_dev, const ff_options* opts, const ff_outputs* outs,
+                                unsigned long long* evals_dev, void* stream, bool noalloc)
 {
-    if (n_scenes < 0) return set_error(FF_EINVAL, "ff_retrieve_batch: n_scenes < 0");
+    const std::string w(who);
+    if (n_scenes < 0) return set_error(FF_EINVAL, w + ": n_scenes < 0");
+    if (noalloc && n_scenes > FF_NOALLOC_MAX_SCENES)
+        return set_error(FF_EINVAL, w + ": at most FF_NOALLOC_MAX_SCENES (" + std::to_string(FF_NOALLOC_MAX_SCENES) +
+                                        ") scenes per call, got " + std::to_string(n_scenes));
     if (n_scenes == 0) return clear_error();
-    if (!scenes || !radiance_dev || !P || !outs) return set_error(FF_EINVAL, "ff_retrieve_batch: NULL array");
+    if (!scenes || !radiance_dev || !P || !outs) return set_error(FF_EINVAL, w + ": NULL array");
     ff_status s = check_prior(prior);
     if (s != FF_OK) return s;
     s = check_options(opts);
     if (s != FF_OK) return s;
     int B = -1;
     for (int i = 0; i < n_scenes; ++i) {
-        if (!scenes[i]) return set_error(FF_EINVAL, "ff_retrieve_batch: NULL scene");
-        if (P[i] < 0) return set_error(FF_EINVAL, "ff_retrieve_batch: P < 0");
+        if (!scenes[i]) return set_error(FF_EINVAL, w + ": NULL scene");
+        if (P[i] < 0) return set_error(FF_EINVAL, w + ": P < 0");
         if (B < 0) B = scenes[i]->n_bands;
-        if (scenes[i]->n_bands != B) return set_error(FF_EINVAL, "ff_retrieve_batch: scenes differ in band count");
-        if (P[i] > 0 && !radiance_dev[i]) return set_error(FF_EINVAL, "ff_retrieve_batch: NULL radiance");
-        if (check_library(prior->model, scenes[i], "ff_retrieve_batch") != FF_OK) return FF_EINVAL;
+        if (scenes[i]->n_bands != B) return set_error(FF_EINVAL, w + ": scenes differ in band count");
+        if (P[i] > 0 && !radiance_dev[i]) return set_error(FF_EINVAL, w + ": NULL radiance");
+        if (check_library(prior->model, scenes[i], who) != FF_OK) return FF_EINVAL;
     }
     BatchSpec bs{scenes, radiance_dev, P, n_scenes, prior, z0_dev, opts, outs, evals_dev, (hipStream_t)stream};
+    if (noalloc) {
+        s = noalloc_scratch(&bs.fixed_scratch, &bs.fixed_bytes);
+        if (s != FF_OK) return s;
+    }
     return dispatch_lm(opts->precision, prior->model, opts->n_quad, bs);
+}
+
+extern "C" ff_status ff_retrieve_batch(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                       const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                       const float* const* z0_dev, const ff_options* opts,
+                                       const ff_outputs* outs, unsigned long long* evals_dev,
+                                       void* stream)
+{
+    return retrieve_batch("ff_retrieve_batch", scenes, radiance_dev, P, n_scenes, prior, z0_dev, opts, outs,
+                          evals_dev, stream, false);
+}
+
+extern "C" ff_status ff_retrieve_batch_noalloc(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                               const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                               const float* const* z0_dev, const ff_options* opts,
+                                               const ff_outputs* outs, unsigned long long* evals_dev,
+                                               void* stream)
+{
+    return retrieve_batch("ff_retrieve_batch_noalloc", scenes, radiance_dev, P, n_scenes, prior, z0_dev, opts,
+                          outs, evals_dev, stream, true);
 }
 
 extern "C" ff_status ff_retrieve_listed(const ff_scene* scene, const float* radiance_dev, int64_t P,

@@ -98,9 +98,15 @@ struct BatchSpec {
     const ff_scene* const* atms = nullptr;  // one scene only: per-pixel atmospheres ...
     int n_atm = 0;
     const int32_t* atm_index = nullptr;     // ... chosen by this [P] index
+    void* fixed_scratch = nullptr;          // if set: queue counters and descriptors go here ...
+    size_t fixed_bytes = 0;                 // ... (its size), instead of the stream's buffer
 };
 
 ff_status dispatch_lm(int precision, int model, int q, const BatchSpec& bs);
+
+// The fixed device array of the allocation-free retrieval on the current
+// device (its address looked up once per device) and its size in bytes.
+ff_status noalloc_scratch(void** ptr, size_t* bytes);
 
 // One staged-Adam launch sequence over a ragged batch of scenes.
 struct AdamSpec {

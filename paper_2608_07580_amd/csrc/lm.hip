@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <string>
 
 #include "solve.hpp"
 
@@ -627,13 +628,18 @@ static ff_status launch_lm(const BatchSpec& bs)
     const size_t n_ctr = (size_t)n_chunks;
     const size_t ctr_bytes = (n_ctr * sizeof(unsigned long long) + 255) / 256 * 256;
     const size_t bytes = ctr_bytes + (size_t)n_chunks * desc_bytes;
-    char* scratch = nullptr;
-    {
-        const ff_status st = stream_scratch(bs.stream, bytes, reinterpret_cast<void**>(&scratch));
+    char* buf = nullptr;
+    if (bs.fixed_scratch) {
+        if (bytes > bs.fixed_bytes)
+            return set_error(FF_EINVAL, "retrieval needs " + std::to_string(bytes) + " bytes of scratch, the fixed array holds " +
+                                            std::to_string(bs.fixed_bytes));
+        buf = static_cast<char*>(bs.fixed_scratch);
+    } else {
+        const ff_status st = stream_scratch(bs.stream, bytes, reinterpret_cast<void**>(&buf));
         if (st != FF_OK) return st;
     }
-    auto* ctr = reinterpret_cast<unsigned long long*>(scratch);
-    char* descs = scratch + ctr_bytes;
+    auto* ctr = reinterpret_cast<unsigned long long*>(buf);
+    char* descs = buf + ctr_bytes;
     hipLaunchKernelGGL(zero_u64, dim3((unsigned)((n_ctr + 255) / 256)), dim3(256), 0, bs.stream, ctr, (int)n_ctr);
     hipError_t e = hipGetLastError();
 
@@ -722,6 +728,40 @@ static ff_status launch_forward(const ff_scene* sc, const void* state, int64_t P
                        sc->n_bands, (const R*)state, P, (R*)L, (R*)J);
     FF_HIP_TRY(hipGetLastError());
     return clear_error();
+}
+
+// ------------------------------------------------ allocation-free scratch
+// The queue counters and launch descriptors of ff_retrieve_batch_noalloc
+// live in this fixed array (each device holds its own copy for the life of
+// the process): one 256-byte block of counters, then one descriptor per
+// launch of at most kMaxScenesPerLaunch scenes.  Host code never passes the
+// array's name to a kernel: it looks the device address up once per device.
+constexpr size_t kNoAllocScratchBytes = 16384;
+static_assert(FF_NOALLOC_MAX_SCENES % kMaxScenesPerLaunch == 0, "whole launches");
+static_assert(256 + (FF_NOALLOC_MAX_SCENES / kMaxScenesPerLaunch) * ((sizeof(LmDesc<double, 32>) + 255) / 256 * 256) <=
+                  kNoAllocScratchBytes, "fixed scratch holds the descriptors of FF_NOALLOC_MAX_SCENES scenes");
+static_assert(sizeof(LmDesc<double, 32>) == sizeof(LmDesc<float, 16>), "descriptor size independent of type and order");
+static_assert((FF_NOALLOC_MAX_SCENES / kMaxScenesPerLaunch) * sizeof(unsigned long long) <= 256, "counters block");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+ff_status noalloc_scratch(void** ptr, size_t* bytes)
+{
+    static std::mutex mtx;
+    static void* addr[64] = {};
+    int dev = 0;
+    FF_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(FF_EUNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lock(mtx);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return set_error(FF_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kNoAllocScratchBytes;
+    return FF_OK;
 }
 
 // ---------------------------------------------------------------- dispatch

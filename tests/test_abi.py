@@ -79,6 +79,26 @@ def test_argument_errors_return_einval_before_any_launch(L):
     assert L.ff_gauss_hermite(0, x.ctypes.data_as(C.POINTER(C.c_double)), x.ctypes.data_as(C.POINTER(C.c_double))) == ff.FF_EINVAL
 
 
+def test_noalloc_retrieval_rejects_bad_arguments_on_the_host(L):
+    """The allocation-free entry point validates like ff_retrieve_batch and
+    refuses more scenes than its fixed array holds descriptors for."""
+    pr = ff.default_prior(1).to_c()
+    o = ff.default_options()
+    n = ff.NOALLOC_MAX_SCENES + 1
+    fake = (C.c_void_p * n)(*([1] * n))
+    P = (C.c_int64 * n)(*([4] * n))
+    outs = (ff.ffOutputs * n)()
+    f = L.ff_retrieve_batch_noalloc
+    assert f(fake, fake, P, n, C.byref(pr), None, C.byref(o), outs, None, None) == ff.FF_EINVAL
+    assert "FF_NOALLOC_MAX_SCENES" in L.ff_last_error().decode()
+    assert f(None, None, None, -1, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_EINVAL
+    assert f(None, None, None, 0, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_OK
+    assert f(None, None, None, 1, C.byref(pr), None, C.byref(o), None, None, None) == ff.FF_EINVAL
+    assert "NULL" in L.ff_last_error().decode()
+    ob = ff.default_options(lanes_per_pixel=3)
+    assert f(fake, fake, P, 1, C.byref(pr), None, C.byref(ob), outs, None, None) == ff.FF_EINVAL
+
+
 def test_tune_rejects_bad_arguments_on_the_host(L):
     pr = ff.default_prior(1).to_c()
     o = ff.default_options()
