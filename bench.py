@@ -35,6 +35,10 @@ import numpy as np  # noqa: E402
 # 1 slot.
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
+# MI355X's published FP32 vector peak (packed FMA counted as 4 flops per lane
+# and cycle) and the non-packed rate (FMA = 2 flops per lane and cycle)
+PEAK_FP32_PUBLISHED = 157.3e12
+PEAK_FP32_UNPACKED = 78.6e12
 
 # HBM bytes per launch of the retrieval kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled by what the
@@ -56,21 +60,36 @@ def measured_traffic(leg: str):
     return TRAFFIC_BYTES[leg] if h.hexdigest() == TRAFFIC_SHA1 else None
 
 
+# Per band and pixel the FP64 residual adds 17 FP64 or conversion
+# instructions (rho, 1 - S rho, the refined reciprocal, the solar term, the
+# residual, F += r^2, the FP32 copy of r) and drops the FP32 solar term's 5.
+RESIDUAL64_SLOTS = 17 - 5
+
+
 def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> int:
     """Algorithmic VALU slots of one model+Jacobian+reduction evaluation of one
     pixel: per (band, node) 7 VALU (x = a u, 2^x - 1, three FMAs and one
     product for the three quadrature sums) + 2 transcendentals (exp2, rcp; 2
     slots each) = 11; per band and component 5 slots of scaling plus 19
     (n=5) / 49 (n=8) for the solar term, basis, residual and the J^T J, J^T r,
-    r.r accumulations."""
+    r.r accumulations, and the FP64 residual's RESIDUAL64_SLOTS."""
     if model == 4:
         # one component; the endmember surface: 5 FMAs for rho and 5 basis
         # products where the linear surface has 2 and 2 (25), and the n = 8
         # accumulations (45)
-        return n_bands * (11 * n_quad + 5 + 25 + 45)
+        return n_bands * (11 * n_quad + 5 + 25 + 45 + RESIDUAL64_SLOTS + 4)
     comps = 1 if model == 1 else 2
-    per_band = comps * (11 * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45)
+    per_band = comps * (11 * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45) + RESIDUAL64_SLOTS
     return n_bands * per_band
+
+
+def flops_per_eval(n_bands: int, n_quad: int) -> int:
+    """Floating-point operations of one evaluation of the one-component model
+    (FMA = 2, exp2 and rcp = 1 each): per (band, node) x = a u (1), 2^x (1),
+    - 1 (1), rcp (1), three FMAs and q q + q (8), x (...) (1) = 13; per band
+    72 for the reflectance, the basis, the FP64 solar term and residual and
+    the J^T J, J^T r, r.r accumulations."""
+    return n_bands * (13 * n_quad + 72)
 
 
 def log(*a):
@@ -103,9 +122,29 @@ def make_workload(args, dev):
     return atm, scene, states, fire, noise, rad
 
 
-def cpu_baseline(args, atm, states, noise, gpu_legs):
-    """The FP64 oracle on a seeded subsample of the same scene, on this host;
-    the GPU legs' results on the same pixels are compared with it."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+PARITY_KEYS = ("both", "same_min", "same_frac", "t_n", "dT_max", "dT_p99", "f_n", "df_max", "drrr_max_same",
+               "dT_over_tol", "df_over_tol", "cov_sd_rel_max", "cov_corr_max", "cov_n", "determined",
+               "loss_worse_determined", "dchi2_max_determined", "flat", "flat_worse_0.001", "flat_better_0.001",
+               "flat_worse_0.1", "flat_better_0.1", "flat_worse_1", "flat_better_1")
+
+
+def cpu_baseline(args, atm, rad, states, gpu_legs):
+    """The FP64 oracle on a seeded subsample of the same scene, on this host,
+    fed the GPU's own float32 radiance rows (the same input both retrieve);
+    the GPU legs' results on the same pixels are compared with it under the
+    tests' parity gate."""
+    import torch
     import oracle
     import scenegen
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -113,8 +152,7 @@ def cpu_baseline(args, atm, states, noise, gpu_legs):
     P = states.shape[0]
     idx = scenegen.subsample(1, 0, P, args.cpu_sample)
     tab = oracle.band_tables(atm)
-    lt = oracle.forward(tab, states[idx], 1)
-    lobs = (lt * (1.0 + noise[idx].astype(np.float64) / args.snr)).astype(np.float32)
+    lobs = rad[torch.from_numpy(idx).to(rad.device)].cpu().numpy()
     lo, hi, x0 = scenegen.default_prior(1)
     cores = len(os.sched_getaffinity(0))
     t0 = time.time()
@@ -123,12 +161,15 @@ def cpu_baseline(args, atm, states, noise, gpu_legs):
     conv = int(r.converged.sum())
     parity = {}
     for name, res in gpu_legs.items():
-        rep = parity_report({k: v[idx] for k, v in res.items() if v is not None}, r)
-        parity[name] = {k: v for k, v in rep.items() if not k.endswith("_mask")}
-    return {"value": conv / dt, "unit": "converged retrievals/s", "cores": cores, "kind": "oracle",
+        rep = parity_report({k: v[idx] for k, v in res.items() if v is not None}, r, 1, tab, lobs)
+        parity[name] = {k: rep[k] for k in PARITY_KEYS if k in rep}
+        parity[name]["gpu_converged"] = int(((res["status"][idx] & 7) != 0).sum())
+    return {"value": conv / dt, "unit": "converged retrievals/s", "cores": cores, "cpu": cpu_model(),
+            "kind": "oracle",
             "sample": f"seeded uniform subsample of {len(idx)} of the {P} scene pixels "
-                      f"({int((states[idx, 0] > 0).sum())} fire), FP64 LM from the default start, "
-                      f"{dt:.1f} s wall, {conv} converged, mean {r.iters.mean():.1f} iterations",
+                      f"({int((states[idx, 0] > 0).sum())} fire), the GPU's own float32 radiance rows, "
+                      f"FP64 LM from the default start, {dt:.1f} s wall, {conv} converged, "
+                      f"mean {r.iters.mean():.1f} iterations",
             "gpu_vs_oracle": parity}
 
 
@@ -169,7 +210,7 @@ def run_leg(args, atm, rad, stream, net):
     if not args.no_tune:
         # launch shape from the tuner's table (tuned on this batch on a miss)
         sc = ff.Scene(atm)
-        z0 = net.infer(rad, stream=stream) if net is not None else None
+        z0 = net.infer_routed(sc, rad, stream=stream)[0] if net is not None else None
         with torch.cuda.stream(stream):
             opts, tms = ff.tune([sc], [rad], prior, z0s=None if z0 is None else [z0], options=opts,
                                 cache_path=args.tune_cache, stream=stream)
@@ -186,7 +227,7 @@ def run_leg(args, atm, rad, stream, net):
 
     def step(timed):
         sc = ff.Scene(atm)
-        z0 = net.infer(rad, stream=stream) if net is not None else None
+        z0 = net.infer_routed(sc, rad, stream=stream)[0] if net is not None else None
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -1195,6 +1236,8 @@ def main():
     head, ev_head = (warm, ev_warm) if args.start == "warm" else (plain, ev_plain)
     spe = slots_per_eval(B, args.n_quad)
     achieved = ev_head * spe / (head["lm_kernel_ms"] * 1e-3)
+    fpe = flops_per_eval(B, args.n_quad)
+    flops = ev_head * fpe / (head["lm_kernel_ms"] * 1e-3)
     start_desc = ("network warm start (trained per atmosphere, not timed) + LM with fallback"
                   if args.start == "warm" else "default start (plain LM)")
     line = {
@@ -1210,8 +1253,13 @@ def main():
                      "unit": "Tops/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(args.start),
                      "traffic_unit": "HBM bytes per launch (calibrated TCC FETCH_SIZE + WRITE_SIZE)",
                      "kernel": "lm_kernel", "kernel_ms": head["lm_kernel_ms"],
-                     "op": "FP32 VALU issue slot per lane (transcendental = 2)",
-                     "ops_per_eval": spe, "evals_per_launch": ev_head},
+                     "op": "VALU issue slot per lane (transcendental = 2)",
+                     "ops_per_eval": spe, "evals_per_launch": ev_head,
+                     "flops_per_eval": fpe, "achieved_TFLOPs": flops / 1e12,
+                     "frac_published": flops / PEAK_FP32_PUBLISHED,
+                     "frac_unpacked": flops / PEAK_FP32_UNPACKED,
+                     "peaks_TFLOPs": {"published_fp32": PEAK_FP32_PUBLISHED / 1e12,
+                                      "unpacked_fp32": PEAK_FP32_UNPACKED / 1e12}},
         "plain_lm": plain,
         "warm_start": warm,
         "h2d": h2d_info,
@@ -1227,7 +1275,7 @@ def main():
         line["quadrature_choice"] = rep
         log(f"quadrature choice: {rep}")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args, atm, states, noise, {"plain": res_plain, "warm": res_warm})
+        line["cpu_baseline"] = cpu_baseline(args, atm, rad, states, {"plain": res_plain, "warm": res_warm})
     print(json.dumps(line), flush=True)
 
 

@@ -174,10 +174,17 @@ typedef struct ff_options {
     int32_t warm_max_iter; /* iteration cap of a solve from a per-pixel start z0 before the fallback
                               to x0 takes over (0 = max_iter; the fallback always gets max_iter) */
     double xtol;           /* default 1e-6 (z units) */
-    double ftol;           /* default 1e-8 */
+    double ftol;           /* default 1e-8: an accepted step whose predicted reduction is <= ftol F
+                              ends the solve (FF_ST_CONVERGED_FTOL) */
     double gtol;           /* default 1e-10 */
     double kappa;          /* accept a step whose predicted reduction is <= kappa F (default 1e-5) */
     double tau;            /* initial damping = tau * max diag(J^T J) (default 1e-6) */
+    double ftol_undetected; /* the decrease test's tolerance while the fire fraction (state
+                               variable 0) is below f_detect: no detectable fire, the thermal
+                               variables unidentified, the loss a noise valley along the
+                               area-temperature degeneracy (default 1e-6, the resolution of F
+                               with an FP32 thermal term) */
+    double f_detect;       /* default 1e-4 (0 = always ftol) */
 } ff_options;
 
 /* Outputs, device arrays owned by the caller (any pointer may be NULL to
@@ -263,8 +270,11 @@ ff_status ff_forward(const ff_scene* scene, int32_t model, int32_t precision, in
 /* Retrieve P pixels of one scene.  radiance_dev: [P][n_bands] float32,
  * row-major (band-interleaved by pixel).  z0_dev: [P][n] per-pixel start in
  * z (for example from a learned warm start) or NULL to start every pixel
- * from prior->x0.  With z0_dev and opts->fallback, pixels whose solve from
- * z0 does not converge are solved again from x0 (FF_ST_USED_FALLBACK).
+ * from prior->x0; a row whose first entry is NaN carries no start (that
+ * pixel is solved from x0 exactly as without z0: no fallback, no
+ * FF_ST_WARM_START), so a warm start can be given to some pixels only.
+ * With z0_dev and opts->fallback, pixels whose solve from z0 does not
+ * converge are solved again from x0 (FF_ST_USED_FALLBACK).
  * evals_dev: optional uint64 counter that receives += the number of model
  * evaluations performed (NULL to skip).  Asynchronous on stream.  The
  * queue counter and launch descriptor live in a library-owned scratch

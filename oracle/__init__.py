@@ -78,7 +78,7 @@ def lib():
         L.orc_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
                                    C.c_int, dp, dp, dp, dp, C.c_long, fp,
                                    C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
-                                   C.c_double, C.c_int,
+                                   C.c_double, C.c_double, C.c_double, C.c_int,
                                    dp, dp, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_uint)]
         L.orc_adam_retrieve.restype = C.c_int
         L.orc_adam_retrieve.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, fp, C.c_int, dp, dp,
@@ -286,7 +286,12 @@ def forward(tab: Tables, state, model: int, q: int = 32, jacobian: bool = False,
 class LMOptions:
     max_iter: int = 50
     xtol: float = 1e-6
-    ftol: float = 1e-8     # relative decrease ~ 3e-6 in chi^2 at SNR 300 (noise-level stop)
+    ftol: float = 1e-8     # predicted relative decrease of an accepted step (~3e-6 chi^2 at SNR 300)
+    # while the fire fraction is below f_detect (the fraction tolerance: no
+    # detectable fire, the thermal variables unidentified) the decrease test
+    # uses ftol_undetected, the resolution of an FP32 thermal term (1e-6 F)
+    ftol_undetected: float = 1e-6
+    f_detect: float = 1e-4
     gtol: float = 1e-10
     kappa: float = 1e-5
     tau: float = 1e-6      # initial damping mu_0 = tau * max diag(J^T J)
@@ -328,7 +333,7 @@ def retrieve(tab: Tables, lobs, model: int, lo, hi, x0, z0=None, q: int = 32,
                             _dp(tab.ratm), _dp(tab.S), _dp(endm), _fp(lsat), q, _dp(gx), _dp(gw),
                             model, _dp(lo), _dp(hi), _dp(x0), _dp(z0c), P, _fp(lobs),
                             opts.max_iter, opts.xtol, opts.ftol, opts.gtol, opts.kappa,
-                            opts.tau, nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),
+                            opts.tau, opts.ftol_undetected, opts.f_detect, nthreads, _dp(out.state), _dp(out.cov), _dp(out.moments),
                             _dp(out.rrr), out.iters.ctypes.data_as(C.POINTER(C.c_int)),
                             out.status.ctypes.data_as(C.POINTER(C.c_uint)))
     if rc != 0:

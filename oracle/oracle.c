@@ -499,6 +499,7 @@ static int trial_point(int n, int sf, const double* z, const double* delta, doub
 typedef struct {
     int max_iter;
     double xtol, ftol, gtol, kappa, tau;
+    double ftol_undetected, f_detect;   /* FTOL while the fire fraction x_0 < f_detect */
 } lmopt_t;
 
 /* Levenberg-Marquardt from z (in/out).  Returns status bits; *iters counts
@@ -596,7 +597,13 @@ static unsigned lm_solve(const problem_t* pb, const lmopt_t* o, double* z,
             mu *= fmax(1.0 / 3.0, 1.0 - t * t * t);
             nu = 2.0;
             for (int j = 0; j < n; ++j) d[j] = fmax(d[j], A[j * n + j]);
-            if (pred <= o->ftol * Fold && !cut) { st = ST_FTOL; break; }
+            /* the decrease test: ftol, or ftol_undetected while the fire
+             * fraction is below the detection level (no identified thermal
+             * variables: the loss there is the noise valley of the
+             * area-temperature degeneracy) */
+            const double xf = pb->lo[0] + 0.5 * (pb->hi[0] - pb->lo[0]) * (z[0] + 1.0);
+            const double ft = xf < o->f_detect ? o->ftol_undetected : o->ftol;
+            if (pred <= ft * Fold && !cut) { st = ST_FTOL; break; }
             if (gradient_small(n, sf, z, A, g, F, o->gtol)) { st = ST_GTOL; break; }
         } else {
             mu *= nu;
@@ -731,7 +738,7 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
                  int model, const double* lo, const double* hi, const double* x0,
                  const double* z0, long P, const float* lobs,
                  int max_iter, double xtol, double ftol, double gtol, double kappa,
-                 double tau, int nthreads,
+                 double tau, double ftol_undetected, double f_detect, int nthreads,
                  double* state, double* cov, double* moments, double* rrr,
                  int* iters, unsigned* status)
 {
@@ -740,7 +747,7 @@ int orc_retrieve(int B, const double* lam, const double* K, const double* tau2,
     for (int j = 0; j < n; ++j) if (!(hi[j] > lo[j])) return -1;
     if (!simplex_box_ok(model, lo, hi)) return -1;
     scene_t sc = {B, lam, K, tau2, tup, ratm, S, Q, gx, gw, endm};
-    lmopt_t o = {max_iter, xtol, ftol, gtol, kappa, tau};
+    lmopt_t o = {max_iter, xtol, ftol, gtol, kappa, tau, ftol_undetected, f_detect};
     if (!(tau > 0.0)) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);

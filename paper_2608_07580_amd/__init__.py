@@ -11,6 +11,7 @@ works but every call raises.
 from __future__ import annotations
 
 import ctypes as C
+from contextlib import nullcontext as _nullcontext
 import os
 from dataclasses import dataclass
 
@@ -87,7 +88,7 @@ class ffOptions(C.Structure):
                 ("warm_max_iter", C.c_int32),
                 ("xtol", C.c_double),
                 ("ftol", C.c_double), ("gtol", C.c_double), ("kappa", C.c_double),
-                ("tau", C.c_double)]
+                ("tau", C.c_double), ("ftol_undetected", C.c_double), ("f_detect", C.c_double)]
 
 
 MAX_ADAM_STAGES = 4
@@ -776,6 +777,23 @@ class WarmStart:
         _check(lib().ff_mlp_infer_listed(self.handle, _ptr(radiance), P, _ptr(index), int(n_listed), _ptr(z0),
                                          _stream_handle(stream)), "ff_mlp_infer_listed")
         return z0
+
+    def infer_routed(self, scene, radiance, threshold: float = HFDI_THRESHOLD, z0=None, stream=None):
+        """Starts for the fire candidates only: the front end's index (Sec. 2.1,
+        ff_hfdi_candidates) picks the pixels, the network (ff_mlp_infer_listed)
+        gives their start rows, every other row is NaN (no start: solved from
+        x0).  Returns (z0 [P, n_out], number of candidates); the candidate
+        count is read back to the host (one synchronisation of the stream)."""
+        torch = _torch()
+        P = radiance.shape[0]
+        idx, cnt, _ = hfdi_candidates(scene, radiance, threshold, with_index_values=False, stream=stream)
+        if z0 is None:
+            z0 = torch.empty((P, self.sizes[4]), dtype=torch.float32, device=radiance.device)
+        with torch.cuda.stream(stream) if stream is not None else _nullcontext():
+            z0.fill_(float("nan"))
+            n = int(cnt.item())
+        self.infer_listed(radiance, idx, n, z0=z0, stream=stream)
+        return z0, n
 
     def gradients(self, radiance, target, stream=None):
         torch = _torch()

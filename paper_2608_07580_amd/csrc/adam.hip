@@ -164,6 +164,7 @@ adam_kernel(const AdamDesc<R, Q>* __restrict__ descp)
         const int B = D->B;
         const float* rad = sd.radiance + pix * B;
         const R* tab = reinterpret_cast<const R*>(sd.table);
+        const double* tab64 = sd.table64;
         const OutPtrs o = out_ptrs(sd);
         int nonfin = 0, nvalid = 0;
         double lnorm2 = 0.0;
@@ -256,10 +257,10 @@ adam_kernel(const AdamDesc<R, Q>* __restrict__ descp)
                 x[j] = D->lo[j] + 0.5 * (D->hi[j] - D->lo[j]) * (z[j] + 1.0);
                 bound = bound || z[j] <= -1.0 || z[j] >= 1.0;
             }
-            R A[NT], g[N];
+            double A[NT], g[N];
             double F = __builtin_nan("");
             if (!bad) {
-                F = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, x, A, g, sub, L);
+                F = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, tab64, x, A, g, sub, L);
                 nevals += head ? 1 : 0;
             }
             const Desc* De = launder(descp);
@@ -323,6 +324,7 @@ static ff_status launch_adam(const AdamSpec& as)
             const ff_outputs& out = as.outs[s];
             d.radiance = as.radiance[s];
             d.table = sizeof(R) == 4 ? (const void*)as.scenes[s]->table_f32 : (const void*)as.scenes[s]->table_f64;
+            d.table64 = as.scenes[s]->table_f64;
             d.P = as.P[s];
             d.offset = off;
             d.z0 = as.z0 ? as.z0[s] : nullptr;

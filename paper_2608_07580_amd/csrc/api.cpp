@@ -91,7 +91,8 @@ static ff_status check_options(const ff_options* o)
         return set_error(FF_EINVAL, "lanes_per_pixel must be 0 or a power of two <= 64");
     if (o->accumulate != FF_ACCUMULATE_FP32 && o->accumulate != FF_ACCUMULATE_FP64)
         return set_error(FF_EINVAL, "unknown accumulate mode");
-    if (!(o->xtol >= 0) || !(o->ftol >= 0) || !(o->gtol >= 0) || !(o->kappa >= 0) || !(o->tau > 0))
+    if (!(o->xtol >= 0) || !(o->ftol >= 0) || !(o->gtol >= 0) || !(o->kappa >= 0) || !(o->tau > 0) ||
+        !(o->ftol_undetected >= 0) || !(o->f_detect >= 0))
         return set_error(FF_EINVAL, "tolerances must be >= 0 and tau > 0");
     return FF_OK;
 }
@@ -166,6 +167,8 @@ extern "C" void ff_options_default(ff_options* o)
     o->gtol = 1e-10;
     o->kappa = 1e-5;
     o->tau = 1e-6;
+    o->ftol_undetected = 1e-6;
+    o->f_detect = 1e-4;
 }
 
 extern "C" ff_status ff_prior_default(int32_t model, ff_prior* p)

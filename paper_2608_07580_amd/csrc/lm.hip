@@ -54,17 +54,19 @@ struct LmDesc {
     int warm_max_iter;             // cap of a solve from z0 (0: max_iter)
     int fallback;
     double xtol, ftol, gtol, kappa, tau;
+    double ftol_undetected, f_detect;   // decrease test while the fire fraction is below f_detect
     double lo[FF_MAX_STATE], hi[FF_MAX_STATE], zdef[FF_MAX_STATE];
     int n_atm;                     // per-pixel atmospheres (with SceneDev::atm)
     const void* atm_tables[FF_MAX_ATMOSPHERES];
+    const double* atm_tables64[FF_MAX_ATMOSPHERES];   // their FP64 tables
 };
 
 namespace {
 
 // Projected-gradient test: max over free j of |g_j| / sqrt(A_jj F) <= gtol.
-template <typename R, int N>
-__device__ __forceinline__ bool gradient_small(const R (&z)[N], const R (&A)[N * (N + 1) / 2],
-                                               const R (&g)[N], double F, double gtol)
+template <int N>
+__device__ __forceinline__ bool gradient_small(const double (&z)[N], const double (&A)[N * (N + 1) / 2],
+                                               const double (&g)[N], double F, double gtol)
 {
     if (!(F > 0.0)) return true;
     bool small = true;
@@ -80,8 +82,8 @@ __device__ __forceinline__ bool gradient_small(const R (&z)[N], const R (&A)[N *
 // Fractions of a simplex block held at zero (Karush-Kuhn-Tucker sign):
 // fraction k at zero is held when its gradient exceeds the mean gradient of
 // the fractions above zero, so moving weight onto it would raise the loss.
-template <typename R, int N, int SF>
-__device__ __forceinline__ void simplex_hold(const R (&z)[N], const R (&g)[N], bool (&act)[N])
+template <int N, int SF>
+__device__ __forceinline__ void simplex_hold(const double (&z)[N], const double (&g)[N], bool (&act)[N])
 {
     double gs = 0.0;
     int m = 0;
@@ -95,9 +97,9 @@ __device__ __forceinline__ void simplex_hold(const R (&z)[N], const R (&g)[N], b
 
 // The projected-gradient test with a simplex block: the free fractions'
 // gradient less its mean over them.
-template <typename R, int N, int SF>
-__device__ __forceinline__ bool gradient_small_simplex(const R (&z)[N], const R (&A)[N * (N + 1) / 2],
-                                                       const R (&g)[N], double F, double gtol)
+template <int N, int SF>
+__device__ __forceinline__ bool gradient_small_simplex(const double (&z)[N], const double (&A)[N * (N + 1) / 2],
+                                                       const double (&g)[N], double F, double gtol)
 {
     if (!(F > 0.0)) return true;
     bool act[N];
@@ -106,7 +108,7 @@ __device__ __forceinline__ bool gradient_small_simplex(const R (&z)[N], const R 
         const double gj = (double)g[j], zj = (double)z[j];
         act[j] = (zj <= -1.0 && gj > 0.0) || (zj >= 1.0 && gj < 0.0);
     }
-    simplex_hold<R, N, SF>(z, g, act);
+    simplex_hold<N, SF>(z, g, act);
     double gs = 0.0;
     int m = 0;
 #pragma unroll
@@ -123,12 +125,12 @@ __device__ __forceinline__ bool gradient_small_simplex(const R (&z)[N], const R 
     return small;
 }
 
-template <int MODEL, typename R, int N>
-__device__ __forceinline__ bool converged_gradient(const R (&z)[N], const R (&A)[N * (N + 1) / 2], const R (&g)[N],
+template <int MODEL, int N>
+__device__ __forceinline__ bool converged_gradient(const double (&z)[N], const double (&A)[N * (N + 1) / 2], const double (&g)[N],
                                                    double F, double gtol)
 {
-    if constexpr (simplex_first_v<MODEL> >= 0) return gradient_small_simplex<R, N, simplex_first_v<MODEL>>(z, A, g, F, gtol);
-    else return gradient_small<R, N>(z, A, g, F, gtol);
+    if constexpr (simplex_first_v<MODEL> >= 0) return gradient_small_simplex<N, simplex_first_v<MODEL>>(z, A, g, F, gtol);
+    else return gradient_small<N>(z, A, g, F, gtol);
 }
 
 // Occupancy target (second launch bound, waves per SIMD), FP32 kernels: the
@@ -160,10 +162,15 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
     int sidx = 0;
     const float* rad = nullptr;
     const R* tab = nullptr;
+    const double* tab64 = nullptr;
     double lnorm2 = 0.0, amax = 1.0;
     int nvalid = 0;
     constexpr int SF = simplex_first_v<MODEL>;
-    R z[N], zt[N], A[NT], g[N], d[N];
+    // z and the trial point in FP64 in every kernel: near a bound an FP32 z
+    // resolves f only to ~1.5e-8 (z spacing 6e-8 near -1), coarser than the
+    // steps of a solve creeping along the f -> 0 valley of a background pixel
+    double z[N], zt[N];
+    double A[NT], g[N], d[N];
     bool cut = false;           // the last step was shortened by the simplex (no convergence test on it)
     double F = 0.0;
     double mu = 0.0, nu = 2.0, pred = 0.0;
@@ -171,7 +178,7 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
     unsigned st = 0;
     unsigned long long nevals = 0;
 #pragma unroll
-    for (int j = 0; j < N; ++j) { z[j] = zt[j] = g[j] = d[j] = (R)0; }
+    for (int j = 0; j < N; ++j) { z[j] = zt[j] = g[j] = d[j] = 0.0; }
 #pragma unroll
     for (int j = 0; j < NT; ++j) A[j] = (R)0;
 
@@ -227,11 +234,13 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                     const int B = D->B;
                     rad = sd.radiance + pix * B;
                     tab = reinterpret_cast<const R*>(sd.table);
+                    tab64 = sd.table64;
                     bool atm_ok = true;
                     if (sd.atm) {
                         const int a = sd.atm[pix];
                         atm_ok = a >= 0 && a < D->n_atm;
                         tab = atm_ok ? reinterpret_cast<const R*>(D->atm_tables[a]) : nullptr;
+                        tab64 = atm_ok ? D->atm_tables64[a] : nullptr;
                     }
                     int nonfin = 0;
                     nvalid = 0;
@@ -255,12 +264,14 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                         }
                     } else {
                         const float* z0 = sd.z0;
-                        warm = z0 != nullptr;
+                        // a start row whose first entry is NaN carries no start:
+                        // the pixel is solved from x0 as without z0
+                        warm = z0 != nullptr && !isnan(z0[pix * N]);
 #pragma unroll
                         for (int j = 0; j < N; ++j) {
                             double zz = warm ? (double)z0[pix * N + j] : D->zdef[j];
                             zz = isfinite(zz) ? zz : D->zdef[j];
-                            z[j] = (R)fmin(1.0, fmax(-1.0, zz));
+                            z[j] = fmin(1.0, fmax(-1.0, zz));
                         }
                         project_block<MODEL>(z);
                         if (warm) st |= FF_ST_WARM_START;
@@ -280,8 +291,8 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                 for (int j = 0; j < N; ++j)
                     xe[j] = D->lo[j] + 0.5 * (D->hi[j] - D->lo[j]) * ((double)(phase == 0 ? z[j] : zt[j]) + 1.0);
             }
-            R At[NT], gt[N];
-            const double Fe = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, xe, At, gt, sub, L);
+            double At[NT], gt[N];
+            const double Fe = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, tab64, xe, At, gt, sub, L);
             nevals += head ? 1 : 0;
 
             // -------------------------------------------- LM bookkeeping
@@ -305,7 +316,7 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                     for (int j = 0; j < N; ++j) amax = fmax(amax, (double)A[tri(j, j)]);
                     if (!(amax > 0.0)) amax = 1.0;
 #pragma unroll
-                    for (int j = 0; j < N; ++j) d[j] = (R)fmax((double)A[tri(j, j)], 1e-12 * amax);
+                    for (int j = 0; j < N; ++j) d[j] = fmax(A[tri(j, j)], 1e-12 * amax);
                     mu = D->tau * amax;
                     nu = 2.0;
                     phase = 1;
@@ -326,8 +337,13 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                     mu *= fmax(1.0 / 3.0, 1.0 - t * t * t);
                     nu = 2.0;
 #pragma unroll
-                    for (int j = 0; j < N; ++j) d[j] = (R)fmax((double)d[j], (double)A[tri(j, j)]);
-                    if (pred <= D->ftol * fold && (SF < 0 || !cut)) {
+                    for (int j = 0; j < N; ++j) d[j] = fmax(d[j], A[tri(j, j)]);
+                    // the decrease test; below the detection level of the fire
+                    // fraction the thermal variables are not identified and the
+                    // loss is a noise valley: the tolerance is the FP32 cost's
+                    const double xf = D->lo[0] + 0.5 * (D->hi[0] - D->lo[0]) * (z[0] + 1.0);
+                    const double ft = xf < D->f_detect ? D->ftol_undetected : D->ftol;
+                    if (pred <= ft * fold && (SF < 0 || !cut)) {
                         st |= FF_ST_CONVERGED_FTOL;
                         done = true;
                     } else if (converged_gradient<MODEL>(z, A, g, F, D->gtol)) {
@@ -387,7 +403,7 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                         cholesky_solve<N>(m, rhs, delta);
 #pragma unroll
                         for (int j = 0; j < N; ++j) {
-                            const R zz = (R)fmin(1.0, fmax(-1.0, (double)z[j] + delta[j]));
+                            const double zz = fmin(1.0, fmax(-1.0, (double)z[j] + delta[j]));
                             zt[j] = zz;
                             hstep[j] = (double)zz - (double)z[j];
                             hmax = fmax(hmax, fabs(hstep[j]));
@@ -412,7 +428,7 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                             const double gj = (double)g[j], zj = (double)z[j];
                             act[j] = (zj <= -1.0 && gj > 0.0) || (zj >= 1.0 && gj < 0.0);
                         }
-                        simplex_hold<R, N, SF>(z, g, act);
+                        simplex_hold<N, SF>(z, g, act);
                         bool factored = true;
 #pragma unroll 1
                         for (int pass = 0; pass <= FF_N_ENDMEMBERS; ++pass) {
@@ -468,10 +484,10 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                             }
                         }
 #pragma unroll
-                        for (int j = 0; j < N; ++j) zt[j] = (R)fmin(1.0, fmax(-1.0, (double)z[j] + a * delta[j]));
+                        for (int j = 0; j < N; ++j) zt[j] = fmin(1.0, fmax(-1.0, (double)z[j] + a * delta[j]));
 #pragma unroll
                         for (int k = SF; k < SF + FF_N_ENDMEMBERS; ++k)
-                            if (k == stop) zt[k] = (R)-1.0;
+                            if (k == stop) zt[k] = -1.0;
                         cut = stop >= 0;
 #pragma unroll
                         for (int j = 0; j < N; ++j) {
@@ -548,7 +564,7 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                     phase = 0;
                     st = 0;
 #pragma unroll
-                    for (int j = 0; j < N; ++j) z[j] = (R)fmin(1.0, fmax(-1.0, D->zdef[j]));
+                    for (int j = 0; j < N; ++j) z[j] = fmin(1.0, fmax(-1.0, D->zdef[j]));
                     project_block<MODEL>(z);
                 }
             }
@@ -652,6 +668,7 @@ static ff_status launch_lm(const BatchSpec& bs)
             const ff_outputs& out = bs.outs[s];
             d.radiance = bs.radiance[s];
             d.table = sizeof(R) == 4 ? (const void*)bs.scenes[s]->table_f32 : (const void*)bs.scenes[s]->table_f64;
+            d.table64 = bs.scenes[s]->table_f64;
             d.P = bs.P[s];
             d.offset = off;
             d.index = bs.index;
@@ -673,8 +690,10 @@ static ff_status launch_lm(const BatchSpec& bs)
         prm.total = off;
         prm.total_dev = bs.count_dev;
         prm.n_atm = bs.atm_index ? bs.n_atm : 0;
-        for (int a = 0; a < prm.n_atm; ++a)
+        for (int a = 0; a < prm.n_atm; ++a) {
             prm.atm_tables[a] = sizeof(R) == 4 ? (const void*)bs.atms[a]->table_f32 : (const void*)bs.atms[a]->table_f64;
+            prm.atm_tables64[a] = bs.atms[a]->table_f64;
+        }
         prm.evals = bs.evals;
         prm.max_iter = o.max_iter;
         prm.warm_max_iter = o.warm_max_iter;
@@ -684,6 +703,8 @@ static ff_status launch_lm(const BatchSpec& bs)
         prm.gtol = o.gtol;
         prm.kappa = o.kappa;
         prm.tau = o.tau;
+        prm.ftol_undetected = o.ftol_undetected;
+        prm.f_detect = o.f_detect;
         const int n = ModelDims<MODEL>::N;
         for (int j = 0; j < FF_MAX_STATE; ++j) {
             prm.lo[j] = j < n ? bs.prior->lo[j] : 0.0;

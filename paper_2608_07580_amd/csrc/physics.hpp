@@ -393,6 +393,48 @@ __device__ __forceinline__ R band_of(const PM& pm, const R* __restrict__ tab, in
         return pm.band(row, o, ub);
 }
 
+// Surface variables of a model: the trailing NS state variables, (rho0,
+// rho1) of the linear reflectance or the endmember fractions.
+template <int MODEL>
+struct SurfaceDims {
+    static constexpr int NS = simplex_first_v<MODEL> >= 0 ? FF_N_ENDMEMBERS : 2;
+};
+
+// Solar term of eq. (solar) at band b in FP64:
+//   L_s = K [rho_atm + tau2 rho / (1 - S rho)],
+// rho = rho0 + rho1 (lambda - 1440 nm) or sum_k x_k E_k, from the scene's
+// FP64 table (band rows, then the library rows) and the FP64 surface
+// variables sv.  1/(1 - S rho) is the FP32 reciprocal refined by one Newton
+// step (relative error ~1e-14; exactly 1 when S rho = 0).
+template <int MODEL>
+__device__ __forceinline__ double solar_fp64(const double* __restrict__ t64, int B, int b,
+                                             const double (&sv)[SurfaceDims<MODEL>::NS])
+{
+    const double* row = t64 + (size_t)b * FF_TABLE_COLS;
+    const double2 p0 = *reinterpret_cast<const double2*>(row);       // lambda, K
+    const double2 p1 = *reinterpret_cast<const double2*>(row + 2);   // tau2, tau_up
+    const double2 p2 = *reinterpret_cast<const double2*>(row + 4);   // rho_atm, S
+    double rho;
+    if constexpr (simplex_first_v<MODEL> >= 0) {
+        const double* e = t64 + (size_t)B * FF_TABLE_COLS + (size_t)b * kEndmCols;
+        const double2 e01 = *reinterpret_cast<const double2*>(e);
+        const double2 e23 = *reinterpret_cast<const double2*>(e + 2);
+        const double e4 = e[4];
+        rho = sv[0] * e01.x;
+        rho = fma(sv[1], e01.y, rho);
+        rho = fma(sv[2], e23.x, rho);
+        rho = fma(sv[3], e23.y, rho);
+        rho = fma(sv[4], e4, rho);
+    } else {
+        const double dl = row[10];
+        rho = fma(sv[1], dl, sv[0]);
+    }
+    const double den = fma(-p2.y, rho, 1.0);
+    const double r0 = (double)__builtin_amdgcn_rcpf((float)den);
+    const double rden = fma(r0, fma(-den, r0, 1.0), r0);
+    return p0.y * fma(p1.x * rho, rden, p2.x);
+}
+
 template <typename R, int Q>
 struct PixelModel<R, FF_MODEL_LOGNORMAL_2, Q> {
     static constexpr int N = 8;

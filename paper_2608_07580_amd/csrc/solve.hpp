@@ -22,6 +22,7 @@ constexpr int kMaxScenesPerLaunch = 16;
 struct SceneDev {
     const float* radiance;
     const void* table;
+    const double* table64;      // the scene's FP64 table (solar term of the residual)
     int64_t P;
     int64_t offset;
     const int64_t* index;
@@ -208,19 +209,34 @@ __device__ __forceinline__ void scan_pixel(const float* __restrict__ rad, const 
 // The L lanes of a pixel's group take bands sub, sub + L, ... and their
 // partial sums are combined across the group before the normal equations.
 // Desc provides B and the box lo, hi.
+//
+// The residual r = L_obs - L_s - L_t and the loss F = sum r^2 are formed in
+// FP64 in every kernel: the solar term L_s (eq. solar) from the FP64 table
+// and the FP64 surface variables, the thermal term L_t = f tau_up I from the
+// kernel's own (FP32 or FP64) quadrature sums.  In an FP32 kernel an FP32
+// solar term would carry ~1e-7 L of rounding per band that changes from one
+// evaluation to the next -- about 3e-5 of the noise sigma (L / 300) per
+// residual and a few 1e-6 of F -- which the gain ratio and the stop tests
+// cannot tell from progress on f = 0 background pixels.
 template <typename R, typename ACC, int MODEL, int Q, typename Desc>
 __device__ __forceinline__ double evaluate(const Desc* descp, const float* __restrict__ rad,
-                                      const R* __restrict__ tab, const double (&x)[ModelDims<MODEL>::N],
-                                      R (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
-                                      R (&g)[ModelDims<MODEL>::N], int sub, int L)
+                                      const R* __restrict__ tab, const double* __restrict__ tab64,
+                                      const double (&x)[ModelDims<MODEL>::N],
+                                      double (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
+                                      double (&g)[ModelDims<MODEL>::N], int sub, int L)
 {
     using PM = PixelModel<R, MODEL, Q>;
     constexpr int N = PM::N;
     constexpr int NT = N * (N + 1) / 2;
+    constexpr int NS = SurfaceDims<MODEL>::NS;
     const int B = launder(descp)->B;
     PM pm;
     pm.setup(x, sub, L);
-    ACC G[NT], h[N], F = (ACC)0;
+    double sv[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) sv[k] = x[N - NS + k];
+    ACC G[NT], h[N];
+    double F = 0.0;
 #pragma unroll
     for (int i = 0; i < NT; ++i) G[i] = (ACC)0;
 #pragma unroll
@@ -248,7 +264,17 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
             R ub[N];
             const R lm = band_of<MODEL>(pm, tab, B, b, o, row, ub);
             const bool msk = (R)lob < row.lsat;
-            const ACC r = msk ? (ACC)((R)lob - lm) : (ACC)0;
+            double r64;
+            if constexpr (sizeof(R) == 8) {
+                r64 = (double)lob - (double)lm;
+                (void)tab64;
+            } else {
+                (void)lm;
+                const R lt = pm.f * ub[0];
+                r64 = ((double)lob - solar_fp64<MODEL>(tab64, B, b, sv)) - (double)lt;
+            }
+            r64 = msk ? r64 : 0.0;
+            const ACC r = (ACC)r64;
             ACC ua[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) ua[i] = msk ? (ACC)ub[i] : (ACC)0;
@@ -258,7 +284,7 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
 #pragma unroll
                 for (int k = 0; k <= i; ++k) G[tri(i, k)] += ua[i] * ua[k];
             }
-            F += r * r;
+            F = fma(r64, r64, F);
         }
     }
     if (L > 1) {
@@ -278,7 +304,7 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
         const int a1 = PM::s1[i], a2 = PM::s2[i];
         double gi = c1[i] * (double)h[a1];
         if (a2 >= 0) gi += c2[i] * (double)h[a2];
-        g[i] = (R)(-dzi * gi);
+        g[i] = -dzi * gi;
 #pragma unroll
         for (int k = 0; k <= i; ++k) {
             const double dzk = 0.5 * (D->hi[k] - D->lo[k]);
@@ -287,7 +313,7 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
             if (b2 >= 0) v += c1[i] * c2[k] * (double)G[tri(a1, b2)];
             if (a2 >= 0) v += c2[i] * c1[k] * (double)G[tri(a2, b1)];
             if (a2 >= 0 && b2 >= 0) v += c2[i] * c2[k] * (double)G[tri(a2, b2)];
-            A[tri(i, k)] = (R)(dzi * dzk * v);
+            A[tri(i, k)] = dzi * dzk * v;
         }
     }
     return F;
@@ -329,7 +355,7 @@ __device__ inline void write_nan(const OutPtrs& o, int64_t pix)
 template <typename R, int MODEL, int Q, typename Desc>
 __device__ __forceinline__ unsigned write_solution(const Desc* D, const OutPtrs& o, int64_t pix,
                                                    const double (&x)[ModelDims<MODEL>::N],
-                                                   const R (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
+                                                   const double (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
                                                    double F, int nvalid)
 {
     using PM = PixelModel<R, MODEL, Q>;

@@ -51,6 +51,11 @@ def test_gauss_hermite_library_matches_oracle(L, oracle_mod):
         np.testing.assert_allclose(w, wo, rtol=1e-12)
 
 
+def oracle_options():
+    import oracle
+    return oracle.LMOptions()
+
+
 def test_default_prior_and_options(L):
     for model in (1, 2):
         p = ff.default_prior(model)
@@ -61,6 +66,9 @@ def test_default_prior_and_options(L):
     o = ff.default_options()
     assert (o.max_iter, o.n_quad, o.precision) == (50, 32, ff.PRECISION_FP32)
     assert (o.lanes_per_pixel, o.fallback, o.ftol) == (1, 1, 1e-8)
+    ora = oracle_options()
+    assert (o.ftol, o.ftol_undetected, o.f_detect, o.xtol, o.gtol, o.kappa, o.tau) == \
+        (ora.ftol, ora.ftol_undetected, ora.f_detect, ora.xtol, ora.gtol, ora.kappa, ora.tau)
     with pytest.raises(ff.FirefitError):
         ff.default_prior(7)
 

@@ -45,7 +45,7 @@ def test_retrieval_with_path_reflectance_and_spherical_albedo(dev):
     assert np.abs(r64["moments"][both, 0] - ref.moments[both, 0]).max() <= 1e-2
     r32 = _np(ff.retrieve(scene, rad, prior))
     torch.cuda.synchronize()
-    assert_parity(r32, ref, min_t=400, label="rho_atm, S")
+    assert_parity(r32, ref, tab=tab, lobs=lobs, min_t=400, label="rho_atm, S")
 
 
 def test_per_pixel_atmosphere_index(dev):
@@ -84,5 +84,5 @@ def test_per_pixel_atmosphere_index(dev):
             np.testing.assert_array_equal(r[k][m], single[k])
         ref = oracle.retrieve(tabs[a], lobs[m], 1, prior.lo, prior.hi, prior.x0)
         sub = {k: v[m] for k, v in r.items() if v is not None}
-        assert_parity(sub, ref, min_same=0.97, min_t=50, label=f"atmosphere {a}")
+        assert_parity(sub, ref, tab=tabs[a], lobs=lobs[m], min_same=0.97, min_t=50, label=f"atmosphere {a}")
     assert int(evals.item()) == int((r["iters"][~bad] + 1).sum())

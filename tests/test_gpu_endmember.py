@@ -141,7 +141,8 @@ def test_lm_parity(world, spectra, dev):
         r32 = ff.retrieve(scene, rad, prior, options=ff.default_options(lanes_per_pixel=lpp, max_iter=200)).numpy()
         torch.cuda.synchronize()
         on_simplex(r32["state"], 3e-6)
-        rep = assert_parity(r32, ref, model=MODEL, min_same=0.9, min_t=50, label=f"model 4 lanes/pixel {lpp}")
+        rep = assert_parity(r32, ref, model=MODEL, tab=tab, lobs=lobs, min_same=0.9, min_t=50,
+                            label=f"model 4 lanes/pixel {lpp}")
         assert rep["both"] >= 450
 
 

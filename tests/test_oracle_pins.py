@@ -366,12 +366,20 @@ def test_covariance_monte_carlo(oracle_mod):
 
 
 def test_stop_rule_lands_at_the_optimum(oracle_mod):
-    """The default stop tests end a noisy (SNR 300) solve where further
-    progress is far below what the data resolve: against the same solve run
-    to machine precision, the retrieved temperature of identified pixels
-    moves by < 0.1 K (the parity target is 0.5 K) and less than 1% of its
-    posterior s.d., and the relative residual by < 1e-5 (f = 0 truth
-    pixels included)."""
+    """The default stop tests end a noisy (SNR 300) solve at the optimum
+    wherever a fire is detected: against the same solve run to machine
+    precision, identified pixels (f >= 1e-4, full rank, posterior s.d. of
+    E[T] <= 100 K) end within 0.1 K and 1 % of a posterior s.d. in E[T] and
+    within 1e-3 chi^2 units of the deep loss, every pixel that holds a fire
+    of f >= 1e-4 at both ends within 1e-2 chi^2 units.  The decrease test's
+    tolerance relaxes from 1e-8 F to 1e-6 F (the resolution of an FP32
+    thermal term) only while the fitted fraction is below 1e-4, where the
+    thermal variables are not identified: a background pixel (f = 0 in
+    truth) whose noise favours a cold thermal component of f ~ 1e-6 would
+    otherwise keep lowering F along the area-temperature degeneracy for
+    hundreds of iterations; there the stop is at most 10 chi^2 units (3.5 %
+    of F) above the deep optimum and f within 1e-5 of it wherever the
+    posterior determines f."""
     tab = _scene(oracle_mod, 1, 0)
     lo, hi, x0 = scenegen.default_prior(1)
     Xf = scenegen.config0_states(200, scene=3)
@@ -381,19 +389,36 @@ def test_stop_rule_lands_at_the_optimum(oracle_mod):
     L = oracle_mod.forward(tab, X, 1)
     lobs = (L * (1 + scenegen.noise_normals(1, 9, len(X), tab.B) / 300)).astype(np.float32)
     deep = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0,
-                               opts=oracle_mod.LMOptions(max_iter=3000, ftol=1e-15, xtol=1e-12, gtol=1e-14))
+                               opts=oracle_mod.LMOptions(max_iter=3000, ftol=1e-15, ftol_undetected=1e-15,
+                                                         xtol=1e-12, gtol=1e-14))
     r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0)
+    o = oracle_mod.LMOptions()
+    assert (o.ftol, o.ftol_undetected, o.f_detect) == (1e-8, 1e-6, 1e-4)
     assert deep.converged.all()
     C = oracle_mod.unpack_cov(deep.cov, 5)
     sd_t = np.nan_to_num(np.sqrt(np.abs(C[:, 1, 1])), nan=np.inf)
+    sd_f = np.nan_to_num(np.sqrt(np.abs(C[:, 0, 0])), nan=np.inf)
     ident = ((deep.status & oracle_mod.ST_COVSING) == 0) & (deep.state[:, 0] >= 1e-4) & (sd_t <= 100)
-    ok = r.converged & ident
+    c = r.converged
+    ok = c & ident
     assert ok.sum() > 100
     dT = np.abs(r.moments[ok, 0] - deep.moments[ok, 0])
     assert dT.max() < 0.1 and np.all(dT < 0.01 * sd_t[ok])
-    c = r.converged
-    assert np.all(r.rrr[c] - deep.rrr[c] >= -1e-9) and np.all(r.rrr[c] - deep.rrr[c] < 1e-5)
-    assert c.mean() > 0.93
+    dchi = (r.rrr ** 2 - deep.rrr ** 2) / (deep.rrr ** 2 / (tab.B - 5))
+    print("chi^2 units above the deep optimum: min", dchi[c].min(), "max", dchi[c].max())
+    assert np.all(dchi[ok] < 1e-3)
+    det = c & (np.minimum(r.state[:, 0], deep.state[:, 0]) >= 1e-4)
+    assert dchi[det].max() < 1e-2
+    assert np.all(np.minimum(r.state[:, 0], deep.state[:, 0])[c & (dchi > 1e-2)] < 1e-4)
+    assert dchi[c].max() < 10.0                        # background: the noise valley
+    fdet = c & (sd_f <= 1e-3)
+    assert np.abs(r.state[fdet, 0] - deep.state[fdet, 0]).max() < 1e-5
+    assert c.mean() > 0.98
+    # with the relaxed tolerance off, the same solves need more iterations to
+    # stop and more of them end at the iteration cap
+    tight = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0, opts=oracle_mod.LMOptions(f_detect=0.0))
+    assert tight.converged.mean() < c.mean() and tight.iters.mean() > r.iters.mean()
+
 
 def test_status_edge_cases(oracle_mod):
     tab = _scene(oracle_mod)
