@@ -481,3 +481,119 @@ def test_generator_sun_and_transmittance():
     assert abs(peak - 2.8977719552e6 / 5778.0) <= 0.5
     t = scenegen.transmittance(grid, np.array([0.95] * 4))
     assert t.min() > 0.04 and t.max() <= 0.9
+
+
+# --------------------------------------------------------------------------
+# Band tables: composition of the eq. (solar) factors (Sec. 2.2) after the
+# Gaussian spectral-response resampling (Sec. 2.4)
+# --------------------------------------------------------------------------
+def _flat_atmosphere(E0, tdn, tup, ratm, s, cos_sza, n_bands=40):
+    lam = np.linspace(420.0, 2400.0, n_bands)
+    hr = np.arange(350.0, 2550.0 + 0.25, 0.5)
+    ones = np.ones_like(hr)
+    return scenegen.Atmosphere(wavelength_nm=lam, fwhm_nm=np.full(n_bands, 8.5), hr_lambda_nm=hr,
+                               e_solar=E0 * ones, tau_down=tdn * ones, tau_up=tup * ones,
+                               rho_atm=ratm * ones, s_sph=s * ones, cos_sza=cos_sza)
+
+
+def test_band_tables_flat_atmosphere_closed_form(oracle_mod):
+    """A spectrally flat atmosphere passes the responses unchanged, so each
+    band's factors are the closed form of eq. (solar): K = E cos(sza) / pi,
+    tau2 = tau_down tau_up, tau_up, rho_atm and S as given -- with
+    tau_down != tau_up and cos(sza) != 1 so a dropped 1/pi or cos(sza), or
+    the two directions swapped, shows."""
+    E0, tdn, tup, ratm, s, mu = 1.7, 0.83, 0.61, 0.031, 0.12, 0.6
+    tab = oracle_mod.band_tables(_flat_atmosphere(E0, tdn, tup, ratm, s, mu))
+    np.testing.assert_allclose(tab.K, E0 * mu / math.pi, rtol=1e-14)
+    np.testing.assert_allclose(tab.tau2, tdn * tup, rtol=1e-14)
+    np.testing.assert_allclose(tab.tup, tup, rtol=1e-14)
+    np.testing.assert_allclose(tab.ratm, ratm, rtol=1e-14)
+    np.testing.assert_allclose(tab.S, s, rtol=1e-14)
+    # and the radiance of a flat surface is eq. (solar) with those factors
+    rho = 0.27
+    L = oracle_mod.forward(tab, np.array([[0.0, 900.0, 100.0, rho, 0.0]]), 1)[0]
+    want = E0 * mu / math.pi * (ratm + tdn * tup * rho / (1.0 - s * rho))
+    np.testing.assert_allclose(L, want, rtol=1e-13)
+
+
+def test_band_tables_solar_integral(oracle_mod):
+    """The synthetic sun (a 5778 K blackbody scaled to 1361 W m^-2 over all
+    wavelengths) resampled onto 284 contiguous bands: sum_b K_b dlambda
+    equals cos(sza)/pi times the irradiance integrated over the bands' span
+    (scipy quadrature of the high-resolution spectrum) to the resolution of
+    the band sum, and the whole-spectrum integral is 1361 W m^-2."""
+    from scipy import integrate as si
+    atm = scenegen.make_atmosphere(0, 0, cos_sza=0.55)
+    tab = oracle_mod.band_tables(atm)
+    lam = tab.lam
+    dl = lam[1] - lam[0]
+    E = lambda x: float(scenegen.solar_irradiance(np.array([x]))[0])
+    span, _ = si.quad(E, lam[0] - dl / 2, lam[-1] + dl / 2, limit=400)
+    total = si.quad(E, 1.0, 1e5, limit=800, points=[300.0, 500.0, 1000.0, 3000.0])[0]
+    assert total == pytest.approx(1361.0, rel=1e-6)
+    assert (tab.K * dl).sum() == pytest.approx(0.55 / math.pi * span, rel=2e-4)
+
+
+def test_covariance_with_unidentified_columns(oracle_mod):
+    """At f = 0 the temperature columns of the Jacobian vanish: the oracle
+    reports COV_SINGULAR, NaN rows and columns for (m, s), and for (f, rho0,
+    rho1) the inverse of the reduced J^T J built here from central
+    differences of the forward model, scaled by s^2 = F / (N - n) with the
+    full state size n = 5 and mapped from z to x."""
+    tab = _scene(oracle_mod)
+    lo, hi, x0 = scenegen.default_prior(1)
+    X = scenegen.config0_states(64, scene=12)
+    X[:, 0] = 0.0
+    L = oracle_mod.forward(tab, X, 1)
+    lobs = (L * (1 + scenegen.noise_normals(0, 12, len(X), tab.B) / 300)).astype(np.float32)
+    r = oracle_mod.retrieve(tab, lobs, 1, lo, hi, x0)
+    at0 = r.converged & (r.state[:, 0] == 0.0)
+    assert at0.sum() >= 10
+    checked = 0
+    for p in np.flatnonzero(at0)[:12]:
+        assert r.status[p] & oracle_mod.ST_COVSING
+        C = oracle_mod.unpack_cov(r.cov[p:p + 1], 5)[0]
+        keep = [0, 3, 4]
+        drop = [1, 2]
+        assert np.isnan(C[drop, :]).all() and np.isnan(C[:, drop]).all()
+        x = r.state[p]
+        J = np.zeros((tab.B, 3))
+        for c, j in enumerate(keep):
+            h = 1e-6 * (hi[j] - lo[j])
+            xp, xm = x.copy(), x.copy()
+            xp[j] += h
+            xm[j] -= h
+            J[:, c] = (oracle_mod.forward(tab, xp[None], 1)[0] - oracle_mod.forward(tab, xm[None], 1)[0]) / (2 * h)
+        res = lobs[p].astype(np.float64) - oracle_mod.forward(tab, x[None], 1)[0]
+        s2 = (res @ res) / (tab.B - 5)
+        want = s2 * np.linalg.inv(J.T @ J)              # in x directly (the z scaling cancels)
+        got = C[np.ix_(keep, keep)]
+        np.testing.assert_allclose(got, want, rtol=2e-5, atol=0)
+        checked += 1
+    assert checked >= 10
+
+
+def test_band_tables_resample_each_direction_before_the_product(oracle_mod):
+    """A Gaussian absorption dip t(lam) = 1 - d exp(-(lam - c)^2 / 2w^2) in
+    both directions: a Gaussian response of s.d. sigma (FWHM 8.5 nm) turns it
+    into 1 - d w / sqrt(w^2 + sigma^2) exp(-(lam_b - c)^2 / 2(w^2 + sigma^2))
+    (the convolution of two Gaussians), and tau2 is the product of the two
+    resampled directions (the reading of eq. solar on band-averaged terms),
+    which at the dip differs from the resampled product t^2 by ~0.05."""
+    d, c, w = 0.9, 1402.3, 4.0
+    atm = _flat_atmosphere(1.0, 1.0, 1.0, 0.0, 0.0, 1.0, n_bands=300)
+    atm.wavelength_nm = np.linspace(1380.0, 1425.0, 300)
+    atm.fwhm_nm = np.full(300, 8.5)
+    t = 1.0 - d * np.exp(-0.5 * ((atm.hr_lambda_nm - c) / w) ** 2)
+    atm.tau_down = t.copy()
+    atm.tau_up = t.copy()
+    tab = oracle_mod.band_tables(atm)
+    sig = 8.5 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    v = w * w + sig * sig
+    want = 1.0 - d * w / math.sqrt(v) * np.exp(-0.5 * (tab.lam - c) ** 2 / v)
+    np.testing.assert_allclose(tab.tup, want, atol=2e-4)
+    np.testing.assert_allclose(tab.tau2, want ** 2, atol=4e-4)
+    v2 = w * w / 2.0 + sig * sig                     # the resampled product, for contrast
+    prod = 1.0 - 2 * d * w / math.sqrt(v) * np.exp(-0.5 * (tab.lam - c) ** 2 / v) \
+        + d * d * (w / math.sqrt(2.0)) / math.sqrt(v2) * np.exp(-0.5 * (tab.lam - c) ** 2 / v2)
+    assert np.abs(prod - want ** 2).max() > 0.04
