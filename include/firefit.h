@@ -43,6 +43,9 @@
  *  - P = 0 is a valid no-op.
  *  - Calls on different streams may run concurrently; one scene handle may
  *    be used by several streams at once (it is read-only after creation).
+ *    Exceptions: calls that use one warm-start network (ff_mlp_*) share its
+ *    activation workspace and must be ordered on one stream, and
+ *    ff_retrieve_batch_noalloc calls on one device share its fixed array.
  */
 #ifndef FIREFIT_H
 #define FIREFIT_H
@@ -554,7 +557,9 @@ ff_status ff_mlp_fit_normalization(ff_mlp* mlp, const float* radiance_dev, int64
                                    void* stream);
 
 /* Warm start: z0_dev [P][n_out] = network(radiance_dev [P][n_in]).
- * Asynchronous on stream; internal activations are processed in chunks. */
+ * Asynchronous on stream; internal activations are processed in chunks in
+ * the network's one workspace (the handle is const but the workspace is
+ * not): calls with one network must be ordered on one stream. */
 ff_status ff_mlp_infer(const ff_mlp* mlp, const float* radiance_dev, int64_t P, float* z0_dev,
                        void* stream);
 
@@ -602,6 +607,38 @@ ff_status ff_mlp_train(ff_mlp* mlp, const ff_scene* scene, const ff_prior* prior
                        int32_t batch, uint64_t seed, double snr, double bg_fraction, float lr,
                        float lr_final, double* loss_history_dev, void* stream);
 
+/* Steps first_step .. first_step + n_steps - 1 of the same schedule of
+ * total_steps steps (ff_mlp_train is the span 0 .. steps - 1): step i
+ * trains on the samples offset i * batch of the seed's counter-based
+ * stream (Philox4x32-10) at the cosine learning rate of step i, so a run
+ * split into spans -- across a checkpoint written by ff_warmstart_save and
+ * read by ff_warmstart_load -- takes exactly the uninterrupted run's
+ * steps.  loss_history_dev [n_steps] or NULL.  Asynchronous on stream.
+ * FF_EINVAL unless 0 <= first_step <= first_step + n_steps <= total_steps. */
+ff_status ff_mlp_train_span(ff_mlp* mlp, const ff_scene* scene, const ff_prior* prior, int64_t total_steps,
+                            int64_t first_step, int64_t n_steps, int32_t batch, uint64_t seed, double snr,
+                            double bg_fraction, float lr, float lr_final, double* loss_history_dev,
+                            void* stream);
+
+/* Schedule steps the network has taken in ff_mlp_train / ff_mlp_train_span
+ * (restored by ff_warmstart_load): the first_step of a resumed span. */
+int64_t ff_mlp_steps_done(const ff_mlp* mlp);
+
+/* The layer sizes (n_in, h1, h2, h3, n_out) into sizes_host[5]. */
+ff_status ff_mlp_sizes(const ff_mlp* mlp, int32_t* sizes_host);
+
+/* Checkpoints of a warm-start network (the learned start of the LM,
+ * trained by the update of Sec. 2.5 eq. adam): ff_warmstart_save writes the
+ * layer sizes, the FP32 master weights, the normalisation, the Adam first
+ * and second moments, the Adam step count and the schedule steps taken to
+ * path (a host file; synchronizes the network's device first);
+ * ff_warmstart_load creates a network on the current device from such a
+ * file (caller destroys it with ff_mlp_destroy).  A run resumed from a
+ * checkpoint with ff_mlp_train_span continues bitwise as the uninterrupted
+ * run.  FF_EINVAL for a missing, foreign, truncated or inconsistent file. */
+ff_status ff_warmstart_save(const ff_mlp* mlp, const char* path);
+ff_status ff_warmstart_load(const char* path, ff_mlp** out);
+
 /* ------------------------------------------------------------------------
  * Graph-captured pipeline.  The launch sequence of one batch shape --
  * network inference of z0 for every scene that has a network (mlps: NULL,
@@ -634,7 +671,8 @@ void ff_pipeline_destroy(ff_pipeline* pipeline);
 /* Retrieval launches use a library-owned scratch buffer per (device,
  * stream) that only grows (so that repeated calls allocate nothing and can
  * be captured); this frees them all after synchronizing each device that
- * holds one.  Call only when no library work is in flight.  Destroy a
+ * holds one, except the buffers of live pipelines' private streams (their
+ * graphs bind them; ff_pipeline_destroy frees them).  Call only when no library work is in flight.  Destroy a
  * stream only after its retrieval work has completed: a new stream that
  * receives the same handle reuses the buffer. */
 ff_status ff_release_scratch(void);

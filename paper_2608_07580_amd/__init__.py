@@ -52,7 +52,8 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_pipeline_destroy", "ff_release_scratch", "ff_adam_options_default", "ff_adam_retrieve_batch",
            "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec",
            "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_tune_quadrature",
-           "ff_retrieve_batch_noalloc")
+           "ff_retrieve_batch_noalloc", "ff_mlp_train_span", "ff_mlp_steps_done", "ff_warmstart_save",
+           "ff_warmstart_load", "ff_mlp_sizes")
 
 
 class FirefitError(RuntimeError):
@@ -176,6 +177,13 @@ def lib():
                                       C.c_double, vp, vp, vp, vp]
         L.ff_mlp_train.argtypes = [vp, vp, C.POINTER(ffPrior), C.c_int64, C.c_int32, C.c_uint64, C.c_double,
                                    C.c_double, C.c_float, C.c_float, vp, vp]
+        L.ff_mlp_train_span.argtypes = [vp, vp, C.POINTER(ffPrior), C.c_int64, C.c_int64, C.c_int64, C.c_int32,
+                                        C.c_uint64, C.c_double, C.c_double, C.c_float, C.c_float, vp, vp]
+        L.ff_mlp_steps_done.argtypes = [vp]
+        L.ff_mlp_steps_done.restype = C.c_int64
+        L.ff_warmstart_save.argtypes = [vp, C.c_char_p]
+        L.ff_warmstart_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+        L.ff_mlp_sizes.argtypes = [vp, C.POINTER(C.c_int32)]
         L.ff_pipeline_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32,
                                          C.POINTER(ffPrior), C.POINTER(vp), C.POINTER(ffOptions),
                                          C.POINTER(ffOutputs), vp, vp, C.POINTER(vp)]
@@ -207,7 +215,8 @@ def lib():
                      "ff_prior_default", "ff_tune",
                      "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
                      "ff_mlp_get_normalization", "ff_mlp_fit_normalization", "ff_mlp_infer",
-                     "ff_mlp_infer_listed", "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train"):
+                     "ff_mlp_infer_listed", "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train",
+                     "ff_mlp_train_span", "ff_warmstart_save", "ff_warmstart_load", "ff_mlp_sizes"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -708,9 +717,13 @@ def generate(scene: Scene, prior: Prior, seed: int, offset: int, P: int, snr: fl
 class WarmStart:
     """The warm-start network (ff_mlp) on the current device."""
 
-    def __init__(self, n_in: int = 284, hidden=(512, 512, 256), n_out: int = 5, seed: int = 0):
+    def __init__(self, n_in: int = 284, hidden=(512, 512, 256), n_out: int = 5, seed: int = 0, _handle=None):
         h = C.c_void_p()
-        _check(lib().ff_mlp_create(n_in, hidden[0], hidden[1], hidden[2], n_out, seed, C.byref(h)), "ff_mlp_create")
+        if _handle is None:
+            _check(lib().ff_mlp_create(n_in, hidden[0], hidden[1], hidden[2], n_out, seed, C.byref(h)),
+                   "ff_mlp_create")
+        else:
+            h = _handle
         self.handle = h
         self.sizes = (n_in, hidden[0], hidden[1], hidden[2], n_out)
         self.n_params = int(lib().ff_mlp_n_params(h))
@@ -813,32 +826,42 @@ class WarmStart:
         return loss
 
     def train(self, scene: Scene, prior: Prior, steps: int, batch: int = 2048, seed: int = 1, snr: float = 300.0,
-              bg_fraction: float = 0.0, lr: float = 1e-3, lr_final: float = 1e-5, stream=None, device=None):
+              bg_fraction: float = 0.0, lr: float = 1e-3, lr_final: float = 1e-5, stream=None, device=None,
+              first_step: int = 0, n_steps: int | None = None):
+        """Steps [first_step, first_step + n_steps) of a schedule of `steps`
+        steps (ff_mlp_train_span; default: the whole schedule)."""
         torch = _torch()
         device = device or torch.device("cuda:0")
-        hist = torch.zeros(steps, dtype=torch.float64, device=device)
+        n_steps = steps - first_step if n_steps is None else n_steps
+        hist = torch.zeros(max(n_steps, 1), dtype=torch.float64, device=device)
         pc = prior.to_c()
-        _check(lib().ff_mlp_train(self.handle, scene.handle, C.byref(pc), steps, batch, seed, snr, bg_fraction, lr,
-                                  lr_final, _ptr(hist), _stream_handle(stream)), "ff_mlp_train")
+        _check(lib().ff_mlp_train_span(self.handle, scene.handle, C.byref(pc), steps, first_step, n_steps, batch,
+                                       seed, snr, bg_fraction, lr, lr_final, _ptr(hist), _stream_handle(stream)),
+               "ff_mlp_train_span")
         # the kernels still write hist after this returns: keep it alive even
         # if the caller drops it (its block must not be handed out to a
         # tensor used on another stream meanwhile)
         self._pending = hist
         return hist
 
+    @property
+    def steps_done(self) -> int:
+        """Schedule steps taken (the first_step of a resumed run)."""
+        return int(lib().ff_mlp_steps_done(self.handle))
+
     def save(self, path: str):
-        mean, inv, fl = self.get_normalization()
-        np.savez(path, params=self.get_params(), mean=mean, inv_std=inv, floor=np.float32(fl),
-                 sizes=np.array(self.sizes))
+        """Checkpoint (ff_warmstart_save): weights, normalisation, Adam
+        moments and step counts."""
+        _check(lib().ff_warmstart_save(self.handle, os.fsencode(path)), "ff_warmstart_save")
 
     @classmethod
     def load(cls, path: str):
-        d = np.load(path, allow_pickle=False)
-        sz = [int(x) for x in d["sizes"]]
-        w = cls(sz[0], tuple(sz[1:4]), sz[4])
-        w.set_params(d["params"])
-        w.set_normalization(d["mean"], d["inv_std"], float(d["floor"]))
-        return w
+        """A network from a checkpoint written by save (ff_warmstart_load)."""
+        h = C.c_void_p()
+        _check(lib().ff_warmstart_load(os.fsencode(path), C.byref(h)), "ff_warmstart_load")
+        sz = (C.c_int32 * 5)()
+        _check(lib().ff_mlp_sizes(h, sz), "ff_mlp_sizes")
+        return cls(sz[0], (sz[1], sz[2], sz[3]), sz[4], _handle=h)
 
 
 class Pipeline:

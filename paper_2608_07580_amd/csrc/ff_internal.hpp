@@ -129,6 +129,7 @@ ff_status dispatch_adam(const AdamSpec& as);
 ff_status stream_scratch(hipStream_t stream, size_t bytes, void** out);
 bool stream_capturing(hipStream_t stream);
 void release_stream_scratch(hipStream_t stream);
+void pin_stream_scratch(hipStream_t stream);
 
 // Input and output widths of a warm-start network; pin/unpin its activation
 // workspace (while pinned, a grown workspace keeps the old buffers alive for

@@ -10,6 +10,8 @@
 //    Moraes, Dror & Shaw 2011) of one-component states, the forward model of
 //    physics.hpp and Box-Muller noise.
 #include <cmath>
+#include <string>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -613,18 +615,35 @@ __global__ void output_listed_kernel(const float* __restrict__ Y, const int64_t*
 }
 
 // out[n] = sum_m D[m][n] for n < N (bias gradients)
-__global__ void colsum_kernel(const __bf16* __restrict__ D, int64_t M, int N, int ld, float* __restrict__ out)
+// Column sums of D [M][N] (the bias gradients), in two deterministic passes
+// that fill the chip: partial sums of 64-row chunks, one workgroup per
+// (64 columns, chunk), then the chunks summed in order per column.
+constexpr int kColChunk = 64;
+
+__global__ void __launch_bounds__(256)
+colsum_part_kernel(const __bf16* __restrict__ D, int64_t M, int N, int ld, float* __restrict__ part)
 {
     const int col = blockIdx.x * 64 + (threadIdx.x & 63);
     const int grp = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * kColChunk;
     float s = 0.f;
     if (col < N)
-        for (int64_t m = grp; m < M; m += 4) s += (float)D[m * ld + col];
+        for (int64_t m = r0 + grp; m < M && m < r0 + kColChunk; m += 4) s += (float)D[m * ld + col];
     __shared__ float red[4][64];
     red[grp][threadIdx.x & 63] = s;
     __syncthreads();
     if (grp == 0 && col < N)
-        out[col] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        part[(int64_t)blockIdx.y * N + col] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ part, int chunks, int N, float* __restrict__ out)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= N) return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * N + col];
+    out[col] = s;
 }
 
 struct LayerMap {
@@ -711,14 +730,23 @@ struct GenArgs {
     double bg;
 };
 
-// Training spectra: one lane per sample (one-component model, FP32 forward).
+// Training spectra (one-component model, FP32 forward), eight bands per
+// lane: the lanes of an aligned quad share one sample -- they draw the same
+// state, compute a quarter of its node temperatures each and gather them
+// with DPP -- so a batch of 2,048 samples is 73,728 lanes instead of 2,048.
+constexpr int kGenBands = 8;
+
+inline int gen_chunks(int B) { return (((B + kGenBands - 1) / kGenBands) + 3) / 4 * 4; }
+
 template <int Q>
 __global__ void __launch_bounds__(256)
-generate_kernel(const float* __restrict__ tab, int B, int64_t P, GenArgs ga, float* __restrict__ rad,
+generate_kernel(const float* __restrict__ tab, int B, int64_t P, int chunks, GenArgs ga, float* __restrict__ rad,
                 float* __restrict__ target, float* __restrict__ state)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P * chunks) return;            // whole quads: P * chunks is a multiple of four
+    const int64_t p = t / chunks;
+    const int q = (int)(t - p * chunks);
     const uint64_t g = ga.offset + (uint64_t)p;
     const uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
     const U32x4 r0 = philox4x32_10(glo, ghi, 0u, 0u, ga.k0, ga.k1);
@@ -735,18 +763,21 @@ generate_kernel(const float* __restrict__ tab, int B, int64_t P, GenArgs ga, flo
         x[1] = ga.x0[1];
         x[2] = ga.x0[2];
     }
+    if (q == 0) {
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        const double z = 2.0 * (x[j] - ga.lo[j]) / (ga.hi[j] - ga.lo[j]) - 1.0;
-        target[p * 5 + j] = (float)fmin(1.0, fmax(-1.0, z));
-        if (state) state[p * 5 + j] = (float)x[j];
+        for (int j = 0; j < 5; ++j) {
+            const double z = 2.0 * (x[j] - ga.lo[j]) / (ga.hi[j] - ga.lo[j]) - 1.0;
+            target[p * 5 + j] = (float)fmin(1.0, fmax(-1.0, z));
+            if (state) state[p * 5 + j] = (float)x[j];
+        }
     }
     PixelModel<float, FF_MODEL_LOGNORMAL_1, Q> pm;
-    pm.setup(x);
+    pm.setup(x, (int)(threadIdx.x & 63), 4);
     const bool noisy = ga.snr > 0.0;
     const float inv_snr = noisy ? (float)(1.0 / ga.snr) : 0.f;
     float nz[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < B; ++b) {
+    const int b0 = q * kGenBands;
+    for (int b = b0; b < b0 + kGenBands && b < B; ++b) {
         if (noisy && (b & 3) == 0) {
             // four normals per Philox block: Box-Muller on (x0, x1) and (x2, x3)
             const U32x4 rn = philox4x32_10(glo, ghi, 2u + (uint32_t)(b >> 2), 0u, ga.k0, ga.k1);
@@ -792,7 +823,8 @@ struct ff_mlp {
     float* mean = nullptr;
     float* inv_std = nullptr;
     float floor_v = 1e-6f;
-    int64_t step = 0;
+    int64_t step = 0;                 // Adam updates taken (bias correction of eq. adam)
+    int64_t train_steps = 0;          // schedule steps taken by ff_mlp_train / ff_mlp_train_span
     int64_t ws_rows = 0;
     __bf16* X = nullptr;
     float* H[3] = {nullptr, nullptr, nullptr};
@@ -800,6 +832,7 @@ struct ff_mlp {
     float* Y = nullptr;
     __bf16* dY = nullptr;
     __bf16* dH[3] = {nullptr, nullptr, nullptr};
+    float* part = nullptr;            // column-sum partials [rows / 64][1024]
     int pins = 0;                     // graphs that bind the workspace (see ff_pipeline_create)
     std::vector<void*> retired;       // workspace buffers replaced while pinned, freed at destroy
 };
@@ -810,14 +843,14 @@ namespace {
 // it -- kept until the network is destroyed.
 void free_ws(ff_mlp* m)
 {
-    void* bufs[12] = {m->X, m->H[0], m->H[1], m->H[2], m->A[0], m->A[1], m->A[2],
-                      m->dH[0], m->dH[1], m->dH[2], m->Y, m->dY};
+    void* bufs[13] = {m->X, m->H[0], m->H[1], m->H[2], m->A[0], m->A[1], m->A[2],
+                      m->dH[0], m->dH[1], m->dH[2], m->Y, m->dY, m->part};
     for (void* b : bufs) {
         if (!b) continue;
         if (m->pins > 0) m->retired.push_back(b);
         else (void)hipFree(b);
     }
-    m->X = nullptr; m->Y = nullptr; m->dY = nullptr;
+    m->X = nullptr; m->Y = nullptr; m->dY = nullptr; m->part = nullptr;
     for (int i = 0; i < 3; ++i) { m->H[i] = nullptr; m->A[i] = nullptr; m->dH[i] = nullptr; }
     m->ws_rows = 0;
 }
@@ -841,6 +874,7 @@ ff_status ensure_ws(ff_mlp* m, int64_t rows, hipStream_t stream)
     }
     if (e == hipSuccess) e = hipMalloc(&m->Y, (size_t)R * 16 * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&m->dY, (size_t)R * 16 * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMalloc(&m->part, (size_t)(R / kColChunk) * 1024 * sizeof(float));
     if (e != hipSuccess) {
         free_ws(m);
         return hip_error(e, "mlp workspace");
@@ -894,6 +928,14 @@ void forward_rows(const ff_mlp* m, int64_t R, bool keep_h, hipStream_t s)
                                       m->h[2], ep, s);
 }
 
+void colsum(ff_mlp* m, const __bf16* D, int64_t R, int N, int ld, float* out, hipStream_t s)
+{
+    const int chunks = (int)cdiv(R, kColChunk);
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((unsigned)cdiv(N, 64), (unsigned)chunks), dim3(256), 0, s, D, R, N,
+                       ld, m->part);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, m->part, chunks, N, out);
+}
+
 // backward pass of R rows: dY in m->dY -> all gradients into m->grads
 void backward_rows(ff_mlp* m, int64_t R, hipStream_t s)
 {
@@ -904,8 +946,7 @@ void backward_rows(ff_mlp* m, int64_t R, hipStream_t s)
     // output layer
     gemm<true, false, EPI_F32>(m->n_out, h3, 16, h3, r, m->dY, 16, m->A[2], h3,
                                EpiArgs{nullptr, gw + mp.off_w[3], h3, nullptr, 0, nullptr, 0}, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cdiv(m->n_out, 64)), dim3(256), 0, s, m->dY, R, m->n_out, 16,
-                       gw + mp.off_b[3]);
+    colsum(m, m->dY, R, m->n_out, 16, gw + mp.off_b[3], s);
     gemm<false, false, EPI_BWD_GELU>(r, h3, r, h3, 16, m->dY, 16, m->wb + mp.off_wb[3], h3,
                                      EpiArgs{nullptr, nullptr, 0, m->dH[2], h3, m->H[2], h3}, s);
     // hidden layers 3, 2, 1
@@ -917,8 +958,7 @@ void backward_rows(ff_mlp* m, int64_t R, hipStream_t s)
         const __bf16* xin = l == 0 ? m->X : m->A[l - 1];
         gemm<true, false, EPI_F32>(nout, nin, nout, nin_pad, r, m->dH[l], nout, xin, nin_pad,
                                    EpiArgs{nullptr, gw + mp.off_w[l], nin, nullptr, 0, nullptr, 0}, s);
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)cdiv(nout, 64)), dim3(256), 0, s, m->dH[l], R, nout, nout,
-                           gw + mp.off_b[l]);
+        colsum(m, m->dH[l], R, nout, nout, gw + mp.off_b[l], s);
         if (l > 0)
             gemm<false, false, EPI_BWD_GELU>(r, nin, r, nin, nout, m->dH[l], nout, m->wb + mp.off_wb[l], nin_pad,
                                              EpiArgs{nullptr, nullptr, 0, m->dH[l - 1], nin, m->H[l - 1], nin}, s);
@@ -1208,9 +1248,42 @@ extern "C" ff_status ff_mlp_generate(const ff_scene* sc, const ff_prior* prior, 
     int dev = 0;
     FF_HIP_TRY(hipGetDevice(&dev));
     if (!ensure_quad<float, 32>(dev)) return set_error(FF_EDEVICE, "quadrature rule could not be placed on the device");
-    hipLaunchKernelGGL(generate_kernel<32>, dim3((unsigned)cdiv(P, 256)), dim3(256), 0, (hipStream_t)stream,
-                       sc->table_f32, sc->n_bands, P, ga, rad, target, state);
+    const int chunks = gen_chunks(sc->n_bands);
+    if (P * chunks / 256 + 1 > 0x7fffffff) return set_error(FF_EINVAL, "ff_mlp_generate: P too large");
+    hipLaunchKernelGGL(generate_kernel<32>, dim3((unsigned)cdiv(P * chunks, 256)), dim3(256), 0, (hipStream_t)stream,
+                       sc->table_f32, sc->n_bands, P, chunks, ga, rad, target, state);
     FF_HIP_TRY(hipGetLastError());
+    return clear_error();
+}
+
+extern "C" ff_status ff_mlp_train_span(ff_mlp* m, const ff_scene* sc, const ff_prior* prior, int64_t total_steps,
+                                       int64_t first_step, int64_t n_steps, int32_t batch, uint64_t seed, double snr,
+                                       double bg, float lr, float lr_final, double* loss_hist, void* stream)
+{
+    if (check_mlp(m, "ff_mlp_train_span")) return FF_EINVAL;
+    if (!sc || sc->n_bands != m->n_in) return set_error(FF_EINVAL, "ff_mlp_train_span: scene band count != n_in");
+    if (total_steps < 0 || first_step < 0 || n_steps < 0 || first_step + n_steps > total_steps || batch <= 0 ||
+        batch > 65536)
+        return set_error(FF_EINVAL, "ff_mlp_train_span: need 0 <= first_step <= first_step + n_steps <= total_steps "
+                                    "and 0 < batch <= 65536");
+    const int64_t steps = total_steps;
+    hipStream_t s = (hipStream_t)stream;
+    float* rad = nullptr;
+    float* tgt = nullptr;
+    FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&rad), (size_t)batch * m->n_in * sizeof(float), s));
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tgt), (size_t)batch * 5 * sizeof(float), s);
+    ff_status st = e == hipSuccess ? FF_OK : hip_error(e, "ff_mlp_train");
+    for (int64_t i = first_step; i < first_step + n_steps && st == FF_OK; ++i) {
+        const double c = steps > 1 ? 0.5 * (1.0 + std::cos(M_PI * (double)i / (double)(steps - 1))) : 1.0;
+        const float lr_i = (float)(lr_final + (lr - lr_final) * c);
+        st = ff_mlp_generate(sc, prior, seed, (uint64_t)i * (uint64_t)batch, batch, snr, bg, rad, tgt, nullptr, s);
+        if (st == FF_OK)
+            st = ff_mlp_train_step(m, rad, tgt, batch, lr_i, loss_hist ? loss_hist + (i - first_step) : nullptr, s);
+        if (st == FF_OK) m->train_steps = i + 1;
+    }
+    hipFreeAsync(rad, s);
+    hipFreeAsync(tgt, s);
+    if (st != FF_OK) return st;
     return clear_error();
 }
 
@@ -1218,23 +1291,100 @@ extern "C" ff_status ff_mlp_train(ff_mlp* m, const ff_scene* sc, const ff_prior*
                                   uint64_t seed, double snr, double bg, float lr, float lr_final,
                                   double* loss_hist, void* stream)
 {
-    if (check_mlp(m, "ff_mlp_train")) return FF_EINVAL;
-    if (!sc || sc->n_bands != m->n_in) return set_error(FF_EINVAL, "ff_mlp_train: scene band count != n_in");
-    if (steps < 0 || batch <= 0 || batch > 65536) return set_error(FF_EINVAL, "ff_mlp_train: bad steps/batch");
-    hipStream_t s = (hipStream_t)stream;
-    float* rad = nullptr;
-    float* tgt = nullptr;
-    FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&rad), (size_t)batch * m->n_in * sizeof(float), s));
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tgt), (size_t)batch * 5 * sizeof(float), s);
-    ff_status st = e == hipSuccess ? FF_OK : hip_error(e, "ff_mlp_train");
-    for (int64_t i = 0; i < steps && st == FF_OK; ++i) {
-        const double c = steps > 1 ? 0.5 * (1.0 + std::cos(M_PI * (double)i / (double)(steps - 1))) : 1.0;
-        const float lr_i = (float)(lr_final + (lr - lr_final) * c);
-        st = ff_mlp_generate(sc, prior, seed, (uint64_t)i * (uint64_t)batch, batch, snr, bg, rad, tgt, nullptr, s);
-        if (st == FF_OK) st = ff_mlp_train_step(m, rad, tgt, batch, lr_i, loss_hist ? loss_hist + i : nullptr, s);
+    return ff_mlp_train_span(m, sc, prior, steps, 0, steps, batch, seed, snr, bg, lr, lr_final, loss_hist, stream);
+}
+
+extern "C" int64_t ff_mlp_steps_done(const ff_mlp* m) { return m ? m->train_steps : -1; }
+
+extern "C" ff_status ff_mlp_sizes(const ff_mlp* m, int32_t* sizes_host)
+{
+    if (check_mlp(m, "ff_mlp_sizes") || !sizes_host) return set_error(FF_EINVAL, "ff_mlp_sizes: NULL argument");
+    sizes_host[0] = m->n_in;
+    for (int i = 0; i < 3; ++i) sizes_host[1 + i] = m->h[i];
+    sizes_host[4] = m->n_out;
+    return clear_error();
+}
+
+// ---------------------------------------------------------------- checkpoints
+// File layout (little-endian): "FFWS" magic, u32 version 1, i32 n_in, h1,
+// h2, h3, n_out, f32 floor, i64 Adam step, i64 schedule steps, i64 n_params,
+// then f32 params, Adam first and second moments [n_params] each, mean and
+// inv_std [n_in].  The BF16 copies are rebuilt from the FP32 master weights.
+namespace {
+constexpr char kMagic[4] = {'F', 'F', 'W', 'S'};
+constexpr uint32_t kVersion = 1;
+}  // namespace
+
+extern "C" ff_status ff_warmstart_save(const ff_mlp* m, const char* path)
+{
+    if (check_mlp(m, "ff_warmstart_save") || !path) return set_error(FF_EINVAL, "ff_warmstart_save: NULL argument");
+    FF_HIP_TRY(hipSetDevice(m->device));
+    FF_HIP_TRY(hipDeviceSynchronize());
+    const size_t np = (size_t)m->n_params;
+    std::vector<float> buf(3 * np + 2 * (size_t)m->n_in);
+    FF_HIP_TRY(hipMemcpy(buf.data(), m->params, np * sizeof(float), hipMemcpyDeviceToHost));
+    FF_HIP_TRY(hipMemcpy(buf.data() + np, m->adam_m, np * sizeof(float), hipMemcpyDeviceToHost));
+    FF_HIP_TRY(hipMemcpy(buf.data() + 2 * np, m->adam_v, np * sizeof(float), hipMemcpyDeviceToHost));
+    FF_HIP_TRY(hipMemcpy(buf.data() + 3 * np, m->mean, m->n_in * sizeof(float), hipMemcpyDeviceToHost));
+    FF_HIP_TRY(hipMemcpy(buf.data() + 3 * np + m->n_in, m->inv_std, m->n_in * sizeof(float), hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return set_error(FF_EINVAL, std::string("ff_warmstart_save: cannot open ") + path);
+    const int32_t dims[5] = {m->n_in, m->h[0], m->h[1], m->h[2], m->n_out};
+    const int64_t counts[3] = {m->step, m->train_steps, m->n_params};
+    bool ok = std::fwrite(kMagic, 1, 4, f) == 4 && std::fwrite(&kVersion, 4, 1, f) == 1 &&
+              std::fwrite(dims, 4, 5, f) == 5 && std::fwrite(&m->floor_v, 4, 1, f) == 1 &&
+              std::fwrite(counts, 8, 3, f) == 3 && std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return set_error(FF_EDEVICE, std::string("ff_warmstart_save: write failed: ") + path);
+    return clear_error();
+}
+
+extern "C" ff_status ff_warmstart_load(const char* path, ff_mlp** out)
+{
+    if (!path || !out) return set_error(FF_EINVAL, "ff_warmstart_load: NULL argument");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_error(FF_EINVAL, std::string("ff_warmstart_load: cannot open ") + path);
+    char magic[4];
+    uint32_t version = 0;
+    int32_t dims[5];
+    float floor_v = 0.f;
+    int64_t counts[3];
+    bool ok = std::fread(magic, 1, 4, f) == 4 && std::memcmp(magic, kMagic, 4) == 0 &&
+              std::fread(&version, 4, 1, f) == 1 && version == kVersion && std::fread(dims, 4, 5, f) == 5 &&
+              std::fread(&floor_v, 4, 1, f) == 1 && std::fread(counts, 8, 3, f) == 3;
+    if (!ok) {
+        std::fclose(f);
+        return set_error(FF_EINVAL, std::string("ff_warmstart_load: not a warm-start checkpoint: ") + path);
     }
-    hipFreeAsync(rad, s);
-    hipFreeAsync(tgt, s);
-    if (st != FF_OK) return st;
+    ff_mlp* m = nullptr;
+    ff_status st = ff_mlp_create(dims[0], dims[1], dims[2], dims[3], dims[4], 0, &m);
+    if (st != FF_OK) {
+        std::fclose(f);
+        return st;
+    }
+    const size_t np = (size_t)m->n_params;
+    std::vector<float> buf(3 * np + 2 * (size_t)m->n_in);
+    ok = counts[2] == m->n_params && counts[0] >= 0 && counts[1] >= 0 &&
+         std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) {
+        ff_mlp_destroy(m);
+        return set_error(FF_EINVAL, std::string("ff_warmstart_load: truncated or inconsistent checkpoint: ") + path);
+    }
+    st = ff_mlp_set_params(m, buf.data());          // rebuilds the BF16 copies, clears Adam
+    if (st == FF_OK) st = ff_mlp_set_normalization(m, buf.data() + 3 * np, buf.data() + 3 * np + m->n_in, floor_v);
+    if (st == FF_OK) {
+        hipError_t e = hipMemcpy(m->adam_m, buf.data() + np, np * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->adam_v, buf.data() + 2 * np, np * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = hip_error(e, "ff_warmstart_load");
+    }
+    if (st != FF_OK) {
+        ff_mlp_destroy(m);
+        return st;
+    }
+    m->step = counts[0];
+    m->train_steps = counts[1];
+    *out = m;
     return clear_error();
 }

@@ -116,6 +116,7 @@ extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const flo
         release(p);
         return st;
     }
+    pin_stream_scratch(s);               // the graph below binds this buffer
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         release(p);

@@ -21,6 +21,7 @@ namespace {
 struct Buf {
     void* ptr = nullptr;
     size_t bytes = 0;
+    bool pinned = false;   // bound by an instantiated graph: never freed by ff_release_scratch
 };
 
 std::mutex g_mutex;
@@ -69,6 +70,18 @@ ff_status stream_scratch(hipStream_t stream, size_t bytes, void** out)
 
 namespace ff {
 
+// Keep the buffer of one stream for as long as its owner lives: a pipeline's
+// graph binds the buffer of its private stream, so ff_release_scratch must
+// not free it (release_stream_scratch, called by the owner, still does).
+void pin_stream_scratch(hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_mutex);
+    auto it = table().find({dev, stream});
+    if (it != table().end()) it->second.pinned = true;
+}
+
 // Drop the buffer of one stream (the stream must still exist: it is
 // synchronized first).  Used by objects that own a private stream.
 void release_stream_scratch(hipStream_t stream)
@@ -98,13 +111,17 @@ extern "C" ff_status ff_release_scratch(void)
         (void)hipSetDevice(d);
         (void)hipDeviceSynchronize();
     }
-    for (auto& kv : ff::table()) {
-        if (kv.second.ptr) {
-            (void)hipSetDevice(kv.first.first);
-            (void)hipFree(kv.second.ptr);
+    for (auto it = ff::table().begin(); it != ff::table().end();) {
+        if (it->second.pinned) {           // a live pipeline's graph binds it
+            ++it;
+            continue;
         }
+        if (it->second.ptr) {
+            (void)hipSetDevice(it->first.first);
+            (void)hipFree(it->second.ptr);
+        }
+        it = ff::table().erase(it);
     }
-    ff::table().clear();
     (void)hipSetDevice(cur);
     return ff::clear_error();
 }

@@ -177,3 +177,23 @@ def test_front_end_rejects_bad_arguments_on_the_host(L):
     # the network on listed rows: a NULL network is refused before any launch
     assert L.ff_mlp_infer_listed(None, one, 4, one, 2, one, None) == ff.FF_EINVAL
     assert "NULL network" in L.ff_last_error().decode()
+
+
+def test_checkpoint_errors_on_the_host(L, tmp_path):
+    """ff_warmstart_load refuses a missing or foreign file before touching a
+    device; NULL arguments are refused."""
+    h = C.c_void_p()
+    assert L.ff_warmstart_load(str(tmp_path / "none.ffws").encode(), C.byref(h)) == ff.FF_EINVAL
+    bad = tmp_path / "bad.ffws"
+    bad.write_bytes(b"NOPE" + bytes(64))
+    assert L.ff_warmstart_load(str(bad).encode(), C.byref(h)) == ff.FF_EINVAL
+    assert "not a warm-start checkpoint" in L.ff_last_error().decode()
+    trunc = tmp_path / "trunc.ffws"
+    trunc.write_bytes(b"FFWS" + (1).to_bytes(4, "little"))
+    assert L.ff_warmstart_load(str(trunc).encode(), C.byref(h)) == ff.FF_EINVAL
+    assert L.ff_warmstart_load(None, C.byref(h)) == ff.FF_EINVAL
+    assert L.ff_warmstart_save(None, str(bad).encode()) == ff.FF_EINVAL
+    assert L.ff_mlp_steps_done(None) == -1
+    pr = ff.default_prior(1).to_c()
+    assert L.ff_mlp_train_span(None, None, C.byref(pr), 10, 0, 10, 64, 1, 300.0, 0.0, 1e-3, 1e-5, None,
+                               None) == ff.FF_EINVAL

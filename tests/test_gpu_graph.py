@@ -118,3 +118,27 @@ def test_release_scratch_then_retrieve_again():
     torch.cuda.synchronize()
     for k in KEYS:
         np.testing.assert_array_equal(a.numpy()[k], b.numpy()[k])
+
+
+def test_release_scratch_keeps_a_live_pipelines_buffer():
+    """ff_release_scratch frees the per-stream buffers but not the one a live
+    pipeline's graph binds: replays after the release still match the eager
+    result bitwise."""
+    dev = torch.device("cuda:0")
+    scenes, rads = _batch(dev, sizes=(50, 7))
+    prior = ff.default_prior(1)
+    stream = torch.cuda.Stream(device=dev)
+    pipe = ff.Pipeline(scenes, rads, prior, options=ff.default_options(lanes_per_pixel=2), stream=stream)
+    torch.cuda.synchronize()
+    ref = [o.numpy() for o in pipe.outputs]
+    assert ff.lib().ff_release_scratch() == ff.FF_OK
+    for o in pipe.outputs:
+        o.state.fill_(-3.0)
+    torch.cuda.synchronize()
+    pipe.launch(stream)
+    torch.cuda.synchronize()
+    for o, r in zip(pipe.outputs, ref):
+        o = o.numpy()
+        for k in KEYS:
+            np.testing.assert_array_equal(o[k], r[k], err_msg=k)
+    pipe.close()

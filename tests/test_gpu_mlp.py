@@ -343,3 +343,44 @@ def test_warm_start_on_clustered_fire_scene(dev):
     ref = oracle.retrieve(tab, lobs[sel], 1, lo, hi, x0)
     sub = {k: v[sel] for k, v in warm.items() if v is not None}
     assert_parity(sub, ref, tab=tab, lobs=lobs[sel], min_same=0.97, label="warm start, clustered-fire scene")
+
+
+def test_checkpoint_resume_is_bitwise(world, dev, tmp_path):
+    """Training is deterministic, and a run saved halfway (weights,
+    normalisation, Adam moments and step counts: ff_warmstart_save),
+    reloaded (ff_warmstart_load) and continued with the second span of the
+    same schedule ends bitwise equal to the uninterrupted run."""
+    tab, scene, prior = world
+    total, half, batch = 240, 110, 512
+
+    def fresh():
+        n = ff.WarmStart(seed=3)
+        n.fit_normalization(ff.generate(scene, prior, 77, 0, 4096, bg_fraction=0.3)[0])
+        return n
+
+    a = fresh()
+    a.train(scene, prior, steps=total, batch=batch, seed=5, bg_fraction=0.3)
+    torch.cuda.synchronize()
+    b = fresh()
+    b.train(scene, prior, steps=total, batch=batch, seed=5, bg_fraction=0.3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.get_params(), b.get_params())
+    c = fresh()
+    c.train(scene, prior, steps=total, batch=batch, seed=5, bg_fraction=0.3, n_steps=half)
+    torch.cuda.synchronize()
+    assert c.steps_done == half
+    path = str(tmp_path / "half.ffws")
+    c.save(path)
+    c.close()
+    d = ff.WarmStart.load(path)
+    assert d.sizes == a.sizes and d.steps_done == half
+    d.train(scene, prior, steps=total, batch=batch, seed=5, bg_fraction=0.3, first_step=d.steps_done)
+    torch.cuda.synchronize()
+    assert d.steps_done == total
+    np.testing.assert_array_equal(d.get_params(), a.get_params())
+    for x, y in zip(d.get_normalization(), a.get_normalization()):
+        np.testing.assert_array_equal(x, y)
+    # and the resumed network infers the same starts
+    X = scenegen.config0_states(256, scene=9)
+    rad = torch.from_numpy(noisy_spectra(tab, X, 1, 0, 9)).to(dev)
+    np.testing.assert_array_equal(d.infer(rad).cpu().numpy(), a.infer(rad).cpu().numpy())
