@@ -28,17 +28,22 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# Roofline of the dominant kernel: FP32 VALU issue slots.  MI355X: 256 CUs x
-# 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s without packed
-# FP32 (packed FP32 is not used).  v_exp_f32 / v_rcp_f32 issue at half rate
-# (2 slots) and do not overlap other VALU work (measured), everything else
-# 1 slot.
-PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# Roofline of the dominant kernel: FP32 vector ALU.  MI355X's published FP32
+# vector peak is 157.3 TFLOP/s = 78.6e12 FMA lanes/s (256 CUs x 4 SIMDs x 32
+# lanes x 2.4 GHz).  Instructions are weighted by their issue cost in FMA
+# equivalents as measured on this GPU by ff_valu_rates (bench.py --workload
+# valu-rates; profiles/valu_rates_mi355x.md): a 32-bit FMA or other simple
+# FP32 op 1, exp2 3.29, rcp 3.33, an FP64 FMA/add/mul 1.92, a float<->double
+# conversion 1.68.  (The same run measures a 32-bit FMA at 60.7e12 lanes/s
+# without packed instructions, 77 % of the published peak.)
+PEAK_FMA32 = 256 * 4 * 32 * 2.4e9
+MEASURED_FMA32 = 60.7e12
+UNIT_FMA = "T FP32-FMA-equivalent lane-ops/s"
+OP_FMA = "issue cost in 32-bit FMA equivalents (measured: exp2 3.29, rcp 3.33, FP64 op 1.92, conversion 1.68)"
+W_EXP2, W_RCP, W_F64, W_CVT = 3.29, 3.33, 1.92, 1.68
 HBM_PEAK = 8.0e12
-# MI355X's published FP32 vector peak (packed FMA counted as 4 flops per lane
-# and cycle) and the non-packed rate (FMA = 2 flops per lane and cycle)
+# MI355X's published FP32 vector peak in flops (an FMA is 2)
 PEAK_FP32_PUBLISHED = 157.3e12
-PEAK_FP32_UNPACKED = 78.6e12
 
 # HBM bytes per launch of the retrieval kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled by what the
@@ -47,8 +52,8 @@ PEAK_FP32_UNPACKED = 78.6e12
 # kernel sources with the SHA-1 below; any other source reports null.
 TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
                    "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
-TRAFFIC_SHA1 = "14e68515d305087764b6fd5c10ee6f554c3a0544"
-TRAFFIC_BYTES = {"plain": 73.10e9, "warm": 71.54e9}
+TRAFFIC_SHA1 = "0befb7eeb3c04855a606cda0fa885145e909dcc2"
+TRAFFIC_BYTES = {"plain": 92.22e9, "warm": 90.39e9}
 
 
 def measured_traffic(leg: str):
@@ -60,26 +65,30 @@ def measured_traffic(leg: str):
     return TRAFFIC_BYTES[leg] if h.hexdigest() == TRAFFIC_SHA1 else None
 
 
-# Per band and pixel the FP64 residual adds 17 FP64 or conversion
-# instructions (rho, 1 - S rho, the refined reciprocal, the solar term, the
-# residual, F += r^2, the FP32 copy of r) and drops the FP32 solar term's 5.
-RESIDUAL64_SLOTS = 17 - 5
+# Issue cost of one Planck node (x = a u, 2^x - 1, three FMAs and one product
+# for the three quadrature sums, the exponential and the reciprocal) and of
+# the FP64 residual per band and pixel (ten FP64 operations for rho, 1 - S rho,
+# the Newton step of the reciprocal, the solar term, the residual and
+# F += r^2, four conversions and the reciprocal seed, less the FP32 solar
+# term's 5), in 32-bit FMA equivalents.
+NODE_W = 7 + W_EXP2 + W_RCP
+RESIDUAL64_W = 10 * W_F64 + 4 * W_CVT + W_RCP - 5
 
 
-def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> int:
-    """Algorithmic VALU slots of one model+Jacobian+reduction evaluation of one
-    pixel: per (band, node) 7 VALU (x = a u, 2^x - 1, three FMAs and one
-    product for the three quadrature sums) + 2 transcendentals (exp2, rcp; 2
-    slots each) = 11; per band and component 5 slots of scaling plus 19
-    (n=5) / 49 (n=8) for the solar term, basis, residual and the J^T J, J^T r,
-    r.r accumulations, and the FP64 residual's RESIDUAL64_SLOTS."""
+def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> float:
+    """Issue cost, in 32-bit FMA equivalents, of one model + Jacobian +
+    reduction evaluation of one pixel: NODE_W per (band, node) and component;
+    per band and component 5 for the scaling (one of them the reciprocal of
+    1 - S rho, counted as simple here), plus 19 (n = 5) / 49 (n = 8) for the
+    solar term, basis, residual and the J^T J, J^T r, r.r accumulations, and
+    the FP64 residual's RESIDUAL64_W."""
     if model == 4:
         # one component; the endmember surface: 5 FMAs for rho and 5 basis
         # products where the linear surface has 2 and 2 (25), and the n = 8
         # accumulations (45)
-        return n_bands * (11 * n_quad + 5 + 25 + 45 + RESIDUAL64_SLOTS + 4)
+        return n_bands * (NODE_W * n_quad + 5 + 25 + 45 + RESIDUAL64_W + 4)
     comps = 1 if model == 1 else 2
-    per_band = comps * (11 * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45) + RESIDUAL64_SLOTS
+    per_band = comps * (NODE_W * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45) + RESIDUAL64_W
     return n_bands * per_band
 
 
@@ -270,6 +279,21 @@ def run_leg(args, atm, rad, stream, net):
     return leg, res, int(evals.item()) / args.steps
 
 
+def run_valu_rates(args):
+    """ff_valu_rates on this GPU: each instruction's sustained lane rate and
+    its weight in issue slots (the 32-bit FMA rate is one slot)."""
+    import torch
+    import paper_2608_07580_amd as ff
+    torch.cuda.init()
+    rates = ff.valu_rates()
+    fma = rates["fma_f32"]
+    out = {"workload": "valu-rates", "lane_ops_per_s": rates,
+           "slots": {k: fma / v for k, v in rates.items()},
+           "fma_f32_frac_of_published_peak": fma / PEAK_FMA32,
+           "published_fma_lanes_per_s": PEAK_FMA32}
+    print(json.dumps(out), flush=True)
+
+
 def make_ragged_workload(args, dev):
     """Sixteen scenes of log-uniform size on four atmospheres; the four
     smallest are 15 x 15 footprint averages of a finer truth.  Radiance by the
@@ -421,10 +445,10 @@ def run_ragged(args):
                                f"log-uniform in [10k, 2.5M], 4 scenes 15x15 footprint averages of a finer "
                                f"truth), network warm start per atmosphere + LM, one graph launch per batch",
                    "pixels": P_tot, "scenes": len(layout), "bands": B, "n_quad": args.n_quad},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tops/s",
-                     "frac": achieved / PEAK_SLOTS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA32 / 1e12, "unit": UNIT_FMA,
+                     "frac": achieved / PEAK_FMA32, "traffic": None,
                      "kernel": "whole graph (network + lm_kernel)", "kernel_ms": w["graph_ms_per_step"],
-                     "op": "FP32 VALU issue slot per lane (transcendental = 2)", "ops_per_eval": spe,
+                     "op": OP_FMA, "ops_per_eval": spe,
                      "evals_per_launch": w["evals"]},
         "warm_start": w, "plain_lm": legs["plain"],
         "eager_batch_ms": eager_ms, "sequential_scene_sum_ms": seq_ms, "per_scene": per_scene,
@@ -530,13 +554,13 @@ def run_precision(args):
 
 
 def adam_slots_per_pixel(lam, stages, n_bands: int, n_quad: int) -> int:
-    """Algorithmic VALU slots of one pixel's staged-Adam solve (one component):
-    per step and band inside the union of the free variables' windows, the
-    thermal quadrature (11 per node + 5), 19 for the solar term, basis and
+    """Issue cost, in 32-bit FMA equivalents, of one pixel's staged-Adam solve
+    (one component): per step and band inside the union of the free
+    variables' windows, the thermal quadrature (NODE_W per node + 5), 19 for the solar term, basis and
     residual, and 12 for the windowed gradient sums (7 products into the
     per-variable sums, 5 window selects); then one full evaluation with the
     normal equations for the outputs (slots_per_eval)."""
-    per_band = 11 * n_quad + 5 + 19 + 12
+    per_band = NODE_W * n_quad + 5 + 19 + 12
     total = 0
     for st in stages:
         lo = min(st["window"][j][0] for j in st["free"])
@@ -652,8 +676,8 @@ def run_solvers(args):
         "adam": {"ms_per_step": ms_ad, "pixels_per_s": P / (ms_ad * 1e-3), "steps_per_pixel": 130,
                  "lanes_per_pixel": args.adam_lpp,
                  "accuracy": accuracy(r_ad["state"], r_ad["moments"], r_ad["rrr"], X),
-                 "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                              "unit": "Tops/s", "frac": achieved / PEAK_SLOTS, "kernel": "adam_kernel",
+                 "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA32 / 1e12,
+                              "unit": UNIT_FMA, "frac": achieved / PEAK_FMA32, "kernel": "adam_kernel",
                               "ops_per_pixel": spp}},
         "oracle_sample": {"pixels": len(idx), "cores": cores, "lm_s": t_olm, "adam_s": t_oad,
                           "lm": accuracy(o_lm.state, o_lm.moments, o_lm.rrr, X[idx]),
@@ -666,15 +690,16 @@ def run_solvers(args):
 
 def grid_slots_per_eval(n_bands: int, n_nodes: int, model: int = 3) -> int:
     """Algorithmic VALU slots of one evaluation of the Gaussian-mixture model
-    on the temperature grid: per (band, node) one Planck ratio shared by the
-    two components (x = a2/T: 1, exp2: 2, minus 1: 1, rcp: 2) and 7 per
+    on the temperature grid, in 32-bit FMA equivalents: per (band, node) one
+    Planck ratio shared by the two components (x = a2/T, exp2, minus 1, rcp)
+    and 7 per
     component for its weight product and the three centred sums; per band 25
     for the scaling, solar term, basis and residual and 45 for the J^T J,
     J^T r, r.r accumulations (n = 8).  The full model (endmember surface,
     n = 11) adds 6 for the five-term reflectance and basis and accumulates
     78."""
     per_band = 25 + 45 if model == 3 else 25 + 6 + 78
-    return n_bands * (n_nodes * (6 + 2 * 7) + per_band)
+    return n_bands * (n_nodes * (2 + W_EXP2 + W_RCP + 2 * 7) + per_band)
 
 
 def run_paper_model(args, model: int = 3):
@@ -779,8 +804,8 @@ def run_paper_model(args, model: int = 3):
         "lm": {"ms_per_step": ms_lm, "converged": conv, "converged_per_s": conv / (ms_lm * 1e-3),
                "evals_per_pixel": ev / P, "accuracy": acc(r_lm),
                "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
-               "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tops/s",
-                            "frac": achieved / PEAK_SLOTS, "kernel": "lm_kernel", "ops_per_eval": spe}},
+               "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA32 / 1e12, "unit": UNIT_FMA,
+                            "frac": achieved / PEAK_FMA32, "kernel": "lm_kernel", "ops_per_eval": spe}},
         "adam": {"ms_per_step": ms_ad, "pixels_per_s": P / (ms_ad * 1e-3), "accuracy": acc(r_ad)},
         "oracle_sample": {"pixels": len(idx), "s": t_or, "converged": int(ref.converged.sum()),
                           "gpu_lm_vs_oracle": {k: v for k, v in rep.items() if not k.endswith("_mask")}},
@@ -878,8 +903,8 @@ def run_endmember(args):
         "lm": {"ms_per_step": ms_lm, "converged": conv, "converged_per_s": conv / (ms_lm * 1e-3),
                "evals_per_pixel": ev / P, "accuracy": acc(r_lm),
                "launch": {"lanes_per_pixel": opts.lanes_per_pixel, "block_size": opts.block_size},
-               "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tops/s",
-                            "frac": achieved / PEAK_SLOTS, "kernel": "lm_kernel", "ops_per_eval": spe}},
+               "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA32 / 1e12, "unit": UNIT_FMA,
+                            "frac": achieved / PEAK_FMA32, "kernel": "lm_kernel", "ops_per_eval": spe}},
         "adam": {"ms_per_step": ms_ad, "pixels_per_s": P / (ms_ad * 1e-3), "accuracy": acc(r_ad)},
         "oracle_sample": {"pixels": len(idx), "s": t_or, "converged": int(ref.converged.sum()),
                           "gpu_lm_vs_oracle": {k: v for k, v in rep.items() if not k.endswith("_mask")}},
@@ -1125,7 +1150,8 @@ def main():
     ap.add_argument("--grid-max-iter", type=int, default=200, help="paper-model workload: LM iteration cap")
     ap.add_argument("--block", type=int, default=12, help="coarsening workload: block side")
     ap.add_argument("--workload", choices=("clustered-fire", "ragged", "precision", "solvers", "front-end",
-                                           "paper-model", "full-model", "endmember-surface", "coarsening"),
+                                           "paper-model", "full-model", "endmember-surface", "coarsening",
+                                           "valu-rates"),
                     default="clustered-fire",
                     help="clustered-fire: the 2.53M-pixel scene (headline); ragged: 16-scene batch; "
                          "precision: FP32/FP64 variants on the two-component stress set; "
@@ -1154,6 +1180,9 @@ def main():
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "valu-rates":
+        run_valu_rates(args)
+        return
     if args.workload == "ragged":
         run_ragged(args)
         return
@@ -1249,17 +1278,17 @@ def main():
                                f"3% fire, SNR {args.snr:g}; {start_desc}",
                    "pixels": P, "bands": B, "n_quad": args.n_quad, "precision": "fp32-bulk/fp64-solve",
                    "start": args.start},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(args.start),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA32 / 1e12,
+                     "unit": UNIT_FMA, "frac": achieved / PEAK_FMA32,
+                     "traffic": measured_traffic(args.start),
                      "traffic_unit": "HBM bytes per launch (calibrated TCC FETCH_SIZE + WRITE_SIZE)",
                      "kernel": "lm_kernel", "kernel_ms": head["lm_kernel_ms"],
-                     "op": "VALU issue slot per lane (transcendental = 2)",
+                     "op": OP_FMA,
                      "ops_per_eval": spe, "evals_per_launch": ev_head,
+                     "frac_of_measured_fma_rate": achieved / MEASURED_FMA32,
                      "flops_per_eval": fpe, "achieved_TFLOPs": flops / 1e12,
                      "frac_published": flops / PEAK_FP32_PUBLISHED,
-                     "frac_unpacked": flops / PEAK_FP32_UNPACKED,
-                     "peaks_TFLOPs": {"published_fp32": PEAK_FP32_PUBLISHED / 1e12,
-                                      "unpacked_fp32": PEAK_FP32_UNPACKED / 1e12}},
+                     "peak_published_TFLOPs": PEAK_FP32_PUBLISHED / 1e12},
         "plain_lm": plain,
         "warm_start": warm,
         "h2d": h2d_info,

@@ -668,6 +668,16 @@ ff_status ff_pipeline_launch(ff_pipeline* pipeline, void* stream);
 const float* ff_pipeline_z0(const ff_pipeline* pipeline);   /* [sum P][n], scene after scene */
 void ff_pipeline_destroy(ff_pipeline* pipeline);
 
+/* Vector-ALU calibration of the current device: sustained lane-operations
+ * per second, in rates_host[0..5], of a 32-bit FMA, the 32-bit base-2
+ * exponential, the 32-bit reciprocal, a 64-bit FMA, a float <-> double
+ * conversion, and one quadrature node of the Planck sums (x = a u,
+ * 1/(2^x - 1), three accumulations: 7 VALU + 2 transcendentals), each over
+ * eight independent chains per lane on a grid that fills every SIMD.  They
+ * weigh the instructions of the retrieval's issue-slot roofline.
+ * Synchronous (allocates and frees two small buffers); n_rates >= 6. */
+ff_status ff_valu_rates(double* rates_host, int32_t n_rates, void* stream);
+
 /* Retrieval launches use a library-owned scratch buffer per (device,
  * stream) that only grows (so that repeated calls allocate nothing and can
  * be captured); this frees them all after synchronizing each device that

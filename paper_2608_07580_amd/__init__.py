@@ -53,7 +53,7 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec",
            "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_tune_quadrature",
            "ff_retrieve_batch_noalloc", "ff_mlp_train_span", "ff_mlp_steps_done", "ff_warmstart_save",
-           "ff_warmstart_load", "ff_mlp_sizes")
+           "ff_warmstart_load", "ff_mlp_sizes", "ff_valu_rates")
 
 
 class FirefitError(RuntimeError):
@@ -184,6 +184,7 @@ def lib():
         L.ff_warmstart_save.argtypes = [vp, C.c_char_p]
         L.ff_warmstart_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.ff_mlp_sizes.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.ff_valu_rates.argtypes = [_dp, C.c_int32, vp]
         L.ff_pipeline_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32,
                                          C.POINTER(ffPrior), C.POINTER(vp), C.POINTER(ffOptions),
                                          C.POINTER(ffOutputs), vp, vp, C.POINTER(vp)]
@@ -216,7 +217,8 @@ def lib():
                      "ff_mlp_create", "ff_mlp_get_params", "ff_mlp_set_params", "ff_mlp_set_normalization",
                      "ff_mlp_get_normalization", "ff_mlp_fit_normalization", "ff_mlp_infer",
                      "ff_mlp_infer_listed", "ff_mlp_gradients", "ff_mlp_train_step", "ff_mlp_generate", "ff_mlp_train",
-                     "ff_mlp_train_span", "ff_warmstart_save", "ff_warmstart_load", "ff_mlp_sizes"):
+                     "ff_mlp_train_span", "ff_warmstart_save", "ff_warmstart_load", "ff_mlp_sizes",
+                     "ff_valu_rates"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -226,6 +228,16 @@ def _check(rc: int, what: str):
     if rc != FF_OK:
         msg = lib().ff_last_error().decode()
         raise FirefitError(f"{what}: {lib().ff_status_string(rc).decode()} ({rc}): {msg}")
+
+
+VALU_RATE_NAMES = ("fma_f32", "exp2_f32", "rcp_f32", "fma_f64", "cvt_f32_f64", "planck_node")
+
+
+def valu_rates(stream=None) -> dict:
+    """ff_valu_rates: sustained lane-operations per second on the current device."""
+    r = np.zeros(6)
+    _check(lib().ff_valu_rates(r.ctypes.data_as(_dp), 6, _stream_handle(stream)), "ff_valu_rates")
+    return dict(zip(VALU_RATE_NAMES, r.tolist()))
 
 
 def version() -> str:
