@@ -78,7 +78,7 @@ def test_resolution_rescaling_analysis_matches_the_oracle(dev):
     move the tails of a footprint's distribution.)  A footprint's fine set can
     still differ by a pixel whose solve converged on one side only; on the
     coarse pixels whose fine sets have the same size the curves agree within
-    1 K at the 95th percentile and on average."""
+    0.1 K everywhere (measured 1e-3 K)."""
     rows = cols = 96
     block = 12
     atm = scenegen.make_atmosphere(1, 2)
@@ -119,6 +119,4 @@ def test_resolution_rescaling_analysis_matches_the_oracle(dev):
     print(f"same-set pixels: empirical p95 {np.percentile(de, 95):.3f} max {de.max():.3f}; "
           f"mixture p95 {np.percentile(dm, 95):.3f} max {dm.max():.3f}")
     assert both.sum() >= 0.9 * max(gv.sum(), valid.sum()) and eq.sum() >= 0.75 * both.sum() and eq.sum() >= 15
-    assert np.percentile(de, 95) <= 1.0 and np.percentile(dm, 95) <= 1.0
-    np.testing.assert_allclose(emp[eq].mean(0), emp_ref[eq].mean(0), atol=1.0)
-    np.testing.assert_allclose(mix[eq].mean(0), mix_ref[eq].mean(0), atol=1.0)
+    assert de.max() <= 0.1 and dm.max() <= 0.1

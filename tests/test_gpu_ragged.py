@@ -51,7 +51,11 @@ def test_ragged_batch_with_footprint_averaged_scene():
         if spec["block"] > 1:
             print(f"\n  footprint-averaged scene: {mask.sum()} of {len(mask)} coarse px hold fire; "
                   f"oracle converged {ref.converged.mean():.3f}")
-        assert_parity(g, ref, tab=tab, lobs=lobs, min_same=0.95, min_t=0, label=f"scene {spec['scene']} block {spec['block']}")
+        # temperatures compared on the footprint-averaged scene and the large
+        # one (the three-pixel scene holds no identified fire)
+        min_t = 20 if spec["block"] > 1 else (100 if len(lobs) > 100 else 0)
+        assert_parity(g, ref, tab=tab, lobs=lobs, min_same=0.99, min_t=min_t,
+                      label=f"scene {spec['scene']} block {spec['block']}")
     # one graph replay of the same batch equals the eager batch
     stream = torch.cuda.Stream(device=dev)
     pipe = ff.Pipeline(scenes, rads, prior, options=opts, stream=stream)
