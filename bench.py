@@ -75,9 +75,17 @@ NODE_W = 7 + W_EXP2 + W_RCP
 RESIDUAL64_W = 10 * W_F64 + 4 * W_CVT + W_RCP - 5
 
 
+def nodes_evaluated(n_quad: int) -> int:
+    """Nodes of the Q-node Gauss-Hermite rule the FP32 lognormal sums
+    evaluate: the coldest nodes, whose weights are below 2^-36 of the largest,
+    contribute less than the sums' FP32 rounding and are left out (4 of 32,
+    2 of 24)."""
+    return n_quad - {32: 4, 24: 2}.get(n_quad, 0)
+
+
 def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> float:
     """Issue cost, in 32-bit FMA equivalents, of one model + Jacobian +
-    reduction evaluation of one pixel: NODE_W per (band, node) and component;
+    reduction evaluation of one pixel: NODE_W per (band, evaluated node) and component;
     per band and component 5 for the scaling (one of them the reciprocal of
     1 - S rho, counted as simple here), plus 19 (n = 5) / 49 (n = 8) for the
     solar term, basis, residual and the J^T J, J^T r, r.r accumulations, and
@@ -86,19 +94,19 @@ def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> float:
         # one component; the endmember surface: 5 FMAs for rho and 5 basis
         # products where the linear surface has 2 and 2 (25), and the n = 8
         # accumulations (45)
-        return n_bands * (NODE_W * n_quad + 5 + 25 + 45 + RESIDUAL64_W + 4)
+        return n_bands * (NODE_W * nodes_evaluated(n_quad) + 5 + 25 + 45 + RESIDUAL64_W + 4)
     comps = 1 if model == 1 else 2
-    per_band = comps * (NODE_W * n_quad + 5) + (19 + 21 if model == 1 else 49 + 45) + RESIDUAL64_W
+    per_band = comps * (NODE_W * nodes_evaluated(n_quad) + 5) + (19 + 21 if model == 1 else 49 + 45) + RESIDUAL64_W
     return n_bands * per_band
 
 
 def flops_per_eval(n_bands: int, n_quad: int) -> int:
     """Floating-point operations of one evaluation of the one-component model
-    (FMA = 2, exp2 and rcp = 1 each): per (band, node) x = a u (1), 2^x (1),
+    (FMA = 2, exp2 and rcp = 1 each): per (band, evaluated node) x = a u (1), 2^x (1),
     - 1 (1), rcp (1), three FMAs and q q + q (8), x (...) (1) = 13; per band
     72 for the reflectance, the basis, the FP64 solar term and residual and
     the J^T J, J^T r, r.r accumulations."""
-    return n_bands * (13 * n_quad + 72)
+    return n_bands * (13 * nodes_evaluated(n_quad) + 72)
 
 
 def log(*a):
@@ -560,7 +568,7 @@ def adam_slots_per_pixel(lam, stages, n_bands: int, n_quad: int) -> int:
     residual, and 12 for the windowed gradient sums (7 products into the
     per-variable sums, 5 window selects); then one full evaluation with the
     normal equations for the outputs (slots_per_eval)."""
-    per_band = NODE_W * n_quad + 5 + 19 + 12
+    per_band = NODE_W * nodes_evaluated(n_quad) + 5 + 19 + 12
     total = 0
     for st in stages:
         lo = min(st["window"][j][0] for j in st["free"])

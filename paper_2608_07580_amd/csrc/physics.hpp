@@ -16,6 +16,7 @@
 // and the reciprocal returns the exact limit 0.
 #pragma once
 
+#include <algorithm>
 #include <mutex>
 
 #include "ff_internal.hpp"
@@ -83,8 +84,26 @@ __device__ inline LogNormal lognormal(double m, double s)
     return r;
 }
 
+// Cold-end nodes left out of the FP32 quadrature sums.  The rule's nodes are
+// in ascending abscissa, so node k < c (c the largest weight) is colder than
+// node c: x_k > x_c.  q(x) = 1/(2^x - 1) and y(x) = x q (1 + q) both fall
+// strictly with x (dy/dx = y/x (1 - z coth(z/2)), z = x ln 2, and
+// z coth(z/2) >= 2), so w_k q_k <= (w_k / w_c) w_c q_c and w_k y_k <=
+// (w_k / w_c) w_c y_c, and |v_k| y_k <= |s_k| (w_k / w_c) w_c y_c with
+// |s_k| < 11.  The first kColdSkip nodes have w_k / w_c < 2^-36 (checked on
+// the host when the rule is built): leaving them out changes sI and sM by
+// less than 2^-34 of themselves and sS by less than 2^-29 of sM's scale, below
+// the rounding of an FP32 sum.  The FP64 sums keep every node.
+template <int Q>
+constexpr int kColdSkip = Q >= 32 ? 4 : (Q >= 24 ? 2 : 0);
+constexpr double kColdSkipRatio = 1.4551915228366852e-11;   // 2^-36
+
+template <typename R, int Q>
+constexpr int cold_skip_v = sizeof(R) == 4 ? kColdSkip<Q> : 0;
+
 // Inverse node temperatures u_k = 1 / T_k = exp(-mu - sqrt2 x_k sig), formed
-// in FP64 and rounded once to R.
+// in FP64 and rounded once to R (the FP32 rule's skipped cold nodes are not
+// formed).
 template <typename R, int Q>
 __device__ inline void node_inverse_temperatures(const LogNormal& ln, R (&u)[Q])
 {
@@ -94,7 +113,9 @@ __device__ inline void node_inverse_temperatures(const LogNormal& ln, R (&u)[Q])
     const int o = opaque_zero();
     double mu = ln.mu;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
+    for (int k = 0; k < cold_skip_v<R, Q>; ++k) u[k] = (R)0;
+#pragma unroll
+    for (int k = cold_skip_v<R, Q>; k < Q; ++k) {
         u[k] = (R)exp(-mu - (double)c_quad<R, Q>.s[k + o] * ln.sig);
         asm volatile("" : "+v"(mu) : "v"(u[k]));
     }
@@ -106,7 +127,8 @@ __device__ inline void node_inverse_temperatures(const LogNormal& ln, R (&u)[Q])
 //   I = cb sI,  dI/dmu = cj sM,  dI/dsig = cj sS.
 // FP32: q = e/(1-e) is taken as 1/(2^x2 - 1): for x2 > 128 the power is +inf
 // and the reciprocal returns the exact limit 0, so no overflow handling is
-// needed; 2 transcendental (exp2, rcp) + 7 VALU per node.
+// needed; 2 transcendental (exp2, rcp) + 7 VALU per node.  The first
+// kColdSkip<Q> nodes are left out (bound above).
 template <int Q>
 __device__ __forceinline__ void thermal_sums(float a2, const float (&u)[Q], int o,
                                              float& sI, float& sM, float& sS)
@@ -120,8 +142,9 @@ __device__ __forceinline__ void thermal_sums(float a2, const float (&u)[Q], int 
     const Quad<float, Q>& qd = c_quad<float, Q>;
     float i0 = 0.f, m0 = 0.f, s0 = 0.f;
     float a = a2;
+    constexpr int k0 = kColdSkip<Q>;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
+    for (int k = k0; k < Q; ++k) {
         const float x = a * u[k];
         const float q = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x) - 1.0f);
         const float wk = qd.w[k + o], vk = qd.v[k + o];
@@ -129,7 +152,7 @@ __device__ __forceinline__ void thermal_sums(float a2, const float (&u)[Q], int 
         const float y = x * __builtin_fmaf(q, q, q);   // x q (1 + q) = x e / (1 - e)^2
         m0 = __builtin_fmaf(wk, y, m0);
         s0 = __builtin_fmaf(vk, y, s0);
-        if ((k + 1) % kGroup == 0) asm volatile("" : "+v"(a) : "v"(i0), "v"(m0), "v"(s0));
+        if ((k + 1 - k0) % kGroup == 0) asm volatile("" : "+v"(a) : "v"(i0), "v"(m0), "v"(s0));
     }
     sI = i0;
     sM = m0;
@@ -258,8 +281,11 @@ __device__ inline void node_inverse_temperatures_split(const LogNormal& ln, R (&
     static_assert(Q % G == 0, "node count must divide among the group");
     const int o = opaque_zero();
     double mu = ln.mu;
+    constexpr int j0 = cold_skip_v<R, Q> / G;
 #pragma unroll
-    for (int j = 0; j < Q / G; ++j) {
+    for (int k = 0; k < j0 * G; ++k) u[k] = (R)0;
+#pragma unroll
+    for (int j = j0; j < Q / G; ++j) {
         double sk = (double)c_quad<R, Q>.s[j * G + o];
 #pragma unroll
         for (int m = 1; m < G; ++m) sk = sub == m ? (double)c_quad<R, Q>.s[j * G + m + o] : sk;
@@ -784,6 +810,12 @@ const Quad<R, Q>* cached_quad()
     std::call_once(once, [] {
         if constexpr (sizeof(R) == 4) ok = make_quad_f32(Q, q.w, q.v, q.s);
         else ok = make_quad_f64(Q, q.w, q.v, q.s);
+        // the FP32 sums leave out the cold-end nodes: their weights must be
+        // below 2^-36 of the largest, in ascending abscissa
+        double wmax = 0.0;
+        for (int k = 0; k < Q; ++k) wmax = std::max(wmax, (double)q.w[k]);
+        for (int k = 0; ok && k < cold_skip_v<R, Q>; ++k)
+            ok = (double)q.w[k] <= kColdSkipRatio * wmax && q.s[k] < q.s[k + 1];
     });
     return ok ? &q : nullptr;
 }
