@@ -1,0 +1,62 @@
+"""The FP32 lognormal sums leave the coldest Gauss-Hermite nodes out (4 of 32,
+2 of 24).  Host-side checks of the bound that justifies it: the left-out
+weights are below 2^-36 of the largest, and over the prior box and the
+284-band range the three node sums change by far less than an FP32 ulp when
+those nodes are dropped (sums taken in FP64 here)."""
+import numpy as np
+import pytest
+
+import paper_2608_07580_amd as ff
+
+SKIP = {32: 4, 24: 2, 16: 0}
+C2_LOG2 = 14387.768775039337 / np.log(2.0)     # second radiation constant (um K), in log2 units
+
+
+def _rule(q):
+    x, w = ff.gauss_hermite(q)
+    x = np.asarray(x, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64) / np.sqrt(np.pi)
+    return np.sqrt(2.0) * x, w
+
+
+@pytest.mark.parametrize("q", [16, 24, 32])
+def test_left_out_weights_are_below_two_to_minus_36(q):
+    s, w = _rule(q)
+    assert np.all(np.diff(s) > 0)                  # ascending: the first nodes are the coldest
+    k0 = SKIP[q]
+    assert np.all(w[:k0] <= 2.0 ** -36 * w.max())
+    if k0 < q:
+        assert w[k0] > 2.0 ** -36 * w.max()        # the cut is the largest one the bound allows
+
+
+def _sums(a2, u, w, v):
+    x = a2 * u
+    with np.errstate(over="ignore"):
+        q = 1.0 / np.expm1(x * np.log(2.0))
+    y = x * q * (1.0 + q)
+    return np.array([np.sum(w * q), np.sum(w * y), np.sum(v * y)]), np.sum(w * y)
+
+
+@pytest.mark.parametrize("q", [24, 32])
+def test_dropping_cold_nodes_is_below_fp32_rounding(q):
+    s, w = _rule(q)
+    v = s * w
+    k0 = SKIP[q]
+    lam = np.linspace(0.38, 2.51, 60)
+    worst = 0.0
+    for m in np.linspace(350.0, 2200.0, 9):
+        for sd in (1.0, 5.0, 30.0, 100.0, 250.0, 500.0):
+            sig = np.sqrt(np.log1p(sd * sd / (m * m)))
+            mu = np.log(m) - 0.5 * sig * sig
+            u = np.exp(-mu - s * sig)
+            for lm in lam:
+                a2 = C2_LOG2 / lm
+                full, scale = _sums(a2, u, w, v)
+                part, _ = _sums(a2, u[k0:], w[k0:], v[k0:])
+                if scale == 0.0:
+                    continue
+                # sI and sM relative to themselves, sS relative to sM's scale
+                rel = np.abs(full - part) / np.array([full[0], full[1], scale])
+                worst = max(worst, float(rel.max()))
+    print(f"\n  Q={q}: largest change {worst:.2e} (2^{np.log2(worst) if worst > 0 else -np.inf:.1f})")
+    assert worst < 2.0 ** -29, worst
