@@ -77,10 +77,10 @@ RESIDUAL64_W = 10 * W_F64 + 4 * W_CVT + W_RCP - 5
 
 def nodes_evaluated(n_quad: int) -> int:
     """Nodes of the Q-node Gauss-Hermite rule the FP32 lognormal sums
-    evaluate: the coldest nodes, whose weights are below 2^-36 of the largest,
-    contribute less than the sums' FP32 rounding and are left out (4 of 32,
+    evaluate: the coldest nodes, whose weights are below 2^-32 of the largest,
+    contribute less than the sums' FP32 rounding and are left out (5 of 32,
     2 of 24)."""
-    return n_quad - {32: 4, 24: 2}.get(n_quad, 0)
+    return n_quad - {32: 5, 24: 2}.get(n_quad, 0)
 
 
 def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> float:

@@ -90,13 +90,13 @@ __device__ inline LogNormal lognormal(double m, double s)
 // strictly with x (dy/dx = y/x (1 - z coth(z/2)), z = x ln 2, and
 // z coth(z/2) >= 2), so w_k q_k <= (w_k / w_c) w_c q_c and w_k y_k <=
 // (w_k / w_c) w_c y_c, and |v_k| y_k <= |s_k| (w_k / w_c) w_c y_c with
-// |s_k| < 11.  The first kColdSkip nodes have w_k / w_c < 2^-36 (checked on
+// |s_k| < 11.  The first kColdSkip nodes have w_k / w_c < 2^-32 (checked on
 // the host when the rule is built): leaving them out changes sI and sM by
-// less than 2^-34 of themselves and sS by less than 2^-29 of sM's scale, below
-// the rounding of an FP32 sum.  The FP64 sums keep every node.
+// less than 2^-29 of themselves and sS by less than 2^-26 of sM's scale, below
+// the rounding of an FP32 sum (2^-24).  The FP64 sums keep every node.
 template <int Q>
-constexpr int kColdSkip = Q >= 32 ? 4 : (Q >= 24 ? 2 : 0);
-constexpr double kColdSkipRatio = 1.4551915228366852e-11;   // 2^-36
+constexpr int kColdSkip = Q >= 32 ? 5 : (Q >= 24 ? 2 : 0);
+constexpr double kColdSkipRatio = 2.3283064365386963e-10;   // 2^-32
 
 template <typename R, int Q>
 constexpr int cold_skip_v = sizeof(R) == 4 ? kColdSkip<Q> : 0;
@@ -811,7 +811,7 @@ const Quad<R, Q>* cached_quad()
         if constexpr (sizeof(R) == 4) ok = make_quad_f32(Q, q.w, q.v, q.s);
         else ok = make_quad_f64(Q, q.w, q.v, q.s);
         // the FP32 sums leave out the cold-end nodes: their weights must be
-        // below 2^-36 of the largest, in ascending abscissa
+        // below 2^-32 of the largest, in ascending abscissa
         double wmax = 0.0;
         for (int k = 0; k < Q; ++k) wmax = std::max(wmax, (double)q.w[k]);
         for (int k = 0; ok && k < cold_skip_v<R, Q>; ++k)

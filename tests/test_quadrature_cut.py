@@ -1,6 +1,6 @@
-"""The FP32 lognormal sums leave the coldest Gauss-Hermite nodes out (4 of 32,
+"""The FP32 lognormal sums leave the coldest Gauss-Hermite nodes out (5 of 32,
 2 of 24).  Host-side checks of the bound that justifies it: the left-out
-weights are below 2^-36 of the largest, and over the prior box and the
+weights are below 2^-32 of the largest, and over the prior box and the
 284-band range the three node sums change by far less than an FP32 ulp when
 those nodes are dropped (sums taken in FP64 here)."""
 import numpy as np
@@ -8,7 +8,7 @@ import pytest
 
 import paper_2608_07580_amd as ff
 
-SKIP = {32: 4, 24: 2, 16: 0}
+SKIP = {32: 5, 24: 2, 16: 0}
 C2_LOG2 = 14387.768775039337 / np.log(2.0)     # second radiation constant (um K), in log2 units
 
 
@@ -20,13 +20,13 @@ def _rule(q):
 
 
 @pytest.mark.parametrize("q", [16, 24, 32])
-def test_left_out_weights_are_below_two_to_minus_36(q):
+def test_left_out_weights_are_below_two_to_minus_32(q):
     s, w = _rule(q)
     assert np.all(np.diff(s) > 0)                  # ascending: the first nodes are the coldest
     k0 = SKIP[q]
-    assert np.all(w[:k0] <= 2.0 ** -36 * w.max())
+    assert np.all(w[:k0] <= 2.0 ** -32 * w.max())
     if k0 < q:
-        assert w[k0] > 2.0 ** -36 * w.max()        # the cut is the largest one the bound allows
+        assert w[k0] > 2.0 ** -32 * w.max()        # the cut is the largest one the bound allows
 
 
 def _sums(a2, u, w, v):
@@ -59,4 +59,4 @@ def test_dropping_cold_nodes_is_below_fp32_rounding(q):
                 rel = np.abs(full - part) / np.array([full[0], full[1], scale])
                 worst = max(worst, float(rel.max()))
     print(f"\n  Q={q}: largest change {worst:.2e} (2^{np.log2(worst) if worst > 0 else -np.inf:.1f})")
-    assert worst < 2.0 ** -29, worst
+    assert worst < 2.0 ** -26, worst
