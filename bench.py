@@ -52,8 +52,8 @@ PEAK_FP32_PUBLISHED = 157.3e12
 # kernel sources with the SHA-1 below; any other source reports null.
 TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
                    "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
-TRAFFIC_SHA1 = "0befb7eeb3c04855a606cda0fa885145e909dcc2"
-TRAFFIC_BYTES = {"plain": 92.22e9, "warm": 90.39e9}
+TRAFFIC_SHA1 = "c5e7a96bc598c7714911a078c32a30630ff0f787"
+TRAFFIC_BYTES = {"plain": 86.12e9, "warm": 84.42e9}
 
 
 def measured_traffic(leg: str):
@@ -92,9 +92,9 @@ def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> float:
     the FP64 residual's RESIDUAL64_W."""
     if model == 4:
         # one component; the endmember surface: 5 FMAs for rho and 5 basis
-        # products where the linear surface has 2 and 2 (25), and the n = 8
-        # accumulations (45)
-        return n_bands * (NODE_W * nodes_evaluated(n_quad) + 5 + 25 + 45 + RESIDUAL64_W + 4)
+        # products where the linear surface has 2 and 2 (25), the n = 8
+        # accumulations (45), and four more FP64 FMAs for the FP64 reflectance
+        return n_bands * (NODE_W * nodes_evaluated(n_quad) + 5 + 25 + 45 + RESIDUAL64_W + 4 * W_F64 + 4)
     comps = 1 if model == 1 else 2
     per_band = comps * (NODE_W * nodes_evaluated(n_quad) + 5) + (19 + 21 if model == 1 else 49 + 45) + RESIDUAL64_W
     return n_bands * per_band
@@ -230,7 +230,7 @@ def run_leg(args, atm, rad, stream, net):
         z0 = net.infer_routed(sc, rad, stream=stream)[0] if net is not None else None
         with torch.cuda.stream(stream):
             opts, tms = ff.tune([sc], [rad], prior, z0s=None if z0 is None else [z0], options=opts,
-                                cache_path=args.tune_cache, stream=stream)
+                                cache_path=args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
         sc.close()
         del z0
@@ -372,7 +372,7 @@ def run_ragged(args):
         with torch.cuda.stream(stream):
             z0s = None if ns is None else [n.infer(r, stream=stream) for n, r in zip(ns, rs)]
             opts, _ = ff.tune(scs, rs, prior, z0s=z0s, options=base,
-                              cache_path=None if args.no_tune else args.tune_cache, stream=stream)
+                              cache_path=None if args.no_tune else args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
         return opts
 
@@ -511,7 +511,7 @@ def run_precision(args):
         opts = ff.default_options(n_quad=args.n_quad, **kw)
         if not args.no_tune:
             with torch.cuda.stream(stream):
-                opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+                opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, retune=args.retune, stream=stream)
             torch.cuda.synchronize()
         outs = ff.allocate_outputs(P, 2, dev, state_f64=kw["precision"] == ff.PRECISION_FP64)
         evals = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -623,7 +623,7 @@ def run_solvers(args):
     opts = ff.default_options(n_quad=args.n_quad)
     if not args.no_tune:
         with torch.cuda.stream(stream):
-            opts, _ = ff.tune([scene], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+            opts, _ = ff.tune([scene], [rad], prior, options=opts, cache_path=args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
     out_lm = ff.allocate_outputs(P, 1, dev)
     ms_lm = timed(lambda: ff.retrieve(scene, rad, prior, options=opts, outputs=out_lm, stream=stream))
@@ -703,11 +703,12 @@ def grid_slots_per_eval(n_bands: int, n_nodes: int, model: int = 3) -> int:
     and 7 per
     component for its weight product and the three centred sums; per band 25
     for the scaling, solar term, basis and residual and 45 for the J^T J,
-    J^T r, r.r accumulations (n = 8).  The full model (endmember surface,
-    n = 11) adds 6 for the five-term reflectance and basis and accumulates
-    78."""
-    per_band = 25 + 45 if model == 3 else 25 + 6 + 78
-    return n_bands * (n_nodes * (2 + W_EXP2 + W_RCP + 2 * 7) + per_band)
+    J^T r, r.r accumulations (n = 8), and the FP64 residual's RESIDUAL64_W.
+    The full model (endmember surface, n = 11) adds 6 for the five-term
+    reflectance and basis, accumulates 78, and forms the FP64 reflectance
+    with four more FP64 FMAs."""
+    per_band = 25 + 45 if model == 3 else 25 + 6 + 78 + 4 * W_F64
+    return n_bands * (n_nodes * (2 + W_EXP2 + W_RCP + 2 * 7) + per_band + RESIDUAL64_W)
 
 
 def run_paper_model(args, model: int = 3):
@@ -750,7 +751,7 @@ def run_paper_model(args, model: int = 3):
     opts = ff.default_options(n_quad=args.n_quad, max_iter=args.grid_max_iter)
     if not args.no_tune:
         with torch.cuda.stream(stream):
-            opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+            opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
 
     def timed(launch):
@@ -856,7 +857,7 @@ def run_endmember(args):
     opts = ff.default_options(n_quad=args.n_quad, max_iter=args.grid_max_iter)
     if not args.no_tune:
         with torch.cuda.stream(stream):
-            opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+            opts, _ = ff.tune([sc], [rad], prior, options=opts, cache_path=args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
 
     def timed(launch):
@@ -938,7 +939,7 @@ def run_coarsening(args):
     opts = ff.default_options(n_quad=args.n_quad)
     if not args.no_tune:
         with torch.cuda.stream(stream):
-            opts, _ = ff.tune([scene], [rad], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+            opts, _ = ff.tune([scene], [rad], prior, options=opts, cache_path=args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
     K = (rows // b) * (cols // b)
     fine = ff.allocate_outputs(P, 1, dev)
@@ -1023,7 +1024,7 @@ def run_front_end(args):
     if not args.no_tune and n > 0:
         sub = rad[idx[:n]].contiguous()
         with torch.cuda.stream(stream):
-            opts, _ = ff.tune([scene], [sub], prior, options=opts, cache_path=args.tune_cache, stream=stream)
+            opts, _ = ff.tune([scene], [sub], prior, options=opts, cache_path=args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
         del sub
     out = ff.allocate_outputs(P, 1, dev)
@@ -1069,7 +1070,7 @@ def run_front_end(args):
         with torch.cuda.stream(stream):
             zs = net.infer(sub, stream=stream)
             wopts, _ = ff.tune([scene], [sub], prior, z0s=[zs], options=wopts, cache_path=args.tune_cache,
-                               stream=stream)
+                               retune=args.retune, stream=stream)
         torch.cuda.synchronize()
         del sub, zs
     wev = []
@@ -1178,6 +1179,8 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2608_07580_amd", "tuning.json"),
                     help="autotuner table (read, and written on a miss)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the launch-shape candidates again and overwrite the tuner table's entries")
     ap.add_argument("--tune-quadrature", action="store_true",
                     help="also run the tuner's quadrature-order choice on the scene and report it "
                          "(the headline keeps --n-quad)")
