@@ -9,6 +9,7 @@
 //  * a training-data generator: Philox4x32-10 counter-based draws (Salmon,
 //    Moraes, Dror & Shaw 2011) of one-component states, the forward model of
 //    physics.hpp and Box-Muller noise.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <cstdio>
@@ -122,6 +123,8 @@ __device__ __forceinline__ void epilogue_store(int m, int n, float v, const EpiA
 // Bop = TB ? B[n][k] : B[k][n] (lda/ldb = row strides of the stored arrays).
 // Loads: m < Ml, n < Nl, k < K (8-element chunks along the contiguous
 // dimension, whose extent must be a multiple of 8); stores: m < M, n < N.
+// With gridDim.z = S > 1 (EPI_F32 only) workgroup z sums the z-th of S
+// kBK-aligned slices of k and stores its partial at outf + z M ldof.
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(kGemmThreads)
 gemm_bf16(int M, int N, int Ml, int Nl, int K, const __bf16* __restrict__ A, int lda,
@@ -139,8 +142,15 @@ gemm_bf16(int M, int N, int Ml, int Nl, int K, const __bf16* __restrict__ A, int
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
     const bf16x8_t zero8 = {};
+    int kbeg = 0, kend = K;
+    if (gridDim.z > 1) {
+        const int kc = ((K + (int)gridDim.z - 1) / (int)gridDim.z + kBK - 1) / kBK * kBK;
+        kbeg = (int)blockIdx.z * kc;
+        kend = min(K, kbeg + kc);
+        ep.outf += (size_t)blockIdx.z * (size_t)M * ep.ldof;
+    }
 
-    for (int k0 = 0; k0 < K; k0 += kBK) {
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
         // ---- A tile -> As[m][k]
         if (!TA) {
             const int r = t >> 2, kc = (t & 3) * 8;
@@ -619,6 +629,19 @@ __global__ void output_listed_kernel(const float* __restrict__ Y, const int64_t*
 // that fill the chip: partial sums of 64-row chunks, one workgroup per
 // (64 columns, chunk), then the chunks summed in order per column.
 constexpr int kColChunk = 64;
+constexpr int kWgradSplit = 8;
+constexpr int64_t kGenPool = 32;     // training steps whose spectra one generator launch makes
+
+// out[i] = sum over the S planes of part[z n + i], in plane order.
+__global__ void __launch_bounds__(256) sum_planes_kernel(const float* __restrict__ part, int S, int64_t n,
+                                                         float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = part[i];
+    for (int z = 1; z < S; ++z) v += part[(size_t)z * n + i];
+    out[i] = v;
+}
 
 __global__ void __launch_bounds__(256)
 colsum_part_kernel(const __bf16* __restrict__ D, int64_t M, int N, int ld, float* __restrict__ part)
@@ -833,24 +856,35 @@ struct ff_mlp {
     __bf16* dY = nullptr;
     __bf16* dH[3] = {nullptr, nullptr, nullptr};
     float* part = nullptr;            // column-sum partials [rows / 64][1024]
+    float* wpart = nullptr;           // split-K weight-gradient partials [kWgradSplit][largest layer]
     int pins = 0;                     // graphs that bind the workspace (see ff_pipeline_create)
     std::vector<void*> retired;       // workspace buffers replaced while pinned, freed at destroy
 };
 
 namespace {
 
+// Largest weight-gradient matrix (outputs x inputs) over the layers.
+int64_t wgrad_max(const ff_mlp* m)
+{
+    int64_t mx = (int64_t)m->n_out * m->h[2];
+    mx = std::max<int64_t>(mx, (int64_t)m->h[0] * m->n_in);
+    mx = std::max<int64_t>(mx, (int64_t)m->h[1] * m->h[0]);
+    mx = std::max<int64_t>(mx, (int64_t)m->h[2] * m->h[1]);
+    return mx;
+}
+
 // Drop the activation workspace: freed, or -- while a captured graph binds
 // it -- kept until the network is destroyed.
 void free_ws(ff_mlp* m)
 {
-    void* bufs[13] = {m->X, m->H[0], m->H[1], m->H[2], m->A[0], m->A[1], m->A[2],
-                      m->dH[0], m->dH[1], m->dH[2], m->Y, m->dY, m->part};
+    void* bufs[14] = {m->X, m->H[0], m->H[1], m->H[2], m->A[0], m->A[1], m->A[2],
+                      m->dH[0], m->dH[1], m->dH[2], m->Y, m->dY, m->part, m->wpart};
     for (void* b : bufs) {
         if (!b) continue;
         if (m->pins > 0) m->retired.push_back(b);
         else (void)hipFree(b);
     }
-    m->X = nullptr; m->Y = nullptr; m->dY = nullptr; m->part = nullptr;
+    m->X = nullptr; m->Y = nullptr; m->dY = nullptr; m->part = nullptr; m->wpart = nullptr;
     for (int i = 0; i < 3; ++i) { m->H[i] = nullptr; m->A[i] = nullptr; m->dH[i] = nullptr; }
     m->ws_rows = 0;
 }
@@ -875,6 +909,7 @@ ff_status ensure_ws(ff_mlp* m, int64_t rows, hipStream_t stream)
     if (e == hipSuccess) e = hipMalloc(&m->Y, (size_t)R * 16 * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&m->dY, (size_t)R * 16 * sizeof(__bf16));
     if (e == hipSuccess) e = hipMalloc(&m->part, (size_t)(R / kColChunk) * 1024 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->wpart, (size_t)kWgradSplit * wgrad_max(m) * sizeof(float));
     if (e != hipSuccess) {
         free_ws(m);
         return hip_error(e, "mlp workspace");
@@ -936,6 +971,29 @@ void colsum(ff_mlp* m, const __bf16* D, int64_t R, int N, int ld, float* out, hi
     hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, m->part, chunks, N, out);
 }
 
+// Weight gradient gw[M][N] = sum_r Dop[r][m] Xop[r][n] over the R = K rows
+// of the batch.  A batch's 2,048-row reduction into at most 512 x 512
+// outputs is only 64 output tiles, a quarter of the CUs: the rows are split
+// into S slices (at least 256 rows each), each slice's partial product goes
+// to its own plane of m->wpart, and the planes are summed in a fixed order,
+// so the result does not depend on scheduling.
+void gemm_wgrad(ff_mlp* m, int M, int N, int Ml, int Nl, int K, const __bf16* D, int ldd, const __bf16* X, int ldx,
+                float* gw, hipStream_t s)
+{
+    const int64_t tiles = cdiv(N, kBN) * cdiv(M, kBM);
+    int S = (int)std::min<int64_t>({(int64_t)kWgradSplit, std::max<int64_t>(1, K / 256), cdiv(512, tiles)});
+    if (S < 1) S = 1;
+    if (S == 1) {
+        gemm<true, false, EPI_F32>(M, N, Ml, Nl, K, D, ldd, X, ldx, EpiArgs{nullptr, gw, N, nullptr, 0, nullptr, 0}, s);
+        return;
+    }
+    dim3 grid((unsigned)cdiv(N, kBN), (unsigned)cdiv(M, kBM), (unsigned)S);
+    hipLaunchKernelGGL((gemm_bf16<true, false, EPI_F32>), grid, dim3(kGemmThreads), 0, s, M, N, Ml, Nl, K, D, ldd, X,
+                       ldx, EpiArgs{nullptr, m->wpart, N, nullptr, 0, nullptr, 0});
+    const int64_t n = (int64_t)M * N;
+    hipLaunchKernelGGL(sum_planes_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, m->wpart, S, n, gw);
+}
+
 // backward pass of R rows: dY in m->dY -> all gradients into m->grads
 void backward_rows(ff_mlp* m, int64_t R, hipStream_t s)
 {
@@ -944,8 +1002,7 @@ void backward_rows(ff_mlp* m, int64_t R, hipStream_t s)
     float* gw = m->grads;
     const LayerMap& mp = m->map;
     // output layer
-    gemm<true, false, EPI_F32>(m->n_out, h3, 16, h3, r, m->dY, 16, m->A[2], h3,
-                               EpiArgs{nullptr, gw + mp.off_w[3], h3, nullptr, 0, nullptr, 0}, s);
+    gemm_wgrad(m, m->n_out, h3, 16, h3, r, m->dY, 16, m->A[2], h3, gw + mp.off_w[3], s);
     colsum(m, m->dY, R, m->n_out, 16, gw + mp.off_b[3], s);
     gemm<false, false, EPI_BWD_GELU>(r, h3, r, h3, 16, m->dY, 16, m->wb + mp.off_wb[3], h3,
                                      EpiArgs{nullptr, nullptr, 0, m->dH[2], h3, m->H[2], h3}, s);
@@ -956,8 +1013,7 @@ void backward_rows(ff_mlp* m, int64_t R, hipStream_t s)
         const int nin = l == 0 ? m->n_in : hs[l - 1];
         const int nin_pad = mp.in_pad[l];
         const __bf16* xin = l == 0 ? m->X : m->A[l - 1];
-        gemm<true, false, EPI_F32>(nout, nin, nout, nin_pad, r, m->dH[l], nout, xin, nin_pad,
-                                   EpiArgs{nullptr, gw + mp.off_w[l], nin, nullptr, 0, nullptr, 0}, s);
+        gemm_wgrad(m, nout, nin, nout, nin_pad, r, m->dH[l], nout, xin, nin_pad, gw + mp.off_w[l], s);
         colsum(m, m->dH[l], R, nout, nout, gw + mp.off_b[l], s);
         if (l > 0)
             gemm<false, false, EPI_BWD_GELU>(r, nin, r, nin, nout, m->dH[l], nout, m->wb + mp.off_wb[l], nin_pad,
@@ -1268,17 +1324,27 @@ extern "C" ff_status ff_mlp_train_span(ff_mlp* m, const ff_scene* sc, const ff_p
                                     "and 0 < batch <= 65536");
     const int64_t steps = total_steps;
     hipStream_t s = (hipStream_t)stream;
+    // The spectra of up to kGenPool steps are generated by one launch (sample
+    // g = i batch + p of step i, the same counter-based stream as one launch
+    // per step), which fills the chip where a single batch would not.
+    const int64_t pool = std::max<int64_t>(1, std::min<int64_t>(kGenPool, n_steps));
     float* rad = nullptr;
     float* tgt = nullptr;
-    FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&rad), (size_t)batch * m->n_in * sizeof(float), s));
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tgt), (size_t)batch * 5 * sizeof(float), s);
+    FF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&rad), (size_t)pool * batch * m->n_in * sizeof(float), s));
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tgt), (size_t)pool * batch * 5 * sizeof(float), s);
     ff_status st = e == hipSuccess ? FF_OK : hip_error(e, "ff_mlp_train");
     for (int64_t i = first_step; i < first_step + n_steps && st == FF_OK; ++i) {
+        const int64_t j = (i - first_step) % pool;
+        if (j == 0) {
+            const int64_t n = std::min<int64_t>(pool, first_step + n_steps - i);
+            st = ff_mlp_generate(sc, prior, seed, (uint64_t)i * (uint64_t)batch, n * batch, snr, bg, rad, tgt, nullptr,
+                                 s);
+            if (st != FF_OK) break;
+        }
         const double c = steps > 1 ? 0.5 * (1.0 + std::cos(M_PI * (double)i / (double)(steps - 1))) : 1.0;
         const float lr_i = (float)(lr_final + (lr - lr_final) * c);
-        st = ff_mlp_generate(sc, prior, seed, (uint64_t)i * (uint64_t)batch, batch, snr, bg, rad, tgt, nullptr, s);
-        if (st == FF_OK)
-            st = ff_mlp_train_step(m, rad, tgt, batch, lr_i, loss_hist ? loss_hist + (i - first_step) : nullptr, s);
+        st = ff_mlp_train_step(m, rad + (size_t)j * batch * m->n_in, tgt + (size_t)j * batch * 5, batch, lr_i,
+                               loss_hist ? loss_hist + (i - first_step) : nullptr, s);
         if (st == FF_OK) m->train_steps = i + 1;
     }
     hipFreeAsync(rad, s);
