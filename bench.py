@@ -370,7 +370,7 @@ def run_ragged(args):
 
     def tuned(scs, rs, ns):
         with torch.cuda.stream(stream):
-            z0s = None if ns is None else [n.infer(r, stream=stream) for n, r in zip(ns, rs)]
+            z0s = None if ns is None else [n.infer_routed(s_, r, stream=stream)[0] for n, s_, r in zip(ns, scs, rs)]
             opts, _ = ff.tune(scs, rs, prior, z0s=z0s, options=base,
                               cache_path=None if args.no_tune else args.tune_cache, retune=args.retune, stream=stream)
         torch.cuda.synchronize()
@@ -394,7 +394,8 @@ def run_ragged(args):
     for name, ns in (("warm", net_of), ("plain", None)):
         opts = tuned(sc, rads, ns) if not args.no_tune else base
         evals = torch.zeros(1, dtype=torch.int64, device=dev)
-        pipe = ff.Pipeline(sc, rads, prior, net=ns, options=opts, evals=evals, stream=stream)
+        pipe = ff.Pipeline(sc, rads, prior, net=ns, options=opts, evals=evals, stream=stream,
+                           route=None if ns is None else ff.HFDI_THRESHOLD)
         ms, ev = time_graph(pipe, evals)
         conv = [int(((o.status.cpu().numpy() & ff.ST_CONVERGED) != 0).sum()) for o in pipe.outputs]
         it = np.concatenate([o.iters.cpu().numpy() for o in pipe.outputs])
@@ -418,7 +419,7 @@ def run_ragged(args):
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(stream)
-            z0s = [n.infer(r, stream=stream) for n, r in zip(net_of, rads)]
+            z0s = [n.infer_routed(s_, r, stream=stream)[0] for n, s_, r in zip(net_of, sc, rads)]
             ff.retrieve_batch(sc, rads, prior, z0s=z0s, options=opts_w, outputs=outs, stream=stream)
         b.record(stream)
     torch.cuda.synchronize()
@@ -427,7 +428,7 @@ def run_ragged(args):
     per_scene = []
     for spec, s1, r, n in zip(layout, sc, rads, net_of):
         o1 = tuned([s1], [r], [n])
-        pipe = ff.Pipeline([s1], [r], prior, net=[n], options=o1, stream=stream)
+        pipe = ff.Pipeline([s1], [r], prior, net=[n], options=o1, stream=stream, route=ff.HFDI_THRESHOLD)
         for _ in range(2):
             pipe.launch()
         torch.cuda.synchronize()

@@ -664,6 +664,21 @@ ff_status ff_pipeline_create(const ff_scene* const* scenes, const float* const* 
                              const int64_t* P, int32_t n_scenes, const ff_prior* prior, const ff_mlp* const* mlps,
                              const ff_options* opts, const ff_outputs* outs, unsigned long long* evals_dev,
                              void* stream, ff_pipeline** out);
+/* The same with the warm start routed by the front end (Keely et al.
+ * Sec. 2.1): for each scene with a network the graph runs ff_hfdi_candidates
+ * at hfdi_threshold (the paper: -0.1) into buffers the pipeline owns, marks
+ * every z0 row "no start" (first entry NaN), and runs the network on the
+ * candidates only, their count read on the device (inference is launched
+ * for all P rows, chunks past the count doing nothing); the retrieval then
+ * solves candidates from the network's start and every other pixel from x0
+ * (ff_options: rows without a start).  The outputs equal those of
+ * ff_hfdi_candidates + ff_mlp_infer_listed + ff_retrieve_batch run eagerly
+ * on the same inputs.  FF_EINVAL for a NaN threshold, else as above. */
+ff_status ff_pipeline_create_routed(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                    const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                    const ff_mlp* const* mlps, double hfdi_threshold, const ff_options* opts,
+                                    const ff_outputs* outs, unsigned long long* evals_dev, void* stream,
+                                    ff_pipeline** out);
 ff_status ff_pipeline_launch(ff_pipeline* pipeline, void* stream);
 const float* ff_pipeline_z0(const ff_pipeline* pipeline);   /* [sum P][n], scene after scene */
 void ff_pipeline_destroy(ff_pipeline* pipeline);

@@ -53,7 +53,7 @@ EXPORTS = ("ff_version", "ff_status_string", "ff_last_error", "ff_options_defaul
            "ff_hfdi_candidates", "ff_retrieve_listed", "ff_retrieve_atm_indexed", "ff_block_mean", "ff_qec",
            "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_tune_quadrature",
            "ff_retrieve_batch_noalloc", "ff_mlp_train_span", "ff_mlp_steps_done", "ff_warmstart_save",
-           "ff_warmstart_load", "ff_mlp_sizes", "ff_valu_rates")
+           "ff_warmstart_load", "ff_mlp_sizes", "ff_valu_rates", "ff_pipeline_create_routed")
 
 
 class FirefitError(RuntimeError):
@@ -188,6 +188,9 @@ def lib():
         L.ff_pipeline_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32,
                                          C.POINTER(ffPrior), C.POINTER(vp), C.POINTER(ffOptions),
                                          C.POINTER(ffOutputs), vp, vp, C.POINTER(vp)]
+        L.ff_pipeline_create_routed.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32,
+                                                C.POINTER(ffPrior), C.POINTER(vp), C.c_double, C.POINTER(ffOptions),
+                                                C.POINTER(ffOutputs), vp, vp, C.POINTER(vp)]
         L.ff_pipeline_launch.argtypes = [vp, vp]
         L.ff_pipeline_z0.argtypes = [vp]
         L.ff_pipeline_z0.restype = vp
@@ -210,7 +213,7 @@ def lib():
         L.ff_qec.argtypes = [C.c_void_p] * 8 + [C.c_int32] * 4 + [C.c_double, C.c_int32, C.c_int32, _dp] + \
             [C.c_void_p] * 4
         for name in ("ff_tune_quadrature", "ff_scene_set_endmembers", "ff_scene_endmembers", "ff_block_mean", "ff_qec", "ff_retrieve_atm_indexed", "ff_hfdi_candidates", "ff_retrieve_listed", "ff_adam_options_default", "ff_adam_retrieve_batch",
-                     "ff_pipeline_create", "ff_pipeline_launch", "ff_release_scratch",
+                     "ff_pipeline_create", "ff_pipeline_create_routed", "ff_pipeline_launch", "ff_release_scratch",
                      "ff_gauss_hermite", "ff_scene_create", "ff_scene_band_tables", "ff_forward",
                      "ff_retrieve_scene", "ff_retrieve_batch", "ff_retrieve_batch_noalloc", "ff_retrieve",
                      "ff_prior_default", "ff_tune",
@@ -882,10 +885,12 @@ class Pipeline:
     The graph binds the radiance tensors, outputs and networks given here;
     rewrite the radiance tensors in place (``rad.copy_(new)``) and call
     ``launch()`` again.  ``outputs`` is a list of Outputs, one per scene.
-    ``net``: one WarmStart for every scene, or a list (entries may be None)."""
+    ``net``: one WarmStart for every scene, or a list (entries may be None).
+    ``route``: an HFDI threshold (the paper: -0.1) to run the network only on
+    the front end's candidates (ff_pipeline_create_routed), or None."""
 
     def __init__(self, scenes, radiances, prior: Prior | None = None, net=None,
-                 options: ffOptions | None = None, evals=None, stream=None):
+                 options: ffOptions | None = None, evals=None, stream=None, route: float | None = None):
         torch = _torch()
         self.prior = prior or default_prior(MODEL_LOGNORMAL_1)
         self.options = options or default_options()
@@ -904,9 +909,15 @@ class Pipeline:
         nets = None
         if any(n is not None for n in self.nets):
             nets = (C.c_void_p * ns)(*[None if n is None else n.handle.value for n in self.nets])
-        _check(lib().ff_pipeline_create(sc, rd, Ps, ns, C.byref(pc), nets,
-                                        C.byref(self.options), oc, _ptr(evals), _stream_handle(self.stream),
-                                        C.byref(h)), "ff_pipeline_create")
+        if route is None:
+            _check(lib().ff_pipeline_create(sc, rd, Ps, ns, C.byref(pc), nets,
+                                            C.byref(self.options), oc, _ptr(evals), _stream_handle(self.stream),
+                                            C.byref(h)), "ff_pipeline_create")
+        else:
+            _check(lib().ff_pipeline_create_routed(sc, rd, Ps, ns, C.byref(pc), nets, float(route),
+                                                   C.byref(self.options), oc, _ptr(evals),
+                                                   _stream_handle(self.stream), C.byref(h)),
+                   "ff_pipeline_create_routed")
         self.handle = h
 
     def launch(self, stream=None):

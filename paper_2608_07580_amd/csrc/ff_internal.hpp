@@ -136,6 +136,9 @@ void pin_stream_scratch(hipStream_t stream);
 // the graphs that bind them).
 void mlp_dims(const ff_mlp* m, int* n_in, int* n_out);
 void mlp_pin(const ff_mlp* m, int delta);
+ff_status mlp_infer_listed_dev(const ff_mlp* m, const float* rad, int64_t P, const int64_t* index,
+                               const int64_t* count_dev, float* z0, hipStream_t s);
+ff_status mark_no_start(float* z0, int64_t P, int n, hipStream_t s);
 ff_status dispatch_forward(int precision, int model, int q, const ff_scene* sc, const void* state,
                            int64_t P, void* L, void* J, hipStream_t stream);
 

@@ -69,7 +69,19 @@ struct EpiArgs {
     int ldob;
     const float* hprev;
     int ldh;
+    // rows read from device memory: only rows m < *mcount - mbase exist
+    // (the rest of the launch's M rows are skipped); null: all M rows
+    const int64_t* mcount = nullptr;
+    int64_t mbase = 0;
 };
+
+// The rows of an M-row launch that exist (see EpiArgs::mcount).
+__device__ __forceinline__ int live_rows(const EpiArgs& ep, int M)
+{
+    if (!ep.mcount) return M;
+    const int64_t c = *ep.mcount - ep.mbase;
+    return c <= 0 ? 0 : (c < (int64_t)M ? (int)c : M);
+}
 
 // GELU in its tanh form, evaluated as x * sigmoid(2u) (equal to
 // 0.5 x (1 + tanh u) with u = sqrt(2/pi) (x + 0.044715 x^3)): one exp2 and one
@@ -136,6 +148,9 @@ gemm_bf16(int M, int N, int Ml, int Nl, int K, const __bf16* __restrict__ A, int
     const int lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    M = live_rows(ep, M);
+    if (m0 >= M) return;
+    Ml = min(Ml, M);
     float4_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -234,6 +249,9 @@ gemm_nt_128(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, 
     const int lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.y * kFM, n0 = blockIdx.x * kFN;
+    M = live_rows(ep, M);
+    if (m0 >= M) return;
+    Ml = min(Ml, M);
     const int lr = t >> 2, lk = (t & 3) * 8;     // this thread's load rows lr, lr + 64 and k chunk
     const bf16x8_t zero8 = {};
     float4_t acc[4][4];
@@ -345,6 +363,9 @@ gemm_nt_lds(int M, int N, int Ml, int K, const __bf16* __restrict__ A, int lda, 
     const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
     if (tile >= n_tiles) return;
     const int m0 = (tile / n_tiles_n) * kFM, n0 = (tile % n_tiles_n) * kFN;
+    M = live_rows(ep, M);
+    if (m0 >= M) return;
+    Ml = min(Ml, M);
     const __bf16* ga[2];
     const __bf16* gb[2];
 #pragma unroll
@@ -554,14 +575,17 @@ __global__ void features_kernel(const float* __restrict__ L, int P, int n_in, in
 
 // features_kernel for listed rows: row r of X is radiance row index[r];
 // entries outside [0, P) give a row of zeros (its output is not stored)
+// count (may be null): only list entries base + r < *count exist
 __global__ void features_listed_kernel(const float* __restrict__ L, const int64_t* __restrict__ index, int64_t P,
                                        int R, int n_in, int kin, const float* __restrict__ mean,
-                                       const float* __restrict__ inv_std, float floor_v, __bf16* __restrict__ X)
+                                       const float* __restrict__ inv_std, float floor_v, __bf16* __restrict__ X,
+                                       const int64_t* __restrict__ count, int64_t base)
 {
     const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned cpr = (unsigned)kin / 8u;
     if (i >= (unsigned)R * cpr) return;
     const unsigned r = i / cpr;
+    if (count && base + (int64_t)r >= *count) return;
     const int b0 = 8 * (int)(i - r * cpr);
     const int64_t p = index[r];
     __bf16* out = X + (size_t)r * kin + b0;
@@ -614,11 +638,13 @@ __global__ void output_kernel(const float* __restrict__ Y, int64_t P, int n_out,
 // output_kernel for listed rows: row r goes to z row index[r] (skipped
 // outside [0, P))
 __global__ void output_listed_kernel(const float* __restrict__ Y, const int64_t* __restrict__ index, int64_t P,
-                                     int64_t R, int n_out, float* __restrict__ z)
+                                     int64_t R, int n_out, float* __restrict__ z, const int64_t* __restrict__ count,
+                                     int64_t base)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R * n_out) return;
     const int64_t r = i / n_out;
+    if (count && base + r >= *count) return;
     const int j = (int)(i - r * n_out);
     const int64_t p = index[r];
     if (p >= 0 && p < P) z[p * n_out + j] = tanhf(Y[r * 16 + j]);
@@ -941,14 +967,16 @@ void gemm_fwd(int M, int N, int K, const __bf16* A, int lda, const __bf16* B, in
 }
 
 // forward pass of R rows of features already in m->X; keep_h: store the
-// pre-activations for the backward pass
-void forward_rows(const ff_mlp* m, int64_t R, bool keep_h, hipStream_t s)
+// pre-activations for the backward pass; mcount (may be null): only rows
+// r < *mcount - mbase exist (see EpiArgs)
+void forward_rows(const ff_mlp* m, int64_t R, bool keep_h, hipStream_t s, const int64_t* mcount = nullptr,
+                  int64_t mbase = 0)
 {
     const int r = (int)R;
     for (int l = 0; l < 3; ++l) {
         const __bf16* in = l == 0 ? m->X : m->A[l - 1];
         const int kin = m->map.in_pad[l];
-        EpiArgs ep{m->params + m->map.off_b[l], m->H[l], m->h[l], m->A[l], m->h[l], nullptr, 0};
+        EpiArgs ep{m->params + m->map.off_b[l], m->H[l], m->h[l], m->A[l], m->h[l], nullptr, 0, mcount, mbase};
         const __bf16* w = m->wb + m->map.off_wb[l];
         if (m->h[l] % kFN == 0) {
             if (keep_h) gemm_fwd<EPI_FWD_GELU>(r, m->h[l], kin, in, kin, w, kin, ep, s);
@@ -958,7 +986,7 @@ void forward_rows(const ff_mlp* m, int64_t R, bool keep_h, hipStream_t s)
         else
             gemm<false, true, EPI_FWD_GELU_NOH>(r, m->h[l], r, m->h[l], kin, in, kin, m->wb + m->map.off_wb[l], kin, ep, s);
     }
-    EpiArgs ep{m->params + m->map.off_b[3], m->Y, 16, nullptr, 0, nullptr, 0};
+    EpiArgs ep{m->params + m->map.off_b[3], m->Y, 16, nullptr, 0, nullptr, 0, mcount, mbase};
     gemm<false, true, EPI_FWD_LINEAR>(r, m->n_out, r, 16, m->h[2], m->A[2], m->h[2], m->wb + m->map.off_wb[3],
                                       m->h[2], ep, s);
 }
@@ -1224,14 +1252,59 @@ extern "C" ff_status ff_mlp_infer_listed(const ff_mlp* mc, const float* rad, int
     for (int64_t i0 = 0; i0 < n_listed; i0 += chunk) {
         const int64_t R = std::min(chunk, n_listed - i0);
         hipLaunchKernelGGL(features_listed_kernel, dim3((unsigned)cdiv(R * m->kin / 8, 256)), dim3(256), 0, s, rad,
-                           index + i0, P, (int)R, m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X);
+                           index + i0, P, (int)R, m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X,
+                           (const int64_t*)nullptr, (int64_t)0);
         forward_rows(m, R, false, s);
         hipLaunchKernelGGL(output_listed_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y,
-                           index + i0, P, R, m->n_out, z0);
+                           index + i0, P, R, m->n_out, z0, (const int64_t*)nullptr, (int64_t)0);
     }
     FF_HIP_TRY(hipGetLastError());
     return clear_error();
 }
+
+namespace ff {
+
+// z0 rows of the first *count_dev entries of index_dev (at most P) from the
+// network; the row count is read on the device, so the launch sequence
+// (sized for all P rows, chunks past the count doing nothing) can be
+// captured into a graph.
+ff_status mlp_infer_listed_dev(const ff_mlp* mc, const float* rad, int64_t P, const int64_t* index,
+                               const int64_t* count_dev, float* z0, hipStream_t s)
+{
+    if (P <= 0) return FF_OK;
+    ff_mlp* m = const_cast<ff_mlp*>(mc);
+    const int64_t chunk = std::min<int64_t>(P, 1 << 18);
+    ff_status st = ensure_ws(m, chunk, s);
+    if (st != FF_OK) return st;
+    for (int64_t i0 = 0; i0 < P; i0 += chunk) {
+        const int64_t R = std::min(chunk, P - i0);
+        hipLaunchKernelGGL(features_listed_kernel, dim3((unsigned)cdiv(R * m->kin / 8, 256)), dim3(256), 0, s, rad,
+                           index + i0, P, (int)R, m->n_in, m->kin, m->mean, m->inv_std, m->floor_v, m->X, count_dev,
+                           i0);
+        forward_rows(m, R, false, s, count_dev, i0);
+        hipLaunchKernelGGL(output_listed_kernel, dim3((unsigned)cdiv(R * m->n_out, 256)), dim3(256), 0, s, m->Y,
+                           index + i0, P, R, m->n_out, z0, count_dev, i0);
+    }
+    FF_HIP_TRY(hipGetLastError());
+    return FF_OK;
+}
+
+// Every row of z0 [P][n] marked "no start" (its first entry NaN).
+__global__ void nan_rows_kernel(float* __restrict__ z0, int64_t P, int n)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) z0[p * n] = __builtin_nanf("");
+}
+
+ff_status mark_no_start(float* z0, int64_t P, int n, hipStream_t s)
+{
+    if (P <= 0) return FF_OK;
+    hipLaunchKernelGGL(nan_rows_kernel, dim3((unsigned)cdiv(P, 256)), dim3(256), 0, s, z0, P, n);
+    FF_HIP_TRY(hipGetLastError());
+    return FF_OK;
+}
+
+}  // namespace ff
 
 static ff_status grads_impl(ff_mlp* m, const float* rad, const float* target, int64_t P, double* loss,
                             hipStream_t s)

@@ -3,9 +3,13 @@
 // retrieval with fallback) recorded once into a HIP graph and replayed with
 // a single graph launch.  The graph binds the buffers it was built with:
 // a serving loop rewrites the radiance buffers in place and relaunches.
+// Routed pipelines run the front end (HFDI, Sec. 2.1) first and the network
+// only on its candidates, whose count stays on the device; every other
+// pixel is solved from the default start.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "ff_internal.hpp"
@@ -18,6 +22,9 @@ struct ff_pipeline {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float* z0 = nullptr;
+    float* hfdi = nullptr;               // routed: index values, candidate lists and counts
+    int64_t* index = nullptr;
+    int64_t* count = nullptr;
     std::vector<const ff_mlp*> pinned;   // networks whose workspace the graph binds
 };
 
@@ -30,6 +37,9 @@ void release(ff_pipeline* p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->z0) (void)hipFree(p->z0);
+    if (p->hfdi) (void)hipFree(p->hfdi);
+    if (p->index) (void)hipFree(p->index);
+    if (p->count) (void)hipFree(p->count);
     if (p->capture) {
         release_stream_scratch(p->capture);
         (void)hipStreamDestroy(p->capture);
@@ -40,12 +50,13 @@ void release(ff_pipeline* p)
 
 }  // namespace
 
-extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const float* const* radiance_dev,
-                                        const int64_t* P, int32_t n_scenes, const ff_prior* prior,
-                                        const ff_mlp* const* mlps, const ff_options* opts, const ff_outputs* outs,
-                                        unsigned long long* evals_dev, void* stream, ff_pipeline** out)
+static ff_status create(const ff_scene* const* scenes, const float* const* radiance_dev, const int64_t* P,
+                        int32_t n_scenes, const ff_prior* prior, const ff_mlp* const* mlps, bool routed,
+                        double threshold, const ff_options* opts, const ff_outputs* outs,
+                        unsigned long long* evals_dev, void* stream, ff_pipeline** out)
 {
     if (!out) return set_error(FF_EINVAL, "ff_pipeline_create: NULL out");
+    if (routed && std::isnan(threshold)) return set_error(FF_EINVAL, "ff_pipeline_create_routed: threshold is NaN");
     *out = nullptr;
     if (n_scenes <= 0 || !scenes || !radiance_dev || !P || !prior || !opts || !outs)
         return set_error(FF_EINVAL, "ff_pipeline_create: NULL argument or empty batch");
@@ -96,11 +107,30 @@ extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const flo
     }
     std::vector<const float*> z0s(n_scenes, nullptr);
     for (int i = 0; i < n_scenes; ++i) z0s[i] = (p->z0 && mlps && mlps[i]) ? p->z0 + off[i] * n : nullptr;
+    if (routed && any_net && total > 0) {
+        hipError_t e = hipMalloc(&p->hfdi, (size_t)total * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&p->index, (size_t)total * sizeof(int64_t));
+        if (e == hipSuccess) e = hipMalloc(&p->count, (size_t)n_scenes * sizeof(int64_t));
+        if (e != hipSuccess) {
+            release(p);
+            return hip_error(e, "ff_pipeline_create_routed: candidate buffers");
+        }
+    }
 
     auto run = [&]() -> ff_status {
         for (int i = 0; any_net && i < n_scenes; ++i) {
             if (P[i] == 0 || !z0s[i]) continue;
-            const ff_status st = ff_mlp_infer(mlps[i], radiance_dev[i], P[i], const_cast<float*>(z0s[i]), cs);
+            float* z = const_cast<float*>(z0s[i]);
+            ff_status st;
+            if (routed) {
+                st = ff_hfdi_candidates(scenes[i], radiance_dev[i], P[i], threshold, p->hfdi + off[i],
+                                        p->index + off[i], p->count + i, cs);
+                if (st == FF_OK) st = mark_no_start(z, P[i], n, s);
+                if (st == FF_OK)
+                    st = mlp_infer_listed_dev(mlps[i], radiance_dev[i], P[i], p->index + off[i], p->count + i, z, s);
+            } else {
+                st = ff_mlp_infer(mlps[i], radiance_dev[i], P[i], z, cs);
+            }
             if (st != FF_OK) return st;
         }
         return ff_retrieve_batch(scenes, radiance_dev, P, n_scenes, prior, any_net ? z0s.data() : nullptr, opts,
@@ -135,6 +165,24 @@ extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const flo
     }
     *out = p;
     return clear_error();
+}
+
+extern "C" ff_status ff_pipeline_create(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                        const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                        const ff_mlp* const* mlps, const ff_options* opts, const ff_outputs* outs,
+                                        unsigned long long* evals_dev, void* stream, ff_pipeline** out)
+{
+    return create(scenes, radiance_dev, P, n_scenes, prior, mlps, false, 0.0, opts, outs, evals_dev, stream, out);
+}
+
+extern "C" ff_status ff_pipeline_create_routed(const ff_scene* const* scenes, const float* const* radiance_dev,
+                                               const int64_t* P, int32_t n_scenes, const ff_prior* prior,
+                                               const ff_mlp* const* mlps, double hfdi_threshold,
+                                               const ff_options* opts, const ff_outputs* outs,
+                                               unsigned long long* evals_dev, void* stream, ff_pipeline** out)
+{
+    return create(scenes, radiance_dev, P, n_scenes, prior, mlps, true, hfdi_threshold, opts, outs, evals_dev,
+                  stream, out);
 }
 
 extern "C" ff_status ff_pipeline_launch(ff_pipeline* p, void* stream)

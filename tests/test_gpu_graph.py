@@ -89,6 +89,64 @@ def test_pipeline_replays_match_eager(warm):
     pipe.close()
 
 
+def test_routed_pipeline_matches_eager_routing():
+    """The routed pipeline (front end + network on the candidates, inside the
+    graph, the candidate count never read back) equals the eager routed
+    sequence -- ff_hfdi_candidates, the network on the listed rows, the
+    retrieval with NaN rows for every other pixel -- bitwise in every output
+    (the status bits included, so the same rows start from the network), on
+    every replay; a scene that is mostly background keeps most of its rows
+    without a start."""
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    scenes, rads = _batch(dev)
+    atm = scenegen.make_atmosphere(1, 0)
+    tab = oracle.band_tables(atm)
+    states, fire = scenegen.config1_states(64, 1234, scene=0)
+    idx = scenegen.subsample(1, 3, len(states), 3000)
+    scenes.append(ff.Scene(atm))
+    rads.append(torch.from_numpy(noisy_spectra(tab, states[idx], 1, 1, 3)).to(dev))
+    prior = ff.default_prior(1)
+    opts = ff.default_options(lanes_per_pixel=4)
+    net = ff.WarmStart(seed=1)
+    net.fit_normalization(ff.generate(scenes[0], prior, 9, 0, 4096)[0])
+    net.train(scenes[0], prior, steps=200, batch=1024, seed=2)
+    torch.cuda.synchronize()
+    nets = [net, None, net, net]
+    stream = torch.cuda.Stream(device=dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def eager():
+        z0s = []
+        for n, sc, r in zip(nets, scenes, rads):
+            z0s.append(None if n is None else n.infer_routed(sc, r, -0.1, stream=stream)[0])
+        with torch.cuda.stream(stream):
+            outs = ff.retrieve_batch(scenes, rads, prior, z0s=z0s, options=opts, stream=stream)
+        torch.cuda.synchronize()
+        return outs, z0s
+
+    pipe = ff.Pipeline(scenes, rads, prior, net=nets, options=opts, evals=evals, stream=stream, route=-0.1)
+    torch.cuda.synchronize()
+    ref, z0s = eager()
+    _same(pipe.outputs, ref)
+    n0 = evals.item()
+    routed = ~np.isnan(z0s[3][:, 0].cpu().numpy())
+    assert 0 < routed.sum() < 0.5 * len(routed)      # mostly background
+    st = pipe.outputs[3].numpy()["status"].astype(np.int64)
+    assert np.array_equal((st & ff.ST_WARM_START) != 0, routed)
+    for rep in range(3):
+        for o in pipe.outputs:
+            for t in (o.state, o.cov, o.moments, o.rrr):
+                t.fill_(-7.0)
+        torch.cuda.synchronize()
+        pipe.launch()
+        torch.cuda.synchronize()
+        _same(pipe.outputs, ref)
+        eager()
+    assert evals.item() == 4 * n0
+    pipe.close()
+
+
 def test_pipeline_argument_checks():
     dev = torch.device("cuda:0")
     scenes, rads = _batch(dev, sizes=(8,))
