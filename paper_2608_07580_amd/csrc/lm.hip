@@ -544,15 +544,15 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                     // re-solves the pixel from the default start right away
                     restart = true;
                 }
-                if (write && head) {
-                    if (valid) {
-                        st |= write_solution<R, MODEL, Q>(D, o, pix, x, A, F, nvalid);
-                    } else {
-                        write_nan<N>(o, pix);
+                if (write) {
+                    // the group's lanes share the covariance's column solves
+                    if (valid) st |= write_solution<R, MODEL, Q>(D, o, pix, x, A, F, nvalid, sub, L);
+                    else if (head) write_nan<N>(o, pix);
+                    if (head) {
+                        if (o.rrr) o.rrr[pix] = (float)rrr_new;
+                        if (o.iters) o.iters[pix] = it_out;
+                        if (o.status) o.status[pix] = st;
                     }
-                    if (o.rrr) o.rrr[pix] = (float)rrr_new;
-                    if (o.iters) o.iters[pix] = it_out;
-                    if (o.status) o.status[pix] = st;
                 }
                 if (restart) {
                     has = true;

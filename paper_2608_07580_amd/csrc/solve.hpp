@@ -185,15 +185,31 @@ template <typename R>
 __device__ __forceinline__ void scan_pixel(const float* __restrict__ rad, const R* __restrict__ tab, int B,
                                            int sub, int L, int& nonfin, int& nvalid, double& lnorm2)
 {
+    // Eight bands per lane per pass with all their loads issued first: a fresh
+    // pixel's row is not in cache, and the wave (whose other lanes wait for
+    // this scan) then waits for a few memory round trips instead of one per
+    // band.  The sums keep the band order of a plain loop.
+    constexpr int kBatch = 8;
     nonfin = 0;
     nvalid = 0;
     lnorm2 = 0.0;
-    for (int b = sub; b < B; b += L) {
-        const float v = rad[b];
-        nonfin += isfinite(v) ? 0 : 1;
-        if ((R)v < tab[(size_t)b * FF_TABLE_COLS + COL_LSAT]) {
-            ++nvalid;
-            lnorm2 += (double)v * (double)v;
+    for (int b0 = sub; b0 < B; b0 += kBatch * L) {
+        float v[kBatch];
+        R ls[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int b = b0 + j * L;
+            v[j] = b < B ? rad[b] : 0.f;
+            ls[j] = b < B ? tab[(size_t)b * FF_TABLE_COLS + COL_LSAT] : (R)0;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            if (b0 + j * L >= B) break;
+            nonfin += isfinite(v[j]) ? 0 : 1;
+            if ((R)v[j] < ls[j]) {
+                ++nvalid;
+                lnorm2 += (double)v[j] * (double)v[j];
+            }
         }
     }
     if (L > 1) {
@@ -351,12 +367,14 @@ __device__ inline void write_nan(const OutPtrs& o, int64_t pix)
 // covariance sigma^2 A^-1 (sigma^2 = F / (N_valid - n)) is formed in z and
 // scaled to x; variables whose Jacobian column is identically zero are
 // unidentified and get NaN rows/columns.  Returns FF_ST_COV_SINGULAR when
-// some rows are NaN, else 0.
+// some rows are NaN, else 0.  The L lanes of a pixel's group (sub = this
+// lane, all holding the same x, A, F) share the covariance: a lane solves and
+// writes columns sub, sub + L, ...; lane 0 writes state and moments.
 template <typename R, int MODEL, int Q, typename Desc>
 __device__ __forceinline__ unsigned write_solution(const Desc* D, const OutPtrs& o, int64_t pix,
                                                    const double (&x)[ModelDims<MODEL>::N],
                                                    const double (&A)[ModelDims<MODEL>::N * (ModelDims<MODEL>::N + 1) / 2],
-                                                   double F, int nvalid)
+                                                   double F, int nvalid, int sub = 0, int L = 1)
 {
     using PM = PixelModel<R, MODEL, Q>;
     constexpr int N = PM::N;
@@ -381,7 +399,7 @@ __device__ __forceinline__ unsigned write_solution(const Desc* D, const OutPtrs&
     if (any_drop || !ok) st |= FF_ST_COV_SINGULAR;
     const double s2 = F / (double)(nvalid - N);
     if (o.cov) {
-        for (int c = 0; c < N; ++c) {
+        for (int c = sub; c < N; c += L) {
             double e[N], col[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) { e[i] = i == c ? 1.0 : 0.0; col[i] = 0.0; }
@@ -401,11 +419,13 @@ __device__ __forceinline__ unsigned write_solution(const Desc* D, const OutPtrs&
             }
         }
     }
-    double et, sd;
-    PM::moments(x, et, sd);
-    if (o.moments) { o.moments[2 * pix] = (float)et; o.moments[2 * pix + 1] = (float)sd; }
-    if (o.state) for (int j = 0; j < N; ++j) o.state[pix * N + j] = (float)x[j];
-    if (o.state64) for (int j = 0; j < N; ++j) o.state64[pix * N + j] = x[j];
+    if (sub == 0) {
+        double et, sd;
+        PM::moments(x, et, sd);
+        if (o.moments) { o.moments[2 * pix] = (float)et; o.moments[2 * pix + 1] = (float)sd; }
+        if (o.state) for (int j = 0; j < N; ++j) o.state[pix * N + j] = (float)x[j];
+        if (o.state64) for (int j = 0; j < N; ++j) o.state64[pix * N + j] = x[j];
+    }
     return st;
 }
 
