@@ -60,6 +60,7 @@ struct ff_scene {
     std::vector<double> fwhm;     // [B] band FWHM, nm
     std::vector<float> lsat;      // [B] saturation levels (+inf: none)
     bool has_endmembers = false;  // the endmember section holds a library
+    bool s_zero = false;          // spherical albedo 0 on every band: 1 - S rho is exactly 1
 };
 
 namespace ff {

@@ -155,6 +155,7 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
 
     // ---- per-lane pixel state (identical on the L lanes of a group) ----
     bool has = false, exhausted = false, warm = false, static_taken = false;
+    bool szero = false;         // the pixel's table has S = 0 on every band
     bool fbmode = false;        // re-solving a failed warm start from the default start
     int it_prev = 0;            // iterations of the failed warm-started solve
     float rrr_prev = 0.f;       // its relative residual
@@ -235,6 +236,7 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                     rad = sd.radiance + pix * B;
                     tab = reinterpret_cast<const R*>(sd.table);
                     tab64 = sd.table64;
+                    szero = sd.s_zero != 0 && !sd.atm;
                     bool atm_ok = true;
                     if (sd.atm) {
                         const int a = sd.atm[pix];
@@ -292,7 +294,26 @@ lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
                     xe[j] = D->lo[j] + 0.5 * (D->hi[j] - D->lo[j]) * ((double)(phase == 0 ? z[j] : zt[j]) + 1.0);
             }
             double At[NT], gt[N];
-            const double Fe = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, tab64, xe, At, gt, sub, L);
+            // FP32 kernels drop the saturation mask when no pixel of the wave
+            // has a saturated band, and the one-component kernel the
+            // 1/(1 - S rho) factor when every pixel's table has S = 0 (the
+            // common cases; the sums are the same either way)
+            double Fe;
+            if constexpr (sizeof(R) == 4) {
+                const bool masked = __ballot(nvalid < launder(descp)->B) != 0ull;
+                bool s0 = false;
+                if constexpr (MODEL == FF_MODEL_LOGNORMAL_1) s0 = !masked && __ballot(!szero) == 0ull;
+                if constexpr (MODEL == FF_MODEL_LOGNORMAL_1) {
+                    if (s0) Fe = evaluate<R, ACC, MODEL, Q, false, true>(descp, rad, tab, tab64, xe, At, gt, sub, L);
+                    else if (masked) Fe = evaluate<R, ACC, MODEL, Q, true>(descp, rad, tab, tab64, xe, At, gt, sub, L);
+                    else Fe = evaluate<R, ACC, MODEL, Q, false>(descp, rad, tab, tab64, xe, At, gt, sub, L);
+                } else {
+                    Fe = masked ? evaluate<R, ACC, MODEL, Q, true>(descp, rad, tab, tab64, xe, At, gt, sub, L)
+                                : evaluate<R, ACC, MODEL, Q, false>(descp, rad, tab, tab64, xe, At, gt, sub, L);
+                }
+            } else {
+                Fe = evaluate<R, ACC, MODEL, Q>(descp, rad, tab, tab64, xe, At, gt, sub, L);
+            }
             nevals += head ? 1 : 0;
 
             // -------------------------------------------- LM bookkeeping
@@ -681,6 +702,7 @@ static ff_status launch_lm(const BatchSpec& bs)
             d.iters = out.iters;
             d.status = out.status;
             d.state64 = out.state_f64;
+            d.s_zero = bs.scenes[s]->s_zero ? 1 : 0;
             off += bs.P[s];
         }
         for (int s = ns; s < kMaxScenesPerLaunch; ++s) prm.sc[s].offset = INT64_MAX;

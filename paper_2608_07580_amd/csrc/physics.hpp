@@ -320,13 +320,16 @@ struct PixelModel<R, FF_MODEL_LOGNORMAL_1, Q> {
         r1 = (R)x[4];
         node_inverse_temperatures_lanes<R, Q>(lognormal(x[1], x[2]), u, lane, L);
     }
-    // Basis u_b (J row = -D M u_b) and model radiance at one band.
+    // Basis u_b (J row = -D M u_b) and model radiance at one band.  S0: the
+    // table's S is 0 on every band, so 1/(1 - S rho) is 1 (the reciprocal of
+    // exactly 1 is exactly 1 on this hardware) and is not formed.
+    template <bool S0 = false>
     __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N]) const
     {
         R sI, sM, sS;
         thermal_sums<Q>(t.a2, u, o, sI, sM, sS);
         const R rho = r0 + r1 * t.dl;
-        const R rden = fast_rcp<R>((R)1 - t.S * rho);
+        const R rden = S0 ? (R)1 : fast_rcp<R>((R)1 - t.S * rho);
         const R ls = t.K * (t.ratm + t.tau2 * rho * rden);
         ub[0] = t.tup * t.cb * sI;
         ub[1] = t.tup * t.cj * sM;
@@ -409,12 +412,15 @@ struct PixelModel<R, FF_MODEL_ENDMEMBER_1, Q> {
 
 // Model radiance and basis at band b of a scene table (tab: band rows, then
 // for the endmember model the library rows); row receives the band row.
-template <int MODEL, typename PM, typename R>
+template <int MODEL, bool S0 = false, typename PM, typename R>
 __device__ __forceinline__ R band_of(const PM& pm, const R* __restrict__ tab, int B, int b, int o,
                                      const BandRow<R>& row, R (&ub)[PM::N])
 {
+    static_assert(!S0 || MODEL == FF_MODEL_LOGNORMAL_1, "the S = 0 path exists for the one-component model");
     if constexpr (simplex_first_v<MODEL> >= 0)
         return pm.band(row, load_endm(tab + (size_t)B * FF_TABLE_COLS + (size_t)b * kEndmCols), o, ub);
+    else if constexpr (S0)
+        return pm.template band<true>(row, o, ub);
     else
         return pm.band(row, o, ub);
 }
@@ -431,10 +437,12 @@ struct SurfaceDims {
 // rho = rho0 + rho1 (lambda - 1440 nm) or sum_k x_k E_k, from the scene's
 // FP64 table (band rows, then the library rows) and the FP64 surface
 // variables sv.  1/(1 - S rho) is the FP32 reciprocal refined by one Newton
-// step (relative error ~1e-14; exactly 1 when S rho = 0).
-template <int MODEL>
+// step (relative error ~1e-14; exactly 1 when S rho = 0).  S0 (S = 0 on every
+// band): the reciprocal is the caller's `one`, an opaque 1, so the FMA and
+// its rounding are those of the general path.
+template <int MODEL, bool S0 = false>
 __device__ __forceinline__ double solar_fp64(const double* __restrict__ t64, int B, int b,
-                                             const double (&sv)[SurfaceDims<MODEL>::NS])
+                                             const double (&sv)[SurfaceDims<MODEL>::NS], double one = 1.0)
 {
     const double* row = t64 + (size_t)b * FF_TABLE_COLS;
     const double2 p0 = *reinterpret_cast<const double2*>(row);       // lambda, K
@@ -455,10 +463,15 @@ __device__ __forceinline__ double solar_fp64(const double* __restrict__ t64, int
         const double dl = row[10];
         rho = fma(sv[1], dl, sv[0]);
     }
-    const double den = fma(-p2.y, rho, 1.0);
-    const double r0 = (double)__builtin_amdgcn_rcpf((float)den);
-    const double rden = fma(r0, fma(-den, r0, 1.0), r0);
-    return p0.y * fma(p1.x * rho, rden, p2.x);
+    if constexpr (S0) {
+        return p0.y * fma(p1.x * rho, one, p2.x);
+    } else {
+        (void)one;
+        const double den = fma(-p2.y, rho, 1.0);
+        const double r0 = (double)__builtin_amdgcn_rcpf((float)den);
+        const double rden = fma(r0, fma(-den, r0, 1.0), r0);
+        return p0.y * fma(p1.x * rho, rden, p2.x);
+    }
 }
 
 template <typename R, int Q>

@@ -1,6 +1,7 @@
 // Scene setup: Gaussian spectral-response resampling of the high-resolution
 // atmosphere onto the instrument bands and the per-band constants of the
 // forward model (eq. solar, eq. thermal).  One workgroup per band, FP64.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -141,6 +142,8 @@ extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm
     sc->n_bands = B;
     sc->lambda.assign(srf->wavelength_nm, srf->wavelength_nm + B);
     sc->fwhm.assign(srf->fwhm_nm, srf->fwhm_nm + B);
+    // every resampled S_b is then exactly 0 (a weighted mean of zeros)
+    sc->s_zero = std::all_of(atm->s_sph, atm->s_sph + H, [](double v) { return v == 0.0; });
     if (atm->sat_level) sc->lsat.assign(atm->sat_level, atm->sat_level + B);
     else sc->lsat.assign(B, INFINITY);
     hipError_t e = hipGetDevice(&sc->device);

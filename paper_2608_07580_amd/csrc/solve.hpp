@@ -35,6 +35,7 @@ struct SceneDev {
     int32_t* iters;
     uint32_t* status;
     double* state64;
+    int32_t s_zero;             // S = 0 on every band of the table (one scene table, no per-pixel atmospheres)
 };
 
 // Hide a pointer's value from the optimiser: loads through the result are
@@ -234,7 +235,14 @@ __device__ __forceinline__ void scan_pixel(const float* __restrict__ rad, const 
 // evaluation to the next -- about 3e-5 of the noise sigma (L / 300) per
 // residual and a few 1e-6 of F -- which the gain ratio and the stop tests
 // cannot tell from progress on f = 0 background pixels.
-template <typename R, typename ACC, int MODEL, int Q, typename Desc>
+//
+// MASKED = false drops the saturation mask from the band loop; it is valid
+// (and gives the same sums) only when every band of the pixel is below its
+// saturation level, which the caller knows from scan_pixel (nvalid == B).
+// S0 = true (one-component model) takes 1/(1 - S rho) as 1 without forming
+// it; valid only for a table whose S is 0 on every band, where the general
+// path's reciprocal is exactly 1 too, so the sums are the same.
+template <typename R, typename ACC, int MODEL, int Q, bool MASKED = true, bool S0 = false, typename Desc>
 __device__ __forceinline__ double evaluate(const Desc* descp, const float* __restrict__ rad,
                                       const R* __restrict__ tab, const double* __restrict__ tab64,
                                       const double (&x)[ModelDims<MODEL>::N],
@@ -253,6 +261,10 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
     for (int k = 0; k < NS; ++k) sv[k] = x[N - NS + k];
     ACC G[NT], h[N];
     double F = 0.0;
+    // the FP64 solar term's 1/(1 - S rho) when S = 0: a 1 the compiler
+    // cannot fold, so the term keeps the general path's FMA and rounding
+    double one = 1.0;
+    if constexpr (S0) asm volatile("" : "+v"(one));
 #pragma unroll
     for (int i = 0; i < NT; ++i) G[i] = (ACC)0;
 #pragma unroll
@@ -278,8 +290,8 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
             const int o = opaque_zero();
             const BandRow<R> row = load_row(tab + (size_t)b * FF_TABLE_COLS);
             R ub[N];
-            const R lm = band_of<MODEL>(pm, tab, B, b, o, row, ub);
-            const bool msk = (R)lob < row.lsat;
+            const R lm = band_of<MODEL, S0>(pm, tab, B, b, o, row, ub);
+            const bool msk = !MASKED || (R)lob < row.lsat;
             double r64;
             if constexpr (sizeof(R) == 8) {
                 r64 = (double)lob - (double)lm;
@@ -287,7 +299,7 @@ __device__ __forceinline__ double evaluate(const Desc* descp, const float* __res
             } else {
                 (void)lm;
                 const R lt = pm.f * ub[0];
-                r64 = ((double)lob - solar_fp64<MODEL>(tab64, B, b, sv)) - (double)lt;
+                r64 = ((double)lob - solar_fp64<MODEL, S0>(tab64, B, b, sv, one)) - (double)lt;
             }
             r64 = msk ? r64 : 0.0;
             const ACC r = (ACC)r64;
