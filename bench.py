@@ -52,8 +52,8 @@ PEAK_FP32_PUBLISHED = 157.3e12
 # kernel sources with the SHA-1 below; any other source reports null.
 TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
                    "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
-TRAFFIC_SHA1 = "187a7fdab8cb193a3e4b21ac71750145b5d3782d"
-TRAFFIC_BYTES = {"plain": 85.03e9, "warm": 83.31e9}
+TRAFFIC_SHA1 = "d6c21d9d5df414feb609bf427d7193f10e4d78c9"
+TRAFFIC_BYTES = {"plain": 85.49e9, "warm": 83.74e9}
 
 
 def measured_traffic(leg: str):
@@ -83,13 +83,22 @@ def nodes_evaluated(n_quad: int) -> int:
     return n_quad - {32: 5, 24: 2}.get(n_quad, 0)
 
 
-def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> float:
+# Issue cost the one-component kernel does not spend per band when the
+# scene's spherical albedo S is 0 on every band (1 - S rho is then exactly 1):
+# in FP32 the reflectance, 1 - S rho, its reciprocal and the two products by
+# it (5); in FP64 1 - S rho, the two Newton FMAs, the two conversions around
+# the FP32 seed and the seed.
+S0_SAVED_W = 5 + 3 * W_F64 + 2 * W_CVT + W_RCP
+
+
+def slots_per_eval(n_bands: int, n_quad: int, model: int = 1, s_zero: bool = False) -> float:
     """Issue cost, in 32-bit FMA equivalents, of one model + Jacobian +
     reduction evaluation of one pixel: NODE_W per (band, evaluated node) and component;
     per band and component 5 for the scaling (one of them the reciprocal of
     1 - S rho, counted as simple here), plus 19 (n = 5) / 49 (n = 8) for the
     solar term, basis, residual and the J^T J, J^T r, r.r accumulations, and
-    the FP64 residual's RESIDUAL64_W."""
+    the FP64 residual's RESIDUAL64_W; less S0_SAVED_W for the one-component
+    model on a scene with S = 0 on every band (s_zero)."""
     if model == 4:
         # one component; the endmember surface: 5 FMAs for rho and 5 basis
         # products where the linear surface has 2 and 2 (25), the n = 8
@@ -97,16 +106,20 @@ def slots_per_eval(n_bands: int, n_quad: int, model: int = 1) -> float:
         return n_bands * (NODE_W * nodes_evaluated(n_quad) + 5 + 25 + 45 + RESIDUAL64_W + 4 * W_F64 + 4)
     comps = 1 if model == 1 else 2
     per_band = comps * (NODE_W * nodes_evaluated(n_quad) + 5) + (19 + 21 if model == 1 else 49 + 45) + RESIDUAL64_W
+    if s_zero and model == 1:
+        per_band -= S0_SAVED_W
     return n_bands * per_band
 
 
-def flops_per_eval(n_bands: int, n_quad: int) -> int:
+def flops_per_eval(n_bands: int, n_quad: int, s_zero: bool = False) -> int:
     """Floating-point operations of one evaluation of the one-component model
     (FMA = 2, exp2 and rcp = 1 each): per (band, evaluated node) x = a u (1), 2^x (1),
     - 1 (1), rcp (1), three FMAs and q q + q (8), x (...) (1) = 13; per band
     72 for the reflectance, the basis, the FP64 solar term and residual and
-    the J^T J, J^T r, r.r accumulations."""
-    return n_bands * (13 * nodes_evaluated(n_quad) + 72)
+    the J^T J, J^T r, r.r accumulations (58 when S = 0 on every band: the
+    FP32 reflectance, 1 - S rho twice, the two reciprocals, the Newton step
+    and the two products by the reciprocal are not needed)."""
+    return n_bands * (13 * nodes_evaluated(n_quad) + (58 if s_zero else 72))
 
 
 def log(*a):
@@ -443,7 +456,7 @@ def run_ragged(args):
         pipe.close()
     seq_ms = sum(p["latency_ms"] for p in per_scene)
     w = legs["warm"]
-    spe = slots_per_eval(B, args.n_quad)
+    spe = slots_per_eval(B, args.n_quad, s_zero=all(not np.any(a.s_sph) for a in atms))
     achieved = w["evals"] * spe / (w["graph_ms_per_step"] * 1e-3)
     line = {
         "metric": "converged pixel retrievals/sec @284 bands, plain LM vs NN warm start, % roofline",
@@ -1275,9 +1288,10 @@ def main():
         torch.cuda.synchronize()
 
     head, ev_head = (warm, ev_warm) if args.start == "warm" else (plain, ev_plain)
-    spe = slots_per_eval(B, args.n_quad)
+    s_zero = not np.any(atm.s_sph)
+    spe = slots_per_eval(B, args.n_quad, s_zero=s_zero)
     achieved = ev_head * spe / (head["lm_kernel_ms"] * 1e-3)
-    fpe = flops_per_eval(B, args.n_quad)
+    fpe = flops_per_eval(B, args.n_quad, s_zero=s_zero)
     flops = ev_head * fpe / (head["lm_kernel_ms"] * 1e-3)
     start_desc = ("network warm start (trained per atmosphere, not timed) + LM with fallback"
                   if args.start == "warm" else "default start (plain LM)")
