@@ -47,6 +47,16 @@ static_assert(FF_TABLE_COLS == 12, "table layout");
 constexpr int kEndmCols = 8;
 static_assert(FF_N_ENDMEMBERS <= kEndmCols, "endmember row");
 
+// The FP32 table then holds the Planck ratios of the Gaussian-grid thermal
+// model on its kGridNodes-node temperature grid, which do not depend on the
+// pixel: row b, q_k = 1/(2^(a2_b / T_k) - 1), starts at
+// table + B * (FF_TABLE_COLS + kEndmCols) + b * kGridNodes (FP32 table only).
+constexpr int kGridNodes = 32;
+
+// Node i of the Q-node temperature grid of the Gaussian-mixture model, K.
+template <int Q>
+__host__ __device__ constexpr double grid_node(int i) { return 350.0 + (2200.0 - 350.0) * i / (Q - 1); }
+
 }  // namespace ff
 
 // Scene handle: per-band tables in device memory, FP32 and FP64 copies, and

@@ -417,7 +417,13 @@ __device__ __forceinline__ R band_of(const PM& pm, const R* __restrict__ tab, in
                                      const BandRow<R>& row, R (&ub)[PM::N])
 {
     static_assert(!S0 || MODEL == FF_MODEL_LOGNORMAL_1, "the S = 0 path exists for the one-component model");
-    if constexpr (simplex_first_v<MODEL> >= 0)
+    // grid models: the band's row of grid Planck ratios (FP32 tables only)
+    const R* qrow = tab + (size_t)B * (FF_TABLE_COLS + kEndmCols) + (size_t)b * kGridNodes;
+    if constexpr (grid_thermal_v<MODEL> && simplex_first_v<MODEL> >= 0)
+        return pm.band(row, load_endm(tab + (size_t)B * FF_TABLE_COLS + (size_t)b * kEndmCols), o, ub, qrow);
+    else if constexpr (grid_thermal_v<MODEL>)
+        return pm.band(row, o, ub, qrow);
+    else if constexpr (simplex_first_v<MODEL> >= 0)
         return pm.band(row, load_endm(tab + (size_t)B * FF_TABLE_COLS + (size_t)b * kEndmCols), o, ub);
     else if constexpr (S0)
         return pm.template band<true>(row, o, ub);
@@ -546,8 +552,7 @@ struct PixelModel<R, FF_MODEL_LOGNORMAL_2, Q> {
 //   S1 = sum p_i (d_i - m1) B_i,  S2 = sum p_i (d_i^2 - m2) B_i
 // (dp_i/dmu = p_i (d_i - m1)/sig^2, dp_i/dsig = p_i (d_i^2 - m2)/sig^3); the
 // centred forms avoid subtracting two large sums in FP32.
-template <int Q>
-__host__ __device__ constexpr double grid_node(int i) { return 350.0 + (2200.0 - 350.0) * i / (Q - 1); }
+// (grid_node<Q>(i), the i-th node temperature, is in ff_internal.hpp)
 
 // Node temperatures and their inverses in constant memory (pairs, so one
 // scalar load fetches both); read with a laundered zero offset at the point
@@ -606,18 +611,31 @@ __device__ inline GridComponent grid_component(double mu, double sig, R (&p)[Q])
 // q = e/(1 - e) (e = 2^(-a2/T_i), as in thermal_sums) shared by the two
 // components, then I, S1, S2 of each: 6 FMA-class + 2 subtractions per
 // component per node.
+// FP32 with the kGridNodes-node grid: the band's ratios come from the scene
+// table (qrow, written at scene creation by the same FP32 operations, so the
+// values are the ones computed here otherwise).
 template <int Q>
 __device__ __forceinline__ void grid_sums(float a2, const float (&ps)[Q], const float (&ph)[Q], float mus, float mus1,
-                                          float m2s, float muh, float muh1, float m2h, int o, float (&out)[6])
+                                          float m2s, float muh, float muh1, float m2h, int o, float (&out)[6],
+                                          const float* __restrict__ qrow)
 {
     float i0 = 0.f, s1 = 0.f, s2 = 0.f, j0 = 0.f, t1 = 0.f, t2 = 0.f;
     float a = a2;
     const GridNodes<float, Q>& gn = c_grid<float, Q>;
+    constexpr bool kTable = Q == kGridNodes;
+    float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         const float T = gn.ti[2 * k + o];
-        const float x = a * gn.ti[2 * k + 1 + o];
-        const float q = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x) - 1.0f);
+        float q;
+        if constexpr (kTable) {
+            if (k % 4 == 0) q4 = reinterpret_cast<const float4*>(qrow)[k / 4];
+            q = k % 4 == 0 ? q4.x : k % 4 == 1 ? q4.y : k % 4 == 2 ? q4.z : q4.w;
+        } else {
+            (void)qrow;
+            const float x = a * gn.ti[2 * k + 1 + o];
+            q = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x) - 1.0f);
+        }
         const float ys = ps[k] * q;
         i0 += ys;
         s1 = __builtin_fmaf(ys, T - mus1, s1);
@@ -636,8 +654,9 @@ __device__ __forceinline__ void grid_sums(float a2, const float (&ps)[Q], const 
 template <int Q>
 __device__ __forceinline__ void grid_sums(double a2, const double (&ps)[Q], const double (&ph)[Q], double mus,
                                           double mus1, double m2s, double muh, double muh1, double m2h, int o,
-                                          double (&out)[6])
+                                          double (&out)[6], const double* qrow)
 {
+    (void)qrow;
     double i0 = 0.0, s1 = 0.0, s2 = 0.0, j0 = 0.0, t1 = 0.0, t2 = 0.0;
     const GridNodes<double, Q>& gn = c_grid<double, Q>;
 #pragma unroll 4
@@ -684,10 +703,11 @@ struct PixelModel<R, FF_MODEL_GAUSS_GRID_2, Q> {
         muh1 = (R)gh.mu1;
         m2h = (R)gh.m2;
     }
-    __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N]) const
+    // qrow: the band's grid Planck ratios in the scene table (FP32)
+    __device__ __forceinline__ R band(const BandRow<R>& t, int o, R (&ub)[N], const R* qrow) const
     {
         R g[6];
-        grid_sums<Q>(t.a2, ps, ph, mus, mus1, m2s, muh, muh1, m2h, o, g);
+        grid_sums<Q>(t.a2, ps, ph, mus, mus1, m2s, muh, muh1, m2h, o, g, qrow);
         const R rho = r0 + r1 * t.dl;
         const R rden = fast_rcp<R>((R)1 - t.S * rho);
         const R ls = t.K * (t.ratm + t.tau2 * rho * rden);
@@ -759,10 +779,11 @@ struct PixelModel<R, FF_MODEL_FULL, Q> {
         muh1 = (R)gh.mu1;
         m2h = (R)gh.m2;
     }
-    __device__ __forceinline__ R band(const BandRow<R>& t, const EndmRow<R>& em, int o, R (&ub)[N]) const
+    __device__ __forceinline__ R band(const BandRow<R>& t, const EndmRow<R>& em, int o, R (&ub)[N],
+                                      const R* qrow) const
     {
         R g[6];
-        grid_sums<Q>(t.a2, ps, ph, mus, mus1, m2s, muh, muh1, m2h, o, g);
+        grid_sums<Q>(t.a2, ps, ph, mus, mus1, m2s, muh, muh1, m2h, o, g, qrow);
         R rho = xs[0] * em.e[0];
 #pragma unroll
         for (int k = 1; k < NE; ++k) rho += xs[k] * em.e[k];

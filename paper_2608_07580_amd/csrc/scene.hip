@@ -118,6 +118,27 @@ srf_endmembers(int B, int H, const double* __restrict__ lam_b, const double* __r
 }  // namespace
 }  // namespace ff
 
+namespace ff {
+namespace {
+
+struct GridInv {
+    float t[kGridNodes];   // 1/T_k of the grid nodes, as the kernels hold them
+};
+
+// Grid Planck ratios of the Gaussian-grid thermal model, one row per band:
+// q_k = 1/(2^(a2 * (1/T_k)) - 1), by the FP32 operations the band loop uses.
+__global__ void grid_planck(int B, const float* __restrict__ tab32, GridInv inv, float* __restrict__ out)
+{
+    const int b = blockIdx.x, k = threadIdx.x;
+    if (b >= B || k >= kGridNodes) return;
+    const float a2 = tab32[(size_t)b * FF_TABLE_COLS + COL_A2];
+    const float x = a2 * inv.t[k];
+    out[(size_t)b * kGridNodes + k] = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(x) - 1.0f);
+}
+
+}  // namespace
+}  // namespace ff
+
 using namespace ff;
 
 extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm, ff_scene** out)
@@ -156,10 +177,11 @@ extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm
     if (e == hipSuccess) e = hipMalloc(&sat_d, (size_t)B * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&bad_d, sizeof(int));
     const size_t n_tab = (size_t)B * (FF_TABLE_COLS + kEndmCols);
+    const size_t n_tab32 = n_tab + (size_t)B * kGridNodes;   // + the grid Planck ratios
     if (e == hipSuccess) e = hipMalloc(&sc->table_f64, n_tab * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&sc->table_f32, n_tab * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&sc->table_f32, n_tab32 * sizeof(float));
     if (e == hipSuccess) e = hipMemset(sc->table_f64, 0, n_tab * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(sc->table_f32, 0, n_tab * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(sc->table_f32, 0, n_tab32 * sizeof(float));
     if (e == hipSuccess) {
         std::vector<double> host(nd);
         std::memcpy(&host[0], srf->wavelength_nm, B * sizeof(double));
@@ -179,6 +201,12 @@ extern "C" ff_status ff_scene_create(const ff_srf* srf, const ff_atmosphere* atm
                            s + 2 * B + 4 * (size_t)H, s + 2 * B + 5 * (size_t)H,
                            atm->sat_level ? sat_d : nullptr, atm->cos_sza, sc->table_f64,
                            sc->table_f32, bad_d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        GridInv inv;
+        for (int k = 0; k < kGridNodes; ++k) inv.t[k] = (float)(1.0 / grid_node<kGridNodes>(k));
+        hipLaunchKernelGGL(grid_planck, dim3(B), dim3(kGridNodes), 0, 0, B, sc->table_f32, inv, sc->table_f32 + n_tab);
         e = hipGetLastError();
     }
     int bad = 0;
