@@ -710,19 +710,25 @@ def run_solvers(args):
     print(json.dumps(line), flush=True)
 
 
+# Grid nodes whose Planck ratios the scene tabulates (the FP32 32-node grid):
+# the ratio is then read, not evaluated per pixel.
+GRID_TABLE_NODES = 32
+
+
 def grid_slots_per_eval(n_bands: int, n_nodes: int, model: int = 3) -> int:
     """Algorithmic VALU slots of one evaluation of the Gaussian-mixture model
-    on the temperature grid, in 32-bit FMA equivalents: per (band, node) one
+    on the temperature grid, in 32-bit FMA equivalents: per (band, node) 7 per
+    component for its weight product and the three centred sums, plus one
     Planck ratio shared by the two components (x = a2/T, exp2, minus 1, rcp)
-    and 7 per
-    component for its weight product and the three centred sums; per band 25
-    for the scaling, solar term, basis and residual and 45 for the J^T J,
-    J^T r, r.r accumulations (n = 8), and the FP64 residual's RESIDUAL64_W.
-    The full model (endmember surface, n = 11) adds 6 for the five-term
-    reflectance and basis, accumulates 78, and forms the FP64 reflectance
-    with four more FP64 FMAs."""
+    unless the scene tabulates the grid's ratios (n_nodes == GRID_TABLE_NODES:
+    they do not depend on the pixel); per band 25 for the scaling, solar term,
+    basis and residual and 45 for the J^T J, J^T r, r.r accumulations (n = 8),
+    and the FP64 residual's RESIDUAL64_W.  The full model (endmember surface,
+    n = 11) adds 6 for the five-term reflectance and basis, accumulates 78,
+    and forms the FP64 reflectance with four more FP64 FMAs."""
     per_band = 25 + 45 if model == 3 else 25 + 6 + 78 + 4 * W_F64
-    return n_bands * (n_nodes * (2 + W_EXP2 + W_RCP + 2 * 7) + per_band + RESIDUAL64_W)
+    ratio = 0 if n_nodes == GRID_TABLE_NODES else 2 + W_EXP2 + W_RCP
+    return n_bands * (n_nodes * (ratio + 2 * 7) + per_band + RESIDUAL64_W)
 
 
 def run_paper_model(args, model: int = 3):
