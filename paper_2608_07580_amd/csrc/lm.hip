@@ -135,14 +135,16 @@ __device__ __forceinline__ bool converged_gradient(const double (&z)[N], const d
 
 // Occupancy target (second launch bound, waves per SIMD), FP32 kernels: the
 // one-component model runs three waves per SIMD (at most 168 VGPRs) and the
-// two-lognormal and endmember models two (256 registers); the band loop stays
-// free of spills and some per-pixel state outside it goes to scratch.  The
-// grid-mixture models are faster at the compiler's one wave (measured), and
-// so is FP64.
+// two-lognormal, endmember and Gaussian-grid models two (256 registers); the
+// band loop stays free of spills and some per-pixel state outside it goes to
+// scratch.  The full model (grid thermal term over the endmember surface) is
+// faster at the compiler's one wave (measured: two waves spill its band
+// loop), and so is FP64.
 template <typename R, typename ACC, int MODEL, int Q>
 __global__ void __launch_bounds__(256, sizeof(R) != 4 ? 1
                                        : MODEL == FF_MODEL_LOGNORMAL_1 ? 3
-                                       : (MODEL == FF_MODEL_LOGNORMAL_2 || MODEL == FF_MODEL_ENDMEMBER_1) ? 2 : 1)
+                                       : (MODEL == FF_MODEL_LOGNORMAL_2 || MODEL == FF_MODEL_ENDMEMBER_1
+                                          || MODEL == FF_MODEL_GAUSS_GRID_2) ? 2 : 1)
 lm_kernel(const LmDesc<R, Q>* __restrict__ descp)
 {
     using PM = PixelModel<R, MODEL, Q>;
