@@ -52,7 +52,7 @@ PEAK_FP32_PUBLISHED = 157.3e12
 # kernel sources with the SHA-1 below; any other source reports null.
 TRAFFIC_SOURCES = ("paper_2608_07580_amd/csrc/lm.hip", "paper_2608_07580_amd/csrc/solve.hpp",
                    "paper_2608_07580_amd/csrc/physics.hpp", "paper_2608_07580_amd/csrc/ff_internal.hpp")
-TRAFFIC_SHA1 = "369569cf1cce342dabf20d341cfe9eea07dff1e4"
+TRAFFIC_SHA1 = "aaabbb54cc282686ea010bf61436005a3b6c5981"
 TRAFFIC_BYTES = {"plain": 85.49e9, "warm": 83.74e9}
 
 
