@@ -153,6 +153,16 @@ def test_pipeline_argument_checks():
     net = ff.WarmStart(n_in=100, seed=1)                    # inputs != 284 bands
     with pytest.raises(ff.FirefitError):
         ff.Pipeline(scenes, rads, ff.default_prior(1), net=net)
+    with pytest.raises(ff.FirefitError):                    # routed with a NaN threshold
+        ff.Pipeline(scenes, rads, ff.default_prior(1), net=ff.WarmStart(seed=1), route=float("nan"))
+    # routed without any network: nothing to route, the plain pipeline's outputs
+    plain = ff.Pipeline(scenes, rads, ff.default_prior(1))
+    routed = ff.Pipeline(scenes, rads, ff.default_prior(1), route=ff.HFDI_THRESHOLD)
+    torch.cuda.synchronize()
+    for k in KEYS:
+        np.testing.assert_array_equal(routed.outputs[0].numpy()[k], plain.outputs[0].numpy()[k])
+    plain.close()
+    routed.close()
     # the default (null) stream is fine for create and launch
     pipe = ff.Pipeline(scenes, rads, ff.default_prior(1), stream=torch.cuda.default_stream(dev))
     ref = pipe.outputs[0].numpy()
