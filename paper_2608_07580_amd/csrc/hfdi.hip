@@ -3,15 +3,16 @@
 // and the list of candidate pixels, in increasing order, built on the device.
 //
 // Three launches, no host round trip: (1) each workgroup takes a tile of
-// kTile pixels, writes their index values and counts its candidates; (2) one
-// workgroup scans the tile counts into tile offsets and the total; (3) each
-// workgroup recomputes its tile's flags and writes the candidates' pixel
-// numbers at its offset, ordered by a wave ballot prefix and a prefix over
-// the waves of the workgroup.  The list is therefore deterministic and
-// sorted, and the total is left in device memory for the retrieval to read.
+// kTile pixels, writes their index values, keeps each wave's candidate flags
+// as one 64-bit ballot per step and counts its candidates; (2) one workgroup
+// scans the tile counts into tile offsets and the total; (3) each workgroup
+// reads its tile's ballots back and writes the candidates' pixel numbers at
+// its offset, ordered by the ballot prefix and a prefix over the waves of
+// the workgroup.  The list is therefore deterministic and sorted, and the
+// total is left in device memory for the retrieval to read.
 //
 // Reads: two radiance values per pixel (separate cache lines of the row),
-// twice; the pass is HBM-latency bound and small next to any retrieval.
+// once; the pass is HBM-latency bound and small next to any retrieval.
 #include <algorithm>
 #include <cmath>
 
@@ -44,20 +45,29 @@ __device__ __forceinline__ bool candidate(const HfdiArgs& a, int64_t p, float& h
     return (double)h >= a.threshold || la >= a.sat_a || lb >= a.sat_b;
 }
 
+// Ballots of one tile: kPerThread steps x (kThreads / 64) waves.
+constexpr int kTileMasks = kPerThread * (kThreads / 64);
+
 __global__ void __launch_bounds__(kThreads) hfdi_count(HfdiArgs a, float* __restrict__ hfdi_out,
-                                                       int64_t* __restrict__ tile_count)
+                                                       int64_t* __restrict__ tile_count,
+                                                       unsigned long long* __restrict__ masks)
 {
     __shared__ int wave_n[kThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int n = 0;
 #pragma unroll 4
     for (int k = 0; k < kPerThread; ++k) {
         const int64_t p = base + (int64_t)k * kThreads + threadIdx.x;
+        bool c = false;
         if (p < a.P) {
             float h;
-            n += candidate(a, p, h) ? 1 : 0;
+            c = candidate(a, p, h);
+            n += c ? 1 : 0;
             if (hfdi_out) hfdi_out[p] = h;
         }
+        const unsigned long long m = __ballot(c);
+        if (lane == 0) masks[(size_t)blockIdx.x * kTileMasks + k * (kThreads / 64) + wave] = m;
     }
     for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off);
     if ((threadIdx.x & 63) == 0) wave_n[threadIdx.x >> 6] = n;
@@ -97,7 +107,8 @@ __global__ void __launch_bounds__(1024) scan_tiles(const int64_t* __restrict__ t
     if (t == 1023) *count = part[1023];
 }
 
-__global__ void __launch_bounds__(kThreads) hfdi_write(HfdiArgs a, const int64_t* __restrict__ tile_off,
+__global__ void __launch_bounds__(kThreads) hfdi_write(const int64_t* __restrict__ tile_off,
+                                                       const unsigned long long* __restrict__ masks,
                                                        int64_t* __restrict__ index_out)
 {
     __shared__ int wave_n[kThreads / 64];
@@ -106,9 +117,9 @@ __global__ void __launch_bounds__(kThreads) hfdi_write(HfdiArgs a, const int64_t
     int64_t off = tile_off[blockIdx.x];
     for (int k = 0; k < kPerThread; ++k) {
         const int64_t p = base + (int64_t)k * kThreads + threadIdx.x;
-        float h;
-        const bool c = p < a.P && candidate(a, p, h);
-        const unsigned long long m = __ballot(c);
+        // the count pass's ballot for this step and wave (pixels past P are 0)
+        const unsigned long long m = masks[(size_t)blockIdx.x * kTileMasks + k * (kThreads / 64) + wave];
+        const bool c = ((m >> lane) & 1ull) != 0;
         const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
         if (lane == 0) wave_n[wave] = __popcll(m);
         __syncthreads();
@@ -154,11 +165,13 @@ extern "C" ff_status ff_hfdi_candidates(const ff_scene* scene, const float* radi
     const int n_tiles = (int)std::max<int64_t>(n_tiles64, 1);
     int64_t* scratch = nullptr;
     {
-        const ff_status st = stream_scratch(s, (size_t)2 * n_tiles * sizeof(int64_t), reinterpret_cast<void**>(&scratch));
+        const size_t bytes = (size_t)2 * n_tiles * sizeof(int64_t) + (size_t)n_tiles * kTileMasks * sizeof(uint64_t);
+        const ff_status st = stream_scratch(s, bytes, reinterpret_cast<void**>(&scratch));
         if (st != FF_OK) return st;
     }
     int64_t* tile_count = scratch;
     int64_t* tile_off = scratch + n_tiles;
+    auto* masks = reinterpret_cast<unsigned long long*>(scratch + 2 * (size_t)n_tiles);
 
     HfdiArgs a;
     a.rad = radiance_dev;
@@ -171,12 +184,12 @@ extern "C" ff_status ff_hfdi_candidates(const ff_scene* scene, const float* radi
     a.threshold = threshold;
 
     // with P = 0 the one tile counts nothing and the total becomes 0
-    hipLaunchKernelGGL(hfdi_count, dim3(n_tiles), dim3(kThreads), 0, s, a, hfdi_dev, tile_count);
+    hipLaunchKernelGGL(hfdi_count, dim3(n_tiles), dim3(kThreads), 0, s, a, hfdi_dev, tile_count, masks);
     FF_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(1024), 0, s, tile_count, n_tiles, tile_off, count_dev);
     FF_HIP_TRY(hipGetLastError());
     if (P > 0) {
-        hipLaunchKernelGGL(hfdi_write, dim3(n_tiles), dim3(kThreads), 0, s, a, tile_off, index_dev);
+        hipLaunchKernelGGL(hfdi_write, dim3(n_tiles), dim3(kThreads), 0, s, tile_off, masks, index_dev);
         FF_HIP_TRY(hipGetLastError());
     }
     return clear_error();
