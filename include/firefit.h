@@ -394,8 +394,10 @@ ff_status ff_retrieve_atm_indexed(const ff_scene* const* atmospheres, int32_t n_
  *   in increasing order in its first *count_dev entries; count_dev: one
  *   int64 in device memory, receives the number of candidates.
  * Asynchronous on stream; the count stays on the device (pass it to
- * ff_retrieve_listed without reading it back).  Per-tile counters live in
- * the stream's scratch buffer (see ff_retrieve_scene).  FF_EINVAL for NULL
+ * ff_retrieve_listed without reading it back).  Per-tile counters and the
+ * candidate flags (one bit per pixel, kept between the counting and the
+ * writing pass) live in the stream's scratch buffer (see
+ * ff_retrieve_scene).  FF_EINVAL for NULL
  * arguments, P < 0 or a NaN threshold. */
 ff_status ff_hfdi_candidates(const ff_scene* scene, const float* radiance_dev, int64_t P, double threshold,
                              float* hfdi_dev, int64_t* index_dev, int64_t* count_dev, void* stream);
