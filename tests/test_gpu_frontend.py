@@ -81,6 +81,34 @@ def test_candidate_list_sizes(dev, P):
     np.testing.assert_array_equal(h, hw)
 
 
+def test_candidates_without_index_values_and_scratch_reuse(dev):
+    """The writing pass takes the candidate decisions the counting pass kept
+    in the stream's scratch, so the list must not depend on whether the
+    index values are written, nor on what an earlier call of another size
+    left in that scratch: calls of 70,000, 1,000 and 70,000 pixels in a row on
+    one stream, with and without index values, each equal to the oracle."""
+    atm = scenegen.make_atmosphere(0, 0)
+    tab = oracle.band_tables(atm)
+    scene = ff.Scene(atm)
+    rng = np.random.default_rng(11)
+    lobs = rng.uniform(0.0, 1.0, (70000, tab.B)).astype(np.float32)
+    stream = torch.cuda.Stream(device=dev)
+    for P, thr, values in ((70000, -0.1, False), (1000, 0.2, True), (70000, 0.05, False), (70000, -0.1, True)):
+        rad = torch.from_numpy(np.ascontiguousarray(lobs[:P])).to(dev)
+        with torch.cuda.stream(stream):
+            idx, cnt, h = ff.hfdi_candidates(scene, rad, thr, with_index_values=values, stream=stream)
+        torch.cuda.synchronize()
+        want, hw = oracle.hfdi_candidates(tab, lobs[:P], thr)
+        n = int(cnt.item())
+        print(f"  P={P} threshold {thr} values {values}: {n} candidates")
+        assert n == len(want)
+        np.testing.assert_array_equal(idx[:n].cpu().numpy(), want)
+        if values:
+            np.testing.assert_array_equal(h.cpu().numpy(), hw)
+        else:
+            assert h is None
+
+
 def test_listed_retrieval_equals_the_full_retrieval(clustered, dev):
     """Listed rows get exactly the full retrieval's outputs (same kernel,
     same launch shape); rows not listed are left untouched; list entries
