@@ -1209,7 +1209,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU per process and this benchmark on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "valu-rates":
         run_valu_rates(args)
